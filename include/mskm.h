@@ -1,0 +1,223 @@
+/*
+ * mskm.h -- C ABI of the MI355X (gfx950) multiscale kernel solver.
+ *
+ * The library computes the monolithic kernel-based multiscale approximation of
+ * Lot & Rieger, "Efficiently parallelizable kernel-based multi-scale algorithm"
+ * (arXiv 2503.04914):
+ *
+ *   given nested (or arbitrary) point sets X_1, ..., X_L in R^d (d = 2, 3),
+ *   support radii delta_1, ..., delta_L and samples f|X_l, find coefficients
+ *   alpha^(l) such that the block-lower-triangular system T_L alpha = f of
+ *   eq. (bigt) holds, with blocks
+ *       B_{k,j}[i][n] = phi(||x_i^(k) - x_n^(j)|| / delta_j),   A_l = B_{l,l},
+ *   phi = phi_{3,1}(r) = (1-r)_+^4 (4r+1) (Section 5). The solve follows the
+ *   split D alpha = beta, T' beta = f of eq. (split): Jacobi sweeps on T'
+ *   (Theorem jacobi) whose inner solves, like the final D alpha = beta, are
+ *   per-level conjugate gradients on the SPD blocks A_l (Theorem cg), all
+ *   levels in one launch. The approximant is
+ *       f_L(y) = sum_l sum_n alpha_n^(l) phi(||y - x_n^(l)|| / delta_l)
+ *   (eq. (fapproximation)).
+ *
+ * Conventions
+ *   - Kernel scaling: unit peak, phi(||x-y||/delta). The paper's eq.
+ *     (kernelscaling) carries an extra factor delta^-d; its coefficients are
+ *     delta_l^d times the ones returned here. The approximant is identical.
+ *   - Support: (i, n) is a structural nonzero iff d2 < delta_j*delta_j with
+ *     d2 = dx*dx + dy*dy (+ dz*dz) evaluated left to right in FP64, each
+ *     operation rounded separately (no fused multiply-add).
+ *   - Indexing: "global input index" = position in the concatenated point
+ *     array (level 0 first). Level l occupies [level_offsets[l],
+ *     level_offsets[l+1]).
+ *   - Multi-RHS vectors are row-major [N][nrhs] (point-major).
+ *
+ * Ownership and memory
+ *   - The caller owns every buffer it passes and allocates every output.
+ *   - Without MSKM_IO_DEVICE, array arguments are host pointers and calls
+ *     return after the results are in host memory.
+ *   - With MSKM_IO_DEVICE in the call's flags, f / alpha / query / out
+ *     arguments are device pointers on the context's device (for instance
+ *     torch tensors); work is issued on the context stream. Calls still wait
+ *     for completion before returning (the solver reads convergence flags).
+ *   - Handles are opaque; a context must not be used from two threads at once.
+ *
+ * Errors
+ *   MSKM_OK (0) on success. Negative values: failure, outputs undefined.
+ *   Positive values: warning, outputs written (MSKM_ENOCONV: tolerance not
+ *   reached within the iteration caps; the report holds what was reached).
+ *   mskm_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef MSKM_H
+#define MSKM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSKM_ABI_VERSION 1
+
+typedef int32_t mskm_status;
+enum {
+  MSKM_OK = 0,
+  MSKM_ENOCONV = 1,   /* warning: tolerance not met, outputs written */
+  MSKM_EINVAL = -1,   /* bad argument */
+  MSKM_ENOMEM = -2,   /* device or host allocation failed */
+  MSKM_EDEVICE = -3,  /* HIP runtime error */
+  MSKM_ELIMIT = -4,   /* a size exceeds an index range (int32 columns etc.) */
+  MSKM_ESTATE = -5    /* handle in the wrong state (e.g. no FP64 values) */
+};
+
+/* kernels */
+enum { MSKM_WENDLAND_3_1 = 31 };
+
+/* flags of mskm_hier_desc.flags */
+enum {
+  MSKM_POINTS_ON_DEVICE = 1 << 0, /* points is a device pointer */
+  MSKM_STORE_FP64 = 1 << 1,       /* keep FP64 block values (plain path) */
+  MSKM_STORE_FP32 = 1 << 2        /* keep FP32 block values (mixed path) */
+};
+
+/* flags of calls taking vectors */
+enum { MSKM_IO_DEVICE = 1 << 0 };
+
+typedef struct mskm_ctx mskm_ctx;
+typedef struct mskm_hier mskm_hier;
+
+/* ---------------------------------------------------------------- context */
+
+/* Bind device `device` and the HIP stream `hip_stream` (a hipStream_t, or
+ * NULL to let the library create its own). The context owns nothing the
+ * caller passed. Fails with MSKM_EDEVICE if the device cannot be used. */
+mskm_status mskm_create(int32_t device, void* hip_stream, mskm_ctx** out);
+mskm_status mskm_destroy(mskm_ctx* ctx);
+
+/* Thread-local description of the last failure ("" if none). */
+const char* mskm_last_error(void);
+
+/* Library ABI version (MSKM_ABI_VERSION). */
+int32_t mskm_abi_version(void);
+
+/* -------------------------------------------------------------- hierarchy */
+
+typedef struct {
+  int32_t dim;                  /* 2 or 3 */
+  int32_t levels;               /* L >= 1 */
+  const int64_t* level_offsets; /* host, [L+1], 0 = off[0] <= off[1] <= ... */
+  const double* points;         /* AoS [N][dim], N = off[L]; host unless POINTS_ON_DEVICE */
+  const double* delta;          /* host, [L], finite and > 0 */
+  int32_t kernel;               /* MSKM_WENDLAND_3_1 */
+  int32_t flags;                /* MSKM_POINTS_ON_DEVICE | MSKM_STORE_FP64 | MSKM_STORE_FP32;
+                                   neither STORE flag means STORE_FP64 */
+} mskm_hier_desc;
+
+/* Cell lists per level, neighbour search for every level pair k >= j and
+ * evaluation of all blocks B_{k,j} (Section 3) into device-resident CSR:
+ * one CSR for the block diagonal D_L and one for the strict lower part
+ * T_L - D_L. Points are copied; the caller may free them on return.
+ * MSKM_ELIMIT if N >= 2^31 or a row would exceed 2^31 entries. */
+mskm_status mskm_hier_create(mskm_ctx* ctx, const mskm_hier_desc* desc, mskm_hier** out);
+mskm_status mskm_hier_destroy(mskm_hier* h);
+
+typedef struct {
+  int32_t dim, levels;
+  int64_t n_total;
+  int64_t nnz_diag;   /* structural nonzeros of D_L */
+  int64_t nnz_lower;  /* structural nonzeros of T_L - D_L */
+  int32_t has_fp64, has_fp32;
+  int64_t device_bytes; /* device memory held by the hierarchy */
+  double assemble_ms;   /* device time of the last assembly */
+} mskm_hier_stats;
+
+mskm_status mskm_hier_stats_get(const mskm_hier* h, mskm_hier_stats* out);
+
+/* The level offsets the hierarchy was created with: off[0..L] (host). */
+mskm_status mskm_hier_offsets(const mskm_hier* h, int64_t* off);
+
+/* Export block B_{row_level, col_level} (row_level >= col_level) in
+ * canonical CSR: rows in input order of level row_level, columns = input
+ * index within level col_level, ascending. rowptr has N(row_level)+1
+ * entries. Pass col == NULL to query the entry count into *nnz_out only.
+ * val may be NULL; it receives FP64 values (or FP32 values widened when
+ * only FP32 is stored). Host pointers. */
+mskm_status mskm_export_block(mskm_ctx* ctx, const mskm_hier* h, int32_t row_level, int32_t col_level,
+                              int64_t* rowptr, int32_t* col, double* val, int64_t* nnz_out);
+
+/* Internal (spatially sorted) order: perm[i] = global input index of
+ * internal position i. Host pointer, [N]. */
+mskm_status mskm_export_perm(mskm_ctx* ctx, const mskm_hier* h, int32_t* perm);
+
+/* ------------------------------------------------------------------ apply */
+
+enum {
+  MSKM_OP_DIAG = 0,  /* y = D_L x      (block diagonal, eq. (matrix_decomposition)) */
+  MSKM_OP_LOWER = 1, /* y = (T_L - D_L) x (strict lower blocks) */
+  MSKM_OP_FULL = 2   /* y = T_L x      (eq. (bigt)) */
+};
+enum { MSKM_PREC_FP64 = 0, MSKM_PREC_FP32 = 1 };
+
+/* y = op x with x, y [N][nrhs] in input order (FP64). prec selects which
+ * stored values are applied (FP32: values and accumulation in FP32, x
+ * rounded to FP32). */
+mskm_status mskm_apply(mskm_ctx* ctx, const mskm_hier* h, int32_t op, int32_t prec, const double* x, int32_t nrhs,
+                       double* y, int32_t flags);
+
+/* ------------------------------------------------------------------ solve */
+
+enum { MSKM_ALG_MONOLITHIC = 0, MSKM_ALG_SEQUENTIAL = 1 };
+enum { MSKM_PRECOND_NONE = 0, MSKM_PRECOND_LEARNED = 1 };
+
+typedef struct mskm_mlp mskm_mlp;
+
+typedef struct {
+  int32_t precision;      /* MSKM_PREC_FP64: plain path. MSKM_PREC_FP32: FP32 values and
+                             accumulation inside, FP64 dots, FP64 residual refinement */
+  int32_t algorithm;      /* MSKM_ALG_MONOLITHIC (Jacobi on T' + CG on D, eq. (split)) or
+                             MSKM_ALG_SEQUENTIAL (block forward substitution, eq. (mas)) */
+  double cg_rtol;         /* per-level CG stop: ||r|| <= cg_rtol * ||b|| */
+  int32_t sweeps;         /* Jacobi sweeps; <= 0 means L */
+  int32_t max_cg_iters;   /* cap per CG solve; <= 0 means 20000 */
+  int32_t warm_start;     /* 1: CG of sweep m starts from sweep m-1's solution */
+  double target_rel_residual; /* mixed path: stop refining when ||f-T alpha||/||f|| <= this */
+  int32_t max_refine;     /* mixed path: cap on refinement steps; <= 0 means 10 */
+  int32_t precond;        /* MSKM_PRECOND_NONE or MSKM_PRECOND_LEARNED (warm start) */
+  const mskm_mlp* mlp;    /* network for MSKM_PRECOND_LEARNED */
+  int32_t check_every;    /* CG convergence poll interval; <= 0 means 8 */
+  int32_t flags;          /* MSKM_IO_DEVICE */
+} mskm_solve_opts;
+
+/* Defaults: FP64, monolithic, cg_rtol 1e-12, L sweeps, no warm start. */
+void mskm_solve_opts_default(mskm_solve_opts* o);
+
+typedef struct {
+  int32_t levels;
+  int32_t sweeps_done;
+  int32_t refine_steps;
+  int64_t cg_iters_total;        /* sum over all CG solves and levels */
+  int32_t cg_iters_last[64];     /* iterations of each level's last CG solve (levels <= 64) */
+  double rel_residual;           /* ||f - T alpha|| / ||f|| (FP64), max over rhs */
+  double solve_ms;               /* device time of the solve */
+  int32_t warm_fallbacks;        /* learned warm starts rejected (||b - A x0|| >= ||b||) */
+} mskm_report;
+
+/* alpha = T_L^-1 f per right-hand side (Section 3). f, alpha: [N][nrhs] FP64
+ * in input order. rep may be NULL. MSKM_ENOCONV when a CG cap or
+ * max_refine was hit. */
+mskm_status mskm_solve(mskm_ctx* ctx, const mskm_hier* h, const double* f, int32_t nrhs,
+                       const mskm_solve_opts* opts, double* alpha, mskm_report* rep);
+
+/* ||f - T_L alpha||_2 / ||f||_2 per right-hand side, FP64 accurate values
+ * (eq. (bigt)). rel_out: host [nrhs]. */
+mskm_status mskm_residual(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, const double* f, int32_t nrhs,
+                          double* rel_out, int32_t flags);
+
+/* f_L at query points (eq. (fapproximation)): out[q][r] = sum over levels.
+ * query: [nq][dim]; out: [nq][nrhs]. */
+mskm_status mskm_evaluate(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, int32_t nrhs, const double* query,
+                          int64_t nq, double* out, int32_t flags);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSKM_H */

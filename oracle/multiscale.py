@@ -78,6 +78,8 @@ def cg(A, b: np.ndarray, rtol: float, x0: np.ndarray | None = None, maxiter: int
     ||r||_2 <= rtol * ||b||_2. Returns (x, iterations).
     """
     b = np.asarray(b, dtype=np.float64)
+    if b.shape[0] == 0:
+        return np.zeros(0), 0
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
     r = b - A @ x if x0 is not None else b.copy()
     bnorm = np.linalg.norm(b)
@@ -103,6 +105,8 @@ def cg(A, b: np.ndarray, rtol: float, x0: np.ndarray | None = None, maxiter: int
 def cholesky_solve(A, b: np.ndarray) -> np.ndarray:
     """Direct solve of the SPD system A x = b by dense Cholesky A = C C^T."""
     Ad = A.toarray() if sp.issparse(A) else np.asarray(A)
+    if Ad.shape[0] == 0:
+        return np.zeros(0)
     C = np.linalg.cholesky(Ad)
     y = sla.solve_triangular(C, b, lower=True)
     return sla.solve_triangular(C.T, y, lower=False)

@@ -1,0 +1,287 @@
+"""MI355X (gfx950) multiscale kernel solver: thin Python binding of ``libmskm.so``.
+
+The functions here carry the C ABI's names (see ``include/mskm.h``) and only
+marshal arguments: every step of assembly, solve, residual and evaluation runs
+in the library's HIP kernels. Host arrays are numpy; device arrays are torch
+tensors on the GPU (the call then passes ``MSKM_IO_DEVICE`` and uses the
+tensor's memory directly, on torch's current stream when the context was
+created with ``stream="torch"``).
+
+The library must be built first (``python -m paper_2503_04914_amd.build``);
+importing the functions without it raises ``MskmLibraryMissing`` -- there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmskm.so")
+
+# status codes (mskm.h)
+MSKM_OK, MSKM_ENOCONV = 0, 1
+MSKM_EINVAL, MSKM_ENOMEM, MSKM_EDEVICE, MSKM_ELIMIT, MSKM_ESTATE = -1, -2, -3, -4, -5
+MSKM_WENDLAND_3_1 = 31
+MSKM_POINTS_ON_DEVICE, MSKM_STORE_FP64, MSKM_STORE_FP32 = 1, 2, 4
+MSKM_IO_DEVICE = 1
+MSKM_OP_DIAG, MSKM_OP_LOWER, MSKM_OP_FULL = 0, 1, 2
+MSKM_PREC_FP64, MSKM_PREC_FP32 = 0, 1
+MSKM_ALG_MONOLITHIC, MSKM_ALG_SEQUENTIAL = 0, 1
+MSKM_PRECOND_NONE, MSKM_PRECOND_LEARNED = 0, 1
+
+EXPORTED = [
+    "mskm_create", "mskm_destroy", "mskm_last_error", "mskm_abi_version",
+    "mskm_hier_create", "mskm_hier_destroy", "mskm_hier_stats_get", "mskm_hier_offsets",
+    "mskm_export_block", "mskm_export_perm", "mskm_apply",
+    "mskm_solve_opts_default", "mskm_solve", "mskm_residual", "mskm_evaluate",
+]
+
+
+class MskmLibraryMissing(RuntimeError):
+    pass
+
+
+class MskmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"mskm status {status}: {msg}")
+        self.status = status
+
+
+class HierDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("levels", C.c_int32), ("level_offsets", C.POINTER(C.c_int64)),
+                ("points", C.c_void_p), ("delta", C.POINTER(C.c_double)), ("kernel", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+class HierStats(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("levels", C.c_int32), ("n_total", C.c_int64), ("nnz_diag", C.c_int64),
+                ("nnz_lower", C.c_int64), ("has_fp64", C.c_int32), ("has_fp32", C.c_int32),
+                ("device_bytes", C.c_int64), ("assemble_ms", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("algorithm", C.c_int32), ("cg_rtol", C.c_double), ("sweeps", C.c_int32),
+                ("max_cg_iters", C.c_int32), ("warm_start", C.c_int32), ("target_rel_residual", C.c_double),
+                ("max_refine", C.c_int32), ("precond", C.c_int32), ("mlp", C.c_void_p), ("check_every", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+class Report(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("sweeps_done", C.c_int32), ("refine_steps", C.c_int32),
+                ("cg_iters_total", C.c_int64), ("cg_iters_last", C.c_int32 * 64), ("rel_residual", C.c_double),
+                ("solve_ms", C.c_double), ("warm_fallbacks", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises MskmLibraryMissing if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MskmLibraryMissing(f"{LIB_PATH} not found: build it with python -m paper_2503_04914_amd.build")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    L.mskm_create.argtypes = [i32, vp, C.POINTER(vp)]
+    L.mskm_destroy.argtypes = [vp]
+    L.mskm_last_error.restype = C.c_char_p
+    L.mskm_abi_version.restype = i32
+    L.mskm_hier_create.argtypes = [vp, C.POINTER(HierDesc), C.POINTER(vp)]
+    L.mskm_hier_destroy.argtypes = [vp]
+    L.mskm_hier_stats_get.argtypes = [vp, C.POINTER(HierStats)]
+    L.mskm_hier_offsets.argtypes = [vp, C.POINTER(i64)]
+    L.mskm_export_block.argtypes = [vp, vp, i32, i32, vp, vp, vp, C.POINTER(i64)]
+    L.mskm_export_perm.argtypes = [vp, vp, vp]
+    L.mskm_apply.argtypes = [vp, vp, i32, i32, vp, i32, vp, i32]
+    L.mskm_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
+    L.mskm_solve_opts_default.restype = None
+    L.mskm_solve.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(Report)]
+    L.mskm_residual.argtypes = [vp, vp, vp, vp, i32, dp, i32]
+    L.mskm_evaluate.argtypes = [vp, vp, vp, i32, vp, i64, vp, i32]
+    for name in EXPORTED:
+        if name not in ("mskm_last_error", "mskm_abi_version", "mskm_solve_opts_default"):
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(st: int, what: str) -> int:
+    if st < 0:
+        msg = lib().mskm_last_error().decode(errors="replace")
+        raise MskmError(st, f"{what}: {msg}")
+    return st
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, dtype):
+    """(pointer, on_device) of a C-contiguous array of the given numpy dtype."""
+    if _is_torch(a):
+        import torch
+
+        want = {np.float64: torch.float64, np.int64: torch.int64, np.int32: torch.int32}[dtype]
+        if a.dtype != want or not a.is_contiguous():
+            raise TypeError(f"tensor must be contiguous {want}")
+        return C.c_void_p(a.data_ptr()), a.is_cuda
+    if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags.c_contiguous):
+        raise TypeError(f"array must be a C-contiguous numpy {np.dtype(dtype).name} array")
+    return C.c_void_p(a.ctypes.data), False
+
+
+# ----------------------------------------------------------------- context
+
+def mskm_abi_version() -> int:
+    return int(lib().mskm_abi_version())
+
+
+def mskm_last_error() -> str:
+    return lib().mskm_last_error().decode(errors="replace")
+
+
+def mskm_create(device: int = 0, stream=None):
+    """Context on `device`. stream: None (library stream), "torch" (torch's
+    current stream) or a raw hipStream_t integer."""
+    if stream == "torch":
+        import torch
+
+        stream = torch.cuda.current_stream(device).cuda_stream
+    out = C.c_void_p()
+    _check(lib().mskm_create(int(device), C.c_void_p(stream) if stream else None, C.byref(out)), "mskm_create")
+    return out
+
+
+def mskm_destroy(ctx) -> None:
+    lib().mskm_destroy(ctx)
+
+
+# --------------------------------------------------------------- hierarchy
+
+def mskm_hier_create(ctx, points, offsets, delta, dim: int | None = None, fp64: bool = True, fp32: bool = False):
+    """Assemble all blocks of a hierarchy. points: [N][dim] float64 (numpy, or
+    a CUDA tensor), offsets: [L+1] int64, delta: [L] float64 (host)."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    delta = np.ascontiguousarray(delta, dtype=np.float64)
+    if dim is None:
+        dim = int(points.shape[1])
+    pp, pdev = _ptr(points, np.float64)
+    flags = (MSKM_POINTS_ON_DEVICE if pdev else 0) | (MSKM_STORE_FP64 if fp64 else 0) | (MSKM_STORE_FP32 if fp32 else 0)
+    d = HierDesc(dim, len(delta), offsets.ctypes.data_as(C.POINTER(C.c_int64)), pp,
+                 delta.ctypes.data_as(C.POINTER(C.c_double)), MSKM_WENDLAND_3_1, flags)
+    out = C.c_void_p()
+    _check(lib().mskm_hier_create(ctx, C.byref(d), C.byref(out)), "mskm_hier_create")
+    return out
+
+
+def mskm_hier_destroy(h) -> None:
+    lib().mskm_hier_destroy(h)
+
+
+def mskm_hier_stats_get(h) -> dict:
+    s = HierStats()
+    _check(lib().mskm_hier_stats_get(h, C.byref(s)), "mskm_hier_stats_get")
+    return {k: getattr(s, k) for k, _ in HierStats._fields_}
+
+
+def mskm_export_block(ctx, h, row_level: int, col_level: int, values: bool = True):
+    """Canonical CSR (rowptr int64, col int32, val float64 or None) of B_{row,col}."""
+    nnz = C.c_int64()
+    _check(lib().mskm_export_block(ctx, h, row_level, col_level, None, None, None, C.byref(nnz)), "export (size)")
+    n = nnz.value
+    off = mskm_hier_offsets(h)
+    rowptr = np.zeros(int(off[row_level + 1] - off[row_level]) + 1, dtype=np.int64)
+    col = np.zeros(max(n, 1), dtype=np.int32)
+    val = np.zeros(max(n, 1), dtype=np.float64) if values else None
+    _check(lib().mskm_export_block(ctx, h, row_level, col_level, C.c_void_p(rowptr.ctypes.data),
+                                   C.c_void_p(col.ctypes.data), C.c_void_p(val.ctypes.data) if values else None,
+                                   C.byref(nnz)), "mskm_export_block")
+    return rowptr, col[:n], (val[:n] if values else None)
+
+
+def mskm_hier_offsets(h) -> np.ndarray:
+    L = mskm_hier_stats_get(h)["levels"]
+    off = np.zeros(L + 1, dtype=np.int64)
+    _check(lib().mskm_hier_offsets(h, off.ctypes.data_as(C.POINTER(C.c_int64))), "mskm_hier_offsets")
+    return off
+
+
+def mskm_export_perm(ctx, h, n_total: int) -> np.ndarray:
+    perm = np.zeros(n_total, dtype=np.int32)
+    _check(lib().mskm_export_perm(ctx, h, C.c_void_p(perm.ctypes.data)), "mskm_export_perm")
+    return perm
+
+
+# ------------------------------------------------------------------- solve
+
+def mskm_apply(ctx, h, op: int, x, y, prec: int = MSKM_PREC_FP64, nrhs: int = 1) -> None:
+    xp, xd = _ptr(x, np.float64)
+    yp, yd = _ptr(y, np.float64)
+    if xd != yd:
+        raise ValueError("x and y must both be host or both be device arrays")
+    _check(lib().mskm_apply(ctx, h, op, prec, xp, nrhs, yp, MSKM_IO_DEVICE if xd else 0), "mskm_apply")
+
+
+def mskm_solve_opts_default() -> SolveOpts:
+    o = SolveOpts()
+    lib().mskm_solve_opts_default(C.byref(o))
+    return o
+
+
+def solve_opts(**kw) -> SolveOpts:
+    o = mskm_solve_opts_default()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class SolveResult:
+    status: int
+    report: dict
+
+
+def mskm_solve(ctx, h, f, alpha, opts: SolveOpts | None = None, nrhs: int = 1) -> SolveResult:
+    """alpha = T_L^-1 f. Returns the status (0 or MSKM_ENOCONV) and the report."""
+    opts = opts or mskm_solve_opts_default()
+    fp, fd = _ptr(f, np.float64)
+    ap, ad = _ptr(alpha, np.float64)
+    if fd != ad:
+        raise ValueError("f and alpha must both be host or both be device arrays")
+    o = SolveOpts()
+    C.pointer(o)[0] = opts
+    o.flags = (o.flags | MSKM_IO_DEVICE) if fd else (o.flags & ~MSKM_IO_DEVICE)
+    rep = Report()
+    st = _check(lib().mskm_solve(ctx, h, fp, nrhs, C.byref(o), ap, C.byref(rep)), "mskm_solve")
+    r = {k: getattr(rep, k) for k, _ in Report._fields_}
+    r["cg_iters_last"] = list(rep.cg_iters_last)[: rep.levels]
+    return SolveResult(st, r)
+
+
+def mskm_residual(ctx, h, alpha, f, nrhs: int = 1) -> np.ndarray:
+    ap, ad = _ptr(alpha, np.float64)
+    fp, fd = _ptr(f, np.float64)
+    if fd != ad:
+        raise ValueError("alpha and f must both be host or both be device arrays")
+    out = np.zeros(nrhs, dtype=np.float64)
+    _check(lib().mskm_residual(ctx, h, ap, fp, nrhs, out.ctypes.data_as(C.POINTER(C.c_double)),
+                               MSKM_IO_DEVICE if ad else 0), "mskm_residual")
+    return out
+
+
+def mskm_evaluate(ctx, h, alpha, query, out, nrhs: int = 1) -> None:
+    ap, ad = _ptr(alpha, np.float64)
+    qp, qd = _ptr(query, np.float64)
+    op, od = _ptr(out, np.float64)
+    if not (ad == qd == od):
+        raise ValueError("alpha, query and out must all be host or all be device arrays")
+    nq = int(query.shape[0])
+    _check(lib().mskm_evaluate(ctx, h, ap, nrhs, qp, nq, op, MSKM_IO_DEVICE if ad else 0), "mskm_evaluate")

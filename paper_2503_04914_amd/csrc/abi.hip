@@ -1,0 +1,244 @@
+// C ABI entry points: argument validation, context and handle lifetime,
+// thread-local error text. The numerical work lives in assemble.hip and
+// solve.hip.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "mskm_internal.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+bool valid_ctx(const mskm_ctx* c) { return c != nullptr; }
+}  // namespace
+
+namespace mskm {
+void set_error(const std::string& msg) { g_last_error = msg; }
+mskm_status fail(mskm_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+}  // namespace mskm
+
+using mskm::fail;
+
+extern "C" {
+
+const char* mskm_last_error(void) { return g_last_error.c_str(); }
+
+int32_t mskm_abi_version(void) { return MSKM_ABI_VERSION; }
+
+mskm_status mskm_create(int32_t device, void* hip_stream, mskm_ctx** out) {
+  if (!out) return fail(MSKM_EINVAL, "mskm_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(MSKM_EDEVICE, "no HIP device");
+  if (device < 0 || device >= ndev) return fail(MSKM_EINVAL, "device index out of range");
+  if (hipSetDevice(device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  auto* c = new (std::nothrow) mskm_ctx();
+  if (!c) return fail(MSKM_ENOMEM, "context allocation");
+  c->device = device;
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(MSKM_EDEVICE, "hipStreamCreate failed");
+    }
+    c->own_stream = true;
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return fail(MSKM_EDEVICE, "hipEventCreate failed");
+  }
+  *out = c;
+  return MSKM_OK;
+}
+
+mskm_status mskm_destroy(mskm_ctx* c) {
+  if (!c) return MSKM_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipEventDestroy(c->ev0);
+  (void)hipEventDestroy(c->ev1);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return MSKM_OK;
+}
+
+mskm_status mskm_hier_create(mskm_ctx* ctx, const mskm_hier_desc* d, mskm_hier** out) {
+  if (!valid_ctx(ctx) || !d || !out) return fail(MSKM_EINVAL, "mskm_hier_create: NULL argument");
+  *out = nullptr;
+  if (d->dim != 2 && d->dim != 3) return fail(MSKM_EINVAL, "dim must be 2 or 3");
+  if (d->levels < 1 || d->levels > mskm::kMaxLevels) return fail(MSKM_EINVAL, "levels must be in 1..64");
+  if (d->kernel != MSKM_WENDLAND_3_1) return fail(MSKM_EINVAL, "unsupported kernel");
+  if (!d->level_offsets || !d->points || !d->delta) return fail(MSKM_EINVAL, "NULL array in descriptor");
+  if (d->level_offsets[0] != 0) return fail(MSKM_EINVAL, "level_offsets[0] must be 0");
+  for (int l = 0; l < d->levels; ++l) {
+    if (d->level_offsets[l + 1] < d->level_offsets[l]) return fail(MSKM_EINVAL, "level_offsets must not decrease");
+    if (!(d->delta[l] > 0.0) || !std::isfinite(d->delta[l])) return fail(MSKM_EINVAL, "delta must be finite and > 0");
+  }
+  const int64_t N = d->level_offsets[d->levels];
+  if (N <= 0) return fail(MSKM_EINVAL, "hierarchy has no points");
+  if (N >= (int64_t)INT32_MAX) return fail(MSKM_ELIMIT, "more than 2^31-1 points");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  const bool pdev = (d->flags & MSKM_POINTS_ON_DEVICE) != 0;
+  if (!pdev) {
+    for (int64_t i = 0; i < N * d->dim; ++i)
+      if (!std::isfinite(d->points[i])) return fail(MSKM_EINVAL, "non-finite point coordinate");
+  }
+  bool want64 = (d->flags & MSKM_STORE_FP64) != 0, want32 = (d->flags & MSKM_STORE_FP32) != 0;
+  if (!want64 && !want32) want64 = true;
+
+  auto* h = new (std::nothrow) mskm_hier();
+  if (!h) return fail(MSKM_ENOMEM, "hierarchy allocation");
+  h->ctx = ctx;
+  h->dim = d->dim;
+  h->L = d->levels;
+  h->N = N;
+  h->h_off.assign(d->level_offsets, d->level_offsets + d->levels + 1);
+  h->h_delta.assign(d->delta, d->delta + d->levels);
+  double* pts = nullptr;
+  mskm_status st = MSKM_OK;
+  if (pdev) {
+    pts = const_cast<double*>(d->points);
+  } else {
+    st = mskm::dalloc(&pts, (size_t)N * d->dim);
+    if (st == MSKM_OK && hipMemcpyAsync(pts, d->points, (size_t)N * d->dim * 8, hipMemcpyHostToDevice, ctx->stream) !=
+                             hipSuccess)
+      st = fail(MSKM_EDEVICE, "point upload failed");
+  }
+  if (st == MSKM_OK) st = mskm::assemble_hierarchy(h, pts, want64, want32);
+  if (st == MSKM_OK) {
+    if (h->diag.nnz >= ((int64_t)1 << 62)) st = fail(MSKM_ELIMIT, "too many nonzeros");
+  }
+  if (st == MSKM_OK) st = mskm::build_work_table(h, &h->wt_cg, 256);
+  if (!pdev) (void)hipFree(pts);
+  if (st != MSKM_OK) {
+    mskm_hier_destroy(h);
+    return st;
+  }
+  *out = h;
+  return MSKM_OK;
+}
+
+mskm_status mskm_hier_destroy(mskm_hier* h) {
+  if (!h) return MSKM_OK;
+  if (h->ctx) {
+    (void)hipSetDevice(h->ctx->device);
+    (void)hipStreamSynchronize(h->ctx->stream);
+  }
+  for (void* p : h->allocs) (void)hipFree(p);
+  delete h;
+  return MSKM_OK;
+}
+
+mskm_status mskm_hier_stats_get(const mskm_hier* h, mskm_hier_stats* o) {
+  if (!h || !o) return fail(MSKM_EINVAL, "mskm_hier_stats_get: NULL argument");
+  std::memset(o, 0, sizeof(*o));
+  o->dim = h->dim;
+  o->levels = h->L;
+  o->n_total = h->N;
+  o->nnz_diag = h->diag.nnz;
+  o->nnz_lower = h->lower.nnz;
+  o->has_fp64 = h->diag.val != nullptr;
+  o->has_fp32 = h->diag.val32 != nullptr;
+  o->device_bytes = h->device_bytes;
+  o->assemble_ms = h->assemble_ms;
+  return MSKM_OK;
+}
+
+mskm_status mskm_hier_offsets(const mskm_hier* h, int64_t* off) {
+  if (!h || !off) return fail(MSKM_EINVAL, "mskm_hier_offsets: NULL argument");
+  for (int l = 0; l <= h->L; ++l) off[l] = h->h_off[l];
+  return MSKM_OK;
+}
+
+mskm_status mskm_export_block(mskm_ctx* ctx, const mskm_hier* h, int32_t row_level, int32_t col_level, int64_t* rowptr,
+                              int32_t* col, double* val, int64_t* nnz_out) {
+  if (!valid_ctx(ctx) || !h) return fail(MSKM_EINVAL, "mskm_export_block: NULL handle");
+  if (row_level < 0 || row_level >= h->L || col_level < 0 || col_level > row_level)
+    return fail(MSKM_EINVAL, "block index out of range (need 0 <= col_level <= row_level < L)");
+  if (col && !rowptr) return fail(MSKM_EINVAL, "rowptr required with col");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::export_block(const_cast<mskm_hier*>(h), row_level, col_level, rowptr, col, val, nnz_out);
+}
+
+mskm_status mskm_export_perm(mskm_ctx* ctx, const mskm_hier* h, int32_t* perm) {
+  if (!valid_ctx(ctx) || !h || !perm) return fail(MSKM_EINVAL, "mskm_export_perm: NULL argument");
+  if (hipMemcpy(perm, h->perm, h->N * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(MSKM_EDEVICE, "perm copy failed");
+  return MSKM_OK;
+}
+
+mskm_status mskm_apply(mskm_ctx* ctx, const mskm_hier* h, int32_t op, int32_t prec, const double* x, int32_t nrhs,
+                       double* y, int32_t flags) {
+  if (!valid_ctx(ctx) || !h || !x || !y) return fail(MSKM_EINVAL, "mskm_apply: NULL argument");
+  if (op < MSKM_OP_DIAG || op > MSKM_OP_FULL) return fail(MSKM_EINVAL, "unknown op");
+  if (prec != MSKM_PREC_FP64 && prec != MSKM_PREC_FP32) return fail(MSKM_EINVAL, "unknown precision");
+  if (nrhs < 1) return fail(MSKM_EINVAL, "nrhs must be >= 1");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::apply_op(const_cast<mskm_hier*>(h), op, prec, x, nrhs, y, (flags & MSKM_IO_DEVICE) != 0);
+}
+
+void mskm_solve_opts_default(mskm_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = MSKM_PREC_FP64;
+  o->algorithm = MSKM_ALG_MONOLITHIC;
+  o->cg_rtol = 1e-12;
+  o->sweeps = 0;
+  o->max_cg_iters = 20000;
+  o->warm_start = 0;
+  o->target_rel_residual = 1e-8;
+  o->max_refine = 10;
+  o->precond = MSKM_PRECOND_NONE;
+  o->mlp = nullptr;
+  o->check_every = 8;
+  o->flags = 0;
+}
+
+mskm_status mskm_solve(mskm_ctx* ctx, const mskm_hier* h, const double* f, int32_t nrhs, const mskm_solve_opts* opts,
+                       double* alpha, mskm_report* rep) {
+  if (!valid_ctx(ctx) || !h || !f || !alpha) return fail(MSKM_EINVAL, "mskm_solve: NULL argument");
+  if (nrhs < 1) return fail(MSKM_EINVAL, "nrhs must be >= 1");
+  mskm_solve_opts o;
+  if (opts) o = *opts;
+  else mskm_solve_opts_default(&o);
+  if (o.precision != MSKM_PREC_FP64 && o.precision != MSKM_PREC_FP32) return fail(MSKM_EINVAL, "unknown precision");
+  if (o.algorithm != MSKM_ALG_MONOLITHIC && o.algorithm != MSKM_ALG_SEQUENTIAL)
+    return fail(MSKM_EINVAL, "unknown algorithm");
+  if (!(o.cg_rtol > 0.0) || !(o.cg_rtol < 1.0)) return fail(MSKM_EINVAL, "cg_rtol must be in (0, 1)");
+  if (o.precision == MSKM_PREC_FP32 && !(o.target_rel_residual > 0.0))
+    return fail(MSKM_EINVAL, "target_rel_residual must be > 0 on the mixed path");
+  if (o.precond == MSKM_PRECOND_LEARNED && !o.mlp) return fail(MSKM_EINVAL, "learned warm start needs an mlp");
+  if (o.precond != MSKM_PRECOND_NONE && o.precond != MSKM_PRECOND_LEARNED) return fail(MSKM_EINVAL, "unknown precond");
+  if (!(o.flags & MSKM_IO_DEVICE)) {
+    for (int64_t i = 0; i < h->N * (int64_t)nrhs; ++i)
+      if (!std::isfinite(f[i])) return fail(MSKM_EINVAL, "non-finite right-hand side");
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::solve(const_cast<mskm_hier*>(h), f, nrhs, &o, alpha, rep);
+}
+
+mskm_status mskm_residual(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, const double* f, int32_t nrhs,
+                          double* rel_out, int32_t flags) {
+  if (!valid_ctx(ctx) || !h || !alpha || !f || !rel_out) return fail(MSKM_EINVAL, "mskm_residual: NULL argument");
+  if (nrhs < 1) return fail(MSKM_EINVAL, "nrhs must be >= 1");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::residual(const_cast<mskm_hier*>(h), alpha, f, nrhs, rel_out, (flags & MSKM_IO_DEVICE) != 0);
+}
+
+mskm_status mskm_evaluate(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, int32_t nrhs, const double* query,
+                          int64_t nq, double* out, int32_t flags) {
+  if (!valid_ctx(ctx) || !h || !alpha || (nq > 0 && (!query || !out)))
+    return fail(MSKM_EINVAL, "mskm_evaluate: NULL argument");
+  if (nrhs < 1 || nq < 0) return fail(MSKM_EINVAL, "nrhs must be >= 1 and nq >= 0");
+  if (nq == 0) return MSKM_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::evaluate(const_cast<mskm_hier*>(h), alpha, nrhs, query, nq, out, (flags & MSKM_IO_DEVICE) != 0);
+}
+
+}  // extern "C"

@@ -1,0 +1,619 @@
+// Hierarchy assembly on gfx950: cell lists per level, neighbour search for
+// every level pair k >= j and evaluation of the Wendland blocks
+// B_{k,j}[i][n] = phi(||x_i^(k) - x_n^(j)|| / delta_j) (Section 3) into CSR.
+//
+// Pipeline (all on the context stream):
+//   bbox per level -> cell key per point -> histogram -> scan -> scatter ->
+//   in-cell rank by input index (deterministic order) -> SoA coordinates ->
+//   count pass (one wave per row, lanes over candidate cells) -> int64 scan ->
+//   fill pass (same traversal; ballot/popcount gives each hit its slot, so
+//   columns come out ascending and writes are contiguous per row).
+#include <algorithm>
+#include <cmath>
+
+#include "device_common.h"
+
+namespace mskm {
+
+// ------------------------------------------------------------------ scans
+
+// Exclusive scan of int64, three passes. Block b scans kScanTile items.
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ void __launch_bounds__(kBlock) k_scan_partials(const int64_t* __restrict__ in, int64_t n,
+                                                          int64_t* __restrict__ part) {
+  __shared__ int64_t sm[kBlock / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Single block: exclusive scan of the partials in place (sequential chunks).
+__global__ void __launch_bounds__(kBlock) k_scan_partials_scan(int64_t* __restrict__ part, int64_t nparts) {
+  __shared__ int64_t sm[kBlock];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nparts; base += kBlock) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t v = i < nparts ? part[i] : 0;
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    // Hillis-Steele inclusive scan in LDS
+    for (int o = 1; o < kBlock; o <<= 1) {
+      int64_t t = threadIdx.x >= o ? sm[threadIdx.x - o] : 0;
+      __syncthreads();
+      sm[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nparts) part[i] = carry + sm[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += sm[kBlock - 1];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_final(const int64_t* __restrict__ in, int64_t n,
+                                                       const int64_t* __restrict__ part, int64_t* __restrict__ out) {
+  __shared__ int64_t sm[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    v[k] = i < n ? in[i] : 0;
+    s += v[k];
+  }
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    int64_t t = threadIdx.x >= o ? sm[threadIdx.x - o] : 0;
+    __syncthreads();
+    sm[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int64_t run = part[blockIdx.x] + sm[threadIdx.x] - s;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+}
+
+// out[0..n) = exclusive scan of in[0..n). in and out may not alias.
+mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n) {
+  if (n <= 0) return MSKM_OK;
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb > (int64_t)INT32_MAX) return fail(MSKM_ELIMIT, "scan too large");
+  int64_t* part = nullptr;
+  MSKM_TRY(dalloc(&part, (size_t)nb));
+  hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, part);
+  hipLaunchKernelGGL(k_scan_partials_scan, dim3(1), dim3(kBlock), 0, s, part, nb);
+  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, part, out);
+  hipError_t e = hipStreamSynchronize(s);
+  (void)hipFree(part);
+  if (e != hipSuccess) return fail(MSKM_EDEVICE, std::string("scan: ") + hipGetErrorString(e));
+  return MSKM_OK;
+}
+
+// ------------------------------------------------------------- cell lists
+
+__global__ void __launch_bounds__(kBlock) k_widen(const int32_t* __restrict__ a, int64_t* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_narrow(const int64_t* __restrict__ a, int32_t* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i] = (int32_t)a[i];
+}
+
+constexpr int kBboxBlocks = 128;
+
+// Per-level bounding box of the input points (AoS). Grid (kBboxBlocks, L).
+__global__ void __launch_bounds__(kBlock) k_bbox_partial(const double* __restrict__ pts, const int64_t* __restrict__ off,
+                                                         int dim, double* __restrict__ part) {
+  __shared__ double smn[3][kBlock], smx[3][kBlock];
+  const int l = blockIdx.y;
+  const int64_t a = off[l], b = off[l + 1];
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = a + (int64_t)blockIdx.x * kBlock + threadIdx.x; i < b; i += (int64_t)gridDim.x * kBlock) {
+    for (int d = 0; d < dim; ++d) {
+      const double v = pts[i * dim + d];
+      // NaN propagates into the box (fmin/fmax would drop it): the host rejects it
+      mn[d] = (v < mn[d] || v != v) ? v : mn[d];
+      mx[d] = (v > mx[d] || v != v) ? v : mx[d];
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    smn[d][threadIdx.x] = mn[d];
+    smx[d][threadIdx.x] = mx[d];
+  }
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      for (int d = 0; d < 3; ++d) {
+        const double u = smn[d][threadIdx.x + s], w = smx[d][threadIdx.x + s];
+        smn[d][threadIdx.x] = (u < smn[d][threadIdx.x] || u != u) ? u : smn[d][threadIdx.x];
+        smx[d][threadIdx.x] = (w > smx[d][threadIdx.x] || w != w) ? w : smx[d][threadIdx.x];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* o = part + ((size_t)l * gridDim.x + blockIdx.x) * 6;
+    for (int d = 0; d < 3; ++d) {
+      o[d] = smn[d][0];
+      o[3 + d] = smx[d][0];
+    }
+  }
+}
+
+// Cell key of every point of level l (row-major, axis 0 fastest).
+__global__ void __launch_bounds__(kBlock) k_cell_key(const double* __restrict__ pts, int dim,
+                                                     const DevLevel* __restrict__ lev, int l, int64_t off, int64_t n,
+                                                     int32_t* __restrict__ key, int32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const DevLevel L = lev[l];
+  const int64_t g = off + i;
+  int k = 0, stride = 1;
+  for (int d = 0; d < dim; ++d) {
+    const int c = cell_coord(pts[g * dim + d], L.lo[d], L.inv_cell, L.nc[d]);
+    k += c * stride;
+    stride *= L.nc[d];
+  }
+  key[g] = k;
+  atomicAdd(&count[L.cs_off + k], 1);
+}
+
+// Unordered placement of each point into its cell's slot range.
+__global__ void __launch_bounds__(kBlock) k_cell_scatter(const DevLevel* __restrict__ lev, int l, int64_t off,
+                                                         int64_t n, const int32_t* __restrict__ key,
+                                                         const int64_t* __restrict__ cs, int32_t* __restrict__ cursor,
+                                                         int32_t* __restrict__ tmp) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int64_t g = off + i;
+  const int c = lev[l].cs_off + key[g];
+  const int pos = atomicAdd(&cursor[c], 1);
+  tmp[cs[c] + pos] = (int32_t)g;
+}
+
+// Final position = cell start + rank of the input index among the cell's
+// points: the in-cell order is ascending input index, independent of the
+// order in which the scatter's atomics landed.
+__global__ void __launch_bounds__(kBlock) k_cell_rank(const DevLevel* __restrict__ lev, int l, int64_t off,
+                                                      int64_t n, int dim, const double* __restrict__ pts,
+                                                      const int32_t* __restrict__ key, const int64_t* __restrict__ cs,
+                                                      const int32_t* __restrict__ tmp, int32_t* __restrict__ perm,
+                                                      int32_t* __restrict__ iperm, double* __restrict__ xs,
+                                                      int64_t N) {
+  const int64_t s = off + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (s >= off + n) return;
+  const int32_t g = tmp[s];
+  const int c = lev[l].cs_off + key[g];
+  const int64_t a = cs[c], b = cs[c + 1];
+  int64_t rank = 0;
+  for (int64_t t = a; t < b; ++t) rank += tmp[t] < g;
+  const int64_t p = a + rank;
+  perm[p] = g;
+  iperm[g] = (int32_t)p;
+  for (int d = 0; d < dim; ++d) xs[(size_t)d * N + p] = pts[(size_t)g * dim + d];
+}
+
+// ------------------------------------------------------- neighbour search
+
+// Visit every candidate of row point (px, py, pz) in level j's grid: the 3^d
+// cells around its cell. With a row-major key the three cells along axis 0
+// are one contiguous slot range, so there are 3 ranges in 2-D and 9 in 3-D.
+// The callback gets (range begin, range end) in internal global indices.
+template <typename F>
+__device__ __forceinline__ void for_each_range(int dim, const DevLevel& L, const int32_t* __restrict__ cs_all,
+                                               double px, double py, double pz, F&& f) {
+  const int cx = cell_coord(px, L.lo[0], L.inv_cell, L.nc[0]);
+  const int cy = cell_coord(py, L.lo[1], L.inv_cell, L.nc[1]);
+  const int cz = dim == 3 ? cell_coord(pz, L.lo[2], L.inv_cell, L.nc[2]) : 0;
+  const int x0 = cx > 0 ? cx - 1 : 0;
+  const int x1 = cx < L.nc[0] - 1 ? cx + 1 : L.nc[0] - 1;
+  const int z0 = dim == 3 ? (cz > 0 ? cz - 1 : 0) : 0;
+  const int z1 = dim == 3 ? (cz < L.nc[2] - 1 ? cz + 1 : L.nc[2] - 1) : 0;
+  const int y0 = cy > 0 ? cy - 1 : 0;
+  const int y1 = cy < L.nc[1] - 1 ? cy + 1 : L.nc[1] - 1;
+  const int32_t* cs = cs_all + L.cs_off;
+  for (int z = z0; z <= z1; ++z) {
+    for (int y = y0; y <= y1; ++y) {
+      const int rowkey = (z * L.nc[1] + y) * L.nc[0];
+      f((int64_t)cs[rowkey + x0], (int64_t)cs[rowkey + x1 + 1]);
+    }
+  }
+}
+
+// One wave per row. Count pass: cnt_d[i] = |{n in level k : d2 < delta_k^2}|,
+// cnt_l[i] = sum_{j<k} |{n in level j : d2 < delta_j^2}|.
+__global__ void __launch_bounds__(kBlock) k_nbr_count(int dim, int k, const DevLevel* __restrict__ lev,
+                                                      const int32_t* __restrict__ cs_all,
+                                                      const double* __restrict__ xs, int64_t N,
+                                                      int64_t* __restrict__ cnt_d, int64_t* __restrict__ cnt_l) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+  const DevLevel Lk = lev[k];
+  const double* X = xs;
+  const double* Y = xs + N;
+  const double* Z = xs + 2 * N;
+  for (int64_t r = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; r < Lk.n; r += waves) {
+    const int64_t i = Lk.off + r;
+    const double px = X[i], py = Y[i], pz = dim == 3 ? Z[i] : 0.0;
+    int64_t lower = 0, diag = 0;
+    for (int j = 0; j <= k; ++j) {
+      const DevLevel Lj = lev[j];
+      int64_t c = 0;
+      for_each_range(dim, Lj, cs_all, px, py, pz, [&](int64_t a, int64_t b) {
+        for (int64_t t = a + lane; t - lane < b; t += kWave) {
+          bool hit = false;
+          if (t < b) hit = sqdist(dim, px, py, pz, X[t], Y[t], dim == 3 ? Z[t] : 0.0) < Lj.d2max;
+          c += __popcll(__ballot(hit));
+        }
+      });
+      if (j == k) diag = c; else lower += c;
+    }
+    if (lane == 0) {
+      cnt_d[i] = diag;
+      cnt_l[i] = lower;
+    }
+  }
+}
+
+// Fill pass: same traversal, each hit written at rowptr[i] + (hits so far).
+__global__ void __launch_bounds__(kBlock) k_nbr_fill(int dim, int k, const DevLevel* __restrict__ lev,
+                                                     const int32_t* __restrict__ cs_all,
+                                                     const double* __restrict__ xs, int64_t N,
+                                                     const int64_t* __restrict__ dptr, int32_t* __restrict__ dcol,
+                                                     double* __restrict__ dval, float* __restrict__ dval32,
+                                                     const int64_t* __restrict__ lptr, int32_t* __restrict__ lcol,
+                                                     double* __restrict__ lval, float* __restrict__ lval32) {
+  const int lane = threadIdx.x % kWave;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+  const DevLevel Lk = lev[k];
+  const double* X = xs;
+  const double* Y = xs + N;
+  const double* Z = xs + 2 * N;
+  for (int64_t r = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; r < Lk.n; r += waves) {
+    const int64_t i = Lk.off + r;
+    const double px = X[i], py = Y[i], pz = dim == 3 ? Z[i] : 0.0;
+    int64_t lpos = lptr[i];
+    for (int j = 0; j <= k; ++j) {
+      const DevLevel Lj = lev[j];
+      const bool is_diag = j == k;
+      int64_t pos = is_diag ? dptr[i] : lpos;
+      int32_t* col = is_diag ? dcol : lcol;
+      double* val = is_diag ? dval : lval;
+      float* val32 = is_diag ? dval32 : lval32;
+      for_each_range(dim, Lj, cs_all, px, py, pz, [&](int64_t a, int64_t b) {
+        for (int64_t t = a + lane; t - lane < b; t += kWave) {
+          bool hit = false;
+          double d2 = 0.0;
+          if (t < b) {
+            d2 = sqdist(dim, px, py, pz, X[t], Y[t], dim == 3 ? Z[t] : 0.0);
+            hit = d2 < Lj.d2max;
+          }
+          const uint64_t m = __ballot(hit);
+          if (hit) {
+            const int64_t p = pos + __popcll(m & below);
+            col[p] = (int32_t)t;
+            const double v = phi31_d2(d2, Lj.delta);
+            if (val) val[p] = v;
+            if (val32) val32[p] = (float)v;
+          }
+          pos += __popcll(m);
+        }
+      });
+      if (!is_diag) lpos = pos;
+    }
+  }
+}
+
+// ------------------------------------------------------------- work table
+
+mskm_status build_work_table(mskm_hier* h, WorkTable* wt, int rows_per_block) {
+  std::vector<int32_t> lev;
+  std::vector<int64_t> r0, r1;
+  wt->h_lev_begin.assign(h->L + 1, 0);
+  for (int l = 0; l < h->L; ++l) {
+    wt->h_lev_begin[l] = (int32_t)lev.size();
+    for (int64_t a = h->h_off[l]; a < h->h_off[l + 1]; a += rows_per_block) {
+      lev.push_back(l);
+      r0.push_back(a);
+      r1.push_back(std::min<int64_t>(a + rows_per_block, h->h_off[l + 1]));
+    }
+  }
+  wt->h_lev_begin[h->L] = (int32_t)lev.size();
+  if (lev.size() > (size_t)INT32_MAX) return fail(MSKM_ELIMIT, "work table too large");
+  wt->nblocks = (int32_t)lev.size();
+  wt->rows_per_block = rows_per_block;
+  MSKM_TRY(halloc(h, &wt->lev, lev.size()));
+  MSKM_TRY(halloc(h, &wt->row0, r0.size()));
+  MSKM_TRY(halloc(h, &wt->row1, r1.size()));
+  MSKM_TRY(halloc(h, &wt->lev_begin, wt->h_lev_begin.size()));
+  hipStream_t s = h->ctx->stream;
+  MSKM_HIP_TRY(hipMemcpyAsync(wt->lev, lev.data(), lev.size() * 4, hipMemcpyHostToDevice, s));
+  MSKM_HIP_TRY(hipMemcpyAsync(wt->row0, r0.data(), r0.size() * 8, hipMemcpyHostToDevice, s));
+  MSKM_HIP_TRY(hipMemcpyAsync(wt->row1, r1.data(), r1.size() * 8, hipMemcpyHostToDevice, s));
+  MSKM_HIP_TRY(hipMemcpyAsync(wt->lev_begin, wt->h_lev_begin.data(), wt->h_lev_begin.size() * 4,
+                              hipMemcpyHostToDevice, s));
+  MSKM_HIP_TRY(hipStreamSynchronize(s));
+  return MSKM_OK;
+}
+
+// ------------------------------------------------------------- assembly
+
+static unsigned grid_for(int64_t n, int per_block) {
+  int64_t g = (n + per_block - 1) / per_block;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 30));
+}
+
+mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, bool want32) {
+  hipStream_t s = h->ctx->stream;
+  const int L = h->L, dim = h->dim;
+  const int64_t N = h->N;
+  MSKM_HIP_TRY(hipEventRecord(h->ctx->ev0, s));
+
+  int64_t* d_off = nullptr;
+  MSKM_TRY(dalloc(&d_off, L + 1));
+  MSKM_HIP_TRY(hipMemcpyAsync(d_off, h->h_off.data(), (L + 1) * 8, hipMemcpyHostToDevice, s));
+
+  // 1. bounding boxes
+  double* d_part = nullptr;
+  MSKM_TRY(dalloc(&d_part, (size_t)L * kBboxBlocks * 6));
+  hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks, L), dim3(kBlock), 0, s, pts, d_off, dim, d_part);
+  std::vector<double> part((size_t)L * kBboxBlocks * 6);
+  MSKM_HIP_TRY(hipMemcpyAsync(part.data(), d_part, part.size() * 8, hipMemcpyDeviceToHost, s));
+  MSKM_HIP_TRY(hipStreamSynchronize(s));
+  (void)hipFree(d_part);
+
+  // 2. level grids (host): cell side delta*(1+1e-6), enlarged if the grid
+  //    would exceed max(4n, 64) cells
+  h->h_lev.resize(L);
+  int64_t cs_total = 0;
+  for (int l = 0; l < L; ++l) {
+    DevLevel& D = h->h_lev[l];
+    D.off = h->h_off[l];
+    D.n = (int32_t)(h->h_off[l + 1] - h->h_off[l]);
+    D.delta = h->h_delta[l];
+    D.d2max = D.delta * D.delta;
+    D.inv_delta = 1.0 / D.delta;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = INFINITY;
+      hi[d] = -INFINITY;
+    }
+    for (int b = 0; b < kBboxBlocks; ++b) {
+      const double* o = &part[((size_t)l * kBboxBlocks + b) * 6];
+      for (int d = 0; d < dim; ++d) {
+        if (std::isnan(o[d]) || std::isnan(o[3 + d])) return fail(MSKM_EINVAL, "non-finite point coordinate");
+        lo[d] = std::min(lo[d], o[d]);
+        hi[d] = std::max(hi[d], o[3 + d]);
+      }
+    }
+    for (int d = 0; d < dim; ++d) {
+      if (D.n > 0 && (!std::isfinite(lo[d]) || !std::isfinite(hi[d])))
+        return fail(MSKM_EINVAL, "non-finite point coordinate");
+      if (D.n == 0) lo[d] = hi[d] = 0.0;
+    }
+    double cell = D.delta * (1.0 + 1e-6);
+    const double maxcells = std::max<double>(64.0, 4.0 * (double)D.n);
+    for (;;) {
+      double tot = 1.0;
+      for (int d = 0; d < dim; ++d) tot *= std::floor((hi[d] - lo[d]) / cell) + 1.0;
+      if (tot <= maxcells) break;
+      cell *= 1.25;
+    }
+    D.inv_cell = 1.0 / cell;
+    int64_t ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+      D.lo[d] = d < dim ? lo[d] : 0.0;
+      D.nc[d] = d < dim ? (int32_t)std::floor((hi[d] - lo[d]) * D.inv_cell) + 1 : 1;
+      if (D.nc[d] < 1) D.nc[d] = 1;
+      ncell *= D.nc[d];
+    }
+    D.ncell_tot = (int32_t)ncell;
+    D.cs_off = (int32_t)cs_total;
+    cs_total += ncell + 1;
+  }
+  if (cs_total >= INT32_MAX) return fail(MSKM_ELIMIT, "cell tables too large");
+  MSKM_TRY(halloc(h, &h->d_lev, L));
+  MSKM_HIP_TRY(hipMemcpyAsync(h->d_lev, h->h_lev.data(), L * sizeof(DevLevel), hipMemcpyHostToDevice, s));
+
+  // 3. counting sort into cells
+  int32_t *key = nullptr, *count = nullptr, *tmp = nullptr;
+  int64_t *count64 = nullptr, *cs64 = nullptr;
+  MSKM_TRY(dalloc(&key, N));
+  MSKM_TRY(dalloc(&count, cs_total));
+  MSKM_TRY(dalloc(&count64, cs_total));
+  MSKM_TRY(dalloc(&cs64, cs_total));
+  MSKM_TRY(dalloc(&tmp, N));
+  MSKM_HIP_TRY(hipMemsetAsync(count, 0, cs_total * 4, s));
+  for (int l = 0; l < L; ++l) {
+    const int64_t n = h->h_lev[l].n;
+    if (n == 0) continue;
+    hipLaunchKernelGGL(k_cell_key, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, pts, dim, h->d_lev, l, h->h_off[l],
+                       n, key, count);
+  }
+  // widen counts and scan over all levels' tables at once: since every
+  // point lands in exactly one cell of its level, the scan value at a
+  // level's first cell equals that level's offset, so cs64 holds internal
+  // global indices directly.
+  MSKM_TRY(halloc(h, &h->cell_start, cs_total));
+  hipLaunchKernelGGL(k_widen, dim3(grid_for(cs_total, kBlock)), dim3(kBlock), 0, s, count, count64, cs_total);
+  MSKM_TRY(exclusive_scan_i64(s, count64, cs64, cs_total));
+  hipLaunchKernelGGL(k_narrow, dim3(grid_for(cs_total, kBlock)), dim3(kBlock), 0, s, cs64, h->cell_start, cs_total);
+  MSKM_HIP_TRY(hipMemsetAsync(count, 0, cs_total * 4, s));  // reuse as cursors
+  MSKM_TRY(halloc(h, &h->perm, N));
+  MSKM_TRY(halloc(h, &h->iperm, N));
+  MSKM_TRY(halloc(h, &h->xs, (size_t)dim * N));
+  for (int l = 0; l < L; ++l) {
+    const int64_t n = h->h_lev[l].n;
+    if (n == 0) continue;
+    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, h->d_lev, l, h->h_off[l], n, key,
+                       cs64, count, tmp);
+  }
+  for (int l = 0; l < L; ++l) {
+    const int64_t n = h->h_lev[l].n;
+    if (n == 0) continue;
+    hipLaunchKernelGGL(k_cell_rank, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, h->d_lev, l, h->h_off[l], n, dim, pts,
+                       key, cs64, tmp, h->perm, h->iperm, h->xs, N);
+  }
+
+  // 4. count pass
+  int64_t *cnt_d = nullptr, *cnt_l = nullptr;
+  MSKM_TRY(dalloc(&cnt_d, N + 1));
+  MSKM_TRY(dalloc(&cnt_l, N + 1));
+  MSKM_HIP_TRY(hipMemsetAsync(cnt_d + N, 0, 8, s));
+  MSKM_HIP_TRY(hipMemsetAsync(cnt_l + N, 0, 8, s));
+  const int rows_per_block = kBlock / kWave;
+  for (int k = 0; k < L; ++k) {
+    const int64_t n = h->h_lev[k].n;
+    if (n == 0) continue;
+    hipLaunchKernelGGL(k_nbr_count, dim3(grid_for(n, rows_per_block)), dim3(kBlock), 0, s, dim, k, h->d_lev,
+                       h->cell_start, h->xs, N, cnt_d, cnt_l);
+  }
+  MSKM_TRY(halloc(h, &h->diag.rowptr, N + 1));
+  MSKM_TRY(halloc(h, &h->lower.rowptr, N + 1));
+  MSKM_TRY(exclusive_scan_i64(s, cnt_d, h->diag.rowptr, N + 1));
+  MSKM_TRY(exclusive_scan_i64(s, cnt_l, h->lower.rowptr, N + 1));
+  MSKM_HIP_TRY(hipMemcpyAsync(&h->diag.nnz, h->diag.rowptr + N, 8, hipMemcpyDeviceToHost, s));
+  MSKM_HIP_TRY(hipMemcpyAsync(&h->lower.nnz, h->lower.rowptr + N, 8, hipMemcpyDeviceToHost, s));
+  MSKM_HIP_TRY(hipStreamSynchronize(s));
+  (void)hipFree(cnt_d);
+  (void)hipFree(cnt_l);
+  (void)hipFree(key);
+  (void)hipFree(count);
+  (void)hipFree(count64);
+  (void)hipFree(cs64);
+  (void)hipFree(tmp);
+  (void)hipFree(d_off);
+
+  // 5. fill pass
+  for (Csr* c : {&h->diag, &h->lower}) {
+    MSKM_TRY(halloc(h, &c->col, (size_t)c->nnz));
+    if (want64) MSKM_TRY(halloc(h, &c->val, (size_t)c->nnz));
+    if (want32) MSKM_TRY(halloc(h, &c->val32, (size_t)c->nnz));
+  }
+  for (int k = 0; k < L; ++k) {
+    const int64_t n = h->h_lev[k].n;
+    if (n == 0) continue;
+    hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(n, rows_per_block)), dim3(kBlock), 0, s, dim, k, h->d_lev,
+                       h->cell_start, h->xs, N, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32,
+                       h->lower.rowptr, h->lower.col, h->lower.val, h->lower.val32);
+  }
+  MSKM_HIP_TRY(hipEventRecord(h->ctx->ev1, s));
+  MSKM_HIP_TRY(hipEventSynchronize(h->ctx->ev1));
+  float ms = 0.f;
+  MSKM_HIP_TRY(hipEventElapsedTime(&ms, h->ctx->ev0, h->ctx->ev1));
+  h->assemble_ms = ms;
+  MSKM_HIP_TRY(hipGetLastError());
+  return MSKM_OK;
+}
+
+// ------------------------------------------------------------------ export
+
+// Entries of block (k, j) in canonical row r: count pass.
+__global__ void __launch_bounds__(kBlock) k_export_count(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                         const int32_t* __restrict__ iperm, int64_t row_off,
+                                                         int64_t nrows, int64_t c0, int64_t c1,
+                                                         int64_t* __restrict__ cnt) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= nrows) return;
+  const int64_t i = iperm[row_off + r];
+  int64_t c = 0;
+  for (int64_t t = rp[i]; t < rp[i + 1]; ++t) c += (col[t] >= c0 && col[t] < c1);
+  cnt[r] = c;
+}
+
+// Fill pass: canonical column = input index within level j; insertion sort
+// of the row (rows are short: tens to a few hundred entries).
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_export_fill(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                        const TV* __restrict__ val, const int32_t* __restrict__ iperm,
+                                                        const int32_t* __restrict__ perm, int64_t row_off,
+                                                        int64_t nrows, int64_t c0, int64_t c1,
+                                                        const int64_t* __restrict__ optr, int32_t* __restrict__ ocol,
+                                                        double* __restrict__ oval) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= nrows) return;
+  const int64_t i = iperm[row_off + r];
+  const int64_t o = optr[r];
+  int64_t n = 0;
+  for (int64_t t = rp[i]; t < rp[i + 1]; ++t) {
+    const int32_t c = col[t];
+    if (c < c0 || c >= c1) continue;
+    const int32_t cc = (int32_t)(perm[c] - c0);
+    const double v = val ? (double)val[t] : 0.0;
+    int64_t p = n;
+    while (p > 0 && ocol[o + p - 1] > cc) {
+      ocol[o + p] = ocol[o + p - 1];
+      if (oval) oval[o + p] = oval[o + p - 1];
+      --p;
+    }
+    ocol[o + p] = cc;
+    if (oval) oval[o + p] = v;
+    ++n;
+  }
+}
+
+mskm_status export_block(mskm_hier* h, int k, int j, int64_t* rowptr, int32_t* col, double* val, int64_t* nnz_out) {
+  hipStream_t s = h->ctx->stream;
+  const Csr& C = (k == j) ? h->diag : h->lower;
+  const int64_t row_off = h->h_off[k], nrows = h->h_off[k + 1] - h->h_off[k];
+  const int64_t c0 = h->h_off[j], c1 = h->h_off[j + 1];
+  int64_t *cnt = nullptr, *optr = nullptr;
+  MSKM_TRY(dalloc(&cnt, nrows + 1));
+  MSKM_TRY(dalloc(&optr, nrows + 1));
+  MSKM_HIP_TRY(hipMemsetAsync(cnt + nrows, 0, 8, s));
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_export_count, dim3(grid_for(nrows, kBlock)), dim3(kBlock), 0, s, C.rowptr, C.col, h->iperm,
+                       row_off, nrows, c0, c1, cnt);
+  mskm_status st = exclusive_scan_i64(s, cnt, optr, nrows + 1);
+  int64_t nnz = 0;
+  if (st == MSKM_OK) {
+    (void)hipMemcpy(&nnz, optr + nrows, 8, hipMemcpyDeviceToHost);
+    if (nnz_out) *nnz_out = nnz;
+  }
+  if (st == MSKM_OK && col != nullptr) {
+    int32_t* ocol = nullptr;
+    double* oval = nullptr;
+    st = dalloc(&ocol, nnz);
+    if (st == MSKM_OK && val) st = dalloc(&oval, nnz);
+    if (st == MSKM_OK && nrows > 0) {
+      if (C.val || !C.val32)
+        hipLaunchKernelGGL(k_export_fill<double>, dim3(grid_for(nrows, kBlock)), dim3(kBlock), 0, s, C.rowptr, C.col,
+                           C.val, h->iperm, h->perm, row_off, nrows, c0, c1, optr, ocol, oval);
+      else
+        hipLaunchKernelGGL(k_export_fill<float>, dim3(grid_for(nrows, kBlock)), dim3(kBlock), 0, s, C.rowptr, C.col,
+                           C.val32, h->iperm, h->perm, row_off, nrows, c0, c1, optr, ocol, oval);
+    }
+    if (st == MSKM_OK) {
+      hipError_t e = hipMemcpyAsync(rowptr, optr, (nrows + 1) * 8, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(col, ocol, nnz * 4, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess && val) e = hipMemcpyAsync(val, oval, nnz * 8, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) st = fail(MSKM_EDEVICE, std::string("export copy: ") + hipGetErrorString(e));
+    }
+    (void)hipFree(ocol);
+    (void)hipFree(oval);
+  } else if (st == MSKM_OK && rowptr) {
+    (void)hipMemcpy(rowptr, optr, (nrows + 1) * 8, hipMemcpyDeviceToHost);
+  }
+  (void)hipFree(cnt);
+  (void)hipFree(optr);
+  return st;
+}
+
+}  // namespace mskm

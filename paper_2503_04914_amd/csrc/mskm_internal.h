@@ -1,0 +1,150 @@
+// Internal declarations of the gfx950 multiscale kernel library.
+//
+// Device data layout (one hierarchy):
+//   * internal order: every level's points are sorted by the row-major key of
+//     their cell in that level's own cell grid (cell side >= delta_l), ties by
+//     input index. Level l occupies internal rows [off_l, off_l + n_l), levels
+//     concatenated coarse to fine. perm[i] = global input index of internal i.
+//   * coordinates: SoA FP64, xs[a][i] for axis a, internal order.
+//   * blocks: CSR over internal rows. "diag" holds A_l = B_{l,l} for every l,
+//     "lower" holds B_{k,j}, j < k. Column = internal global index (int32),
+//     row pointers int64; columns ascend within a row (a row of "lower" lists
+//     level 0's neighbours first, then level 1's, ...).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mskm.h"
+
+namespace mskm {
+
+constexpr int kMaxLevels = 64;
+constexpr int kBlock = 256;  // threads per block of every streaming / SpMV kernel
+
+// Per-level descriptor read by the kernels (all fields uniform per wave).
+struct DevLevel {
+  int64_t off;       // first internal row
+  int32_t n;         // points of the level
+  int32_t ncell_tot; // cells of the level's grid
+  double delta;      // support radius
+  double d2max;      // delta * delta (FP64, round to nearest)
+  double inv_delta;  // 1 / delta
+  double lo[3];      // grid origin
+  double inv_cell;   // 1 / cell side
+  int32_t nc[3];     // cells per axis
+  int32_t cs_off;    // offset of this level's cell_start table in the shared array
+};
+
+// A launch table: block b works on rows [row0[b], row1[b]) of level lev[b].
+// Blocks of one level are contiguous: [lev_begin[l], lev_begin[l+1]).
+struct WorkTable {
+  int32_t nblocks = 0;
+  int32_t rows_per_block = 0;
+  int32_t* lev = nullptr;     // device [nblocks]
+  int64_t* row0 = nullptr;    // device [nblocks]
+  int64_t* row1 = nullptr;    // device [nblocks]
+  int32_t* lev_begin = nullptr;  // device [L+1]
+  std::vector<int32_t> h_lev_begin;
+};
+
+struct Csr {
+  int64_t nnz = 0;
+  int64_t* rowptr = nullptr;  // [N+1]
+  int32_t* col = nullptr;     // [nnz]
+  double* val = nullptr;      // [nnz] FP64 values (optional)
+  float* val32 = nullptr;     // [nnz] FP32 values (optional)
+};
+
+}  // namespace mskm
+
+struct mskm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // pinned host scratch for small readbacks
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+};
+
+struct mskm_hier {
+  mskm_ctx* ctx = nullptr;
+  int32_t dim = 0, L = 0;
+  int64_t N = 0;
+  std::vector<int64_t> h_off;           // [L+1]
+  std::vector<double> h_delta;          // [L]
+  std::vector<mskm::DevLevel> h_lev;    // [L]
+  mskm::DevLevel* d_lev = nullptr;      // device [L]
+  double* xs = nullptr;                 // device [dim][N] SoA, internal order
+  int32_t* perm = nullptr;              // device [N] internal -> input
+  int32_t* iperm = nullptr;             // device [N] input -> internal
+  int32_t* cell_start = nullptr;        // device, all levels' tables
+  mskm::Csr diag, lower;
+  mskm::WorkTable wt_cg;                // table for per-level CG / SpMV launches
+  int64_t device_bytes = 0;
+  double assemble_ms = 0.0;
+  std::vector<void*> allocs;            // everything to free
+};
+
+namespace mskm {
+
+// error helpers (abi.hip)
+void set_error(const std::string& msg);
+mskm_status fail(mskm_status st, const std::string& msg);
+
+#define MSKM_HIP_TRY(...)                                                                    \
+  do {                                                                                       \
+    hipError_t _e = (__VA_ARGS__);                                                           \
+    if (_e != hipSuccess)                                                                    \
+      return ::mskm::fail(_e == hipErrorOutOfMemory ? MSKM_ENOMEM : MSKM_EDEVICE,            \
+                          std::string(#__VA_ARGS__) + ": " + hipGetErrorString(_e));         \
+  } while (0)
+
+#define MSKM_TRY(...)               \
+  do {                              \
+    mskm_status _s = (__VA_ARGS__); \
+    if (_s < 0) return _s;          \
+  } while (0)
+
+// device allocation tracked by the hierarchy
+template <typename T>
+mskm_status halloc(mskm_hier* h, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+  if (e != hipSuccess) return fail(MSKM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  h->allocs.push_back(*p);
+  h->device_bytes += static_cast<int64_t>(count * sizeof(T));
+  return MSKM_OK;
+}
+
+// scratch allocation owned by the caller (freed with hipFree)
+template <typename T>
+mskm_status dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+  if (e != hipSuccess) return fail(MSKM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  return MSKM_OK;
+}
+
+// assemble.hip
+mskm_status assemble_hierarchy(mskm_hier* h, const double* points_dev, bool want64, bool want32);
+mskm_status export_block(mskm_hier* h, int row_level, int col_level, int64_t* rowptr, int32_t* col, double* val,
+                         int64_t* nnz_out);
+mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n);
+mskm_status build_work_table(mskm_hier* h, WorkTable* wt, int rows_per_block);
+
+// solve.hip
+mskm_status apply_op(mskm_hier* h, int op, int prec, const double* x_in, int nrhs, double* y_in, bool io_dev);
+mskm_status solve(mskm_hier* h, const double* f, int nrhs, const mskm_solve_opts* o, double* alpha,
+                  mskm_report* rep);
+mskm_status residual(mskm_hier* h, const double* alpha, const double* f, int nrhs, double* rel_out, bool io_dev);
+mskm_status evaluate(mskm_hier* h, const double* alpha, int nrhs, const double* query, int64_t nq, double* out,
+                     bool io_dev);
+
+}  // namespace mskm

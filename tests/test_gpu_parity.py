@@ -1,0 +1,202 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Bars:
+* neighbour lists / CSR structure: bit-exact (rowptr and columns of every
+  block B_{k,j} in canonical order);
+* block values: <= 4 ulp-ish (1e-15 relative; the same FP64 formula on both sides);
+* FP64 SpMV: <= 1e-14 relative; FP64 solve: coefficients <= 1e-10 relative
+  per level against the oracle's exact sequential solve;
+* mixed path (FP32 values inside, FP64 refinement): <= 1e-8 relative;
+* approximant values at query points: same bars, relative to max |f_L|.
+Sizes span many 256-row tiles and ragged tails (levels of 81..32768 points).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import multiscale as ms
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["grid4", "halton5", "uniform3d3", "table1_5"]
+
+
+def _case(name):
+    if name == "grid4":
+        h = synth.grid_hierarchy()
+        return h, synth.gauss_sine(h.points)
+    if name == "halton5":
+        h = synth.halton_hierarchy(5)
+        return h, synth.fourier_target(1000)(h.points)
+    if name == "uniform3d3":
+        h = synth.uniform3d_hierarchy(3)
+        return h, synth.fourier_target(2001, 3)(h.points)
+    if name == "table1_5":
+        h = synth.table1_hierarchy(5)
+        return h, synth.franke(h.points)
+    raise KeyError(name)
+
+
+@pytest.fixture(scope="module")
+def mod():
+    import paper_2503_04914_amd as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mod):
+    c = mod.mskm_create(0)
+    yield c
+    mod.mskm_destroy(c)
+
+
+_cache = {}
+
+
+def _setup(mod, ctx, name):
+    if name not in _cache:
+        print(f"[parity] case {name}", flush=True)
+        h, f = _case(name)
+        blk = ms.assemble(h.points, h.offsets, h.delta)
+        hd = mod.mskm_hier_create(ctx, h.points, h.offsets, h.delta, fp64=True, fp32=True)
+        a_ref = oracle.sequential_solve(blk, f)
+        _cache[name] = (h, f, blk, hd, a_ref)
+    return _cache[name]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_structure_bit_exact(mod, ctx, name):
+    h, f, blk, hd, _ = _setup(mod, ctx, name)
+    st = mod.mskm_hier_stats_get(hd)
+    assert st["nnz_diag"] == sum(blk.nnz(l, l) for l in range(h.levels))
+    assert st["nnz_lower"] == sum(blk.nnz(k, j) for k in range(h.levels) for j in range(k))
+    for k in range(h.levels):
+        for j in range(k + 1):
+            rp, col, val = mod.mskm_export_block(ctx, hd, k, j)
+            orp, ocol, oval = blk.csr[(k, j)]
+            assert np.array_equal(rp, orp), (k, j)
+            assert np.array_equal(col, ocol), (k, j)
+            np.testing.assert_allclose(val, oval, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_spmv_fp64_and_fp32(mod, ctx, name):
+    h, f, blk, hd, _ = _setup(mod, ctx, name)
+    x = np.random.default_rng(3).standard_normal(h.n_total)
+    D = [blk.mat(l, l) for l in range(h.levels)]
+    off = h.offsets
+    yd = np.concatenate([D[l] @ x[off[l]:off[l + 1]] for l in range(h.levels)])
+    yl = ms.lower_matrix(blk) @ x
+    for op, ref in ((mod.MSKM_OP_DIAG, yd), (mod.MSKM_OP_LOWER, yl), (mod.MSKM_OP_FULL, yd + yl)):
+        y = np.zeros_like(x)
+        mod.mskm_apply(ctx, hd, op, x, y, prec=mod.MSKM_PREC_FP64)
+        assert _rel(y, ref) <= 1e-14, op
+        y32 = np.zeros_like(x)
+        mod.mskm_apply(ctx, hd, op, x, y32, prec=mod.MSKM_PREC_FP32)
+        assert _rel(y32, ref) <= 1e-5, op  # FP32 values, FP32 accumulation
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("alg", ["monolithic", "sequential", "monolithic_warm"])
+def test_solve_fp64(mod, ctx, name, alg):
+    h, f, blk, hd, a_ref = _setup(mod, ctx, name)
+    alpha = np.zeros_like(f)
+    o = mod.solve_opts(cg_rtol=1e-14, max_cg_iters=20000,
+                       algorithm=mod.MSKM_ALG_SEQUENTIAL if alg == "sequential" else mod.MSKM_ALG_MONOLITHIC,
+                       warm_start=1 if alg == "monolithic_warm" else 0)
+    res = mod.mskm_solve(ctx, hd, f, alpha, o)
+    assert res.status == mod.MSKM_OK
+    for l in range(h.levels):
+        sl = slice(h.offsets[l], h.offsets[l + 1])
+        assert _rel(alpha[sl], a_ref[sl]) <= 1e-10, (l, _rel(alpha[sl], a_ref[sl]))
+    rel_o, _, _ = oracle.residual(blk, alpha, f)
+    assert rel_o <= 1e-12
+    assert res.report["rel_residual"] == pytest.approx(rel_o, rel=1e-3, abs=1e-15)
+
+
+@pytest.mark.parametrize("name", ["halton5", "uniform3d3"])
+def test_solve_mixed_refined(mod, ctx, name):
+    h, f, blk, hd, a_ref = _setup(mod, ctx, name)
+    alpha = np.zeros_like(f)
+    o = mod.solve_opts(precision=mod.MSKM_PREC_FP32, cg_rtol=1e-6, target_rel_residual=1e-13, max_refine=20)
+    res = mod.mskm_solve(ctx, hd, f, alpha, o)
+    assert res.status == mod.MSKM_OK, res.report
+    assert res.report["refine_steps"] >= 2
+    for l in range(h.levels):
+        sl = slice(h.offsets[l], h.offsets[l + 1])
+        assert _rel(alpha[sl], a_ref[sl]) <= 1e-8, (l, _rel(alpha[sl], a_ref[sl]))
+    assert oracle.residual(blk, alpha, f)[0] <= 1e-12
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_residual_and_evaluate(mod, ctx, name):
+    h, f, blk, hd, a_ref = _setup(mod, ctx, name)
+    rng = np.random.default_rng(17)
+    a = a_ref + 1e-6 * rng.standard_normal(a_ref.shape)  # not the solution: nonzero residual
+    rel = mod.mskm_residual(ctx, hd, a, f)[0]
+    assert rel == pytest.approx(oracle.residual(blk, a, f)[0], rel=1e-10)
+    q = rng.random((3000, h.dim)) * 1.2 - 0.1  # includes points outside the hull
+    q = np.concatenate([q, h.level_points(h.levels - 1)[:500]])
+    out = np.zeros(len(q))
+    mod.mskm_evaluate(ctx, hd, a_ref, q, out)
+    ref = oracle.evaluate(h.points, h.offsets, h.delta, a_ref, q)
+    assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_bad_arguments_fail_cleanly(mod, ctx):
+    with pytest.raises(mod.MskmError) as e:
+        mod.mskm_hier_create(ctx, np.zeros((4, 2)), np.array([0, 4]), np.array([-1.0]))
+    assert e.value.status == mod.MSKM_EINVAL
+    pts = np.zeros((4, 2))
+    pts[2, 1] = np.nan
+    with pytest.raises(mod.MskmError):
+        mod.mskm_hier_create(ctx, pts, np.array([0, 4]), np.array([0.5]))
+    h, f, blk, hd, _ = _setup(mod, ctx, "grid4")
+    with pytest.raises(mod.MskmError):
+        mod.mskm_export_block(ctx, hd, 1, 2)  # column level above row level
+    # iteration cap hit: warning status with outputs written
+    alpha = np.zeros_like(f)
+    res = mod.mskm_solve(ctx, hd, f, alpha, mod.solve_opts(max_cg_iters=2))
+    assert res.status == mod.MSKM_ENOCONV
+    assert np.all(np.isfinite(alpha))
+
+
+def test_degenerate_hierarchies(mod, ctx):
+    # single level, single point; empty middle level; coincident coarse/fine points
+    for pts, off, dl in [
+        (np.array([[0.3, 0.4]]), [0, 1], [0.1]),
+        (np.array([[0.1, 0.1], [0.9, 0.9], [0.5, 0.5], [0.2, 0.7]]), [0, 2, 2, 4], [0.8, 0.5, 0.6]),
+        (np.random.default_rng(1).random((700, 2)), [0, 100, 100, 700], [0.3, 0.2, 0.08]),
+    ]:
+        pts = np.ascontiguousarray(pts)
+        off = np.array(off, dtype=np.int64)
+        dl = np.array(dl)
+        blk = ms.assemble(pts, off, dl)
+        f = np.sin(pts[:, 0] * 3) + pts[:, 1]
+        hd = mod.mskm_hier_create(ctx, pts, off, dl)
+        try:
+            for k in range(len(dl)):
+                for j in range(k + 1):
+                    rp, col, _ = mod.mskm_export_block(ctx, hd, k, j)
+                    assert np.array_equal(rp, blk.csr[(k, j)][0]) and np.array_equal(col, blk.csr[(k, j)][1])
+            alpha = np.zeros_like(f)
+            mod.mskm_solve(ctx, hd, f, alpha, mod.solve_opts(cg_rtol=1e-14))
+            ref = oracle.sequential_solve(blk, f, solver="cholesky")
+            assert _rel(alpha, ref) <= 1e-10
+        finally:
+            mod.mskm_hier_destroy(hd)
+
+
+def test_deterministic_repeat(mod, ctx):
+    h, f, blk, hd, _ = _setup(mod, ctx, "halton5")
+    a1, a2 = np.zeros_like(f), np.zeros_like(f)
+    o = mod.solve_opts(cg_rtol=1e-12)
+    mod.mskm_solve(ctx, hd, f, a1, o)
+    mod.mskm_solve(ctx, hd, f, a2, o)
+    assert np.array_equal(a1, a2)
