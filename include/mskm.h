@@ -163,6 +163,32 @@ enum { MSKM_PREC_FP64 = 0, MSKM_PREC_FP32 = 1 };
 mskm_status mskm_apply(mskm_ctx* ctx, const mskm_hier* h, int32_t op, int32_t prec, const double* x, int32_t nrhs,
                        double* y, int32_t flags);
 
+/* y = op x on device vectors kept in the internal (cell-sorted) order of the
+ * hierarchy (see mskm_export_perm), launched `repeats` (>= 1) times back to
+ * back on the context stream. x, y: device arrays of N FP64 values for
+ * MSKM_PREC_FP64 or N FP32 values for MSKM_PREC_FP32; y must not alias x.
+ * avg_ms (nullable) receives the mean device time per launch from HIP events
+ * recorded around the launches. Used for bandwidth measurement and by callers
+ * that work in the internal order throughout. */
+mskm_status mskm_apply_internal(mskm_ctx* ctx, const mskm_hier* h, int32_t op, int32_t prec, const void* x, void* y,
+                                int32_t repeats, float* avg_ms);
+
+/* Autotuner: times every CSR SpMV variant -- lanes per row 4, 8, 16, 32, 64,
+ * each with per-entry loads and with 16-byte loads (variant codes w and
+ * w + 1000) -- for each operator (DIAG, LOWER, FULL) and each stored
+ * precision on this hierarchy's own blocks (`repeats` >= 1 timed launches
+ * per variant) and keeps the fastest for later apply / solve calls.
+ * times_ms (nullable, host, [3][2][10]) receives the mean ms per launch of
+ * every [op][precision][variant] (order 4..64 then 4+1000..64+1000; 0 where
+ * a precision is not stored).
+ * The choice is also remembered by the context: hierarchies created later
+ * on it with the same dimension, level count, point count and nonzero
+ * counts start with the tuned widths. */
+mskm_status mskm_autotune(mskm_ctx* ctx, mskm_hier* h, int32_t repeats, float* times_ms);
+
+/* Current SpMV variant code for op (MSKM_OP_*) and prec (MSKM_PREC_*). */
+mskm_status mskm_spmv_width(const mskm_hier* h, int32_t op, int32_t prec, int32_t* width);
+
 /* ------------------------------------------------------------------ solve */
 
 enum { MSKM_ALG_MONOLITHIC = 0, MSKM_ALG_SEQUENTIAL = 1 };

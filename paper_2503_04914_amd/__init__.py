@@ -36,7 +36,8 @@ MSKM_PRECOND_NONE, MSKM_PRECOND_LEARNED = 0, 1
 EXPORTED = [
     "mskm_create", "mskm_destroy", "mskm_last_error", "mskm_abi_version",
     "mskm_hier_create", "mskm_hier_destroy", "mskm_hier_stats_get", "mskm_hier_offsets",
-    "mskm_export_block", "mskm_export_perm", "mskm_apply",
+    "mskm_export_block", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
+    "mskm_autotune", "mskm_spmv_width",
     "mskm_solve_opts_default", "mskm_solve", "mskm_residual", "mskm_evaluate",
 ]
 
@@ -99,6 +100,9 @@ def lib():
     L.mskm_export_block.argtypes = [vp, vp, i32, i32, vp, vp, vp, C.POINTER(i64)]
     L.mskm_export_perm.argtypes = [vp, vp, vp]
     L.mskm_apply.argtypes = [vp, vp, i32, i32, vp, i32, vp, i32]
+    L.mskm_apply_internal.argtypes = [vp, vp, i32, i32, vp, vp, i32, C.POINTER(C.c_float)]
+    L.mskm_autotune.argtypes = [vp, vp, i32, C.POINTER(C.c_float)]
+    L.mskm_spmv_width.argtypes = [vp, i32, i32, C.POINTER(i32)]
     L.mskm_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
     L.mskm_solve_opts_default.restype = None
     L.mskm_solve.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(Report)]
@@ -226,6 +230,33 @@ def mskm_apply(ctx, h, op: int, x, y, prec: int = MSKM_PREC_FP64, nrhs: int = 1)
     if xd != yd:
         raise ValueError("x and y must both be host or both be device arrays")
     _check(lib().mskm_apply(ctx, h, op, prec, xp, nrhs, yp, MSKM_IO_DEVICE if xd else 0), "mskm_apply")
+
+
+def mskm_apply_internal(ctx, h, op: int, x, y, prec: int = MSKM_PREC_FP64, repeats: int = 1) -> float:
+    """y = op x on CUDA tensors in the internal order; returns mean ms per launch."""
+    if not (_is_torch(x) and _is_torch(y) and x.is_cuda and y.is_cuda):
+        raise TypeError("mskm_apply_internal takes CUDA tensors")
+    ms = C.c_float()
+    _check(lib().mskm_apply_internal(ctx, h, op, prec, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), repeats,
+                                     C.byref(ms)), "mskm_apply_internal")
+    return float(ms.value)
+
+
+TUNE_VARIANTS = [4, 8, 16, 32, 64, 1004, 1008, 1016, 1032, 1064]
+
+
+def mskm_autotune(ctx, h, repeats: int = 5) -> np.ndarray:
+    """Pick the fastest SpMV variant per operator/precision; returns the
+    [3][2][10] table of mean ms per launch (op, precision, TUNE_VARIANTS)."""
+    t = np.zeros(60, dtype=np.float32)
+    _check(lib().mskm_autotune(ctx, h, repeats, t.ctypes.data_as(C.POINTER(C.c_float))), "mskm_autotune")
+    return t.reshape(3, 2, 10)
+
+
+def mskm_spmv_width(h, op: int, prec: int = MSKM_PREC_FP64) -> int:
+    w = C.c_int32()
+    _check(lib().mskm_spmv_width(h, op, prec, C.byref(w)), "mskm_spmv_width")
+    return int(w.value)
 
 
 def mskm_solve_opts_default() -> SolveOpts:

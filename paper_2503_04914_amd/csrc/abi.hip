@@ -111,10 +111,15 @@ mskm_status mskm_hier_create(mskm_ctx* ctx, const mskm_hier_desc* d, mskm_hier**
       st = fail(MSKM_EDEVICE, "point upload failed");
   }
   if (st == MSKM_OK) st = mskm::assemble_hierarchy(h, pts, want64, want32);
-  if (st == MSKM_OK) {
-    if (h->diag.nnz >= ((int64_t)1 << 62)) st = fail(MSKM_ELIMIT, "too many nonzeros");
+  if (st == MSKM_OK) {  // widths tuned earlier on this context for the same shape
+    for (const auto& t : ctx->tune_cache)
+      if (t.dim == h->dim && t.L == h->L && t.N == h->N && t.nnz_diag == h->diag.nnz && t.nnz_lower == h->lower.nnz)
+        std::memcpy(h->spmv_g, t.g, sizeof(t.g));
   }
-  if (st == MSKM_OK) st = mskm::build_work_table(h, &h->wt_cg, 256);
+  // SpMV phase: 64 rows per block (one to four passes depending on the
+  // lanes per row); streaming phase: 1024 rows per block (4 per thread)
+  if (st == MSKM_OK) st = mskm::build_work_table(h, &h->wt_spmv, 64, 1 << 30);
+  if (st == MSKM_OK) st = mskm::build_work_table(h, &h->wt_vec, 4 * mskm::kBlock, 1 << 30);
   if (!pdev) (void)hipFree(pts);
   if (st != MSKM_OK) {
     mskm_hier_destroy(h);
@@ -181,6 +186,33 @@ mskm_status mskm_apply(mskm_ctx* ctx, const mskm_hier* h, int32_t op, int32_t pr
   if (nrhs < 1) return fail(MSKM_EINVAL, "nrhs must be >= 1");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
   return mskm::apply_op(const_cast<mskm_hier*>(h), op, prec, x, nrhs, y, (flags & MSKM_IO_DEVICE) != 0);
+}
+
+mskm_status mskm_apply_internal(mskm_ctx* ctx, const mskm_hier* h, int32_t op, int32_t prec, const void* x, void* y,
+                                int32_t repeats, float* avg_ms) {
+  if (!valid_ctx(ctx) || !h || !x || !y) return fail(MSKM_EINVAL, "mskm_apply_internal: NULL argument");
+  if (x == y) return fail(MSKM_EINVAL, "mskm_apply_internal: y aliases x");
+  if (op < MSKM_OP_DIAG || op > MSKM_OP_FULL) return fail(MSKM_EINVAL, "unknown op");
+  if (prec != MSKM_PREC_FP64 && prec != MSKM_PREC_FP32) return fail(MSKM_EINVAL, "unknown precision");
+  if (repeats < 1) return fail(MSKM_EINVAL, "repeats must be >= 1");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::apply_internal(const_cast<mskm_hier*>(h), op, prec, x, y, repeats, avg_ms);
+}
+
+mskm_status mskm_autotune(mskm_ctx* ctx, mskm_hier* h, int32_t repeats, float* times_ms) {
+  if (!valid_ctx(ctx) || !h) return fail(MSKM_EINVAL, "mskm_autotune: NULL argument");
+  if (repeats < 1) return fail(MSKM_EINVAL, "repeats must be >= 1");
+  if (times_ms) std::memset(times_ms, 0, sizeof(float) * 3 * 2 * mskm::kTuneVariants);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::autotune(h, repeats, times_ms);
+}
+
+mskm_status mskm_spmv_width(const mskm_hier* h, int32_t op, int32_t prec, int32_t* width) {
+  if (!h || !width) return fail(MSKM_EINVAL, "mskm_spmv_width: NULL argument");
+  if (op < MSKM_OP_DIAG || op > MSKM_OP_FULL || (prec != MSKM_PREC_FP64 && prec != MSKM_PREC_FP32))
+    return fail(MSKM_EINVAL, "unknown op or precision");
+  *width = h->spmv_g[op][prec];
+  return MSKM_OK;
 }
 
 void mskm_solve_opts_default(mskm_solve_opts* o) {

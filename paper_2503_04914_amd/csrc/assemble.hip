@@ -322,22 +322,24 @@ __global__ void __launch_bounds__(kBlock) k_nbr_fill(int dim, int k, const DevLe
 
 // ------------------------------------------------------------- work table
 
-mskm_status build_work_table(mskm_hier* h, WorkTable* wt, int rows_per_block) {
+mskm_status build_work_table(mskm_hier* h, WorkTable* wt, int min_rows, int max_blocks_per_level) {
   std::vector<int32_t> lev;
   std::vector<int64_t> r0, r1;
   wt->h_lev_begin.assign(h->L + 1, 0);
   for (int l = 0; l < h->L; ++l) {
     wt->h_lev_begin[l] = (int32_t)lev.size();
-    for (int64_t a = h->h_off[l]; a < h->h_off[l + 1]; a += rows_per_block) {
+    const int64_t n = h->h_off[l + 1] - h->h_off[l];
+    const int64_t rpb = std::max<int64_t>(min_rows, (n + max_blocks_per_level - 1) / max_blocks_per_level);
+    for (int64_t a = h->h_off[l]; a < h->h_off[l + 1]; a += rpb) {
       lev.push_back(l);
       r0.push_back(a);
-      r1.push_back(std::min<int64_t>(a + rows_per_block, h->h_off[l + 1]));
+      r1.push_back(std::min<int64_t>(a + rpb, h->h_off[l + 1]));
     }
   }
   wt->h_lev_begin[h->L] = (int32_t)lev.size();
   if (lev.size() > (size_t)INT32_MAX) return fail(MSKM_ELIMIT, "work table too large");
   wt->nblocks = (int32_t)lev.size();
-  wt->rows_per_block = rows_per_block;
+  wt->rows_per_block = min_rows;
   MSKM_TRY(halloc(h, &wt->lev, lev.size()));
   MSKM_TRY(halloc(h, &wt->row0, r0.size()));
   MSKM_TRY(halloc(h, &wt->row1, r1.size()));
@@ -502,9 +504,13 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
 
   // 5. fill pass
   for (Csr* c : {&h->diag, &h->lower}) {
-    MSKM_TRY(halloc(h, &c->col, (size_t)c->nnz));
-    if (want64) MSKM_TRY(halloc(h, &c->val, (size_t)c->nnz));
-    if (want32) MSKM_TRY(halloc(h, &c->val32, (size_t)c->nnz));
+    MSKM_TRY(halloc(h, &c->col, (size_t)c->nnz + kCsrPad));
+    if (want64) MSKM_TRY(halloc(h, &c->val, (size_t)c->nnz + kCsrPad));
+    if (want32) MSKM_TRY(halloc(h, &c->val32, (size_t)c->nnz + kCsrPad));
+    // pads hold finite values (never used: the loads that reach them are masked)
+    MSKM_HIP_TRY(hipMemsetAsync(c->col + c->nnz, 0, kCsrPad * 4, s));
+    if (want64) MSKM_HIP_TRY(hipMemsetAsync(c->val + c->nnz, 0, kCsrPad * 8, s));
+    if (want32) MSKM_HIP_TRY(hipMemsetAsync(c->val32 + c->nnz, 0, kCsrPad * 4, s));
   }
   for (int k = 0; k < L; ++k) {
     const int64_t n = h->h_lev[k].n;

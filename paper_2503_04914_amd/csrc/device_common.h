@@ -17,6 +17,7 @@ constexpr int kWave = 64;
 // rows (which share most of their gathered x entries) stay in one L2.
 __device__ __forceinline__ int xcd_block_id(int nblocks) {
   const int b = blockIdx.x;
+  // blocks are dispatched round-robin over the 8 XCDs
   const int per = nblocks / 8;
   const int rem = nblocks % 8;
   const int xcd = b % 8;

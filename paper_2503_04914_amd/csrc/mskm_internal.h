@@ -24,6 +24,9 @@ namespace mskm {
 
 constexpr int kMaxLevels = 64;
 constexpr int kBlock = 256;  // threads per block of every streaming / SpMV kernel
+constexpr int kCsrPad = 16;  // tail pad (entries) of CSR column and value arrays
+constexpr int kVecFlag = 1000;  // SpMV variant code: lanes per row + kVecFlag = 16-byte loads
+constexpr int kTuneVariants = 10;  // widths 4..64, scalar and 16-byte loads
 
 // Per-level descriptor read by the kernels (all fields uniform per wave).
 struct DevLevel {
@@ -61,7 +64,17 @@ struct Csr {
 
 }  // namespace mskm
 
+namespace mskm {
+// Autotuner result remembered by the context for hierarchies of one shape.
+struct TuneEntry {
+  int32_t dim, L;
+  int64_t N, nnz_diag, nnz_lower;
+  int32_t g[3][2];
+};
+}  // namespace mskm
+
 struct mskm_ctx {
+  std::vector<mskm::TuneEntry> tune_cache;  // shape -> SpMV widths
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -84,7 +97,9 @@ struct mskm_hier {
   int32_t* iperm = nullptr;             // device [N] input -> internal
   int32_t* cell_start = nullptr;        // device, all levels' tables
   mskm::Csr diag, lower;
-  mskm::WorkTable wt_cg;                // table for per-level CG / SpMV launches
+  mskm::WorkTable wt_spmv;              // per-level one-pass SpMV blocks (CG phase 1)
+  mskm::WorkTable wt_vec;               // per-level streaming blocks (CG phase 3)
+  int32_t spmv_g[3][2] = {{8, 8}, {32, 32}, {32, 32}};  // lanes per row [op][FP64, FP32]
   int64_t device_bytes = 0;
   double assemble_ms = 0.0;
   std::vector<void*> allocs;            // everything to free
@@ -137,10 +152,14 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* points_dev, bool want
 mskm_status export_block(mskm_hier* h, int row_level, int col_level, int64_t* rowptr, int32_t* col, double* val,
                          int64_t* nnz_out);
 mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n);
-mskm_status build_work_table(mskm_hier* h, WorkTable* wt, int rows_per_block);
+// Rows of each level split into blocks of max(min_rows, n_l / max_blocks) rows,
+// so that no level has more than max_blocks blocks.
+mskm_status build_work_table(mskm_hier* h, WorkTable* wt, int min_rows, int max_blocks_per_level);
 
 // solve.hip
 mskm_status apply_op(mskm_hier* h, int op, int prec, const double* x_in, int nrhs, double* y_in, bool io_dev);
+mskm_status apply_internal(mskm_hier* h, int op, int prec, const void* x, void* y, int repeats, float* avg_ms);
+mskm_status autotune(mskm_hier* h, int repeats, float* times_out);
 mskm_status solve(mskm_hier* h, const double* f, int nrhs, const mskm_solve_opts* o, double* alpha,
                   mskm_report* rep);
 mskm_status residual(mskm_hier* h, const double* alpha, const double* f, int nrhs, double* rel_out, bool io_dev);

@@ -63,6 +63,38 @@ __device__ __forceinline__ TA csr_row_dot(const int64_t* __restrict__ rp, const 
   return group_sum<G>(acc);
 }
 
+// Same dot with 16-byte loads: each lane takes V = 16/sizeof(TV) consecutive
+// entries (values as one 16-byte load, columns as one 8- or 16-byte load)
+// starting from the row start rounded down to a multiple of V; entries
+// outside the row are masked. Value and column arrays carry a tail pad of
+// kCsrPad entries, so the rounded loads never leave their allocation.
+template <int G, typename TV, typename TX, typename TA>
+__device__ __forceinline__ TA csr_row_dot_v(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                            const TV* __restrict__ val, const TX* __restrict__ x, int64_t row,
+                                            int gl) {
+  constexpr int V = 16 / sizeof(TV);
+  const int64_t s = rp[row], e = rp[row + 1];
+  TA acc = 0;
+  for (int64_t k = (s & ~(int64_t)(V - 1)) + (int64_t)gl * V; k < e; k += (int64_t)G * V) {
+    TV v[V];
+    int32_t c[V];
+    if constexpr (V == 2) {
+      const double2 vv = *reinterpret_cast<const double2*>(val + k);
+      const int2 cc = *reinterpret_cast<const int2*>(col + k);
+      v[0] = vv.x; v[1] = vv.y; c[0] = cc.x; c[1] = cc.y;
+    } else {
+      const float4 vv = *reinterpret_cast<const float4*>(val + k);
+      const int4 cc = *reinterpret_cast<const int4*>(col + k);
+      v[0] = vv.x; v[1] = vv.y; v[2] = vv.z; v[3] = vv.w;
+      c[0] = cc.x; c[1] = cc.y; c[2] = cc.z; c[3] = cc.w;
+    }
+#pragma unroll
+    for (int u = 0; u < V; ++u)
+      if (k + u >= s && k + u < e) acc += (TA)v[u] * (TA)x[c[u]];
+  }
+  return group_sum<G>(acc);
+}
+
 // y[i] = beta_b * b[i] + sign * (A1 x)[i] + sign * (A2 x)[i]  for i in [0, n)
 // (A2 optional). G lanes per row, grid-stride over rows.
 template <int G, typename TV, typename TX, typename TA>
@@ -79,157 +111,183 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// --------------------------------------------------------------------- CG
+template <int G, typename TV, typename TX, typename TA>
+__global__ void __launch_bounds__(kBlock)
+    k_spmv_v(const int64_t* __restrict__ rp1, const int32_t* __restrict__ c1, const TV* __restrict__ v1,
+             const int64_t* __restrict__ rp2, const int32_t* __restrict__ c2, const TV* __restrict__ v2,
+             const TX* __restrict__ x, const TX* __restrict__ b, TX* __restrict__ y, TA sign, int64_t r0, int64_t r1) {
+  const int gl = threadIdx.x % G;
+  const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
+  for (int64_t i = r0 + (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
+    TA acc = csr_row_dot_v<G, TV, TX, TA>(rp1, c1, v1, x, i, gl);
+    if (rp2) acc += csr_row_dot_v<G, TV, TX, TA>(rp2, c2, v2, x, i, gl);
+    if (gl == 0) y[i] = (TX)((b ? (TA)b[i] : (TA)0) + sign * acc);
+  }
+}
 
-// Per-system state (one system = one level of one right-hand side).
-struct CgState {
-  double bnorm2;   // ||b||^2
-  double rr;       // r.r of the current iterate
-  double alpha;    // step of the current iteration
-  double beta;     // direction update of the current iteration
-  double rtol2;    // rtol^2
-  int32_t active;  // 1 while iterating
-  int32_t iters;   // iterations done
-  int32_t capped;  // 1 if stopped by the iteration cap
-  int32_t maxit;
-  uint32_t ticket; // arrival counter of the current reduction
+// --------------------------------------------------------------------- CG
+//
+// Conjugate gradients on A_l x_l = b_l for every participating level l, all
+// levels in each launch. Four kernels per iteration, no grid-wide fences:
+//   spmv   (iteration i): p_new = r + beta p_old for the block's rows and
+//          q = A p_new, gathering r and p_old (q_i = sum_j a_ij (r_j + beta
+//          p_old_j)); partial p_new.q per block.
+//   red_a  one block per level: alpha = rr / sum(partials).
+//   update x += alpha p_new; r -= alpha q; partial r.r per block.
+//   red_b  one block per level: rr_new, stop test ||r|| <= rtol ||b|| or the
+//          iteration cap, beta = rr_new / rr.
+// The per-level scalars are written only by the reduce kernels and read by the
+// big kernels of the next phase; the kernel boundaries order and publish them.
+// Partial sums are reduced in block order: the result is deterministic.
+
+// Per-level solve control and state (one struct per level).
+struct CgLevel {
+  double rtol2;   // rtol^2 (host)
+  double bb;      // b.b
+  double rr;      // r.r of the current iterate
+  double alpha;   // step of the current iteration
+  double beta;    // direction coefficient for the next spmv
+  int32_t maxit;  // iteration cap (host)
+  int32_t on;     // participates (host)
+  int32_t iters;  // iterations done
+  int32_t done;   // stopped (converged, capped or broken down)
+  int32_t capped; // stopped by the cap or by non-finite data
   int32_t pad;
 };
 
-// Arrival protocol: returns true in every thread of the last block of level
-// `l` to finish; that block may then read all partials of the level.
-__device__ __forceinline__ bool arrive_last(CgState* st, int nblk_level, bool* sflag) {
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t t = atomicAdd(&st->ticket, 1u);
-    *sflag = (t == (uint32_t)(nblk_level - 1));
-  }
-  __syncthreads();
-  const bool last = *sflag;
-  if (last) __threadfence();
-  return last;
-}
+constexpr int kRedBlock = 1024;  // threads of the per-level reduce kernels
 
-// Fixed-order sum of partial[a..b) by one block (result in thread 0).
-__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int a, int b, double* smem) {
+// Fixed-order block sum of part[a..e), result in thread 0.
+__device__ __forceinline__ double block_range_sum(const double* __restrict__ part, int a, int e, double* sm) {
   double s = 0.0;
-  for (int i = a + threadIdx.x; i < b; i += kBlock) s += part[i];
-  return block_sum(s, smem);
+  for (int i = a + (int)threadIdx.x; i < e; i += (int)blockDim.x) s += part[i];
+  return block_sum(s, sm);
 }
 
-// Init: x = 0 (or keep x0), r = b - A x0, p = r; rr, ||b||^2.
-// Non-participating levels (mask bit clear) are set inactive and untouched.
+// Block sum written to part[slot] by thread 0.
+__device__ __forceinline__ void block_partial(double v, double* sm, double* __restrict__ part, int slot) {
+  v = block_sum(v, sm);
+  if (threadIdx.x == 0) part[slot] = v;
+}
+
+// Init: x = x0 (warm) or 0; r = b - A x; p_old = 0; partials b.b and r.r
+// (over the SpMV table's blocks).
 template <int G, typename TV, typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_cg_init(const WorkTable wt, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
               const TV* __restrict__ val, const TX* __restrict__ b, TX* __restrict__ x, TX* __restrict__ r,
-              TX* __restrict__ p, CgState* __restrict__ st, const uint64_t* __restrict__ mask, int warm,
-              double* __restrict__ part, double* __restrict__ part2, int32_t* __restrict__ n_active) {
+              TX* __restrict__ p0, const CgLevel* __restrict__ st, int warm, double* __restrict__ bbp,
+              double* __restrict__ rrp, int base) {
   __shared__ double sm[kBlock / kWave];
-  __shared__ bool last;
-  const int blk = xcd_block_id(wt.nblocks);
+  const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
-  const bool on = (mask[l >> 6] >> (l & 63)) & 1ull;
+  const bool on = st[l].on != 0;
   const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
   double sb = 0.0, sr = 0.0;
   if (on) {
     const int gl = threadIdx.x % G;
     for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
-      double ri;
-      if (warm) {
-        const double ax = csr_row_dot<G, TV, TX, double>(rp, col, val, x, i, gl);
-        ri = (double)b[i] - ax;
-      } else {
-        ri = (double)b[i];
-      }
+      double ri = (double)b[i];
+      if (warm) ri -= csr_row_dot<G, TV, TX, double>(rp, col, val, x, i, gl);
       if (gl == 0) {
         const double bi = (double)b[i];
         if (!warm) x[i] = (TX)0;
         r[i] = (TX)ri;
-        p[i] = (TX)ri;
+        p0[i] = (TX)0;
         sb += bi * bi;
-        sr += ri * ri;
+        sr += (double)(TX)ri * (double)(TX)ri;
       }
     }
   }
-  sb = block_sum(sb, sm);
-  sr = block_sum(sr, sm);
+  block_partial(sb, sm, bbp, blk);
+  block_partial(sr, sm, rrp, blk);
+}
+
+// One block per level: initial b.b, r.r and stop test.
+__global__ void __launch_bounds__(kRedBlock) k_cg_red_init(int lev0, const int32_t* __restrict__ lev_begin,
+                                                        const double* __restrict__ bbp, const double* __restrict__ rrp,
+                                                        CgLevel* __restrict__ st) {
+  __shared__ double sm[kRedBlock / kWave];
+  const int l = lev0 + blockIdx.x;
+  const double bb = block_range_sum(bbp, lev_begin[l], lev_begin[l + 1], sm);
+  const double rr = block_range_sum(rrp, lev_begin[l], lev_begin[l + 1], sm);
   if (threadIdx.x == 0) {
-    part[blk] = sb;
-    part2[blk] = sr;
-  }
-  const int a = wt.lev_begin[l], e = wt.lev_begin[l + 1];
-  if (arrive_last(&st[l], e - a, &last)) {
-    const double tb = reduce_partials(part, a, e, sm);
-    const double tr = reduce_partials(part2, a, e, sm);
-    if (threadIdx.x == 0) {
-      CgState& S = st[l];
-      S.ticket = 0;
-      S.iters = 0;
-      S.capped = 0;
-      S.bnorm2 = on ? tb : 0.0;
-      S.rr = on ? tr : 0.0;
-      S.alpha = S.beta = 0.0;
-      const int act = on && tb > 0.0 && tr > S.rtol2 * tb && S.maxit > 0;
-      if (on && !act && tb > 0.0 && tr > S.rtol2 * tb) S.capped = 1;
-      S.active = act;
-      if (act) atomicAdd(n_active, 1);
-    }
+    CgLevel& S = st[l];
+    S.bb = bb;
+    S.rr = rr;
+    S.alpha = 0.0;
+    S.beta = 0.0;
+    S.iters = 0;
+    S.capped = 0;
+    const bool finite = isfinite(bb) && isfinite(rr);
+    const bool conv = finite && !(rr > S.rtol2 * bb);
+    S.capped = S.on && !conv && (!finite || S.maxit <= 0);
+    S.done = !S.on || conv || S.capped;
   }
 }
 
-// K1: q = A p on active levels; alpha = rr / (p.q) by the level's last block.
+// spmv phase: p_new = r + beta p_old; q = A p_new; partial p_new.q per wave
+// (kBlock / 64 partials per block, no block barrier). Launched over the
+// table blocks [base, base + gridDim.x) of the participating levels.
 template <int G, typename TV, typename TX>
 __global__ void __launch_bounds__(kBlock)
-    k_cg_spmv(const WorkTable wt, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-              const TV* __restrict__ val, const TX* __restrict__ p, TX* __restrict__ q, CgState* __restrict__ st,
-              double* __restrict__ part, int32_t* __restrict__ n_active) {
-  __shared__ double sm[kBlock / kWave];
-  __shared__ bool last;
-  const int blk = xcd_block_id(wt.nblocks);
+    k_cg_spmv(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+              const TV* __restrict__ val, const TX* __restrict__ r, const TX* __restrict__ p_old,
+              TX* __restrict__ p_new, TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ pqp) {
+  const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
-  if (!st[l].active) return;
+  if (st[l].done) return;
+  const TX beta = (TX)st[l].beta;
   const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
   const int gl = threadIdx.x % G;
   double s = 0.0;
   for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
-    const TX qi = (TX)csr_row_dot<G, TV, TX, TX>(rp, col, val, p, i, gl);
+    const int64_t ke = rp[i + 1];
+    TX acc = 0;
+    for (int64_t k = rp[i] + gl; k < ke; k += G) {
+      const int32_t j = col[k];
+      acc += (TX)val[k] * (r[j] + beta * p_old[j]);
+    }
+    acc = group_sum<G>(acc);
     if (gl == 0) {
-      q[i] = qi;
-      s += (double)p[i] * (double)qi;
+      const TX pn = r[i] + beta * p_old[i];
+      p_new[i] = pn;
+      q[i] = acc;
+      s += (double)pn * (double)acc;
     }
   }
-  s = block_sum(s, sm);
-  if (threadIdx.x == 0) part[blk] = s;
-  const int a = wt.lev_begin[l], e = wt.lev_begin[l + 1];
-  if (arrive_last(&st[l], e - a, &last)) {
-    const double pq = reduce_partials(part, a, e, sm);
-    if (threadIdx.x == 0) {
-      CgState& S = st[l];
-      S.ticket = 0;
-      if (pq > 0.0 && std::isfinite(pq)) {
-        S.alpha = S.rr / pq;
-      } else {  // breakdown (p = 0 or non-finite data): stop this system
-        S.alpha = 0.0;
-        S.active = 0;
-        S.capped = !(S.rr <= S.rtol2 * S.bnorm2);
-        atomicSub(n_active, 1);
-      }
+  s = wave_sum(s);
+  if (threadIdx.x % kWave == 0) pqp[(size_t)blk * (kBlock / kWave) + threadIdx.x / kWave] = s;
+}
+
+// One block per level: alpha = rr / p.q.
+__global__ void __launch_bounds__(kRedBlock) k_cg_red_a(int lev0, const int32_t* __restrict__ lev_begin,
+                                                     const double* __restrict__ pqp, CgLevel* __restrict__ st) {
+  __shared__ double sm[kRedBlock / kWave];
+  const int l = lev0 + blockIdx.x;
+  if (st[l].done) return;
+  const double pq = block_range_sum(pqp, lev_begin[l] * (kBlock / kWave), lev_begin[l + 1] * (kBlock / kWave), sm);
+  if (threadIdx.x == 0) {
+    CgLevel& S = st[l];
+    if (pq > 0.0 && isfinite(pq)) {
+      S.alpha = S.rr / pq;
+    } else {  // p.q <= 0 cannot happen for SPD A and p != 0: stop this level
+      S.alpha = 0.0;
+      S.done = 1;
+      S.capped = !(S.rr <= S.rtol2 * S.bb);
     }
   }
 }
 
-// K2: x += alpha p, r -= alpha q; rr_new; convergence test and beta.
+// update phase: x += alpha p; r -= alpha q; partial r.r.
 template <typename TX>
 __global__ void __launch_bounds__(kBlock)
-    k_cg_update(const WorkTable wt, TX* __restrict__ x, TX* __restrict__ r, const TX* __restrict__ p,
-                const TX* __restrict__ q, CgState* __restrict__ st, double* __restrict__ part,
-                int32_t* __restrict__ n_active) {
+    k_cg_update(const WorkTable wt, int base, TX* __restrict__ x, TX* __restrict__ r, const TX* __restrict__ p,
+                const TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ rrp) {
   __shared__ double sm[kBlock / kWave];
-  __shared__ bool last;
-  const int blk = xcd_block_id(wt.nblocks);
+  const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
-  if (!st[l].active) return;
+  if (st[l].done) return;
   const double alpha = st[l].alpha;
   const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
   double s = 0.0;
@@ -239,73 +297,79 @@ __global__ void __launch_bounds__(kBlock)
     r[i] = ri;
     s += (double)ri * (double)ri;
   }
-  s = block_sum(s, sm);
-  if (threadIdx.x == 0) part[blk] = s;
-  const int a = wt.lev_begin[l], e = wt.lev_begin[l + 1];
-  if (arrive_last(&st[l], e - a, &last)) {
-    const double rr = reduce_partials(part, a, e, sm);
-    if (threadIdx.x == 0) {
-      CgState& S = st[l];
-      S.ticket = 0;
-      S.iters += 1;
-      const double old = S.rr;
-      S.rr = rr;
-      if (rr <= S.rtol2 * S.bnorm2 || !std::isfinite(rr)) {
-        S.active = 0;
-        S.capped = !std::isfinite(rr);
-        atomicSub(n_active, 1);
-      } else if (S.iters >= S.maxit) {
-        S.active = 0;
-        S.capped = 1;
-        atomicSub(n_active, 1);
-      } else {
-        S.beta = rr / old;
-      }
+  block_partial(s, sm, rrp, blk);
+}
+
+// One block per level: rr_new, stop test, beta.
+__global__ void __launch_bounds__(kRedBlock) k_cg_red_b(int lev0, const int32_t* __restrict__ lev_begin,
+                                                     const double* __restrict__ rrp, CgLevel* __restrict__ st) {
+  __shared__ double sm[kRedBlock / kWave];
+  const int l = lev0 + blockIdx.x;
+  if (st[l].done) return;
+  const double rr = block_range_sum(rrp, lev_begin[l], lev_begin[l + 1], sm);
+  if (threadIdx.x == 0) {
+    CgLevel& S = st[l];
+    S.iters += 1;
+    const double old = S.rr;
+    S.rr = rr;
+    const bool finite = isfinite(rr);
+    if (finite && !(rr > S.rtol2 * S.bb)) {
+      S.done = 1;
+    } else if (!finite || S.iters >= S.maxit) {
+      S.done = 1;
+      S.capped = 1;
+    } else {
+      S.beta = rr / old;
     }
   }
 }
 
-// K3: p = r + beta p.
-template <typename TX>
-__global__ void __launch_bounds__(kBlock) k_cg_dir(const WorkTable wt, const TX* __restrict__ r, TX* __restrict__ p,
-                                                   const CgState* __restrict__ st) {
-  const int blk = xcd_block_id(wt.nblocks);
-  const int l = wt.lev[blk];
-  if (!st[l].active) return;
-  const double beta = st[l].beta;
-  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
-  for (int64_t i = row0 + threadIdx.x; i < row1; i += kBlock) p[i] = (TX)((double)r[i] + beta * (double)p[i]);
-}
-
 // ---------------------------------------------------------- solver driver
+
+template <typename TV, typename TX>
+static void launch_cg_spmv(hipStream_t s, int G, const WorkTable& wt, int base, int nb, const Csr& A, const TV* val,
+                           const TX* r, const TX* p_old, TX* p_new, TX* q, const CgLevel* st, double* pqp) {
+#define MSKM_CGSPMV_CASE(GG)                                                                                     \
+  case GG:                                                                                                      \
+    hipLaunchKernelGGL((k_cg_spmv<GG, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, val, r, \
+                       p_old, p_new, q, st, pqp);                                                               \
+    break;
+  switch (G) {
+    MSKM_CGSPMV_CASE(4)
+    MSKM_CGSPMV_CASE(16)
+    MSKM_CGSPMV_CASE(32)
+    default:
+      MSKM_CGSPMV_CASE(8)
+  }
+#undef MSKM_CGSPMV_CASE
+}
 
 constexpr int kGDiag = 8;    // lanes per row for the diagonal blocks (40-60 entries)
 constexpr int kGLower = 32;  // lanes per row for the strict lower part (up to ~300)
 
 struct Workspace {
-  double* part = nullptr;
-  double* part2 = nullptr;
-  CgState* st = nullptr;
-  uint64_t* mask = nullptr;
-  int32_t* n_active = nullptr;
-  int32_t* h_n_active = nullptr;  // pinned
+  double* part_s = nullptr;  // partials over the SpMV table
+  double* part_s2 = nullptr;
+  double* part_v = nullptr;  // partials over the streaming table
+  CgLevel* st = nullptr;
+  CgLevel* h_st = nullptr;  // pinned
+  int L = 0;
   ~Workspace() {
-    (void)hipFree(part);
-    (void)hipFree(part2);
+    (void)hipFree(part_s);
+    (void)hipFree(part_s2);
+    (void)hipFree(part_v);
     (void)hipFree(st);
-    (void)hipFree(mask);
-    (void)hipFree(n_active);
-    if (h_n_active) (void)hipHostFree(h_n_active);
+    if (h_st) (void)hipHostFree(h_st);
   }
 };
 
 static mskm_status ws_init(mskm_hier* h, Workspace& w) {
-  MSKM_TRY(dalloc(&w.part, h->wt_cg.nblocks));
-  MSKM_TRY(dalloc(&w.part2, h->wt_cg.nblocks));
+  w.L = h->L;
+  MSKM_TRY(dalloc(&w.part_s, (size_t)h->wt_spmv.nblocks * (kBlock / kWave)));
+  MSKM_TRY(dalloc(&w.part_s2, h->wt_spmv.nblocks));
+  MSKM_TRY(dalloc(&w.part_v, h->wt_vec.nblocks));
   MSKM_TRY(dalloc(&w.st, h->L));
-  MSKM_TRY(dalloc(&w.mask, 1));
-  MSKM_TRY(dalloc(&w.n_active, 1));
-  MSKM_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_n_active), sizeof(int32_t), hipHostMallocDefault));
+  MSKM_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_st), h->L * sizeof(CgLevel), hipHostMallocDefault));
   return MSKM_OK;
 }
 
@@ -315,58 +379,78 @@ struct CgStats {
   bool capped = false;
 };
 
-// Per-level CG on A_l x_l = b_l for the levels in `mask`, all in one launch
-// per step. x holds x0 if warm (else it is overwritten with the result).
+// Per-level CG on A_l x_l = b_l for the levels in `mask`. x holds x0 if warm
+// (else it is overwritten). pA, pB: direction buffers.
 template <typename TV, typename TX>
-static mskm_status cg_run(mskm_hier* h, Workspace& w, const TV* dval, uint64_t mask, const TX* b, TX* x, TX* r, TX* p,
-                          TX* q, double rtol, int maxit, bool warm, int check_every, CgStats* cs) {
+static mskm_status cg_run(mskm_hier* h, Workspace& w, const TV* dval, uint64_t mask, const TX* b, TX* x, TX* r, TX* pA,
+                          TX* pB, TX* q, double rtol, int maxit, bool warm, int check_every, CgStats* cs) {
   hipStream_t s = h->ctx->stream;
-  const WorkTable& wt = h->wt_cg;
-  std::vector<CgState> init(h->L);
-  for (auto& S : init) {
+  const WorkTable& ws = h->wt_spmv;
+  const WorkTable& wv = h->wt_vec;
+  for (int l = 0; l < h->L; ++l) {
+    CgLevel& S = w.h_st[l];
     std::memset(&S, 0, sizeof(S));
     S.rtol2 = rtol * rtol;
     S.maxit = maxit;
+    S.on = (int32_t)((mask >> l) & 1ull);
+    S.done = 1;
   }
-  MSKM_HIP_TRY(hipMemcpyAsync(w.st, init.data(), h->L * sizeof(CgState), hipMemcpyHostToDevice, s));
-  MSKM_HIP_TRY(hipMemcpyAsync(w.mask, &mask, 8, hipMemcpyHostToDevice, s));
-  MSKM_HIP_TRY(hipMemsetAsync(w.n_active, 0, 4, s));
-  const dim3 grid(wt.nblocks), blk(kBlock);
-  hipLaunchKernelGGL((k_cg_init<kGDiag, TV, TX>), grid, blk, 0, s, wt, h->diag.rowptr, h->diag.col, dval, b, x, r, p,
-                     w.st, w.mask, warm ? 1 : 0, w.part, w.part2, w.n_active);
-  int done = 0;
+  MSKM_HIP_TRY(hipMemcpyAsync(w.st, w.h_st, h->L * sizeof(CgLevel), hipMemcpyHostToDevice, s));
+  TX* p[2] = {pA, pB};
+  // participating levels lo..hi (the mask is contiguous in every caller);
+  // only their blocks are launched
+  int lo = 0, hi = h->L - 1;
+  while (lo < h->L && !((mask >> lo) & 1ull)) ++lo;
+  while (hi >= 0 && !((mask >> hi) & 1ull)) --hi;
+  if (lo > hi) return MSKM_OK;
+  const int nlev = hi - lo + 1;
+  const int sb0 = ws.h_lev_begin[lo], sbn = ws.h_lev_begin[hi + 1] - sb0;
+  const int vb0 = wv.h_lev_begin[lo], vbn = wv.h_lev_begin[hi + 1] - vb0;
+  const int G = h->spmv_g[MSKM_OP_DIAG][sizeof(TX) == 4 ? 1 : 0] % kVecFlag;
+  if (sbn > 0)
+    hipLaunchKernelGGL((k_cg_init<kGDiag, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, h->diag.rowptr, h->diag.col,
+                       dval, b, x, r, p[0], w.st, warm ? 1 : 0, w.part_s, w.part_s2, sb0);
+  hipLaunchKernelGGL(k_cg_red_init, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, w.part_s, w.part_s2, w.st);
+  int it = 0;
   for (;;) {
-    MSKM_HIP_TRY(hipMemcpyAsync(w.h_n_active, w.n_active, 4, hipMemcpyDeviceToHost, s));
-    MSKM_HIP_TRY(hipStreamSynchronize(s));
-    if (*w.h_n_active <= 0 || done >= maxit) break;
-    for (int c = 0; c < check_every; ++c) {
-      hipLaunchKernelGGL((k_cg_spmv<kGDiag, TV, TX>), grid, blk, 0, s, wt, h->diag.rowptr, h->diag.col, dval, p, q,
-                         w.st, w.part, w.n_active);
-      hipLaunchKernelGGL(k_cg_update<TX>, grid, blk, 0, s, wt, x, r, p, q, w.st, w.part, w.n_active);
-      hipLaunchKernelGGL(k_cg_dir<TX>, grid, blk, 0, s, wt, r, p, w.st);
+    for (int c = 0; c < check_every && it < maxit; ++c, ++it) {
+      if (sbn > 0) launch_cg_spmv<TV, TX>(s, G, ws, sb0, sbn, h->diag, dval, r, p[it & 1], p[(it + 1) & 1], q, w.st,
+                                          w.part_s);
+      hipLaunchKernelGGL(k_cg_red_a, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, w.part_s, w.st);
+      if (vbn > 0)
+        hipLaunchKernelGGL(k_cg_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p[(it + 1) & 1], q, w.st,
+                           w.part_v);
+      hipLaunchKernelGGL(k_cg_red_b, dim3(nlev), dim3(kRedBlock), 0, s, lo, wv.lev_begin, w.part_v, w.st);
     }
-    done += check_every;
+    MSKM_HIP_TRY(hipMemcpyAsync(w.h_st, w.st, h->L * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
+    MSKM_HIP_TRY(hipStreamSynchronize(s));
+    bool any = false;
+    for (int l = 0; l < h->L; ++l) any |= w.h_st[l].done == 0;
+    if (!any || it >= maxit) break;
   }
   MSKM_HIP_TRY(hipGetLastError());
-  std::vector<CgState> fin(h->L);
-  MSKM_HIP_TRY(hipMemcpy(fin.data(), w.st, h->L * sizeof(CgState), hipMemcpyDeviceToHost));
   for (int l = 0; l < h->L; ++l) {
     if (!((mask >> l) & 1ull)) continue;
-    cs->iters_total += fin[l].iters;
-    if (l < kMaxLevels) cs->last_iters[l] = fin[l].iters;
-    if (fin[l].capped) cs->capped = true;
+    const CgLevel& o = w.h_st[l];
+    cs->iters_total += o.iters;
+    if (l < kMaxLevels) cs->last_iters[l] = o.iters;
+    if (o.capped || !o.done) cs->capped = true;
   }
   return MSKM_OK;
 }
 
 // y = b - A x over all rows (A = strict lower part), i.e. the Jacobi update
 // beta = f - (T - D) t, or its restriction to rows [r0, r1).
+template <typename T>
+static void spmv_launch(hipStream_t s, int G, const Csr* A1, const T* v1, const Csr* A2, const T* v2, const T* x,
+                        const T* b, T* y, T sign, int64_t r0, int64_t r1);
+
+// beta = f - (T - D) t on rows [r0, r1): the Jacobi update, or one level's
+// right-hand side of the forward substitution.
 template <typename TV, typename TX>
 static void lower_update(mskm_hier* h, const TV* lval, const TX* t, const TX* f, TX* beta, int64_t r0, int64_t r1) {
-  if (r1 <= r0) return;
-  hipLaunchKernelGGL((k_spmv<kGLower, TV, TX, TX>), dim3(nblk(r1 - r0, kBlock / kGLower)), dim3(kBlock), 0,
-                     h->ctx->stream, h->lower.rowptr, h->lower.col, lval, (const int64_t*)nullptr,
-                     (const int32_t*)nullptr, (const TV*)nullptr, t, f, beta, (TX)-1, r0, r1);
+  spmv_launch<TX>(h->ctx->stream, h->spmv_g[MSKM_OP_LOWER][sizeof(TX) == 4 ? 1 : 0], &h->lower, lval, nullptr,
+                  nullptr, t, f, beta, (TX)-1, r0, r1);
 }
 
 template <typename TV, typename TX>
@@ -375,18 +459,19 @@ static mskm_status solve_internal(mskm_hier* h, Workspace& w, const TV* dval, co
   hipStream_t s = h->ctx->stream;
   const int64_t N = h->N;
   const int L = h->L;
-  TX *beta = nullptr, *t = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+  TX *beta = nullptr, *t = nullptr, *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
   MSKM_TRY(dalloc(&beta, N));
   MSKM_TRY(dalloc(&t, N));
   MSKM_TRY(dalloc(&r, N));
   MSKM_TRY(dalloc(&p, N));
+  MSKM_TRY(dalloc(&p2, N));
   MSKM_TRY(dalloc(&q, N));
   struct Free {
-    TX** v[5];
+    TX** v[6];
     ~Free() {
       for (auto pp : v) (void)hipFree(*pp);
     }
-  } fr{{&beta, &t, &r, &p, &q}};
+  } fr{{&beta, &t, &r, &p, &p2, &q}};
   const int maxit = o->max_cg_iters > 0 ? o->max_cg_iters : 20000;
   const int check = o->check_every > 0 ? o->check_every : 8;
   const uint64_t all = L >= 64 ? ~0ull : ((1ull << L) - 1);
@@ -395,7 +480,7 @@ static mskm_status solve_internal(mskm_hier* h, Workspace& w, const TV* dval, co
     MSKM_HIP_TRY(hipMemsetAsync(alpha, 0, N * sizeof(TX), s));
     for (int l = 0; l < L; ++l) {
       lower_update<TV, TX>(h, lval, alpha, f, beta, h->h_off[l], h->h_off[l + 1]);
-      MSKM_TRY(cg_run<TV, TX>(h, w, dval, 1ull << l, beta, alpha, r, p, q, o->cg_rtol, maxit, false, check, cs));
+      MSKM_TRY(cg_run<TV, TX>(h, w, dval, 1ull << l, beta, alpha, r, p, p2, q, o->cg_rtol, maxit, false, check, cs));
     }
     *sweeps_done = 0;
     return MSKM_OK;
@@ -406,13 +491,13 @@ static mskm_status solve_internal(mskm_hier* h, Workspace& w, const TV* dval, co
   MSKM_HIP_TRY(hipMemsetAsync(t, 0, N * sizeof(TX), s));
   const uint64_t lower_levels = L >= 65 ? ~0ull : (all >> 1);  // levels 0..L-2
   for (int sw = 0; sw < S && L > 1; ++sw) {
-    MSKM_TRY(cg_run<TV, TX>(h, w, dval, lower_levels, beta, t, r, p, q, o->cg_rtol, maxit, o->warm_start != 0 && sw > 0,
+    MSKM_TRY(cg_run<TV, TX>(h, w, dval, lower_levels, beta, t, r, p, p2, q, o->cg_rtol, maxit, o->warm_start != 0 && sw > 0,
                             check, cs));
     lower_update<TV, TX>(h, lval, t, f, beta, h->h_off[1], N);
     *sweeps_done = sw + 1;
   }
   if (o->warm_start) MSKM_HIP_TRY(hipMemcpyAsync(alpha, t, N * sizeof(TX), hipMemcpyDeviceToDevice, s));
-  MSKM_TRY(cg_run<TV, TX>(h, w, dval, all, beta, alpha, r, p, q, o->cg_rtol, maxit, o->warm_start != 0, check, cs));
+  MSKM_TRY(cg_run<TV, TX>(h, w, dval, all, beta, alpha, r, p, p2, q, o->cg_rtol, maxit, o->warm_start != 0, check, cs));
   return MSKM_OK;
 }
 
@@ -604,6 +689,115 @@ mskm_status stage_out_copy(hipStream_t s, double* dst, size_t n, bool io_dev, De
 }
 }  // namespace
 
+// y = bsign_b + sign * (A1 + A2) x over rows [r0, r1) with G lanes per row,
+// G chosen at run time among the compiled widths.
+template <typename T>
+static void spmv_launch(hipStream_t s, int G, const Csr* A1, const T* v1, const Csr* A2, const T* v2, const T* x,
+                        const T* b, T* y, T sign, int64_t r0, int64_t r1) {
+  if (r1 <= r0) return;
+  const int64_t* rp2 = A2 ? A2->rowptr : nullptr;
+  const int32_t* c2 = A2 ? A2->col : nullptr;
+#define MSKM_SPMV_CASE(GG)                                                                                      \
+  case GG:                                                                                                     \
+    hipLaunchKernelGGL((k_spmv<GG, T, T, T>), dim3(nblk(r1 - r0, kBlock / GG)), dim3(kBlock), 0, s, A1->rowptr, \
+                       A1->col, v1, rp2, c2, v2, x, b, y, sign, r0, r1);                                        \
+    break;                                                                                                     \
+  case GG + kVecFlag:                                                                                          \
+    hipLaunchKernelGGL((k_spmv_v<GG, T, T, T>), dim3(nblk(r1 - r0, kBlock / GG)), dim3(kBlock), 0, s,          \
+                       A1->rowptr, A1->col, v1, rp2, c2, v2, x, b, y, sign, r0, r1);                            \
+    break;
+  switch (G) {
+    MSKM_SPMV_CASE(4)
+    MSKM_SPMV_CASE(8)
+    MSKM_SPMV_CASE(16)
+    MSKM_SPMV_CASE(32)
+    MSKM_SPMV_CASE(64)
+    default:
+      hipLaunchKernelGGL((k_spmv<32, T, T, T>), dim3(nblk(r1 - r0, kBlock / 32)), dim3(kBlock), 0, s, A1->rowptr,
+                         A1->col, v1, rp2, c2, v2, x, b, y, sign, r0, r1);
+  }
+#undef MSKM_SPMV_CASE
+}
+
+// One SpMV launch of op in internal order (no permutation).
+template <typename T>
+static void launch_apply(mskm_hier* h, int op, const T* v1, const T* v2, const T* x, T* y) {
+  const Csr* A1 = op == MSKM_OP_LOWER ? &h->lower : &h->diag;
+  const Csr* A2 = op == MSKM_OP_FULL ? &h->lower : nullptr;
+  const int G = h->spmv_g[op][sizeof(T) == 4 ? 1 : 0];
+  spmv_launch<T>(h->ctx->stream, G, A1, v1, A2, v2, x, (const T*)nullptr, y, (T)1, 0, h->N);
+}
+
+mskm_status apply_internal(mskm_hier* h, int op, int prec, const void* x, void* y, int repeats, float* avg_ms) {
+  const bool f32 = prec == MSKM_PREC_FP32;
+  if (f32 ? !h->diag.val32 : !h->diag.val) return fail(MSKM_ESTATE, "requested precision's values are not stored");
+  hipStream_t s = h->ctx->stream;
+  const Csr* A1 = op == MSKM_OP_LOWER ? &h->lower : &h->diag;
+  MSKM_HIP_TRY(hipEventRecord(h->ctx->ev0, s));
+  for (int k = 0; k < repeats; ++k) {
+    if (f32)
+      launch_apply<float>(h, op, A1->val32, h->lower.val32, (const float*)x, (float*)y);
+    else
+      launch_apply<double>(h, op, A1->val, h->lower.val, (const double*)x, (double*)y);
+  }
+  MSKM_HIP_TRY(hipEventRecord(h->ctx->ev1, s));
+  MSKM_HIP_TRY(hipEventSynchronize(h->ctx->ev1));
+  MSKM_HIP_TRY(hipGetLastError());
+  float ms = 0.f;
+  MSKM_HIP_TRY(hipEventElapsedTime(&ms, h->ctx->ev0, h->ctx->ev1));
+  if (avg_ms) *avg_ms = ms / repeats;
+  return MSKM_OK;
+}
+
+// Autotuner: for every operator and stored precision, time each lanes-per-row
+// width on the hierarchy's own matrices (scratch vectors, `repeats` launches
+// each after one warm-up) and keep the fastest.
+mskm_status autotune(mskm_hier* h, int repeats, float* times_out) {
+  static const int widths[] = {4, 8, 16, 32, 64, 4 + kVecFlag, 8 + kVecFlag, 16 + kVecFlag, 32 + kVecFlag,
+                               64 + kVecFlag};
+  double* x = nullptr;
+  double* y = nullptr;
+  MSKM_TRY(dalloc(&x, h->N));
+  MSKM_TRY(dalloc(&y, h->N));
+  hipStream_t s = h->ctx->stream;
+  mskm_status st = MSKM_OK;
+  if (hipMemsetAsync(x, 0, h->N * 8, s) != hipSuccess) st = fail(MSKM_EDEVICE, "memset");
+  for (int op = 0; op < 3 && st == MSKM_OK; ++op) {
+    for (int prec = 0; prec < 2 && st == MSKM_OK; ++prec) {
+      if (prec == 0 ? !h->diag.val : !h->diag.val32) continue;
+      float best = 1e30f;
+      int bestg = h->spmv_g[op][prec];
+      for (int wi = 0; wi < kTuneVariants && st == MSKM_OK; ++wi) {
+        h->spmv_g[op][prec] = widths[wi];
+        float ms = 0.f;
+        st = apply_internal(h, op, prec, x, y, 1, nullptr);
+        if (st == MSKM_OK) st = apply_internal(h, op, prec, x, y, repeats, &ms);
+        if (times_out) times_out[(op * 2 + prec) * kTuneVariants + wi] = ms;
+        if (st == MSKM_OK && ms < best) {
+          best = ms;
+          bestg = widths[wi];
+        }
+      }
+      h->spmv_g[op][prec] = bestg;
+    }
+  }
+  (void)hipFree(x);
+  (void)hipFree(y);
+  if (st == MSKM_OK) {  // remember for hierarchies of the same shape on this context
+    TuneEntry e{h->dim, h->L, h->N, h->diag.nnz, h->lower.nnz, {}};
+    std::memcpy(e.g, h->spmv_g, sizeof(e.g));
+    auto& c = h->ctx->tune_cache;
+    bool found = false;
+    for (auto& t : c)
+      if (t.dim == e.dim && t.L == e.L && t.N == e.N && t.nnz_diag == e.nnz_diag && t.nnz_lower == e.nnz_lower) {
+        t = e;
+        found = true;
+      }
+    if (!found) c.push_back(e);
+  }
+  return st;
+}
+
 mskm_status apply_op(mskm_hier* h, int op, int prec, const double* x_in, int nrhs, double* y_in, bool io_dev) {
   hipStream_t s = h->ctx->stream;
   const int64_t N = h->N;
@@ -615,35 +809,17 @@ mskm_status apply_op(mskm_hier* h, int op, int prec, const double* x_in, int nrh
   void *xi = nullptr, *yi = nullptr;
   MSKM_TRY(dalloc(reinterpret_cast<double**>(&xi), N));
   MSKM_TRY(dalloc(reinterpret_cast<double**>(&yi), N));
+  const Csr* A1 = op == MSKM_OP_LOWER ? &h->lower : &h->diag;
   for (int r = 0; r < nrhs; ++r) {
-    const Csr* A1 = op == MSKM_OP_LOWER ? &h->lower : &h->diag;
-    const Csr* A2 = op == MSKM_OP_FULL ? &h->lower : nullptr;
-    const int G = op == MSKM_OP_DIAG ? kGDiag : kGLower;
     if (f32) {
       hipLaunchKernelGGL(k_to_internal<float>, dim3(nblk(N)), dim3(kBlock), 0, s, X.p, h->perm, (float*)xi, N, nrhs, r);
-      auto v2 = A2 ? A2->val32 : nullptr;
-      if (G == kGDiag)
-        hipLaunchKernelGGL((k_spmv<kGDiag, float, float, float>), dim3(nblk(N, kBlock / kGDiag)), dim3(kBlock), 0, s,
-                           A1->rowptr, A1->col, A1->val32, A2 ? A2->rowptr : nullptr, A2 ? A2->col : nullptr, v2,
-                           (const float*)xi, (const float*)nullptr, (float*)yi, 1.0f, (int64_t)0, N);
-      else
-        hipLaunchKernelGGL((k_spmv<kGLower, float, float, float>), dim3(nblk(N, kBlock / kGLower)), dim3(kBlock), 0, s,
-                           A1->rowptr, A1->col, A1->val32, A2 ? A2->rowptr : nullptr, A2 ? A2->col : nullptr, v2,
-                           (const float*)xi, (const float*)nullptr, (float*)yi, 1.0f, (int64_t)0, N);
+      launch_apply<float>(h, op, A1->val32, h->lower.val32, (const float*)xi, (float*)yi);
       hipLaunchKernelGGL(k_to_input<float>, dim3(nblk(N)), dim3(kBlock), 0, s, (const float*)yi, h->perm, Y.p, N, nrhs,
                          r);
     } else {
       hipLaunchKernelGGL(k_to_internal<double>, dim3(nblk(N)), dim3(kBlock), 0, s, X.p, h->perm, (double*)xi, N, nrhs,
                          r);
-      auto v2 = A2 ? A2->val : nullptr;
-      if (G == kGDiag)
-        hipLaunchKernelGGL((k_spmv<kGDiag, double, double, double>), dim3(nblk(N, kBlock / kGDiag)), dim3(kBlock), 0, s,
-                           A1->rowptr, A1->col, A1->val, A2 ? A2->rowptr : nullptr, A2 ? A2->col : nullptr, v2,
-                           (const double*)xi, (const double*)nullptr, (double*)yi, 1.0, (int64_t)0, N);
-      else
-        hipLaunchKernelGGL((k_spmv<kGLower, double, double, double>), dim3(nblk(N, kBlock / kGLower)), dim3(kBlock), 0,
-                           s, A1->rowptr, A1->col, A1->val, A2 ? A2->rowptr : nullptr, A2 ? A2->col : nullptr, v2,
-                           (const double*)xi, (const double*)nullptr, (double*)yi, 1.0, (int64_t)0, N);
+      launch_apply<double>(h, op, A1->val, h->lower.val, (const double*)xi, (double*)yi);
       hipLaunchKernelGGL(k_to_input<double>, dim3(nblk(N)), dim3(kBlock), 0, s, (const double*)yi, h->perm, Y.p, N,
                          nrhs, r);
     }

@@ -200,3 +200,39 @@ def test_deterministic_repeat(mod, ctx):
     mod.mskm_solve(ctx, hd, f, a1, o)
     mod.mskm_solve(ctx, hd, f, a2, o)
     assert np.array_equal(a1, a2)
+
+
+@pytest.mark.parametrize("check_every", [1, 3, 8, 64])
+def test_result_independent_of_poll_interval(mod, ctx, check_every):
+    # levels stop at different iterations while the host keeps launching
+    # iterations for the slower ones: a stopped level must stay stopped
+    h, f, blk, hd, a_ref = _setup(mod, ctx, "halton5")
+    for alg in (mod.MSKM_ALG_MONOLITHIC, mod.MSKM_ALG_SEQUENTIAL):
+        for rt in (1e-8, 1e-11):
+            alpha = np.zeros_like(f)
+            res = mod.mskm_solve(ctx, hd, f, alpha, mod.solve_opts(cg_rtol=rt, algorithm=alg, check_every=check_every))
+            assert res.status == mod.MSKM_OK
+            assert res.report["rel_residual"] < 1e3 * rt
+            assert max(res.report["cg_iters_last"]) < 2000
+
+
+def test_autotune_keeps_results(mod, ctx):
+    h, f, blk, hd, a_ref = _setup(mod, ctx, "uniform3d3")
+    x = np.random.default_rng(5).standard_normal(h.n_total)
+    y0 = np.zeros_like(x)
+    mod.mskm_apply(ctx, hd, mod.MSKM_OP_FULL, x, y0)
+    t = mod.mskm_autotune(ctx, hd, repeats=2)
+    assert t.shape == (3, 2, 10) and np.all(t > 0)
+    for op in range(3):
+        for pr in range(2):
+            assert mod.mskm_spmv_width(hd, op, pr) in mod.TUNE_VARIANTS
+    y1 = np.zeros_like(x)
+    mod.mskm_apply(ctx, hd, mod.MSKM_OP_FULL, x, y1)
+    assert _rel(y1, y0) <= 1e-14
+    # a hierarchy of the same shape created on this context inherits the widths
+    hd2 = mod.mskm_hier_create(ctx, h.points, h.offsets, h.delta, fp64=True, fp32=True)
+    try:
+        for op in range(3):
+            assert mod.mskm_spmv_width(hd2, op, 0) == mod.mskm_spmv_width(hd, op, 0)
+    finally:
+        mod.mskm_hier_destroy(hd2)
