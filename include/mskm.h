@@ -144,6 +144,14 @@ mskm_status mskm_hier_offsets(const mskm_hier* h, int64_t* off);
 mskm_status mskm_export_block(mskm_ctx* ctx, const mskm_hier* h, int32_t row_level, int32_t col_level,
                               int64_t* rowptr, int32_t* col, double* val, int64_t* nnz_out);
 
+/* Like mskm_export_block for the listed rows only: rows[0..nrows) are row
+ * indices within level row_level (any order, repeats allowed); output row
+ * r of the CSR is row rows[r]. rowptr has nrows+1 entries. Host pointers.
+ * For spot checks of very large blocks. */
+mskm_status mskm_export_rows(mskm_ctx* ctx, const mskm_hier* h, int32_t row_level, int32_t col_level,
+                             const int64_t* rows, int64_t nrows, int64_t* rowptr, int32_t* col, double* val,
+                             int64_t* nnz_out);
+
 /* Internal (spatially sorted) order: perm[i] = global input index of
  * internal position i. Host pointer, [N]. */
 mskm_status mskm_export_perm(mskm_ctx* ctx, const mskm_hier* h, int32_t* perm);

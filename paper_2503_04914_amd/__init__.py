@@ -36,7 +36,7 @@ MSKM_PRECOND_NONE, MSKM_PRECOND_LEARNED = 0, 1
 EXPORTED = [
     "mskm_create", "mskm_destroy", "mskm_last_error", "mskm_abi_version",
     "mskm_hier_create", "mskm_hier_destroy", "mskm_hier_stats_get", "mskm_hier_offsets",
-    "mskm_export_block", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
+    "mskm_export_block", "mskm_export_rows", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
     "mskm_autotune", "mskm_spmv_width",
     "mskm_solve_opts_default", "mskm_solve", "mskm_residual", "mskm_evaluate",
 ]
@@ -99,6 +99,7 @@ def lib():
     L.mskm_hier_offsets.argtypes = [vp, C.POINTER(i64)]
     L.mskm_export_block.argtypes = [vp, vp, i32, i32, vp, vp, vp, C.POINTER(i64)]
     L.mskm_export_perm.argtypes = [vp, vp, vp]
+    L.mskm_export_rows.argtypes = [vp, vp, i32, i32, vp, i64, vp, vp, vp, C.POINTER(i64)]
     L.mskm_apply.argtypes = [vp, vp, i32, i32, vp, i32, vp, i32]
     L.mskm_apply_internal.argtypes = [vp, vp, i32, i32, vp, vp, i32, C.POINTER(C.c_float)]
     L.mskm_autotune.argtypes = [vp, vp, i32, C.POINTER(C.c_float)]
@@ -206,6 +207,22 @@ def mskm_export_block(ctx, h, row_level: int, col_level: int, values: bool = Tru
     _check(lib().mskm_export_block(ctx, h, row_level, col_level, C.c_void_p(rowptr.ctypes.data),
                                    C.c_void_p(col.ctypes.data), C.c_void_p(val.ctypes.data) if values else None,
                                    C.byref(nnz)), "mskm_export_block")
+    return rowptr, col[:n], (val[:n] if values else None)
+
+
+def mskm_export_rows(ctx, h, row_level: int, col_level: int, rows, values: bool = True):
+    """Canonical CSR of the listed rows (indices within row_level) of B_{row,col}."""
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    nnz = C.c_int64()
+    _check(lib().mskm_export_rows(ctx, h, row_level, col_level, C.c_void_p(rows.ctypes.data), len(rows), None, None,
+                                  None, C.byref(nnz)), "export_rows (size)")
+    n = nnz.value
+    rowptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    col = np.zeros(max(n, 1), dtype=np.int32)
+    val = np.zeros(max(n, 1), dtype=np.float64) if values else None
+    _check(lib().mskm_export_rows(ctx, h, row_level, col_level, C.c_void_p(rows.ctypes.data), len(rows),
+                                  C.c_void_p(rowptr.ctypes.data), C.c_void_p(col.ctypes.data),
+                                  C.c_void_p(val.ctypes.data) if values else None, C.byref(nnz)), "mskm_export_rows")
     return rowptr, col[:n], (val[:n] if values else None)
 
 

@@ -135,6 +135,7 @@ mskm_status mskm_hier_destroy(mskm_hier* h) {
     (void)hipSetDevice(h->ctx->device);
     (void)hipStreamSynchronize(h->ctx->stream);
   }
+  if (h->solve_ws_free) h->solve_ws_free(h->solve_ws);
   for (void* p : h->allocs) (void)hipFree(p);
   delete h;
   return MSKM_OK;
@@ -169,6 +170,25 @@ mskm_status mskm_export_block(mskm_ctx* ctx, const mskm_hier* h, int32_t row_lev
   if (col && !rowptr) return fail(MSKM_EINVAL, "rowptr required with col");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
   return mskm::export_block(const_cast<mskm_hier*>(h), row_level, col_level, rowptr, col, val, nnz_out);
+}
+
+mskm_status mskm_export_rows(mskm_ctx* ctx, const mskm_hier* h, int32_t row_level, int32_t col_level,
+                             const int64_t* rows, int64_t nrows, int64_t* rowptr, int32_t* col, double* val,
+                             int64_t* nnz_out) {
+  if (!valid_ctx(ctx) || !h || !rows || nrows < 0) return fail(MSKM_EINVAL, "mskm_export_rows: NULL argument");
+  if (row_level < 0 || row_level >= h->L || col_level < 0 || col_level > row_level)
+    return fail(MSKM_EINVAL, "block index out of range (need 0 <= col_level <= row_level < L)");
+  if (col && !rowptr) return fail(MSKM_EINVAL, "rowptr required with col");
+  const int64_t n = h->h_off[row_level + 1] - h->h_off[row_level];
+  for (int64_t i = 0; i < nrows; ++i)
+    if (rows[i] < 0 || rows[i] >= n) return fail(MSKM_EINVAL, "row index outside the row level");
+  if (nrows == 0) {
+    if (rowptr) rowptr[0] = 0;
+    if (nnz_out) *nnz_out = 0;
+    return MSKM_OK;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::export_block(const_cast<mskm_hier*>(h), row_level, col_level, rowptr, col, val, nnz_out, rows, nrows);
 }
 
 mskm_status mskm_export_perm(mskm_ctx* ctx, const mskm_hier* h, int32_t* perm) {

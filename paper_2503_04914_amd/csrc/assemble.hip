@@ -530,14 +530,15 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
 
 // ------------------------------------------------------------------ export
 
-// Entries of block (k, j) in canonical row r: count pass.
+// Entries of block (k, j) in canonical row r (or in row rows[r] of level k
+// when a row list is given): count pass.
 __global__ void __launch_bounds__(kBlock) k_export_count(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                          const int32_t* __restrict__ iperm, int64_t row_off,
                                                          int64_t nrows, int64_t c0, int64_t c1,
-                                                         int64_t* __restrict__ cnt) {
+                                                         const int64_t* __restrict__ rows, int64_t* __restrict__ cnt) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= nrows) return;
-  const int64_t i = iperm[row_off + r];
+  const int64_t i = iperm[row_off + (rows ? rows[r] : r)];
   int64_t c = 0;
   for (int64_t t = rp[i]; t < rp[i + 1]; ++t) c += (col[t] >= c0 && col[t] < c1);
   cnt[r] = c;
@@ -550,11 +551,12 @@ __global__ void __launch_bounds__(kBlock) k_export_fill(const int64_t* __restric
                                                         const TV* __restrict__ val, const int32_t* __restrict__ iperm,
                                                         const int32_t* __restrict__ perm, int64_t row_off,
                                                         int64_t nrows, int64_t c0, int64_t c1,
+                                                        const int64_t* __restrict__ rows,
                                                         const int64_t* __restrict__ optr, int32_t* __restrict__ ocol,
                                                         double* __restrict__ oval) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= nrows) return;
-  const int64_t i = iperm[row_off + r];
+  const int64_t i = iperm[row_off + (rows ? rows[r] : r)];
   const int64_t o = optr[r];
   int64_t n = 0;
   for (int64_t t = rp[i]; t < rp[i + 1]; ++t) {
@@ -574,18 +576,29 @@ __global__ void __launch_bounds__(kBlock) k_export_fill(const int64_t* __restric
   }
 }
 
-mskm_status export_block(mskm_hier* h, int k, int j, int64_t* rowptr, int32_t* col, double* val, int64_t* nnz_out) {
+mskm_status export_block(mskm_hier* h, int k, int j, int64_t* rowptr, int32_t* col, double* val, int64_t* nnz_out,
+                         const int64_t* rows_host, int64_t nrows_sel) {
   hipStream_t s = h->ctx->stream;
   const Csr& C = (k == j) ? h->diag : h->lower;
-  const int64_t row_off = h->h_off[k], nrows = h->h_off[k + 1] - h->h_off[k];
+  const int64_t row_off = h->h_off[k];
+  const int64_t nrows = rows_host ? nrows_sel : h->h_off[k + 1] - h->h_off[k];
   const int64_t c0 = h->h_off[j], c1 = h->h_off[j + 1];
+  int64_t* rows = nullptr;
+  if (rows_host) {
+    MSKM_TRY(dalloc(&rows, nrows));
+    MSKM_HIP_TRY(hipMemcpy(rows, rows_host, nrows * 8, hipMemcpyHostToDevice));
+  }
+  struct FreeRows {
+    int64_t* p;
+    ~FreeRows() { (void)hipFree(p); }
+  } free_rows{rows};
   int64_t *cnt = nullptr, *optr = nullptr;
   MSKM_TRY(dalloc(&cnt, nrows + 1));
   MSKM_TRY(dalloc(&optr, nrows + 1));
   MSKM_HIP_TRY(hipMemsetAsync(cnt + nrows, 0, 8, s));
   if (nrows > 0)
     hipLaunchKernelGGL(k_export_count, dim3(grid_for(nrows, kBlock)), dim3(kBlock), 0, s, C.rowptr, C.col, h->iperm,
-                       row_off, nrows, c0, c1, cnt);
+                       row_off, nrows, c0, c1, rows, cnt);
   mskm_status st = exclusive_scan_i64(s, cnt, optr, nrows + 1);
   int64_t nnz = 0;
   if (st == MSKM_OK) {
@@ -600,10 +613,10 @@ mskm_status export_block(mskm_hier* h, int k, int j, int64_t* rowptr, int32_t* c
     if (st == MSKM_OK && nrows > 0) {
       if (C.val || !C.val32)
         hipLaunchKernelGGL(k_export_fill<double>, dim3(grid_for(nrows, kBlock)), dim3(kBlock), 0, s, C.rowptr, C.col,
-                           C.val, h->iperm, h->perm, row_off, nrows, c0, c1, optr, ocol, oval);
+                           C.val, h->iperm, h->perm, row_off, nrows, c0, c1, rows, optr, ocol, oval);
       else
         hipLaunchKernelGGL(k_export_fill<float>, dim3(grid_for(nrows, kBlock)), dim3(kBlock), 0, s, C.rowptr, C.col,
-                           C.val32, h->iperm, h->perm, row_off, nrows, c0, c1, optr, ocol, oval);
+                           C.val32, h->iperm, h->perm, row_off, nrows, c0, c1, rows, optr, ocol, oval);
     }
     if (st == MSKM_OK) {
       hipError_t e = hipMemcpyAsync(rowptr, optr, (nrows + 1) * 8, hipMemcpyDeviceToHost, s);

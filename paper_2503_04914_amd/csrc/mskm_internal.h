@@ -103,6 +103,8 @@ struct mskm_hier {
   int64_t device_bytes = 0;
   double assemble_ms = 0.0;
   std::vector<void*> allocs;            // everything to free
+  void* solve_ws = nullptr;             // solver workspace (solve.hip), created on first solve
+  void (*solve_ws_free)(void*) = nullptr;
 };
 
 namespace mskm {
@@ -149,8 +151,10 @@ mskm_status dalloc(T** p, size_t count) {
 
 // assemble.hip
 mskm_status assemble_hierarchy(mskm_hier* h, const double* points_dev, bool want64, bool want32);
+// rows_host == nullptr: every row of the level; else the listed rows (indices
+// within the row level, host array of nrows_sel entries).
 mskm_status export_block(mskm_hier* h, int row_level, int col_level, int64_t* rowptr, int32_t* col, double* val,
-                         int64_t* nnz_out);
+                         int64_t* nnz_out, const int64_t* rows_host = nullptr, int64_t nrows_sel = 0);
 mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n);
 // Rows of each level split into blocks of max(min_rows, n_l / max_blocks) rows,
 // so that no level has more than max_blocks blocks.

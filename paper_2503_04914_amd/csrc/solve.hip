@@ -226,14 +226,15 @@ __global__ void __launch_bounds__(kRedBlock) k_cg_red_init(int lev0, const int32
   }
 }
 
-// spmv phase: p_new = r + beta p_old; q = A p_new; partial p_new.q per wave
-// (kBlock / 64 partials per block, no block barrier). Launched over the
-// table blocks [base, base + gridDim.x) of the participating levels.
-template <int G, typename TV, typename TX>
+// spmv phase: p_new = r + beta p_old; q = A p_new; partial p_new.q per block.
+// Launched over the table blocks [base, base + gridDim.x) of the
+// participating levels. VEC: 16-byte value/column loads (as csr_row_dot_v).
+template <int G, bool VEC, typename TV, typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_cg_spmv(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
               const TV* __restrict__ val, const TX* __restrict__ r, const TX* __restrict__ p_old,
               TX* __restrict__ p_new, TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ pqp) {
+  __shared__ double sm[kBlock / kWave];
   const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
   if (st[l].done) return;
@@ -242,11 +243,32 @@ __global__ void __launch_bounds__(kBlock)
   const int gl = threadIdx.x % G;
   double s = 0.0;
   for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
-    const int64_t ke = rp[i + 1];
+    const int64_t ks = rp[i], ke = rp[i + 1];
     TX acc = 0;
-    for (int64_t k = rp[i] + gl; k < ke; k += G) {
-      const int32_t j = col[k];
-      acc += (TX)val[k] * (r[j] + beta * p_old[j]);
+    if constexpr (VEC) {
+      constexpr int V = 16 / sizeof(TV);
+      for (int64_t k = (ks & ~(int64_t)(V - 1)) + (int64_t)gl * V; k < ke; k += (int64_t)G * V) {
+        TV v[V];
+        int32_t c[V];
+        if constexpr (V == 2) {
+          const double2 vv = *reinterpret_cast<const double2*>(val + k);
+          const int2 cc = *reinterpret_cast<const int2*>(col + k);
+          v[0] = vv.x; v[1] = vv.y; c[0] = cc.x; c[1] = cc.y;
+        } else {
+          const float4 vv = *reinterpret_cast<const float4*>(val + k);
+          const int4 cc = *reinterpret_cast<const int4*>(col + k);
+          v[0] = vv.x; v[1] = vv.y; v[2] = vv.z; v[3] = vv.w;
+          c[0] = cc.x; c[1] = cc.y; c[2] = cc.z; c[3] = cc.w;
+        }
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+          if (k + u >= ks && k + u < ke) acc += (TX)v[u] * (r[c[u]] + beta * p_old[c[u]]);
+      }
+    } else {
+      for (int64_t k = ks + gl; k < ke; k += G) {
+        const int32_t j = col[k];
+        acc += (TX)val[k] * (r[j] + beta * p_old[j]);
+      }
     }
     acc = group_sum<G>(acc);
     if (gl == 0) {
@@ -256,8 +278,46 @@ __global__ void __launch_bounds__(kBlock)
       s += (double)pn * (double)acc;
     }
   }
-  s = wave_sum(s);
-  if (threadIdx.x % kWave == 0) pqp[(size_t)blk * (kBlock / kWave) + threadIdx.x / kWave] = s;
+  block_partial(s, sm, pqp, blk);
+}
+
+// direction phase: p = r + beta p on the rows of not-stopped levels.
+template <typename TX>
+__global__ void __launch_bounds__(kBlock) k_cg_dir(const WorkTable wt, int base, const TX* __restrict__ r,
+                                                   TX* __restrict__ p, const CgLevel* __restrict__ st) {
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (st[l].done) return;
+  const TX beta = (TX)st[l].beta;
+  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
+  for (int64_t i = row0 + threadIdx.x; i < row1; i += kBlock) p[i] = r[i] + beta * p[i];
+}
+
+// spmv phase after a separate direction update: q = A p; partial p.q per block.
+template <int G, bool VEC, typename TV, typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_cg_spmv1(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+               const TV* __restrict__ val, const TX* __restrict__ p, TX* __restrict__ q,
+               const CgLevel* __restrict__ st, double* __restrict__ pqp) {
+  __shared__ double sm[kBlock / kWave];
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (st[l].done) return;
+  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
+  const int gl = threadIdx.x % G;
+  double s = 0.0;
+  for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
+    TX acc;
+    if constexpr (VEC)
+      acc = csr_row_dot_v<G, TV, TX, TX>(rp, col, val, p, i, gl);
+    else
+      acc = csr_row_dot<G, TV, TX, TX>(rp, col, val, p, i, gl);
+    if (gl == 0) {
+      q[i] = acc;
+      s += (double)p[i] * (double)acc;
+    }
+  }
+  block_partial(s, sm, pqp, blk);
 }
 
 // One block per level: alpha = rr / p.q.
@@ -266,7 +326,7 @@ __global__ void __launch_bounds__(kRedBlock) k_cg_red_a(int lev0, const int32_t*
   __shared__ double sm[kRedBlock / kWave];
   const int l = lev0 + blockIdx.x;
   if (st[l].done) return;
-  const double pq = block_range_sum(pqp, lev_begin[l] * (kBlock / kWave), lev_begin[l + 1] * (kBlock / kWave), sm);
+  const double pq = block_range_sum(pqp, lev_begin[l], lev_begin[l + 1], sm);
   if (threadIdx.x == 0) {
     CgLevel& S = st[l];
     if (pq > 0.0 && isfinite(pq)) {
@@ -326,50 +386,116 @@ __global__ void __launch_bounds__(kRedBlock) k_cg_red_b(int lev0, const int32_t*
 
 // ---------------------------------------------------------- solver driver
 
+constexpr int kGDiag = 8;  // lanes per row of the CG init kernel (diagonal rows hold 40-60 entries)
+
 template <typename TV, typename TX>
-static void launch_cg_spmv(hipStream_t s, int G, const WorkTable& wt, int base, int nb, const Csr& A, const TV* val,
-                           const TX* r, const TX* p_old, TX* p_new, TX* q, const CgLevel* st, double* pqp) {
-#define MSKM_CGSPMV_CASE(GG)                                                                                     \
-  case GG:                                                                                                      \
-    hipLaunchKernelGGL((k_cg_spmv<GG, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, val, r, \
-                       p_old, p_new, q, st, pqp);                                                               \
+static void launch_cg_spmv(hipStream_t s, int code, const WorkTable& wt, int base, int nb, const Csr& A,
+                           const TV* val, const TX* r, const TX* p_old, TX* p_new, TX* q, const CgLevel* st,
+                           double* pqp) {
+#define MSKM_CGSPMV_CASE(GG)                                                                                    \
+  case GG:                                                                                                     \
+    hipLaunchKernelGGL((k_cg_spmv<GG, false, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
+                       val, r, p_old, p_new, q, st, pqp);                                                       \
+    break;                                                                                                     \
+  case GG + kVecFlag:                                                                                          \
+    hipLaunchKernelGGL((k_cg_spmv<GG, true, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col,  \
+                       val, r, p_old, p_new, q, st, pqp);                                                       \
     break;
-  switch (G) {
+  switch (code) {
     MSKM_CGSPMV_CASE(4)
+    MSKM_CGSPMV_CASE(8)
     MSKM_CGSPMV_CASE(16)
     MSKM_CGSPMV_CASE(32)
     default:
-      MSKM_CGSPMV_CASE(8)
+      hipLaunchKernelGGL((k_cg_spmv<8, false, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col,
+                         val, r, p_old, p_new, q, st, pqp);
   }
 #undef MSKM_CGSPMV_CASE
 }
 
-constexpr int kGDiag = 8;    // lanes per row for the diagonal blocks (40-60 entries)
-constexpr int kGLower = 32;  // lanes per row for the strict lower part (up to ~300)
+template <typename TV, typename TX>
+static void launch_cg_spmv1(hipStream_t s, int code, const WorkTable& wt, int base, int nb, const Csr& A,
+                            const TV* val, const TX* p, TX* q, const CgLevel* st, double* pqp) {
+#define MSKM_CGSPMV1_CASE(GG)                                                                                    \
+  case GG:                                                                                                      \
+    hipLaunchKernelGGL((k_cg_spmv1<GG, false, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
+                       val, p, q, st, pqp);                                                                     \
+    break;                                                                                                      \
+  case GG + kVecFlag:                                                                                           \
+    hipLaunchKernelGGL((k_cg_spmv1<GG, true, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col,  \
+                       val, p, q, st, pqp);                                                                     \
+    break;
+  switch (code) {
+    MSKM_CGSPMV1_CASE(4)
+    MSKM_CGSPMV1_CASE(8)
+    MSKM_CGSPMV1_CASE(16)
+    MSKM_CGSPMV1_CASE(32)
+    default:
+      hipLaunchKernelGGL((k_cg_spmv1<8, false, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col,
+                         val, p, q, st, pqp);
+  }
+#undef MSKM_CGSPMV1_CASE
+}
 
-struct Workspace {
-  double* part_s = nullptr;  // partials over the SpMV table
-  double* part_s2 = nullptr;
-  double* part_v = nullptr;  // partials over the streaming table
+// Persistent solver workspace of one hierarchy, created at its first solve:
+// vectors in the internal order (sized for N doubles; the FP32 path uses the
+// same memory as float), reduction partials, per-level CG state, and the
+// cache of instantiated CG chunk graphs. Stable pointers let a chunk of CG
+// iterations be captured once and replayed by every later solve.
+struct SolveWS {
+  double *beta = nullptr, *t = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+  double *fi = nullptr, *ai = nullptr, *res = nullptr;  // FP64 f, alpha, residual (internal order)
+  float *f32 = nullptr, *a32 = nullptr;                 // FP32 rhs and correction (mixed path)
+  double *part_s = nullptr, *part_s2 = nullptr, *part_v = nullptr;
   CgLevel* st = nullptr;
   CgLevel* h_st = nullptr;  // pinned
-  int L = 0;
-  ~Workspace() {
-    (void)hipFree(part_s);
-    (void)hipFree(part_s2);
-    (void)hipFree(part_v);
-    (void)hipFree(st);
+  struct Graph {
+    int tx;
+    const void* val;
+    int lo, hi;
+    const void* x;
+    int K, G;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+  ~SolveWS() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    for (void* p : {(void*)beta, (void*)t, (void*)r, (void*)p0, (void*)p1, (void*)q, (void*)fi, (void*)ai,
+                    (void*)res, (void*)f32, (void*)a32, (void*)part_s, (void*)part_s2, (void*)part_v, (void*)st})
+      (void)hipFree(p);
     if (h_st) (void)hipHostFree(h_st);
   }
 };
 
-static mskm_status ws_init(mskm_hier* h, Workspace& w) {
-  w.L = h->L;
-  MSKM_TRY(dalloc(&w.part_s, (size_t)h->wt_spmv.nblocks * (kBlock / kWave)));
-  MSKM_TRY(dalloc(&w.part_s2, h->wt_spmv.nblocks));
-  MSKM_TRY(dalloc(&w.part_v, h->wt_vec.nblocks));
-  MSKM_TRY(dalloc(&w.st, h->L));
-  MSKM_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_st), h->L * sizeof(CgLevel), hipHostMallocDefault));
+static void free_solve_ws(void* p) { delete static_cast<SolveWS*>(p); }
+
+static mskm_status get_ws(mskm_hier* h, SolveWS** out) {
+  if (h->solve_ws) {
+    *out = static_cast<SolveWS*>(h->solve_ws);
+    return MSKM_OK;
+  }
+  auto* w = new (std::nothrow) SolveWS();
+  if (!w) return fail(MSKM_ENOMEM, "workspace allocation");
+  const size_t N = (size_t)h->N;
+  mskm_status st = MSKM_OK;
+  for (double** v : {&w->beta, &w->t, &w->r, &w->p0, &w->p1, &w->q, &w->fi, &w->ai, &w->res})
+    if (st == MSKM_OK) st = dalloc(v, N);
+  if (st == MSKM_OK) st = dalloc(&w->f32, N);
+  if (st == MSKM_OK) st = dalloc(&w->a32, N);
+  if (st == MSKM_OK) st = dalloc(&w->part_s, (size_t)h->wt_spmv.nblocks);
+  if (st == MSKM_OK) st = dalloc(&w->part_s2, h->wt_spmv.nblocks);
+  if (st == MSKM_OK) st = dalloc(&w->part_v, h->wt_vec.nblocks);
+  if (st == MSKM_OK) st = dalloc(&w->st, h->L);
+  if (st == MSKM_OK &&
+      hipHostMalloc(reinterpret_cast<void**>(&w->h_st), h->L * sizeof(CgLevel), hipHostMallocDefault) != hipSuccess)
+    st = fail(MSKM_ENOMEM, "pinned state allocation");
+  if (st != MSKM_OK) {
+    delete w;
+    return st;
+  }
+  h->solve_ws = w;
+  h->solve_ws_free = free_solve_ws;
+  *out = w;
   return MSKM_OK;
 }
 
@@ -379,59 +505,96 @@ struct CgStats {
   bool capped = false;
 };
 
-// Per-level CG on A_l x_l = b_l for the levels in `mask`. x holds x0 if warm
-// (else it is overwritten). pA, pB: direction buffers.
+// K CG iterations (4 kernels each) on levels lo..hi, starting at an even
+// iteration index; K is even, so every chunk sees the same buffer parity.
 template <typename TV, typename TX>
-static mskm_status cg_run(mskm_hier* h, Workspace& w, const TV* dval, uint64_t mask, const TX* b, TX* x, TX* r, TX* pA,
-                          TX* pB, TX* q, double rtol, int maxit, bool warm, int check_every, CgStats* cs) {
+static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int hi, TX* x, int K, int G) {
   hipStream_t s = h->ctx->stream;
   const WorkTable& ws = h->wt_spmv;
   const WorkTable& wv = h->wt_vec;
+  const int nlev = hi - lo + 1;
+  const int sb0 = ws.h_lev_begin[lo], sbn = ws.h_lev_begin[hi + 1] - sb0;
+  const int vb0 = wv.h_lev_begin[lo], vbn = wv.h_lev_begin[hi + 1] - vb0;
+  TX* p[2] = {(TX*)W.p0, (TX*)W.p1};
+  TX* r = (TX*)W.r;
+  TX* q = (TX*)W.q;
+  for (int it = 0; it < K; ++it) {
+    // direction update (beta = 0 on the first iteration after the init, p0 = 0 there)
+    if (vbn > 0) hipLaunchKernelGGL(k_cg_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, r, p[0], W.st);
+    if (sbn > 0) launch_cg_spmv1<TV, TX>(s, G, ws, sb0, sbn, h->diag, dval, p[0], q, W.st, W.part_s);
+    hipLaunchKernelGGL(k_cg_red_a, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.st);
+    if (vbn > 0)
+      hipLaunchKernelGGL(k_cg_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p[0], q, W.st, W.part_v);
+    hipLaunchKernelGGL(k_cg_red_b, dim3(nlev), dim3(kRedBlock), 0, s, lo, wv.lev_begin, W.part_v, W.st);
+  }
+}
+
+// Instantiated graph of one chunk (captured on first use).
+template <typename TV, typename TX>
+static mskm_status chunk_graph(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int hi, TX* x, int K, int G,
+                               hipGraphExec_t* out) {
+  const int tx = (int)sizeof(TX);
+  for (const auto& g : W.graphs)
+    if (g.tx == tx && g.val == dval && g.lo == lo && g.hi == hi && g.x == x && g.K == K && g.G == G) {
+      *out = g.exec;
+      return MSKM_OK;
+    }
+  hipStream_t s = h->ctx->stream;
+  hipGraph_t graph = nullptr;
+  MSKM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  enqueue_chunk<TV, TX>(h, W, dval, lo, hi, x, K, G);
+  MSKM_HIP_TRY(hipStreamEndCapture(s, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(MSKM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  W.graphs.push_back(SolveWS::Graph{tx, dval, lo, hi, x, K, G, exec});
+  *out = exec;
+  return MSKM_OK;
+}
+
+// Per-level CG on A_l x_l = b_l for the levels in `mask` (contiguous bits).
+// x holds x0 if warm, else it is overwritten. Iterations run as replays of a
+// captured chunk of K iterations; the host reads the per-level state after
+// each chunk and stops when every level has stopped.
+template <typename TV, typename TX>
+static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, uint64_t mask, const TX* b, TX* x, double rtol,
+                          int maxit, bool warm, int K, CgStats* cs) {
+  hipStream_t s = h->ctx->stream;
+  const WorkTable& ws = h->wt_spmv;
+  int lo = 0, hi = h->L - 1;
+  while (lo < h->L && !((mask >> lo) & 1ull)) ++lo;
+  while (hi >= 0 && !((mask >> hi) & 1ull)) --hi;
+  if (lo > hi) return MSKM_OK;
   for (int l = 0; l < h->L; ++l) {
-    CgLevel& S = w.h_st[l];
+    CgLevel& S = W.h_st[l];
     std::memset(&S, 0, sizeof(S));
     S.rtol2 = rtol * rtol;
     S.maxit = maxit;
     S.on = (int32_t)((mask >> l) & 1ull);
     S.done = 1;
   }
-  MSKM_HIP_TRY(hipMemcpyAsync(w.st, w.h_st, h->L * sizeof(CgLevel), hipMemcpyHostToDevice, s));
-  TX* p[2] = {pA, pB};
-  // participating levels lo..hi (the mask is contiguous in every caller);
-  // only their blocks are launched
-  int lo = 0, hi = h->L - 1;
-  while (lo < h->L && !((mask >> lo) & 1ull)) ++lo;
-  while (hi >= 0 && !((mask >> hi) & 1ull)) --hi;
-  if (lo > hi) return MSKM_OK;
+  MSKM_HIP_TRY(hipMemcpyAsync(W.st, W.h_st, h->L * sizeof(CgLevel), hipMemcpyHostToDevice, s));
   const int nlev = hi - lo + 1;
   const int sb0 = ws.h_lev_begin[lo], sbn = ws.h_lev_begin[hi + 1] - sb0;
-  const int vb0 = wv.h_lev_begin[lo], vbn = wv.h_lev_begin[hi + 1] - vb0;
-  const int G = h->spmv_g[MSKM_OP_DIAG][sizeof(TX) == 4 ? 1 : 0] % kVecFlag;
+  const int G = h->spmv_g[MSKM_OP_DIAG][sizeof(TX) == 4 ? 1 : 0];
   if (sbn > 0)
     hipLaunchKernelGGL((k_cg_init<kGDiag, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, h->diag.rowptr, h->diag.col,
-                       dval, b, x, r, p[0], w.st, warm ? 1 : 0, w.part_s, w.part_s2, sb0);
-  hipLaunchKernelGGL(k_cg_red_init, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, w.part_s, w.part_s2, w.st);
-  int it = 0;
-  for (;;) {
-    for (int c = 0; c < check_every && it < maxit; ++c, ++it) {
-      if (sbn > 0) launch_cg_spmv<TV, TX>(s, G, ws, sb0, sbn, h->diag, dval, r, p[it & 1], p[(it + 1) & 1], q, w.st,
-                                          w.part_s);
-      hipLaunchKernelGGL(k_cg_red_a, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, w.part_s, w.st);
-      if (vbn > 0)
-        hipLaunchKernelGGL(k_cg_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p[(it + 1) & 1], q, w.st,
-                           w.part_v);
-      hipLaunchKernelGGL(k_cg_red_b, dim3(nlev), dim3(kRedBlock), 0, s, lo, wv.lev_begin, w.part_v, w.st);
-    }
-    MSKM_HIP_TRY(hipMemcpyAsync(w.h_st, w.st, h->L * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
+                       dval, b, x, (TX*)W.r, (TX*)W.p0, W.st, warm ? 1 : 0, W.part_s, W.part_s2, sb0);
+  hipLaunchKernelGGL(k_cg_red_init, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.part_s2, W.st);
+  hipGraphExec_t exec = nullptr;
+  MSKM_TRY((chunk_graph<TV, TX>(h, W, dval, lo, hi, x, K, G, &exec)));
+  for (int it = 0; it < maxit; it += K) {
+    MSKM_HIP_TRY(hipGraphLaunch(exec, s));
+    MSKM_HIP_TRY(hipMemcpyAsync(W.h_st, W.st, h->L * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
     MSKM_HIP_TRY(hipStreamSynchronize(s));
     bool any = false;
-    for (int l = 0; l < h->L; ++l) any |= w.h_st[l].done == 0;
-    if (!any || it >= maxit) break;
+    for (int l = lo; l <= hi; ++l) any |= W.h_st[l].done == 0;
+    if (!any) break;
   }
   MSKM_HIP_TRY(hipGetLastError());
-  for (int l = 0; l < h->L; ++l) {
-    if (!((mask >> l) & 1ull)) continue;
-    const CgLevel& o = w.h_st[l];
+  for (int l = lo; l <= hi; ++l) {
+    const CgLevel& o = W.h_st[l];
     cs->iters_total += o.iters;
     if (l < kMaxLevels) cs->last_iters[l] = o.iters;
     if (o.capped || !o.done) cs->capped = true;
@@ -439,8 +602,6 @@ static mskm_status cg_run(mskm_hier* h, Workspace& w, const TV* dval, uint64_t m
   return MSKM_OK;
 }
 
-// y = b - A x over all rows (A = strict lower part), i.e. the Jacobi update
-// beta = f - (T - D) t, or its restriction to rows [r0, r1).
 template <typename T>
 static void spmv_launch(hipStream_t s, int G, const Csr* A1, const T* v1, const Csr* A2, const T* v2, const T* x,
                         const T* b, T* y, T sign, int64_t r0, int64_t r1);
@@ -453,34 +614,27 @@ static void lower_update(mskm_hier* h, const TV* lval, const TX* t, const TX* f,
                   nullptr, t, f, beta, (TX)-1, r0, r1);
 }
 
+// alpha = T^-1 f in the internal order: monolithic (Jacobi sweeps on T' with
+// CG on the levels below the top, then CG on D) or sequential (block forward
+// substitution, one CG per level).
 template <typename TV, typename TX>
-static mskm_status solve_internal(mskm_hier* h, Workspace& w, const TV* dval, const TV* lval, const TX* f, TX* alpha,
+static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, const TV* lval, const TX* f, TX* alpha,
                                   const mskm_solve_opts* o, int* sweeps_done, CgStats* cs) {
   hipStream_t s = h->ctx->stream;
   const int64_t N = h->N;
   const int L = h->L;
-  TX *beta = nullptr, *t = nullptr, *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
-  MSKM_TRY(dalloc(&beta, N));
-  MSKM_TRY(dalloc(&t, N));
-  MSKM_TRY(dalloc(&r, N));
-  MSKM_TRY(dalloc(&p, N));
-  MSKM_TRY(dalloc(&p2, N));
-  MSKM_TRY(dalloc(&q, N));
-  struct Free {
-    TX** v[6];
-    ~Free() {
-      for (auto pp : v) (void)hipFree(*pp);
-    }
-  } fr{{&beta, &t, &r, &p, &p2, &q}};
+  TX* beta = (TX*)W.beta;
+  TX* t = (TX*)W.t;
   const int maxit = o->max_cg_iters > 0 ? o->max_cg_iters : 20000;
-  const int check = o->check_every > 0 ? o->check_every : 8;
+  int K = o->check_every > 0 ? o->check_every : 8;
+  K += K & 1;  // even chunk length
   const uint64_t all = L >= 64 ? ~0ull : ((1ull << L) - 1);
   if (o->algorithm == MSKM_ALG_SEQUENTIAL) {
     // block forward substitution: rhs_l = f_l - sum_{k<l} B_{l,k} alpha_k
     MSKM_HIP_TRY(hipMemsetAsync(alpha, 0, N * sizeof(TX), s));
     for (int l = 0; l < L; ++l) {
       lower_update<TV, TX>(h, lval, alpha, f, beta, h->h_off[l], h->h_off[l + 1]);
-      MSKM_TRY(cg_run<TV, TX>(h, w, dval, 1ull << l, beta, alpha, r, p, p2, q, o->cg_rtol, maxit, false, check, cs));
+      MSKM_TRY((cg_run<TV, TX>(h, W, dval, 1ull << l, beta, alpha, o->cg_rtol, maxit, false, K, cs)));
     }
     *sweeps_done = 0;
     return MSKM_OK;
@@ -489,15 +643,15 @@ static mskm_status solve_internal(mskm_hier* h, Workspace& w, const TV* dval, co
   const int S = o->sweeps > 0 ? o->sweeps : L;
   MSKM_HIP_TRY(hipMemcpyAsync(beta, f, N * sizeof(TX), hipMemcpyDeviceToDevice, s));
   MSKM_HIP_TRY(hipMemsetAsync(t, 0, N * sizeof(TX), s));
-  const uint64_t lower_levels = L >= 65 ? ~0ull : (all >> 1);  // levels 0..L-2
+  const uint64_t lower_levels = all >> 1;  // levels 0..L-2
   for (int sw = 0; sw < S && L > 1; ++sw) {
-    MSKM_TRY(cg_run<TV, TX>(h, w, dval, lower_levels, beta, t, r, p, p2, q, o->cg_rtol, maxit, o->warm_start != 0 && sw > 0,
-                            check, cs));
+    MSKM_TRY((cg_run<TV, TX>(h, W, dval, lower_levels, beta, t, o->cg_rtol, maxit, o->warm_start != 0 && sw > 0, K,
+                             cs)));
     lower_update<TV, TX>(h, lval, t, f, beta, h->h_off[1], N);
     *sweeps_done = sw + 1;
   }
   if (o->warm_start) MSKM_HIP_TRY(hipMemcpyAsync(alpha, t, N * sizeof(TX), hipMemcpyDeviceToDevice, s));
-  MSKM_TRY(cg_run<TV, TX>(h, w, dval, all, beta, alpha, r, p, p2, q, o->cg_rtol, maxit, o->warm_start != 0, check, cs));
+  MSKM_TRY((cg_run<TV, TX>(h, W, dval, all, beta, alpha, o->cg_rtol, maxit, o->warm_start != 0, K, cs)));
   return MSKM_OK;
 }
 
@@ -841,25 +995,11 @@ mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_o
   DevBuf F, A;
   MSKM_TRY(stage_in(s, f_in, (size_t)N * nrhs, io_dev, F));
   MSKM_TRY(stage_out_alloc(alpha_out, (size_t)N * nrhs, io_dev, A));
-  Workspace w;
-  MSKM_TRY(ws_init(h, w));
-  double *fi = nullptr, *ai = nullptr, *res = nullptr, *da = nullptr;
-  float *f32 = nullptr, *a32 = nullptr;
-  MSKM_TRY(dalloc(&fi, N));
-  MSKM_TRY(dalloc(&ai, N));
-  struct Free {
-    void* v[6];
-    ~Free() {
-      for (auto p : v) (void)hipFree(p);
-    }
-  };
-  if (mixed) {
-    MSKM_TRY(dalloc(&res, N));
-    MSKM_TRY(dalloc(&da, N));
-    MSKM_TRY(dalloc(&f32, N));
-    MSKM_TRY(dalloc(&a32, N));
-  }
-  Free fr{{fi, ai, res, da, f32, a32}};
+  SolveWS* Wp = nullptr;
+  MSKM_TRY(get_ws(h, &Wp));
+  SolveWS& W = *Wp;
+  double* fi = W.fi;
+  double* ai = W.ai;
   CgStats cs;
   int sweeps_done = 0, refine = 0;
   double worst_rel = 0.0;
@@ -868,21 +1008,26 @@ mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_o
     hipLaunchKernelGGL(k_to_internal<double>, dim3(nblk(N)), dim3(kBlock), 0, s, F.p, h->perm, fi, N, nrhs, r);
     double rel = 0.0;
     if (!mixed) {
-      MSKM_TRY((solve_internal<double, double>(h, w, h->diag.val, h->lower.val, fi, ai, o, &sweeps_done, &cs)));
+      MSKM_TRY((solve_internal<double, double>(h, W, h->diag.val, h->lower.val, fi, ai, o, &sweeps_done, &cs)));
       MSKM_TRY(residual_internal(h, ai, fi, &rel, nullptr));
     } else {
       // FP64 residual refinement around FP32 inner solves (values, vectors and
       // SpMV accumulation in FP32, dots in FP64)
       const int maxref = o->max_refine > 0 ? o->max_refine : 10;
       MSKM_HIP_TRY(hipMemsetAsync(ai, 0, N * 8, s));
-      MSKM_HIP_TRY(hipMemcpyAsync(res, fi, N * 8, hipMemcpyDeviceToDevice, s));
       refine = 0;
       for (;;) {
-        MSKM_TRY(residual_internal(h, ai, fi, &rel, res));
+        MSKM_TRY(residual_internal(h, ai, fi, &rel, W.res));
         if (rel <= o->target_rel_residual || refine >= maxref) break;
-        hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(N)), dim3(kBlock), 0, s, (const double*)res, f32, N);
-        MSKM_TRY((solve_internal<float, float>(h, w, h->diag.val32, h->lower.val32, f32, a32, o, &sweeps_done, &cs)));
-        hipLaunchKernelGGL(k_axpy_f32, dim3(nblk(N)), dim3(kBlock), 0, s, a32, ai, N);
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(N)), dim3(kBlock), 0, s, (const double*)W.res, W.f32,
+                           N);
+        // inner tolerance: cg_rtol for the first round; later rounds only
+        // need to shrink the current residual to the target (with margin)
+        mskm_solve_opts oi = *o;
+        if (refine > 0) oi.cg_rtol = std::min(0.1, std::max(o->cg_rtol, 0.5 * o->target_rel_residual / rel));
+        MSKM_TRY((solve_internal<float, float>(h, W, h->diag.val32, h->lower.val32, W.f32, W.a32, &oi, &sweeps_done,
+                                               &cs)));
+        hipLaunchKernelGGL(k_axpy_f32, dim3(nblk(N)), dim3(kBlock), 0, s, W.a32, ai, N);
         ++refine;
       }
     }
