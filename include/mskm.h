@@ -118,6 +118,17 @@ typedef struct {
  * T_L - D_L. Points are copied; the caller may free them on return.
  * MSKM_ELIMIT if N >= 2^31 or a row would exceed 2^31 entries. */
 mskm_status mskm_hier_create(mskm_ctx* ctx, const mskm_hier_desc* desc, mskm_hier** out);
+
+/* One hierarchy object holding `count` independent hierarchies (groups), for
+ * solving many uneven hierarchies in the same launches. All descriptors need
+ * the same dim and storage flags; at most 4096 levels in total. Inputs and
+ * outputs of later calls (f, alpha) are the groups' vectors concatenated in
+ * descriptor order, each in its own input order. Internally the levels are
+ * ordered depth-major, so the levels of one depth across all groups are
+ * solved together; mskm_hier_level_info maps level indices to (group,
+ * depth). mskm_export_* and mskm_apply work on batches; mskm_evaluate does
+ * not (EINVAL). */
+mskm_status mskm_hier_create_batch(mskm_ctx* ctx, const mskm_hier_desc* descs, int32_t count, mskm_hier** out);
 mskm_status mskm_hier_destroy(mskm_hier* h);
 
 typedef struct {
@@ -128,14 +139,28 @@ typedef struct {
   int32_t has_fp64, has_fp32;
   int64_t device_bytes; /* device memory held by the hierarchy */
   double assemble_ms;   /* device time of the last assembly */
+  int32_t ngroups;      /* independent hierarchies held (1 unless created as a batch) */
 } mskm_hier_stats;
 
 mskm_status mskm_hier_stats_get(const mskm_hier* h, mskm_hier_stats* out);
 
-/* The level offsets the hierarchy was created with: off[0..L] (host). */
+/* Cumulative level sizes in level order: level l holds off[l+1]-off[l]
+ * points (host, [L+1]). For a single hierarchy these are the level offsets
+ * it was created with. */
 mskm_status mskm_hier_offsets(const mskm_hier* h, int64_t* off);
 
-/* Export block B_{row_level, col_level} (row_level >= col_level) in
+typedef struct {
+  int32_t group;        /* hierarchy (descriptor index) the level belongs to */
+  int32_t depth;        /* level index within its hierarchy (0 = coarsest) */
+  int64_t n;            /* points */
+  int64_t input_offset; /* first point in the concatenated input order */
+  double delta;         /* support radius */
+} mskm_level_info;
+
+mskm_status mskm_hier_level_info(const mskm_hier* h, int32_t level, mskm_level_info* info);
+
+/* Export block B_{row_level, col_level} (levels of one hierarchy, the column
+ * level not finer than the row level; EINVAL otherwise) in
  * canonical CSR: rows in input order of level row_level, columns = input
  * index within level col_level, ascending. rowptr has N(row_level)+1
  * entries. Pass col == NULL to query the entry count into *nnz_out only.
@@ -236,13 +261,19 @@ typedef struct {
 } mskm_report;
 
 /* alpha = T_L^-1 f per right-hand side (Section 3). f, alpha: [N][nrhs] FP64
- * in input order. rep may be NULL. MSKM_ENOCONV when a CG cap or
- * max_refine was hit. */
+ * in input order. With 2 <= nrhs <= 512 all right-hand sides are solved in
+ * the same launches (one CG system per level and right-hand side, every
+ * matrix entry applied to all of them at once; no warm start); above 512
+ * they are solved one after another. rep may be NULL (cg_iters_last then
+ * holds the maximum over right-hand sides, rel_residual the maximum over
+ * right-hand sides and groups). MSKM_ENOCONV when a CG cap or max_refine
+ * was hit. */
 mskm_status mskm_solve(mskm_ctx* ctx, const mskm_hier* h, const double* f, int32_t nrhs,
                        const mskm_solve_opts* opts, double* alpha, mskm_report* rep);
 
-/* ||f - T_L alpha||_2 / ||f||_2 per right-hand side, FP64 accurate values
- * (eq. (bigt)). rel_out: host [nrhs]. */
+/* ||f - T_L alpha||_2 / ||f||_2 per right-hand side and per group (for a
+ * batch, each hierarchy's own relative residual), FP64-accurate values
+ * (eq. (bigt)). rel_out: host [nrhs][ngroups]. */
 mskm_status mskm_residual(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, const double* f, int32_t nrhs,
                           double* rel_out, int32_t flags);
 

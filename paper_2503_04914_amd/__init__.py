@@ -35,7 +35,8 @@ MSKM_PRECOND_NONE, MSKM_PRECOND_LEARNED = 0, 1
 
 EXPORTED = [
     "mskm_create", "mskm_destroy", "mskm_last_error", "mskm_abi_version",
-    "mskm_hier_create", "mskm_hier_destroy", "mskm_hier_stats_get", "mskm_hier_offsets",
+    "mskm_hier_create", "mskm_hier_create_batch", "mskm_hier_destroy", "mskm_hier_stats_get", "mskm_hier_offsets",
+    "mskm_hier_level_info",
     "mskm_export_block", "mskm_export_rows", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
     "mskm_autotune", "mskm_spmv_width",
     "mskm_solve_opts_default", "mskm_solve", "mskm_residual", "mskm_evaluate",
@@ -61,7 +62,12 @@ class HierDesc(C.Structure):
 class HierStats(C.Structure):
     _fields_ = [("dim", C.c_int32), ("levels", C.c_int32), ("n_total", C.c_int64), ("nnz_diag", C.c_int64),
                 ("nnz_lower", C.c_int64), ("has_fp64", C.c_int32), ("has_fp32", C.c_int32),
-                ("device_bytes", C.c_int64), ("assemble_ms", C.c_double)]
+                ("device_bytes", C.c_int64), ("assemble_ms", C.c_double), ("ngroups", C.c_int32)]
+
+
+class LevelInfo(C.Structure):
+    _fields_ = [("group", C.c_int32), ("depth", C.c_int32), ("n", C.c_int64), ("input_offset", C.c_int64),
+                ("delta", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -97,6 +103,8 @@ def lib():
     L.mskm_hier_destroy.argtypes = [vp]
     L.mskm_hier_stats_get.argtypes = [vp, C.POINTER(HierStats)]
     L.mskm_hier_offsets.argtypes = [vp, C.POINTER(i64)]
+    L.mskm_hier_create_batch.argtypes = [vp, C.POINTER(HierDesc), i32, C.POINTER(vp)]
+    L.mskm_hier_level_info.argtypes = [vp, i32, C.POINTER(LevelInfo)]
     L.mskm_export_block.argtypes = [vp, vp, i32, i32, vp, vp, vp, C.POINTER(i64)]
     L.mskm_export_perm.argtypes = [vp, vp, vp]
     L.mskm_export_rows.argtypes = [vp, vp, i32, i32, vp, i64, vp, vp, vp, C.POINTER(i64)]
@@ -183,6 +191,31 @@ def mskm_hier_create(ctx, points, offsets, delta, dim: int | None = None, fp64: 
     out = C.c_void_p()
     _check(lib().mskm_hier_create(ctx, C.byref(d), C.byref(out)), "mskm_hier_create")
     return out
+
+
+def mskm_hier_create_batch(ctx, hierarchies, fp64: bool = True, fp32: bool = False):
+    """One object holding several independent hierarchies; `hierarchies` is a
+    list of (points [N_g][dim], offsets [L_g+1], delta [L_g]) host arrays."""
+    keep = []
+    descs = (HierDesc * len(hierarchies))()
+    for g, (points, offsets, delta) in enumerate(hierarchies):
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        delta = np.ascontiguousarray(delta, dtype=np.float64)
+        pp, pdev = _ptr(points, np.float64)
+        keep += [offsets, delta, points]
+        flags = (MSKM_POINTS_ON_DEVICE if pdev else 0) | (MSKM_STORE_FP64 if fp64 else 0) | \
+                (MSKM_STORE_FP32 if fp32 else 0)
+        descs[g] = HierDesc(int(points.shape[1]), len(delta), offsets.ctypes.data_as(C.POINTER(C.c_int64)), pp,
+                            delta.ctypes.data_as(C.POINTER(C.c_double)), MSKM_WENDLAND_3_1, flags)
+    out = C.c_void_p()
+    _check(lib().mskm_hier_create_batch(ctx, descs, len(hierarchies), C.byref(out)), "mskm_hier_create_batch")
+    return out
+
+
+def mskm_hier_level_info(h, level: int) -> dict:
+    i = LevelInfo()
+    _check(lib().mskm_hier_level_info(h, level, C.byref(i)), "mskm_hier_level_info")
+    return {k: getattr(i, k) for k, _ in LevelInfo._fields_}
 
 
 def mskm_hier_destroy(h) -> None:
@@ -315,11 +348,12 @@ def mskm_solve(ctx, h, f, alpha, opts: SolveOpts | None = None, nrhs: int = 1) -
 
 
 def mskm_residual(ctx, h, alpha, f, nrhs: int = 1) -> np.ndarray:
+    """Relative FP64 residual per right-hand side and group: [nrhs * ngroups]."""
     ap, ad = _ptr(alpha, np.float64)
     fp, fd = _ptr(f, np.float64)
     if fd != ad:
         raise ValueError("alpha and f must both be host or both be device arrays")
-    out = np.zeros(nrhs, dtype=np.float64)
+    out = np.zeros(nrhs * mskm_hier_stats_get(h)["ngroups"], dtype=np.float64)
     _check(lib().mskm_residual(ctx, h, ap, fp, nrhs, out.ctypes.data_as(C.POINTER(C.c_double)),
                                MSKM_IO_DEVICE if ad else 0), "mskm_residual")
     return out

@@ -1,9 +1,11 @@
 // C ABI entry points: argument validation, context and handle lifetime,
 // thread-local error text. The numerical work lives in assemble.hip and
 // solve.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "mskm_internal.h"
 
@@ -11,6 +13,11 @@ namespace {
 thread_local std::string g_last_error;
 
 bool valid_ctx(const mskm_ctx* c) { return c != nullptr; }
+
+// B_{k,j} exists for levels k, j of one hierarchy with depth(j) <= depth(k)
+bool valid_block(const mskm_hier* h, int k, int j) {
+  return k >= 0 && k < h->L && j >= 0 && j < h->L && h->h_group[k] == h->h_group[j] && h->h_depth[j] <= h->h_depth[k];
+}
 }  // namespace
 
 namespace mskm {
@@ -68,11 +75,12 @@ mskm_status mskm_destroy(mskm_ctx* c) {
   return MSKM_OK;
 }
 
-mskm_status mskm_hier_create(mskm_ctx* ctx, const mskm_hier_desc* d, mskm_hier** out) {
-  if (!valid_ctx(ctx) || !d || !out) return fail(MSKM_EINVAL, "mskm_hier_create: NULL argument");
-  *out = nullptr;
+namespace {
+
+// Validation of one descriptor; returns its point count in *n.
+mskm_status check_desc(const mskm_hier_desc* d, int64_t* n) {
   if (d->dim != 2 && d->dim != 3) return fail(MSKM_EINVAL, "dim must be 2 or 3");
-  if (d->levels < 1 || d->levels > mskm::kMaxLevels) return fail(MSKM_EINVAL, "levels must be in 1..64");
+  if (d->levels < 1 || d->levels > mskm::kMaxLevels) return fail(MSKM_EINVAL, "levels out of range");
   if (d->kernel != MSKM_WENDLAND_3_1) return fail(MSKM_EINVAL, "unsupported kernel");
   if (!d->level_offsets || !d->points || !d->delta) return fail(MSKM_EINVAL, "NULL array in descriptor");
   if (d->level_offsets[0] != 0) return fail(MSKM_EINVAL, "level_offsets[0] must be 0");
@@ -80,34 +88,81 @@ mskm_status mskm_hier_create(mskm_ctx* ctx, const mskm_hier_desc* d, mskm_hier**
     if (d->level_offsets[l + 1] < d->level_offsets[l]) return fail(MSKM_EINVAL, "level_offsets must not decrease");
     if (!(d->delta[l] > 0.0) || !std::isfinite(d->delta[l])) return fail(MSKM_EINVAL, "delta must be finite and > 0");
   }
-  const int64_t N = d->level_offsets[d->levels];
+  *n = d->level_offsets[d->levels];
+  if (!(d->flags & MSKM_POINTS_ON_DEVICE)) {
+    for (int64_t i = 0; i < *n * d->dim; ++i)
+      if (!std::isfinite(d->points[i])) return fail(MSKM_EINVAL, "non-finite point coordinate");
+  }
+  return MSKM_OK;
+}
+
+// One hierarchy object from `count` independent hierarchies (groups). Levels
+// are ordered depth-major; inputs (points, and later f / alpha) are the
+// groups' arrays concatenated in descriptor order.
+mskm_status create_groups(mskm_ctx* ctx, const mskm_hier_desc* ds, int32_t count, mskm_hier** out) {
+  if (!valid_ctx(ctx) || !ds || !out || count < 1) return fail(MSKM_EINVAL, "hierarchy create: NULL argument");
+  *out = nullptr;
+  std::vector<int64_t> gn(count);
+  int64_t N = 0;
+  int Ltot = 0, Dmax = 0;
+  for (int g = 0; g < count; ++g) {
+    MSKM_TRY(check_desc(&ds[g], &gn[g]));
+    if (ds[g].dim != ds[0].dim) return fail(MSKM_EINVAL, "all hierarchies of a batch need the same dim");
+    if ((ds[g].flags & (MSKM_STORE_FP64 | MSKM_STORE_FP32)) != (ds[0].flags & (MSKM_STORE_FP64 | MSKM_STORE_FP32)))
+      return fail(MSKM_EINVAL, "all hierarchies of a batch need the same storage flags");
+    N += gn[g];
+    Ltot += ds[g].levels;
+    Dmax = std::max(Dmax, (int)ds[g].levels);
+    if (Ltot > mskm::kMaxLevels) return fail(MSKM_ELIMIT, "more than 4096 levels in one hierarchy object");
+  }
   if (N <= 0) return fail(MSKM_EINVAL, "hierarchy has no points");
   if (N >= (int64_t)INT32_MAX) return fail(MSKM_ELIMIT, "more than 2^31-1 points");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
-  const bool pdev = (d->flags & MSKM_POINTS_ON_DEVICE) != 0;
-  if (!pdev) {
-    for (int64_t i = 0; i < N * d->dim; ++i)
-      if (!std::isfinite(d->points[i])) return fail(MSKM_EINVAL, "non-finite point coordinate");
-  }
-  bool want64 = (d->flags & MSKM_STORE_FP64) != 0, want32 = (d->flags & MSKM_STORE_FP32) != 0;
+  bool want64 = (ds[0].flags & MSKM_STORE_FP64) != 0, want32 = (ds[0].flags & MSKM_STORE_FP32) != 0;
   if (!want64 && !want32) want64 = true;
 
   auto* h = new (std::nothrow) mskm_hier();
   if (!h) return fail(MSKM_ENOMEM, "hierarchy allocation");
   h->ctx = ctx;
-  h->dim = d->dim;
-  h->L = d->levels;
+  h->dim = ds[0].dim;
+  h->L = Ltot;
   h->N = N;
-  h->h_off.assign(d->level_offsets, d->level_offsets + d->levels + 1);
-  h->h_delta.assign(d->delta, d->delta + d->levels);
+  h->ngroups = count;
+  h->h_group_in_off.assign(count + 1, 0);
+  for (int g = 0; g < count; ++g) {
+    h->h_group_in_off[g + 1] = h->h_group_in_off[g] + gn[g];
+    h->h_group_levels.push_back(ds[g].levels);
+  }
+  // depth-major level order
+  std::vector<std::vector<int32_t>> idx(count, std::vector<int32_t>(Dmax, -1));
+  h->h_off.assign(1, 0);
+  for (int d = 0; d < Dmax; ++d) {
+    h->h_depth_begin.push_back((int32_t)h->h_delta.size());
+    for (int g = 0; g < count; ++g) {
+      if (d >= ds[g].levels) continue;
+      idx[g][d] = (int32_t)h->h_delta.size();
+      const int64_t n = ds[g].level_offsets[d + 1] - ds[g].level_offsets[d];
+      h->h_off.push_back(h->h_off.back() + n);
+      h->h_in_off.push_back(h->h_group_in_off[g] + ds[g].level_offsets[d]);
+      h->h_delta.push_back(ds[g].delta[d]);
+      h->h_group.push_back(g);
+      h->h_depth.push_back(d);
+    }
+  }
+  h->h_depth_begin.push_back(Ltot);
+  h->h_first.assign(Ltot, 0);
+  h->h_next.assign(Ltot, -1);
+  for (int l = 0; l < Ltot; ++l) {
+    const int g = h->h_group[l], d = h->h_depth[l];
+    h->h_first[l] = idx[g][0];
+    h->h_next[l] = d + 1 < ds[g].levels ? idx[g][d + 1] : -1;
+  }
   double* pts = nullptr;
-  mskm_status st = MSKM_OK;
-  if (pdev) {
-    pts = const_cast<double*>(d->points);
-  } else {
-    st = mskm::dalloc(&pts, (size_t)N * d->dim);
-    if (st == MSKM_OK && hipMemcpyAsync(pts, d->points, (size_t)N * d->dim * 8, hipMemcpyHostToDevice, ctx->stream) !=
-                             hipSuccess)
+  mskm_status st = mskm::dalloc(&pts, (size_t)N * h->dim);
+  for (int g = 0; g < count && st == MSKM_OK; ++g) {
+    const bool dev = (ds[g].flags & MSKM_POINTS_ON_DEVICE) != 0;
+    if (gn[g] > 0 && hipMemcpyAsync(pts + h->h_group_in_off[g] * h->dim, ds[g].points, (size_t)gn[g] * h->dim * 8,
+                                    dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
       st = fail(MSKM_EDEVICE, "point upload failed");
   }
   if (st == MSKM_OK) st = mskm::assemble_hierarchy(h, pts, want64, want32);
@@ -120,13 +175,24 @@ mskm_status mskm_hier_create(mskm_ctx* ctx, const mskm_hier_desc* d, mskm_hier**
   // lanes per row); streaming phase: 1024 rows per block (4 per thread)
   if (st == MSKM_OK) st = mskm::build_work_table(h, &h->wt_spmv, 64, 1 << 30);
   if (st == MSKM_OK) st = mskm::build_work_table(h, &h->wt_vec, 4 * mskm::kBlock, 1 << 30);
-  if (!pdev) (void)hipFree(pts);
+  (void)hipFree(pts);
   if (st != MSKM_OK) {
     mskm_hier_destroy(h);
     return st;
   }
   *out = h;
   return MSKM_OK;
+}
+
+}  // namespace
+
+mskm_status mskm_hier_create(mskm_ctx* ctx, const mskm_hier_desc* d, mskm_hier** out) {
+  if (!d) return fail(MSKM_EINVAL, "mskm_hier_create: NULL descriptor");
+  return create_groups(ctx, d, 1, out);
+}
+
+mskm_status mskm_hier_create_batch(mskm_ctx* ctx, const mskm_hier_desc* descs, int32_t count, mskm_hier** out) {
+  return create_groups(ctx, descs, count, out);
 }
 
 mskm_status mskm_hier_destroy(mskm_hier* h) {
@@ -153,6 +219,18 @@ mskm_status mskm_hier_stats_get(const mskm_hier* h, mskm_hier_stats* o) {
   o->has_fp32 = h->diag.val32 != nullptr;
   o->device_bytes = h->device_bytes;
   o->assemble_ms = h->assemble_ms;
+  o->ngroups = h->ngroups;
+  return MSKM_OK;
+}
+
+mskm_status mskm_hier_level_info(const mskm_hier* h, int32_t level, mskm_level_info* info) {
+  if (!h || !info) return fail(MSKM_EINVAL, "mskm_hier_level_info: NULL argument");
+  if (level < 0 || level >= h->L) return fail(MSKM_EINVAL, "level out of range");
+  info->group = h->h_group[level];
+  info->depth = h->h_depth[level];
+  info->n = h->h_off[level + 1] - h->h_off[level];
+  info->input_offset = h->h_in_off[level];
+  info->delta = h->h_delta[level];
   return MSKM_OK;
 }
 
@@ -165,8 +243,8 @@ mskm_status mskm_hier_offsets(const mskm_hier* h, int64_t* off) {
 mskm_status mskm_export_block(mskm_ctx* ctx, const mskm_hier* h, int32_t row_level, int32_t col_level, int64_t* rowptr,
                               int32_t* col, double* val, int64_t* nnz_out) {
   if (!valid_ctx(ctx) || !h) return fail(MSKM_EINVAL, "mskm_export_block: NULL handle");
-  if (row_level < 0 || row_level >= h->L || col_level < 0 || col_level > row_level)
-    return fail(MSKM_EINVAL, "block index out of range (need 0 <= col_level <= row_level < L)");
+  if (!valid_block(h, row_level, col_level))
+    return fail(MSKM_EINVAL, "no such block: need levels of one hierarchy with depth(col) <= depth(row)");
   if (col && !rowptr) return fail(MSKM_EINVAL, "rowptr required with col");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
   return mskm::export_block(const_cast<mskm_hier*>(h), row_level, col_level, rowptr, col, val, nnz_out);
@@ -176,8 +254,8 @@ mskm_status mskm_export_rows(mskm_ctx* ctx, const mskm_hier* h, int32_t row_leve
                              const int64_t* rows, int64_t nrows, int64_t* rowptr, int32_t* col, double* val,
                              int64_t* nnz_out) {
   if (!valid_ctx(ctx) || !h || !rows || nrows < 0) return fail(MSKM_EINVAL, "mskm_export_rows: NULL argument");
-  if (row_level < 0 || row_level >= h->L || col_level < 0 || col_level > row_level)
-    return fail(MSKM_EINVAL, "block index out of range (need 0 <= col_level <= row_level < L)");
+  if (!valid_block(h, row_level, col_level))
+    return fail(MSKM_EINVAL, "no such block: need levels of one hierarchy with depth(col) <= depth(row)");
   if (col && !rowptr) return fail(MSKM_EINVAL, "rowptr required with col");
   const int64_t n = h->h_off[row_level + 1] - h->h_off[row_level];
   for (int64_t i = 0; i < nrows; ++i)
@@ -289,6 +367,7 @@ mskm_status mskm_evaluate(mskm_ctx* ctx, const mskm_hier* h, const double* alpha
     return fail(MSKM_EINVAL, "mskm_evaluate: NULL argument");
   if (nrhs < 1 || nq < 0) return fail(MSKM_EINVAL, "nrhs must be >= 1 and nq >= 0");
   if (nq == 0) return MSKM_OK;
+  if (h->ngroups != 1) return fail(MSKM_EINVAL, "mskm_evaluate takes a single hierarchy, not a batch");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
   return mskm::evaluate(const_cast<mskm_hier*>(h), alpha, nrhs, query, nq, out, (flags & MSKM_IO_DEVICE) != 0);
 }

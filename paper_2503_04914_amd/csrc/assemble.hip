@@ -116,12 +116,13 @@ __global__ void __launch_bounds__(kBlock) k_narrow(const int64_t* __restrict__ a
 
 constexpr int kBboxBlocks = 128;
 
-// Per-level bounding box of the input points (AoS). Grid (kBboxBlocks, L).
-__global__ void __launch_bounds__(kBlock) k_bbox_partial(const double* __restrict__ pts, const int64_t* __restrict__ off,
+// Per-level bounding box of the input points (AoS); level l spans input
+// points [rng[2l], rng[2l+1]). Grid (kBboxBlocks, L).
+__global__ void __launch_bounds__(kBlock) k_bbox_partial(const double* __restrict__ pts, const int64_t* __restrict__ rng,
                                                          int dim, double* __restrict__ part) {
   __shared__ double smn[3][kBlock], smx[3][kBlock];
   const int l = blockIdx.y;
-  const int64_t a = off[l], b = off[l + 1];
+  const int64_t a = rng[2 * l], b = rng[2 * l + 1];
   double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int64_t i = a + (int64_t)blockIdx.x * kBlock + threadIdx.x; i < b; i += (int64_t)gridDim.x * kBlock) {
     for (int d = 0; d < dim; ++d) {
@@ -251,7 +252,8 @@ __global__ void __launch_bounds__(kBlock) k_nbr_count(int dim, int k, const DevL
     const int64_t i = Lk.off + r;
     const double px = X[i], py = Y[i], pz = dim == 3 ? Z[i] : 0.0;
     int64_t lower = 0, diag = 0;
-    for (int j = 0; j <= k; ++j) {
+    // this hierarchy's levels from the coarsest up to k (ascending index)
+    for (int j = Lk.first;; j = lev[j].next) {
       const DevLevel Lj = lev[j];
       int64_t c = 0;
       for_each_range(dim, Lj, cs_all, px, py, pz, [&](int64_t a, int64_t b) {
@@ -261,7 +263,11 @@ __global__ void __launch_bounds__(kBlock) k_nbr_count(int dim, int k, const DevL
           c += __popcll(__ballot(hit));
         }
       });
-      if (j == k) diag = c; else lower += c;
+      if (j == k) {
+        diag = c;
+        break;
+      }
+      lower += c;
     }
     if (lane == 0) {
       cnt_d[i] = diag;
@@ -289,7 +295,7 @@ __global__ void __launch_bounds__(kBlock) k_nbr_fill(int dim, int k, const DevLe
     const int64_t i = Lk.off + r;
     const double px = X[i], py = Y[i], pz = dim == 3 ? Z[i] : 0.0;
     int64_t lpos = lptr[i];
-    for (int j = 0; j <= k; ++j) {
+    for (int j = Lk.first;; j = lev[j].next) {
       const DevLevel Lj = lev[j];
       const bool is_diag = j == k;
       int64_t pos = is_diag ? dptr[i] : lpos;
@@ -315,7 +321,8 @@ __global__ void __launch_bounds__(kBlock) k_nbr_fill(int dim, int k, const DevLe
           pos += __popcll(m);
         }
       });
-      if (!is_diag) lpos = pos;
+      if (is_diag) break;
+      lpos = pos;
     }
   }
 }
@@ -367,9 +374,14 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   const int64_t N = h->N;
   MSKM_HIP_TRY(hipEventRecord(h->ctx->ev0, s));
 
+  std::vector<int64_t> rng(2 * (size_t)L);
+  for (int l = 0; l < L; ++l) {
+    rng[2 * l] = h->h_in_off[l];
+    rng[2 * l + 1] = h->h_in_off[l] + (h->h_off[l + 1] - h->h_off[l]);
+  }
   int64_t* d_off = nullptr;
-  MSKM_TRY(dalloc(&d_off, L + 1));
-  MSKM_HIP_TRY(hipMemcpyAsync(d_off, h->h_off.data(), (L + 1) * 8, hipMemcpyHostToDevice, s));
+  MSKM_TRY(dalloc(&d_off, 2 * (size_t)L));
+  MSKM_HIP_TRY(hipMemcpyAsync(d_off, rng.data(), rng.size() * 8, hipMemcpyHostToDevice, s));
 
   // 1. bounding boxes
   double* d_part = nullptr;
@@ -388,6 +400,8 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
     DevLevel& D = h->h_lev[l];
     D.off = h->h_off[l];
     D.n = (int32_t)(h->h_off[l + 1] - h->h_off[l]);
+    D.first = h->h_first[l];
+    D.next = h->h_next[l];
     D.delta = h->h_delta[l];
     D.d2max = D.delta * D.delta;
     D.inv_delta = 1.0 / D.delta;
@@ -445,7 +459,7 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   for (int l = 0; l < L; ++l) {
     const int64_t n = h->h_lev[l].n;
     if (n == 0) continue;
-    hipLaunchKernelGGL(k_cell_key, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, pts, dim, h->d_lev, l, h->h_off[l],
+    hipLaunchKernelGGL(k_cell_key, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, pts, dim, h->d_lev, l, h->h_in_off[l],
                        n, key, count);
   }
   // widen counts and scan over all levels' tables at once: since every
@@ -463,7 +477,7 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   for (int l = 0; l < L; ++l) {
     const int64_t n = h->h_lev[l].n;
     if (n == 0) continue;
-    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, h->d_lev, l, h->h_off[l], n, key,
+    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, h->d_lev, l, h->h_in_off[l], n, key,
                        cs64, count, tmp);
   }
   for (int l = 0; l < L; ++l) {
@@ -550,7 +564,7 @@ template <typename TV>
 __global__ void __launch_bounds__(kBlock) k_export_fill(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                         const TV* __restrict__ val, const int32_t* __restrict__ iperm,
                                                         const int32_t* __restrict__ perm, int64_t row_off,
-                                                        int64_t nrows, int64_t c0, int64_t c1,
+                                                        int64_t nrows, int64_t c0, int64_t c1, int64_t cin,
                                                         const int64_t* __restrict__ rows,
                                                         const int64_t* __restrict__ optr, int32_t* __restrict__ ocol,
                                                         double* __restrict__ oval) {
@@ -562,7 +576,7 @@ __global__ void __launch_bounds__(kBlock) k_export_fill(const int64_t* __restric
   for (int64_t t = rp[i]; t < rp[i + 1]; ++t) {
     const int32_t c = col[t];
     if (c < c0 || c >= c1) continue;
-    const int32_t cc = (int32_t)(perm[c] - c0);
+    const int32_t cc = (int32_t)(perm[c] - cin);
     const double v = val ? (double)val[t] : 0.0;
     int64_t p = n;
     while (p > 0 && ocol[o + p - 1] > cc) {
@@ -580,9 +594,10 @@ mskm_status export_block(mskm_hier* h, int k, int j, int64_t* rowptr, int32_t* c
                          const int64_t* rows_host, int64_t nrows_sel) {
   hipStream_t s = h->ctx->stream;
   const Csr& C = (k == j) ? h->diag : h->lower;
-  const int64_t row_off = h->h_off[k];
+  const int64_t row_off = h->h_in_off[k];
   const int64_t nrows = rows_host ? nrows_sel : h->h_off[k + 1] - h->h_off[k];
   const int64_t c0 = h->h_off[j], c1 = h->h_off[j + 1];
+  const int64_t cin = h->h_in_off[j];
   int64_t* rows = nullptr;
   if (rows_host) {
     MSKM_TRY(dalloc(&rows, nrows));
@@ -613,10 +628,10 @@ mskm_status export_block(mskm_hier* h, int k, int j, int64_t* rowptr, int32_t* c
     if (st == MSKM_OK && nrows > 0) {
       if (C.val || !C.val32)
         hipLaunchKernelGGL(k_export_fill<double>, dim3(grid_for(nrows, kBlock)), dim3(kBlock), 0, s, C.rowptr, C.col,
-                           C.val, h->iperm, h->perm, row_off, nrows, c0, c1, rows, optr, ocol, oval);
+                           C.val, h->iperm, h->perm, row_off, nrows, c0, c1, cin, rows, optr, ocol, oval);
       else
         hipLaunchKernelGGL(k_export_fill<float>, dim3(grid_for(nrows, kBlock)), dim3(kBlock), 0, s, C.rowptr, C.col,
-                           C.val32, h->iperm, h->perm, row_off, nrows, c0, c1, rows, optr, ocol, oval);
+                           C.val32, h->iperm, h->perm, row_off, nrows, c0, c1, cin, rows, optr, ocol, oval);
     }
     if (st == MSKM_OK) {
       hipError_t e = hipMemcpyAsync(rowptr, optr, (nrows + 1) * 8, hipMemcpyDeviceToHost, s);

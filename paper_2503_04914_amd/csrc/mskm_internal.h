@@ -3,8 +3,11 @@
 // Device data layout (one hierarchy):
 //   * internal order: every level's points are sorted by the row-major key of
 //     their cell in that level's own cell grid (cell side >= delta_l), ties by
-//     input index. Level l occupies internal rows [off_l, off_l + n_l), levels
-//     concatenated coarse to fine. perm[i] = global input index of internal i.
+//     input index. Level l occupies internal rows [off_l, off_l + n_l). A
+//     hierarchy object holds one or more independent hierarchies ("groups");
+//     its levels are ordered depth-major (depth 0 of every group, then depth
+//     1, ...), so the levels of one depth are contiguous. perm[i] = global
+//     input index of internal i (inputs are group-major, coarse to fine).
 //   * coordinates: SoA FP64, xs[a][i] for axis a, internal order.
 //   * blocks: CSR over internal rows. "diag" holds A_l = B_{l,l} for every l,
 //     "lower" holds B_{k,j}, j < k. Column = internal global index (int32),
@@ -22,7 +25,7 @@
 
 namespace mskm {
 
-constexpr int kMaxLevels = 64;
+constexpr int kMaxLevels = 4096;  // levels of one hierarchy object (all groups of a batch)
 constexpr int kBlock = 256;  // threads per block of every streaming / SpMV kernel
 constexpr int kCsrPad = 16;  // tail pad (entries) of CSR column and value arrays
 constexpr int kVecFlag = 1000;  // SpMV variant code: lanes per row + kVecFlag = 16-byte loads
@@ -40,6 +43,8 @@ struct DevLevel {
   double inv_cell;   // 1 / cell side
   int32_t nc[3];     // cells per axis
   int32_t cs_off;    // offset of this level's cell_start table in the shared array
+  int32_t first;     // first (coarsest) level of this level's hierarchy
+  int32_t next;      // next finer level of the same hierarchy (-1 at its top)
 };
 
 // A launch table: block b works on rows [row0[b], row1[b]) of level lev[b].
@@ -88,7 +93,13 @@ struct mskm_hier {
   mskm_ctx* ctx = nullptr;
   int32_t dim = 0, L = 0;
   int64_t N = 0;
-  std::vector<int64_t> h_off;           // [L+1]
+  std::vector<int64_t> h_off;           // [L+1] internal offsets (level order)
+  std::vector<int64_t> h_in_off;        // [L] input offset of each level
+  std::vector<int32_t> h_group, h_depth, h_first, h_next;  // [L] level graph
+  int32_t ngroups = 1;
+  std::vector<int32_t> h_group_levels;  // [ngroups] levels per group
+  std::vector<int64_t> h_group_in_off;  // [ngroups+1] input offsets of the groups
+  std::vector<int32_t> h_depth_begin;   // [Dmax+1] level range of each depth
   std::vector<double> h_delta;          // [L]
   std::vector<mskm::DevLevel> h_lev;    // [L]
   mskm::DevLevel* d_lev = nullptr;      // device [L]
@@ -166,6 +177,10 @@ mskm_status apply_internal(mskm_hier* h, int op, int prec, const void* x, void* 
 mskm_status autotune(mskm_hier* h, int repeats, float* times_out);
 mskm_status solve(mskm_hier* h, const double* f, int nrhs, const mskm_solve_opts* o, double* alpha,
                   mskm_report* rep);
+// solve_mr.hip: many right-hand sides in the same launches (2 <= nrhs <= 512)
+bool mr_supported(int nrhs);
+mskm_status solve_multi(mskm_hier* h, const double* f, int nrhs, const mskm_solve_opts* o, double* alpha,
+                        mskm_report* rep);
 mskm_status residual(mskm_hier* h, const double* alpha, const double* f, int nrhs, double* rel_out, bool io_dev);
 mskm_status evaluate(mskm_hier* h, const double* alpha, int nrhs, const double* query, int64_t nq, double* out,
                      bool io_dev);

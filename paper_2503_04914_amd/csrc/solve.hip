@@ -558,20 +558,20 @@ static mskm_status chunk_graph(mskm_hier* h, SolveWS& W, const TV* dval, int lo,
 // captured chunk of K iterations; the host reads the per-level state after
 // each chunk and stops when every level has stopped.
 template <typename TV, typename TX>
-static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, uint64_t mask, const TX* b, TX* x, double rtol,
-                          int maxit, bool warm, int K, CgStats* cs) {
+static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::vector<char>& on, const TX* b, TX* x,
+                          double rtol, int maxit, bool warm, int K, CgStats* cs) {
   hipStream_t s = h->ctx->stream;
   const WorkTable& ws = h->wt_spmv;
   int lo = 0, hi = h->L - 1;
-  while (lo < h->L && !((mask >> lo) & 1ull)) ++lo;
-  while (hi >= 0 && !((mask >> hi) & 1ull)) --hi;
+  while (lo < h->L && !on[lo]) ++lo;
+  while (hi >= 0 && !on[hi]) --hi;
   if (lo > hi) return MSKM_OK;
   for (int l = 0; l < h->L; ++l) {
     CgLevel& S = W.h_st[l];
     std::memset(&S, 0, sizeof(S));
     S.rtol2 = rtol * rtol;
     S.maxit = maxit;
-    S.on = (int32_t)((mask >> l) & 1ull);
+    S.on = on[l] ? 1 : 0;
     S.done = 1;
   }
   MSKM_HIP_TRY(hipMemcpyAsync(W.st, W.h_st, h->L * sizeof(CgLevel), hipMemcpyHostToDevice, s));
@@ -594,6 +594,7 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, uint64_t mas
   }
   MSKM_HIP_TRY(hipGetLastError());
   for (int l = lo; l <= hi; ++l) {
+    if (!on[l]) continue;
     const CgLevel& o = W.h_st[l];
     cs->iters_total += o.iters;
     if (l < kMaxLevels) cs->last_iters[l] = o.iters;
@@ -628,97 +629,60 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
   const int maxit = o->max_cg_iters > 0 ? o->max_cg_iters : 20000;
   int K = o->check_every > 0 ? o->check_every : 8;
   K += K & 1;  // even chunk length
-  const uint64_t all = L >= 64 ? ~0ull : ((1ull << L) - 1);
+  std::vector<char> on(L, 0);
   if (o->algorithm == MSKM_ALG_SEQUENTIAL) {
-    // block forward substitution: rhs_l = f_l - sum_{k<l} B_{l,k} alpha_k
+    // block forward substitution, depth by depth (every group's level of
+    // that depth in the same launches): rhs_l = f_l - sum_{k<l} B_{l,k} alpha_k
     MSKM_HIP_TRY(hipMemsetAsync(alpha, 0, N * sizeof(TX), s));
-    for (int l = 0; l < L; ++l) {
-      lower_update<TV, TX>(h, lval, alpha, f, beta, h->h_off[l], h->h_off[l + 1]);
-      MSKM_TRY((cg_run<TV, TX>(h, W, dval, 1ull << l, beta, alpha, o->cg_rtol, maxit, false, K, cs)));
+    const int D = (int)h->h_depth_begin.size() - 1;
+    for (int d = 0; d < D; ++d) {
+      const int l0 = h->h_depth_begin[d], l1 = h->h_depth_begin[d + 1];
+      lower_update<TV, TX>(h, lval, alpha, f, beta, h->h_off[l0], h->h_off[l1]);
+      std::fill(on.begin(), on.end(), 0);
+      for (int l = l0; l < l1; ++l) on[l] = 1;
+      MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, false, K, cs)));
     }
     *sweeps_done = 0;
     return MSKM_OK;
   }
   // monolithic: Jacobi on T' beta = f from beta_0 = f, then D alpha = beta
-  const int S = o->sweeps > 0 ? o->sweeps : L;
+  int Lmax = 0;
+  for (int g = 0; g < h->ngroups; ++g) Lmax = std::max(Lmax, (int)h->h_group_levels[g]);
+  const int S = o->sweeps > 0 ? o->sweeps : Lmax;
   MSKM_HIP_TRY(hipMemcpyAsync(beta, f, N * sizeof(TX), hipMemcpyDeviceToDevice, s));
   MSKM_HIP_TRY(hipMemsetAsync(t, 0, N * sizeof(TX), s));
-  const uint64_t lower_levels = all >> 1;  // levels 0..L-2
-  for (int sw = 0; sw < S && L > 1; ++sw) {
-    MSKM_TRY((cg_run<TV, TX>(h, W, dval, lower_levels, beta, t, o->cg_rtol, maxit, o->warm_start != 0 && sw > 0, K,
-                             cs)));
-    lower_update<TV, TX>(h, lval, t, f, beta, h->h_off[1], N);
+  for (int l = 0; l < L; ++l) on[l] = h->h_next[l] >= 0;  // every level below its hierarchy's top
+  for (int sw = 0; sw < S && Lmax > 1; ++sw) {
+    MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, t, o->cg_rtol, maxit, o->warm_start != 0 && sw > 0, K, cs)));
+    lower_update<TV, TX>(h, lval, t, f, beta, 0, N);
     *sweeps_done = sw + 1;
   }
   if (o->warm_start) MSKM_HIP_TRY(hipMemcpyAsync(alpha, t, N * sizeof(TX), hipMemcpyDeviceToDevice, s));
-  MSKM_TRY((cg_run<TV, TX>(h, W, dval, all, beta, alpha, o->cg_rtol, maxit, o->warm_start != 0, K, cs)));
+  std::fill(on.begin(), on.end(), 1);
+  MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, o->warm_start != 0, K, cs)));
   return MSKM_OK;
 }
 
 // ------------------------------------------------------------- residual
+//
+// r = f - (D + Lo) alpha over the level-aligned blocks of the SpMV table,
+// with per-block partials of r.r and f.f (summed per level, then per group,
+// on the host in block order).
 
-// r = f - (D + Lo) alpha with FP64 values (stored), per-block partials of
-// r.r and f.f.
 __global__ void __launch_bounds__(kBlock)
-    k_residual64(const int64_t* __restrict__ drp, const int32_t* __restrict__ dc, const double* __restrict__ dv,
-                 const int64_t* __restrict__ lrp, const int32_t* __restrict__ lc, const double* __restrict__ lv,
-                 const double* __restrict__ a, const double* __restrict__ f, int64_t n, double* __restrict__ part) {
+    k_residual64(const WorkTable wt, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
+                 const double* __restrict__ dv, const int64_t* __restrict__ lrp, const int32_t* __restrict__ lc,
+                 const double* __restrict__ lv, const double* __restrict__ a, const double* __restrict__ f,
+                 double* __restrict__ part, double* __restrict__ rout) {
   constexpr int G = 16;
   __shared__ double sm[kBlock / kWave];
+  const int blk = xcd_block_id(gridDim.x);
+  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
   const int gl = threadIdx.x % G;
   double srr = 0.0, sff = 0.0;
-  const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
-  for (int64_t i = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; i < n; i += groups) {
+  for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
     double acc = csr_row_dot<G, double, double, double>(drp, dc, dv, a, i, gl);
     acc += csr_row_dot<G, double, double, double>(lrp, lc, lv, a, i, gl);
-    if (gl == 0) {
-      const double ri = f[i] - acc;
-      srr += ri * ri;
-      sff += f[i] * f[i];
-    }
-  }
-  srr = block_sum(srr, sm);
-  sff = block_sum(sff, sm);
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = srr;
-    part[2 * blockIdx.x + 1] = sff;
-  }
-}
-
-// Same with FP64 values recomputed from the coordinates (when only FP32 values
-// are stored): v = phi(sqrt(d2)/delta_j), the level j of a column found by a
-// monotone scan of the level offsets (columns ascend within a row).
-template <int G>
-__device__ __forceinline__ double row_dot_recompute(int dim, const DevLevel* __restrict__ lev, int L,
-                                                    const double* __restrict__ xs, int64_t N,
-                                                    const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                    const double* __restrict__ a, int64_t i, int gl) {
-  const double px = xs[i], py = xs[N + i], pz = dim == 3 ? xs[2 * N + i] : 0.0;
-  double acc = 0.0;
-  int j = 0;
-  for (int64_t k = rp[i] + gl; k < rp[i + 1]; k += G) {
-    const int64_t c = col[k];
-    while (j + 1 < L && c >= lev[j + 1].off) ++j;
-    const double d2 = sqdist(dim, px, py, pz, xs[c], xs[N + c], dim == 3 ? xs[2 * N + c] : 0.0);
-    acc += phi31_d2(d2, lev[j].delta) * a[c];
-  }
-  return group_sum<G>(acc);
-}
-
-__global__ void __launch_bounds__(kBlock)
-    k_residual_recompute(int dim, const DevLevel* __restrict__ lev, int L, const double* __restrict__ xs, int64_t N,
-                         const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
-                         const int64_t* __restrict__ lrp, const int32_t* __restrict__ lc,
-                         const double* __restrict__ a, const double* __restrict__ f, double* __restrict__ part,
-                         double* __restrict__ rout) {
-  constexpr int G = 16;
-  __shared__ double sm[kBlock / kWave];
-  const int gl = threadIdx.x % G;
-  double srr = 0.0, sff = 0.0;
-  const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
-  for (int64_t i = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; i < N; i += groups) {
-    double acc = row_dot_recompute<G>(dim, lev, L, xs, N, drp, dc, a, i, gl);
-    acc += row_dot_recompute<G>(dim, lev, L, xs, N, lrp, lc, a, i, gl);
     if (gl == 0) {
       const double ri = f[i] - acc;
       if (rout) rout[i] = ri;
@@ -729,36 +693,98 @@ __global__ void __launch_bounds__(kBlock)
   srr = block_sum(srr, sm);
   sff = block_sum(sff, sm);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = srr;
-    part[2 * blockIdx.x + 1] = sff;
+    part[2 * blk] = srr;
+    part[2 * blk + 1] = sff;
   }
 }
 
-constexpr int kResidBlocks = 2048;
-
-// ||f - T a|| / ||f|| in internal order (device vectors).
-static mskm_status residual_internal(mskm_hier* h, const double* a, const double* f, double* rel, double* rout) {
-  hipStream_t s = h->ctx->stream;
-  double* part = nullptr;
-  MSKM_TRY(dalloc(&part, 2 * kResidBlocks));
-  if (h->diag.val && h->lower.val && !rout) {
-    hipLaunchKernelGGL(k_residual64, dim3(kResidBlocks), dim3(kBlock), 0, s, h->diag.rowptr, h->diag.col, h->diag.val,
-                       h->lower.rowptr, h->lower.col, h->lower.val, a, f, h->N, part);
-  } else {
-    hipLaunchKernelGGL(k_residual_recompute, dim3(kResidBlocks), dim3(kBlock), 0, s, h->dim, h->d_lev, h->L, h->xs,
-                       h->N, h->diag.rowptr, h->diag.col, h->lower.rowptr, h->lower.col, a, f, part, rout);
+// Same with FP64 values recomputed from the coordinates (when only FP32 values
+// are stored): v = phi(sqrt(d2)/delta_j). A row of level k holds columns of
+// its hierarchy's levels first(k) .. k in ascending order; the level of a
+// column follows by walking that chain (each lane's columns ascend).
+template <int G>
+__device__ __forceinline__ double row_dot_recompute(int dim, const DevLevel* __restrict__ lev, int j0,
+                                                    const double* __restrict__ xs, int64_t N,
+                                                    const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                    const double* __restrict__ a, int64_t i, int gl) {
+  const double px = xs[i], py = xs[N + i], pz = dim == 3 ? xs[2 * N + i] : 0.0;
+  double acc = 0.0;
+  int j = j0;
+  for (int64_t k = rp[i] + gl; k < rp[i + 1]; k += G) {
+    const int64_t c = col[k];
+    while (c >= lev[j].off + lev[j].n && lev[j].next >= 0) j = lev[j].next;
+    const double d2 = sqdist(dim, px, py, pz, xs[c], xs[N + c], dim == 3 ? xs[2 * N + c] : 0.0);
+    acc += phi31_d2(d2, lev[j].delta) * a[c];
   }
-  std::vector<double> hp(2 * kResidBlocks);
+  return group_sum<G>(acc);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_residual_recompute(const WorkTable wt, int dim, const DevLevel* __restrict__ lev, const double* __restrict__ xs,
+                         int64_t N, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
+                         const int64_t* __restrict__ lrp, const int32_t* __restrict__ lc,
+                         const double* __restrict__ a, const double* __restrict__ f, double* __restrict__ part,
+                         double* __restrict__ rout) {
+  constexpr int G = 16;
+  __shared__ double sm[kBlock / kWave];
+  const int blk = xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
+  const int gl = threadIdx.x % G;
+  double srr = 0.0, sff = 0.0;
+  for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
+    double acc = row_dot_recompute<G>(dim, lev, l, xs, N, drp, dc, a, i, gl);
+    acc += row_dot_recompute<G>(dim, lev, lev[l].first, xs, N, lrp, lc, a, i, gl);
+    if (gl == 0) {
+      const double ri = f[i] - acc;
+      if (rout) rout[i] = ri;
+      srr += ri * ri;
+      sff += f[i] * f[i];
+    }
+  }
+  srr = block_sum(srr, sm);
+  sff = block_sum(sff, sm);
+  if (threadIdx.x == 0) {
+    part[2 * blk] = srr;
+    part[2 * blk + 1] = sff;
+  }
+}
+
+// ||f - T a|| / ||f|| per group (rel_groups, host [ngroups]) and the maximum
+// over groups (*rel), internal order device vectors. rout (nullable)
+// receives r. FP64 values are used when stored, else recomputed.
+static mskm_status residual_internal(mskm_hier* h, const double* a, const double* f, double* rel, double* rout,
+                                     double* rel_groups = nullptr) {
+  hipStream_t s = h->ctx->stream;
+  const WorkTable& wt = h->wt_spmv;
+  double* part = nullptr;
+  MSKM_TRY(dalloc(&part, 2 * (size_t)wt.nblocks));
+  if (h->diag.val && h->lower.val) {
+    hipLaunchKernelGGL(k_residual64, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->diag.rowptr, h->diag.col,
+                       h->diag.val, h->lower.rowptr, h->lower.col, h->lower.val, a, f, part, rout);
+  } else {
+    hipLaunchKernelGGL(k_residual_recompute, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->dim, h->d_lev, h->xs, h->N,
+                       h->diag.rowptr, h->diag.col, h->lower.rowptr, h->lower.col, a, f, part, rout);
+  }
+  std::vector<double> hp(2 * (size_t)wt.nblocks);
   hipError_t e = hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(part);
   if (e != hipSuccess) return fail(MSKM_EDEVICE, std::string("residual: ") + hipGetErrorString(e));
-  double rr = 0.0, ff = 0.0;
-  for (int b = 0; b < kResidBlocks; ++b) {
-    rr += hp[2 * b];
-    ff += hp[2 * b + 1];
+  std::vector<double> rr(h->ngroups, 0.0), ff(h->ngroups, 0.0);
+  for (int l = 0; l < h->L; ++l) {
+    const int g = h->h_group[l];
+    for (int b = wt.h_lev_begin[l]; b < wt.h_lev_begin[l + 1]; ++b) {
+      rr[g] += hp[2 * b];
+      ff[g] += hp[2 * b + 1];
+    }
   }
-  *rel = ff > 0.0 ? std::sqrt(rr / ff) : std::sqrt(rr);
+  *rel = 0.0;
+  for (int g = 0; g < h->ngroups; ++g) {
+    const double rg = ff[g] > 0.0 ? std::sqrt(rr[g] / ff[g]) : std::sqrt(rr[g]);
+    if (rel_groups) rel_groups[g] = rg;
+    *rel = std::max(*rel, rg);
+  }
   return MSKM_OK;
 }
 
@@ -987,6 +1013,7 @@ mskm_status apply_op(mskm_hier* h, int op, int prec, const double* x_in, int nrh
 
 mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_opts* o, double* alpha_out,
                   mskm_report* rep) {
+  if (nrhs > 1 && mr_supported(nrhs)) return solve_multi(h, f_in, nrhs, o, alpha_out, rep);
   hipStream_t s = h->ctx->stream;
   const int64_t N = h->N;
   const bool io_dev = (o->flags & MSKM_IO_DEVICE) != 0;
@@ -1048,7 +1075,7 @@ mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_o
     rep->sweeps_done = sweeps_done;
     rep->refine_steps = refine;
     rep->cg_iters_total = cs.iters_total;
-    for (int l = 0; l < std::min(h->L, 64); ++l) rep->cg_iters_last[l] = cs.last_iters[l];
+    for (int l = 0; l < std::min(h->L, 64); ++l) rep->cg_iters_last[l] = cs.last_iters[l];  // first 64 levels
     rep->rel_residual = worst_rel;
     rep->solve_ms = ms;
   }
@@ -1069,7 +1096,8 @@ mskm_status residual(mskm_hier* h, const double* alpha, const double* f, int nrh
   for (int r = 0; r < nrhs && st == MSKM_OK; ++r) {
     hipLaunchKernelGGL(k_to_internal<double>, dim3(nblk(N)), dim3(kBlock), 0, s, A.p, h->perm, ai, N, nrhs, r);
     hipLaunchKernelGGL(k_to_internal<double>, dim3(nblk(N)), dim3(kBlock), 0, s, F.p, h->perm, fi, N, nrhs, r);
-    st = residual_internal(h, ai, fi, &rel_out[r], nullptr);
+    double worst = 0.0;
+    st = residual_internal(h, ai, fi, &worst, nullptr, rel_out + (size_t)r * h->ngroups);
   }
   (void)hipFree(ai);
   (void)hipFree(fi);

@@ -1,0 +1,633 @@
+// Many right-hand sides in the same launches: CG on A_l X_l = B_l for every
+// (level, right-hand side) pair, Jacobi sweeps / forward substitution with a
+// multi-vector SpMM, FP64 residuals per right-hand side. Vectors are
+// point-major [N][R] in the internal order, so the R values gathered for one
+// column are contiguous and a group of lanes reads them in one coalesced
+// access; every matrix entry is loaded once per SpMM and applied to all R
+// right-hand sides.
+//
+// Lane mapping: a group of LR lanes (LR = 64 for R >= 64, else the power of
+// two >= R) handles one row; lane t of the group owns right-hand sides
+// t, t + LR, ... (at most kMaxRPerLane of them).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "device_common.h"
+
+namespace mskm {
+
+constexpr int kMaxRPerLane = 8;  // R <= 64 * 8 = 512
+
+struct MrCfg {
+  int R, LR, RM;  // right-hand sides, lanes per row, right-hand sides per lane
+};
+
+static MrCfg mr_cfg(int R) {
+  int LR = 1;
+  while (LR < R && LR < 64) LR <<= 1;
+  return MrCfg{R, LR, (R + LR - 1) / LR};
+}
+
+// Per-(level, rhs) CG state (index l * R + r).
+struct MrState {
+  double rtol2, bb, rr, alpha, beta;
+  int32_t maxit, on, iters, done, capped, pad;
+};
+
+static unsigned mr_nblk(int64_t n, int per) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 1 << 30));
+}
+
+// out[i*R + r] = in[perm[i]*R + r] (input -> internal), or the inverse.
+template <typename TO>
+__global__ void __launch_bounds__(kBlock) k_mr_to_internal(const double* __restrict__ in, const int32_t* __restrict__ perm,
+                                                           TO* __restrict__ out, int64_t n, int R) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n * R) return;
+  const int64_t i = e / R, r = e % R;
+  out[e] = (TO)in[(int64_t)perm[i] * R + r];
+}
+
+template <typename TI>
+__global__ void __launch_bounds__(kBlock) k_mr_to_input(const TI* __restrict__ in, const int32_t* __restrict__ perm,
+                                                        double* __restrict__ out, int64_t n, int R) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n * R) return;
+  const int64_t i = e / R, r = e % R;
+  out[(int64_t)perm[i] * R + r] = (double)in[e];
+}
+
+// Y[i][:] = b[i][:] + sign * (A X)[i][:] for rows [r0, r1) (b nullable).
+template <typename TV, typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_mr_spmm(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, const TV* __restrict__ val,
+              const TX* __restrict__ x, const TX* __restrict__ b, TX* __restrict__ y, TX sign, int64_t r0, int64_t r1,
+              MrCfg c) {
+  const int gl = threadIdx.x % c.LR;
+  const int groups_per_block = kBlock / c.LR;
+  const int64_t groups = (int64_t)gridDim.x * groups_per_block;
+  for (int64_t i = r0 + (int64_t)blockIdx.x * groups_per_block + threadIdx.x / c.LR; i < r1; i += groups) {
+    TX acc[kMaxRPerLane];
+#pragma unroll
+    for (int m = 0; m < kMaxRPerLane; ++m) acc[m] = 0;
+    const int64_t ke = rp[i + 1];
+    for (int64_t k = rp[i]; k < ke; ++k) {
+      const TX v = (TX)val[k];
+      const TX* xr = x + (int64_t)col[k] * c.R;
+#pragma unroll
+      for (int m = 0; m < kMaxRPerLane; ++m) {
+        const int r = gl + m * c.LR;
+        if (m < c.RM && r < c.R) acc[m] += v * xr[r];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxRPerLane; ++m) {
+      const int r = gl + m * c.LR;
+      if (m < c.RM && r < c.R) y[i * c.R + r] = (b ? b[i * c.R + r] : (TX)0) + sign * acc[m];
+    }
+  }
+}
+
+// Block partials of per-rhs sums: each lane holds acc[m] for rhs gl + m*LR;
+// the block's row groups are combined in LDS; part[blk*R + r].
+__device__ __forceinline__ void mr_block_partial(const double* acc, const MrCfg& c, double* sm, double* part,
+                                                 int blk) {
+  const int gl = threadIdx.x % c.LR, grp = threadIdx.x / c.LR, ngrp = kBlock / c.LR;
+  for (int m = 0; m < c.RM; ++m) {
+    const int r = gl + m * c.LR;
+    if (r < c.R) sm[grp * c.R + r] = acc[m];
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < c.R; r += kBlock) {
+    double s = 0.0;
+    for (int g = 0; g < ngrp; ++g) s += sm[g * c.R + r];
+    part[(size_t)blk * c.R + r] = s;
+  }
+  __syncthreads();
+}
+
+constexpr int kMrLds = kBlock * kMaxRPerLane;  // doubles of LDS for block partials
+
+// init: X = 0, Rv = B, P = 0; partials of b.b and r.r per rhs.
+template <typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_mr_init(const WorkTable wt, int base, const TX* __restrict__ b, TX* __restrict__ x, TX* __restrict__ r,
+              TX* __restrict__ p, const MrState* __restrict__ st, double* __restrict__ bbp, MrCfg c) {
+  __shared__ double sm[kMrLds];
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  const int gl = threadIdx.x % c.LR;
+  double acc[kMaxRPerLane];
+  for (int m = 0; m < kMaxRPerLane; ++m) acc[m] = 0.0;
+  for (int64_t i = wt.row0[blk] + threadIdx.x / c.LR; i < wt.row1[blk]; i += kBlock / c.LR) {
+    for (int m = 0; m < c.RM; ++m) {
+      const int rr = gl + m * c.LR;
+      if (rr >= c.R || !st[(size_t)l * c.R + rr].on) continue;
+      const int64_t e = i * c.R + rr;
+      const TX bi = b[e];
+      x[e] = (TX)0;
+      r[e] = bi;
+      p[e] = (TX)0;
+      acc[m] += (double)bi * (double)bi;
+    }
+  }
+  mr_block_partial(acc, c, sm, bbp, blk);
+}
+
+// One block per level, threads over rhs: initial state (r = b, so rr = bb).
+__global__ void __launch_bounds__(kBlock) k_mr_red_init(int lev0, const int32_t* __restrict__ lev_begin,
+                                                        const double* __restrict__ bbp, MrState* __restrict__ st,
+                                                        int32_t* __restrict__ lev_done, MrCfg c) {
+  __shared__ int any;
+  const int l = lev0 + blockIdx.x;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < c.R; r += kBlock) {
+    double bb = 0.0;
+    for (int b = lev_begin[l]; b < lev_begin[l + 1]; ++b) bb += bbp[(size_t)b * c.R + r];
+    MrState& S = st[(size_t)l * c.R + r];
+    S.bb = bb;
+    S.rr = bb;
+    S.alpha = S.beta = 0.0;
+    S.iters = 0;
+    const bool finite = isfinite(bb);
+    const bool conv = finite && !(bb > S.rtol2 * bb);
+    S.capped = S.on && !conv && (!finite || S.maxit <= 0);
+    S.done = !S.on || conv || S.capped;
+    if (!S.done) any = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) lev_done[l] = !any;
+}
+
+// p = r + beta p (per element of not-stopped systems).
+template <typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_mr_dir(const WorkTable wt, int base, const TX* __restrict__ r, TX* __restrict__ p,
+             const MrState* __restrict__ st, const int32_t* __restrict__ lev_done, MrCfg c) {
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (lev_done[l]) return;
+  const int64_t e0 = wt.row0[blk] * c.R, e1 = wt.row1[blk] * c.R;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+    const MrState& S = st[(size_t)l * c.R + (int)(e % c.R)];
+    if (!S.done) p[e] = r[e] + (TX)S.beta * p[e];
+  }
+}
+
+// Q = A P on the block's rows; partial p.q per rhs.
+template <typename TV, typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_mr_cg_spmm(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                 const TV* __restrict__ val, const TX* __restrict__ p, TX* __restrict__ q,
+                 const int32_t* __restrict__ lev_done, double* __restrict__ pqp, MrCfg c) {
+  __shared__ double sm[kMrLds];
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (lev_done[l]) return;
+  const int gl = threadIdx.x % c.LR;
+  double part[kMaxRPerLane];
+#pragma unroll
+  for (int m = 0; m < kMaxRPerLane; ++m) part[m] = 0.0;
+  for (int64_t i = wt.row0[blk] + threadIdx.x / c.LR; i < wt.row1[blk]; i += kBlock / c.LR) {
+    TX acc[kMaxRPerLane];
+#pragma unroll
+    for (int m = 0; m < kMaxRPerLane; ++m) acc[m] = 0;
+    const int64_t ke = rp[i + 1];
+    for (int64_t k = rp[i]; k < ke; ++k) {
+      const TX v = (TX)val[k];
+      const TX* pr = p + (int64_t)col[k] * c.R;
+#pragma unroll
+      for (int m = 0; m < kMaxRPerLane; ++m) {
+        const int r = gl + m * c.LR;
+        if (m < c.RM && r < c.R) acc[m] += v * pr[r];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxRPerLane; ++m) {
+      const int r = gl + m * c.LR;
+      if (m < c.RM && r < c.R) {
+        q[i * c.R + r] = acc[m];
+        part[m] += (double)p[i * c.R + r] * (double)acc[m];
+      }
+    }
+  }
+  mr_block_partial(part, c, sm, pqp, blk);
+}
+
+__global__ void __launch_bounds__(kBlock) k_mr_red_a(int lev0, const int32_t* __restrict__ lev_begin,
+                                                     const double* __restrict__ pqp, MrState* __restrict__ st,
+                                                     const int32_t* __restrict__ lev_done, MrCfg c) {
+  const int l = lev0 + blockIdx.x;
+  if (lev_done[l]) return;
+  for (int r = threadIdx.x; r < c.R; r += kBlock) {
+    MrState& S = st[(size_t)l * c.R + r];
+    if (S.done) continue;
+    double pq = 0.0;
+    for (int b = lev_begin[l]; b < lev_begin[l + 1]; ++b) pq += pqp[(size_t)b * c.R + r];
+    if (pq > 0.0 && isfinite(pq)) {
+      S.alpha = S.rr / pq;
+    } else {
+      S.alpha = 0.0;
+      S.done = 1;
+      S.capped = !(S.rr <= S.rtol2 * S.bb);
+    }
+  }
+}
+
+// X += alpha P; R -= alpha Q; partial r.r per rhs.
+template <typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_mr_update(const WorkTable wt, int base, TX* __restrict__ x, TX* __restrict__ r, const TX* __restrict__ p,
+                const TX* __restrict__ q, const MrState* __restrict__ st, const int32_t* __restrict__ lev_done,
+                double* __restrict__ rrp, MrCfg c) {
+  __shared__ double sm[kMrLds];
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (lev_done[l]) return;
+  const int gl = threadIdx.x % c.LR;
+  double acc[kMaxRPerLane];
+  for (int m = 0; m < kMaxRPerLane; ++m) acc[m] = 0.0;
+  for (int64_t i = wt.row0[blk] + threadIdx.x / c.LR; i < wt.row1[blk]; i += kBlock / c.LR) {
+    for (int m = 0; m < c.RM; ++m) {
+      const int rr = gl + m * c.LR;
+      if (rr >= c.R) continue;
+      const MrState& S = st[(size_t)l * c.R + rr];
+      const int64_t e = i * c.R + rr;
+      if (!S.done) {
+        x[e] = (TX)((double)x[e] + S.alpha * (double)p[e]);
+        r[e] = (TX)((double)r[e] - S.alpha * (double)q[e]);
+      }
+      acc[m] += (double)r[e] * (double)r[e];
+    }
+  }
+  mr_block_partial(acc, c, sm, rrp, blk);
+}
+
+__global__ void __launch_bounds__(kBlock) k_mr_red_b(int lev0, const int32_t* __restrict__ lev_begin,
+                                                     const double* __restrict__ rrp, MrState* __restrict__ st,
+                                                     int32_t* __restrict__ lev_done, MrCfg c) {
+  __shared__ int any;
+  const int l = lev0 + blockIdx.x;
+  if (lev_done[l]) return;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < c.R; r += kBlock) {
+    MrState& S = st[(size_t)l * c.R + r];
+    if (!S.done) {
+      double rr = 0.0;
+      for (int b = lev_begin[l]; b < lev_begin[l + 1]; ++b) rr += rrp[(size_t)b * c.R + r];
+      S.iters += 1;
+      const double old = S.rr;
+      S.rr = rr;
+      if (isfinite(rr) && !(rr > S.rtol2 * S.bb)) {
+        S.done = 1;
+      } else if (!isfinite(rr) || S.iters >= S.maxit) {
+        S.done = 1;
+        S.capped = 1;
+      } else {
+        S.beta = rr / old;
+      }
+    }
+    if (!S.done) any = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) lev_done[l] = !any;
+}
+
+// FP64 residual per rhs over the level-aligned SpMV table: partials
+// rr[blk][r], ff[blk][r]. Values: stored FP64, or recomputed from coordinates.
+__global__ void __launch_bounds__(kBlock)
+    k_mr_residual(const WorkTable wt, int dim, const DevLevel* __restrict__ lev, const double* __restrict__ xs,
+                  int64_t N, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
+                  const double* __restrict__ dv, const int64_t* __restrict__ lrp, const int32_t* __restrict__ lc,
+                  const double* __restrict__ lv, const double* __restrict__ a, const double* __restrict__ f,
+                  double* __restrict__ rout, double* __restrict__ rrp, double* __restrict__ ffp, MrCfg c) {
+  __shared__ double sm[kMrLds];
+  const int blk = xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  const int gl = threadIdx.x % c.LR;
+  double prr[kMaxRPerLane], pff[kMaxRPerLane];
+  for (int m = 0; m < kMaxRPerLane; ++m) prr[m] = pff[m] = 0.0;
+  for (int64_t i = wt.row0[blk] + threadIdx.x / c.LR; i < wt.row1[blk]; i += kBlock / c.LR) {
+    double acc[kMaxRPerLane];
+    for (int m = 0; m < kMaxRPerLane; ++m) acc[m] = 0.0;
+    const double px = xs[i], py = xs[N + i], pz = dim == 3 ? xs[2 * N + i] : 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int64_t* rp = pass == 0 ? drp : lrp;
+      const int32_t* col = pass == 0 ? dc : lc;
+      const double* val = pass == 0 ? dv : lv;
+      int j = pass == 0 ? l : lev[l].first;
+      for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int64_t cc = col[k];
+        double v;
+        if (val) {
+          v = val[k];
+        } else {
+          while (cc >= lev[j].off + lev[j].n && lev[j].next >= 0) j = lev[j].next;
+          v = phi31_d2(sqdist(dim, px, py, pz, xs[cc], xs[N + cc], dim == 3 ? xs[2 * N + cc] : 0.0), lev[j].delta);
+        }
+        const double* ar = a + cc * c.R;
+        for (int m = 0; m < c.RM; ++m) {
+          const int r = gl + m * c.LR;
+          if (r < c.R) acc[m] += v * ar[r];
+        }
+      }
+    }
+    for (int m = 0; m < c.RM; ++m) {
+      const int r = gl + m * c.LR;
+      if (r >= c.R) continue;
+      const double fi = f[i * c.R + r];
+      const double ri = fi - acc[m];
+      if (rout) rout[i * c.R + r] = ri;
+      prr[m] += ri * ri;
+      pff[m] += fi * fi;
+    }
+  }
+  mr_block_partial(prr, c, sm, rrp, blk);
+  mr_block_partial(pff, c, sm, ffp, blk);
+}
+
+__global__ void __launch_bounds__(kBlock) k_mr_axpy(const float* __restrict__ d, double* __restrict__ a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) a[i] += (double)d[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_mr_to_f32(const double* __restrict__ in, float* __restrict__ out,
+                                                      int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+// ------------------------------------------------------------------ driver
+
+namespace {
+
+struct MrWS {
+  MrCfg c{};
+  size_t NR = 0;
+  double *fi = nullptr, *ai = nullptr, *res = nullptr;
+  void *beta = nullptr, *t = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *f32 = nullptr, *a32 = nullptr;
+  double *part_s = nullptr, *part_v = nullptr, *part_v2 = nullptr;
+  MrState* st = nullptr;
+  int32_t* lev_done = nullptr;
+  int32_t* h_lev_done = nullptr;
+  ~MrWS() {
+    for (void* v : {(void*)fi, (void*)ai, (void*)res, beta, t, r, p, q, f32, a32, (void*)part_s, (void*)part_v,
+                    (void*)part_v2, (void*)st, (void*)lev_done})
+      (void)hipFree(v);
+    if (h_lev_done) (void)hipHostFree(h_lev_done);
+  }
+};
+
+struct MrStats {
+  int64_t iters_total = 0;
+  std::vector<int32_t> last_iters;
+  bool capped = false;
+};
+
+template <typename TV, typename TX>
+mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>& on, const TX* b, TX* x, double rtol,
+                  int maxit, int K, MrStats* ms) {
+  hipStream_t s = h->ctx->stream;
+  const MrCfg c = W.c;
+  const WorkTable& ws = h->wt_spmv;
+  const WorkTable& wv = h->wt_vec;
+  int lo = 0, hi = h->L - 1;
+  while (lo < h->L && !on[lo]) ++lo;
+  while (hi >= 0 && !on[hi]) --hi;
+  if (lo > hi) return MSKM_OK;
+  std::vector<MrState> hs((size_t)h->L * c.R);
+  for (int l = 0; l < h->L; ++l)
+    for (int r = 0; r < c.R; ++r) {
+      MrState& S = hs[(size_t)l * c.R + r];
+      std::memset(&S, 0, sizeof(S));
+      S.rtol2 = rtol * rtol;
+      S.maxit = maxit;
+      S.on = on[l] ? 1 : 0;
+      S.done = 1;
+    }
+  MSKM_HIP_TRY(hipMemcpyAsync(W.st, hs.data(), hs.size() * sizeof(MrState), hipMemcpyHostToDevice, s));
+  std::vector<int32_t> ld(h->L, 1);
+  MSKM_HIP_TRY(hipMemcpyAsync(W.lev_done, ld.data(), h->L * 4, hipMemcpyHostToDevice, s));
+  const int nlev = hi - lo + 1;
+  const int sb0 = ws.h_lev_begin[lo], sbn = ws.h_lev_begin[hi + 1] - sb0;
+  const int vb0 = wv.h_lev_begin[lo], vbn = wv.h_lev_begin[hi + 1] - vb0;
+  TX* r = (TX*)W.r;
+  TX* p = (TX*)W.p;
+  TX* q = (TX*)W.q;
+  if (vbn > 0)
+    hipLaunchKernelGGL(k_mr_init<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, b, x, r, p, W.st, W.part_v, c);
+  hipLaunchKernelGGL(k_mr_red_init, dim3(nlev), dim3(kBlock), 0, s, lo, wv.lev_begin, W.part_v, W.st, W.lev_done, c);
+  for (int it = 0; it < maxit; it += K) {
+    for (int kk = 0; kk < K; ++kk) {
+      if (vbn > 0)
+        hipLaunchKernelGGL(k_mr_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, r, p, W.st, W.lev_done, c);
+      if (sbn > 0)
+        hipLaunchKernelGGL((k_mr_cg_spmm<TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, h->diag.rowptr, h->diag.col,
+                           dval, p, q, W.lev_done, W.part_s, c);
+      hipLaunchKernelGGL(k_mr_red_a, dim3(nlev), dim3(kBlock), 0, s, lo, ws.lev_begin, W.part_s, W.st, W.lev_done, c);
+      if (vbn > 0)
+        hipLaunchKernelGGL(k_mr_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p, q, W.st, W.lev_done,
+                           W.part_v, c);
+      hipLaunchKernelGGL(k_mr_red_b, dim3(nlev), dim3(kBlock), 0, s, lo, wv.lev_begin, W.part_v, W.st, W.lev_done, c);
+    }
+    MSKM_HIP_TRY(hipMemcpyAsync(W.h_lev_done, W.lev_done, h->L * 4, hipMemcpyDeviceToHost, s));
+    MSKM_HIP_TRY(hipStreamSynchronize(s));
+    bool any = false;
+    for (int l = lo; l <= hi; ++l) any |= on[l] && !W.h_lev_done[l];
+    if (!any) break;
+  }
+  MSKM_HIP_TRY(hipGetLastError());
+  MSKM_HIP_TRY(hipMemcpy(hs.data(), W.st, hs.size() * sizeof(MrState), hipMemcpyDeviceToHost));
+  for (int l = lo; l <= hi; ++l) {
+    if (!on[l]) continue;
+    int32_t mx = 0;
+    for (int r2 = 0; r2 < c.R; ++r2) {
+      const MrState& S = hs[(size_t)l * c.R + r2];
+      ms->iters_total += S.iters;
+      mx = std::max(mx, S.iters);
+      if (S.capped || !S.done) ms->capped = true;
+    }
+    ms->last_iters[l] = mx;
+  }
+  return MSKM_OK;
+}
+
+template <typename TV, typename TX>
+void mr_lower(mskm_hier* h, const TV* lval, const TX* t, const TX* f, TX* y, int64_t r0, int64_t r1, const MrCfg& c) {
+  if (r1 <= r0) return;
+  hipLaunchKernelGGL((k_mr_spmm<TV, TX>), dim3(mr_nblk(r1 - r0, kBlock / c.LR)), dim3(kBlock), 0, h->ctx->stream,
+                     h->lower.rowptr, h->lower.col, lval, t, f, y, (TX)-1, r0, r1, c);
+}
+
+template <typename TV, typename TX>
+mskm_status mr_solve_internal(mskm_hier* h, MrWS& W, const TV* dval, const TV* lval, const TX* f, TX* alpha,
+                              const mskm_solve_opts* o, int* sweeps_done, MrStats* ms) {
+  hipStream_t s = h->ctx->stream;
+  const MrCfg c = W.c;
+  const int L = h->L;
+  TX* beta = (TX*)W.beta;
+  TX* t = (TX*)W.t;
+  const size_t NR = W.NR;
+  const int maxit = o->max_cg_iters > 0 ? o->max_cg_iters : 20000;
+  const int K = o->check_every > 0 ? o->check_every : 8;
+  std::vector<char> on(L, 0);
+  if (o->algorithm == MSKM_ALG_SEQUENTIAL) {
+    MSKM_HIP_TRY(hipMemsetAsync(alpha, 0, NR * sizeof(TX), s));
+    const int D = (int)h->h_depth_begin.size() - 1;
+    for (int d = 0; d < D; ++d) {
+      const int l0 = h->h_depth_begin[d], l1 = h->h_depth_begin[d + 1];
+      mr_lower<TV, TX>(h, lval, alpha, f, beta, h->h_off[l0], h->h_off[l1], c);
+      std::fill(on.begin(), on.end(), 0);
+      for (int l = l0; l < l1; ++l) on[l] = 1;
+      MSKM_TRY((mr_cg<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, K, ms)));
+    }
+    *sweeps_done = 0;
+    return MSKM_OK;
+  }
+  int Lmax = 0;
+  for (int g = 0; g < h->ngroups; ++g) Lmax = std::max(Lmax, (int)h->h_group_levels[g]);
+  const int S = o->sweeps > 0 ? o->sweeps : Lmax;
+  MSKM_HIP_TRY(hipMemcpyAsync(beta, f, NR * sizeof(TX), hipMemcpyDeviceToDevice, s));
+  for (int l = 0; l < L; ++l) on[l] = h->h_next[l] >= 0;
+  for (int sw = 0; sw < S && Lmax > 1; ++sw) {
+    MSKM_TRY((mr_cg<TV, TX>(h, W, dval, on, beta, t, o->cg_rtol, maxit, K, ms)));
+    mr_lower<TV, TX>(h, lval, t, f, beta, 0, h->N, c);
+    *sweeps_done = sw + 1;
+  }
+  std::fill(on.begin(), on.end(), 1);
+  MSKM_TRY((mr_cg<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, K, ms)));
+  return MSKM_OK;
+}
+
+// Per-rhs, per-group relative residuals (host rel[R][ngroups]); rout nullable.
+mskm_status mr_residual(mskm_hier* h, MrWS& W, const double* a, const double* f, double* rout, std::vector<double>& rel) {
+  hipStream_t s = h->ctx->stream;
+  const MrCfg c = W.c;
+  const WorkTable& wt = h->wt_spmv;
+  hipLaunchKernelGGL(k_mr_residual, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->dim, h->d_lev, h->xs, h->N,
+                     h->diag.rowptr, h->diag.col, h->diag.val, h->lower.rowptr, h->lower.col, h->lower.val, a, f, rout,
+                     W.part_s, W.part_v2, c);
+  std::vector<double> prr((size_t)wt.nblocks * c.R), pff((size_t)wt.nblocks * c.R);
+  MSKM_HIP_TRY(hipMemcpyAsync(prr.data(), W.part_s, prr.size() * 8, hipMemcpyDeviceToHost, s));
+  MSKM_HIP_TRY(hipMemcpyAsync(pff.data(), W.part_v2, pff.size() * 8, hipMemcpyDeviceToHost, s));
+  MSKM_HIP_TRY(hipStreamSynchronize(s));
+  rel.assign((size_t)c.R * h->ngroups, 0.0);
+  std::vector<double> rr((size_t)c.R * h->ngroups, 0.0), ff((size_t)c.R * h->ngroups, 0.0);
+  for (int l = 0; l < h->L; ++l) {
+    const int g = h->h_group[l];
+    for (int b = wt.h_lev_begin[l]; b < wt.h_lev_begin[l + 1]; ++b)
+      for (int r = 0; r < c.R; ++r) {
+        rr[(size_t)r * h->ngroups + g] += prr[(size_t)b * c.R + r];
+        ff[(size_t)r * h->ngroups + g] += pff[(size_t)b * c.R + r];
+      }
+  }
+  for (size_t i = 0; i < rel.size(); ++i) rel[i] = ff[i] > 0.0 ? std::sqrt(rr[i] / ff[i]) : std::sqrt(rr[i]);
+  return MSKM_OK;
+}
+
+}  // namespace
+
+bool mr_supported(int nrhs) { return nrhs >= 2 && nrhs <= 64 * kMaxRPerLane; }
+
+// Multi-rhs solve: f, alpha [N][nrhs] (input order; device if io_dev).
+mskm_status solve_multi(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_opts* o, double* alpha_out,
+                        mskm_report* rep) {
+  hipStream_t s = h->ctx->stream;
+  const bool io_dev = (o->flags & MSKM_IO_DEVICE) != 0;
+  const bool mixed = o->precision == MSKM_PREC_FP32;
+  if (mixed ? !h->diag.val32 : !h->diag.val) return fail(MSKM_ESTATE, "requested precision's values are not stored");
+  MrWS W;
+  W.c = mr_cfg(nrhs);
+  W.NR = (size_t)h->N * nrhs;
+  const size_t NR = W.NR;
+  for (double** v : {&W.fi, &W.ai}) MSKM_TRY(dalloc(v, NR));
+  if (mixed) MSKM_TRY(dalloc(&W.res, NR));
+  const size_t xs = mixed ? 4 : 8;
+  for (void** v : {&W.beta, &W.t, &W.r, &W.p, &W.q}) MSKM_TRY(dalloc(reinterpret_cast<char**>(v), NR * xs));
+  if (mixed) {
+    MSKM_TRY(dalloc(reinterpret_cast<float**>(&W.f32), NR));
+    MSKM_TRY(dalloc(reinterpret_cast<float**>(&W.a32), NR));
+  }
+  const size_t nbp = (size_t)std::max(h->wt_spmv.nblocks, h->wt_vec.nblocks) * nrhs;
+  MSKM_TRY(dalloc(&W.part_s, nbp));
+  MSKM_TRY(dalloc(&W.part_v, nbp));
+  MSKM_TRY(dalloc(&W.part_v2, nbp));
+  MSKM_TRY(dalloc(&W.st, (size_t)h->L * nrhs));
+  MSKM_TRY(dalloc(&W.lev_done, h->L));
+  MSKM_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&W.h_lev_done), h->L * 4, hipHostMallocDefault));
+  const double* fdev = f_in;
+  double* fstage = nullptr;
+  if (!io_dev) {
+    MSKM_TRY(dalloc(&fstage, NR));
+    MSKM_HIP_TRY(hipMemcpyAsync(fstage, f_in, NR * 8, hipMemcpyHostToDevice, s));
+    fdev = fstage;
+  }
+  MrStats ms;
+  ms.last_iters.assign(h->L, 0);
+  int sweeps_done = 0, refine = 0;
+  std::vector<double> rel;
+  MSKM_HIP_TRY(hipEventRecord(h->ctx->ev0, s));
+  hipLaunchKernelGGL(k_mr_to_internal<double>, dim3(mr_nblk(NR, kBlock)), dim3(kBlock), 0, s, fdev, h->perm, W.fi, h->N,
+                     nrhs);
+  mskm_status st = MSKM_OK;
+  if (!mixed) {
+    st = mr_solve_internal<double, double>(h, W, h->diag.val, h->lower.val, W.fi, W.ai, o, &sweeps_done, &ms);
+    if (st == MSKM_OK) st = mr_residual(h, W, W.ai, W.fi, nullptr, rel);
+  } else {
+    const int maxref = o->max_refine > 0 ? o->max_refine : 10;
+    MSKM_HIP_TRY(hipMemsetAsync(W.ai, 0, NR * 8, s));
+    for (;;) {
+      st = mr_residual(h, W, W.ai, W.fi, W.res, rel);
+      if (st != MSKM_OK) break;
+      const double worst = *std::max_element(rel.begin(), rel.end());
+      if (worst <= o->target_rel_residual || refine >= maxref) break;
+      hipLaunchKernelGGL(k_mr_to_f32, dim3(mr_nblk(NR, kBlock)), dim3(kBlock), 0, s, W.res, (float*)W.f32, (int64_t)NR);
+      mskm_solve_opts oi = *o;
+      if (refine > 0) oi.cg_rtol = std::min(0.1, std::max(o->cg_rtol, 0.5 * o->target_rel_residual / worst));
+      st = mr_solve_internal<float, float>(h, W, h->diag.val32, h->lower.val32, (const float*)W.f32, (float*)W.a32, &oi,
+                                           &sweeps_done, &ms);
+      if (st != MSKM_OK) break;
+      hipLaunchKernelGGL(k_mr_axpy, dim3(mr_nblk(NR, kBlock)), dim3(kBlock), 0, s, (const float*)W.a32, W.ai,
+                         (int64_t)NR);
+      ++refine;
+    }
+  }
+  if (st == MSKM_OK) {
+    double* adev = alpha_out;
+    double* astage = nullptr;
+    if (!io_dev) st = dalloc(&astage, NR), adev = astage;
+    if (st == MSKM_OK) {
+      hipLaunchKernelGGL(k_mr_to_input<double>, dim3(mr_nblk(NR, kBlock)), dim3(kBlock), 0, s, (const double*)W.ai,
+                         h->perm, adev, h->N, nrhs);
+      if (hipEventRecord(h->ctx->ev1, s) != hipSuccess) st = fail(MSKM_EDEVICE, "event");
+      if (st == MSKM_OK && !io_dev &&
+          hipMemcpyAsync(alpha_out, astage, NR * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = fail(MSKM_EDEVICE, "alpha copy");
+      if (st == MSKM_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(MSKM_EDEVICE, "sync");
+    }
+    (void)hipFree(astage);
+  }
+  (void)hipFree(fstage);
+  MSKM_TRY(st);
+  float msec = 0.f;
+  MSKM_HIP_TRY(hipEventElapsedTime(&msec, h->ctx->ev0, h->ctx->ev1));
+  const double worst = rel.empty() ? 0.0 : *std::max_element(rel.begin(), rel.end());
+  const bool enoconv = mixed ? worst > o->target_rel_residual : ms.capped;
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->levels = h->L;
+    rep->sweeps_done = sweeps_done;
+    rep->refine_steps = refine;
+    rep->cg_iters_total = ms.iters_total;
+    for (int l = 0; l < std::min(h->L, 64); ++l) rep->cg_iters_last[l] = ms.last_iters[l];
+    rep->rel_residual = worst;
+    rep->solve_ms = msec;
+  }
+  MSKM_HIP_TRY(hipGetLastError());
+  return enoconv ? MSKM_ENOCONV : MSKM_OK;
+}
+
+}  // namespace mskm

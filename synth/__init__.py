@@ -42,6 +42,7 @@ __all__ = [
     "franke",
     "gauss_sine",
     "config_hierarchy",
+    "batch_hierarchies",
     "NU_2D_40",
     "NU_3D_60",
 ]
@@ -264,6 +265,27 @@ def gauss_sine(x: np.ndarray) -> np.ndarray:
     X, Y = x[:, 0], x[:, 1]
     return (np.exp(-((X - 0.5) ** 2 + (Y - 0.5) ** 2) / 0.1)
             + np.sin(2 * math.pi * X) * np.cos(2 * math.pi * Y))
+
+
+def batch_hierarchies(count: int = 64, seed: int = 4000, n_min: int = 10_000, n_max: int = 200_000,
+                      levels_choice=(5, 6, 7)) -> list[tuple[Hierarchy, np.ndarray]]:
+    """Independent 2-D Halton hierarchies of uneven sizes.
+
+    Hierarchy h starts its Halton run at index 1 + 10^6 h, has L_h levels drawn
+    from ``levels_choice`` and a top level of N_top,h points drawn uniformly
+    in [n_min, n_max]; level l holds ceil(N_top,h * 4^(l - L_h + 1)) points
+    (prefix-nested), delta_l = sqrt(40/pi) * N_l^(-1/2). Its target is the
+    32-mode Fourier sum with seed ``seed + h``. Draws use SplitMix64(seed).
+    """
+    u = uniform01(seed, 0, 2 * count).reshape(count, 2)
+    out = []
+    for h in range(count):
+        L = int(levels_choice[min(int(u[h, 0] * len(levels_choice)), len(levels_choice) - 1)])
+        ntop = int(n_min + math.floor(u[h, 1] * (n_max - n_min + 1)))
+        sizes = [int(math.ceil(ntop * 4.0 ** (l - L + 1))) for l in range(L)]
+        hh = halton_hierarchy(sizes=sizes, start=1 + 1_000_000 * h)
+        out.append((hh, fourier_target(seed + h, 2)(hh.points)))
+    return out
 
 
 def config_hierarchy(name: str, levels: int | None = None) -> tuple[Hierarchy, np.ndarray]:
