@@ -101,6 +101,82 @@ def cpu_baseline(levels_sample: int, rtol: float):
             "n_points": h.n_total, "levels": h.levels}
 
 
+def batched(m, ctx, hd, h, pts_dev, dev, fast_opts, rt_fast, nrhs, count):
+    """Many right-hand sides on the bench hierarchy and many independent
+    uneven hierarchies, each solved in shared launches (fast form)."""
+    import torch
+
+    import synth
+
+    out = {}
+    if nrhs > 1:
+        log(f"batched: {nrhs} right-hand sides")
+        F = torch.stack([synth.fourier_target(3000 + r).torch_eval(pts_dev) for r in range(nrhs)], dim=1).contiguous()
+        A = torch.zeros_like(F)
+        o = m.solve_opts(cg_rtol=rt_fast, **fast_opts)
+        m.mskm_solve(ctx, hd, F, A, o, nrhs=nrhs)  # warm-up (allocations, code objects)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = m.mskm_solve(ctx, hd, F, A, o, nrhs=nrhs)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        rel = m.mskm_residual(ctx, hd, A, F, nrhs=nrhs)
+        out["multi_rhs"] = {"nrhs": nrhs, "time_to_1e-8_ms": round(wall, 2), "ms_per_rhs": round(wall / nrhs, 3),
+                            "max_rel_residual": float(rel.max()), "status": res.status,
+                            "cg_iters_total": res.report["cg_iters_total"], "refine": res.report["refine_steps"]}
+        log("multi_rhs", out["multi_rhs"])
+        del F, A
+        torch.cuda.empty_cache()
+    if count > 0:
+        log(f"batched: {count} hierarchies")
+        hs = synth.batch_hierarchies(count)
+        f = np.concatenate([fb for _, fb in hs])
+        f_dev = torch.from_numpy(f).to(dev)
+        a_dev = torch.zeros_like(f_dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hb = m.mskm_hier_create_batch(ctx, [(hh.points, hh.offsets, hh.delta) for hh, _ in hs], fp64=False, fp32=True)
+        torch.cuda.synchronize()
+        t_asm = (time.perf_counter() - t0) * 1e3
+        st = m.mskm_hier_stats_get(hb)
+        o = m.solve_opts(cg_rtol=rt_fast, **fast_opts)
+        m.mskm_solve(ctx, hb, f_dev, a_dev, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = m.mskm_solve(ctx, hb, f_dev, a_dev, o)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        rel = m.mskm_residual(ctx, hb, a_dev, f_dev)
+        out["multi_hierarchy"] = {"hierarchies": count, "n_points": st["n_total"], "levels": st["levels"],
+                                  "nnz": st["nnz_diag"] + st["nnz_lower"], "assemble_ms": round(t_asm, 2),
+                                  "time_to_1e-8_ms": round(wall, 2), "max_rel_residual": float(rel.max()),
+                                  "status": res.status, "cg_iters_total": res.report["cg_iters_total"]}
+        log("multi_hierarchy", out["multi_hierarchy"])
+        m.mskm_hier_destroy(hb)
+    return out
+
+
+def train_warm_start(m, ctx, args):
+    """Train the warm-start network on (rhs -> correction) pairs from plain
+    solves of a 6-level Halton hierarchy with random Fourier targets."""
+    import synth
+
+    h6 = synth.halton_hierarchy(6)
+    ntr = args.train_rhs
+    F = np.ascontiguousarray(np.stack([synth.fourier_target(5000 + r)(h6.points) for r in range(ntr)], axis=1))
+    h6d = m.mskm_hier_create(ctx, h6.points, h6.offsets, h6.delta, fp64=True, fp32=False)
+    t0 = time.perf_counter()
+    net, loss = m.mskm_mlp_train(ctx, h6d, F, nrhs=ntr, samples=args.train_samples, steps=args.train_steps, lr=1e-3,
+                                 seed=5000, cg_rtol=1e-10)
+    train_ms = (time.perf_counter() - t0) * 1e3
+    m.mskm_hier_destroy(h6d)
+    info = {"train_hierarchy": f"halton2d_L6 ({h6.n_total} points)", "train_rhs": ntr,
+            "samples": args.train_samples, "steps": args.train_steps, "train_ms": round(train_ms, 1),
+            "loss_first": float(loss[0]), "loss_last": float(loss[-1])}
+    log("warm start trained", info)
+    return net, info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +187,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=6)
     ap.add_argument("--nq", type=int, default=65536)
+    ap.add_argument("--rhs", type=int, default=256, help="right-hand sides of the batched solve (0: skip)")
+    ap.add_argument("--train-rhs", type=int, default=16)
+    ap.add_argument("--train-samples", type=int, default=10000)
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--spmv-only", action="store_true",
+                    help="assemble, autotune, then only time the FP64 full-T SpMV and a 1 GiB device copy "
+                         "(the counter-collection runs)")
+    ap.add_argument("--batch-count", type=int, default=64, help="hierarchies of the batched solve (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -136,6 +221,28 @@ def main():
 
     # ---- calibration of the tolerances (untimed)
     hd = m.mskm_hier_create(ctx, pts_dev, h.offsets, h.delta, fp64=True, fp32=True)
+    if args.spmv_only:
+        st = m.mskm_hier_stats_get(hd)
+        m.mskm_autotune(ctx, hd, repeats=3)
+        x = torch.randn(N, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        ms = m.mskm_apply_internal(ctx, hd, m.MSKM_OP_FULL, x, y, repeats=args.spmv_repeats)
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.spmv_repeats):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        b = spmv_bytes(st["nnz_diag"] + st["nnz_lower"], N, 2, 8, 8)
+        print(json.dumps({"spmv_full_fp64_ms": ms, "spmv_bytes": b, "spmv_GBps": b / ms / 1e6,
+                          "variant": m.mskm_spmv_width(hd, m.MSKM_OP_FULL, 0),
+                          "copy_bytes_each_way": 1 << 30, "copy_ms": e0.elapsed_time(e1) / args.spmv_repeats}))
+        m.mskm_hier_destroy(hd)
+        m.mskm_destroy(ctx)
+        return
     stats = m.mskm_hier_stats_get(hd)
     log("hierarchy", stats)
     tune = m.mskm_autotune(ctx, hd, repeats=5)
@@ -146,6 +253,33 @@ def main():
                      max_refine=8)
     plain_opts = dict(precision=m.MSKM_PREC_FP64, algorithm=m.MSKM_ALG_MONOLITHIC)
     rt_fast = calibrate(m, ctx, hd, f_dev, alpha_dev, fast_opts, "fast")
+    learned = None
+    if not args.no_learned:
+        net, tinfo = train_warm_start(m, ctx, args)
+        # held-out target (seed 6000) on the bench hierarchy: with vs without warm start
+        import synth
+
+        f_ho = torch.from_numpy(synth.fourier_target(6000)(h.points)).to(dev)
+        cmp = {}
+        for label, extra in (("zero_start", {}), ("learned_start", {"precond": m.MSKM_PRECOND_LEARNED,
+                                                                     "mlp": net.value})):
+            o = m.solve_opts(cg_rtol=rt_fast, **fast_opts, **extra)
+            m.mskm_solve(ctx, hd, f_ho, alpha_dev, o)
+            ts = []
+            for _ in range(2):
+                r = m.mskm_solve(ctx, hd, f_ho, alpha_dev, o)
+                ts.append(r.report["solve_ms"])
+            rel = float(m.mskm_residual(ctx, hd, alpha_dev, f_ho)[0])
+            cmp[label] = {"time_to_1e-8_ms": round(float(np.median(ts)), 3), "rel_residual": rel,
+                          "cg_iters_total": r.report["cg_iters_total"], "warm_fallbacks": r.report["warm_fallbacks"],
+                          "status": r.status}
+        learned = {**tinfo, "held_out_seed": 6000, **cmp}
+        log("learned", learned)
+        use = (cmp["learned_start"]["time_to_1e-8_ms"] < cmp["zero_start"]["time_to_1e-8_ms"]
+               and cmp["learned_start"]["rel_residual"] <= TARGET)
+        learned["used_in_fast_form"] = bool(use)
+        if use:
+            fast_opts = dict(fast_opts, precond=m.MSKM_PRECOND_LEARNED, mlp=net.value)
     fast = m.solve_opts(cg_rtol=rt_fast, **fast_opts)
 
     def step():
@@ -216,6 +350,7 @@ def main():
         b = spmv_bytes(nnz, N, nrp, sval, sx)
         spmv[name] = {"ms": ms, "bytes": b, "GBps": b / ms / 1e6}
     log("spmv", spmv)
+    bt = batched(m, ctx, hd, h, pts_dev, dev, fast_opts, rt_fast, args.rhs, args.batch_count)
     m.mskm_hier_destroy(hd)
     m.mskm_destroy(ctx)
 
@@ -236,7 +371,9 @@ def main():
         "config": {"workload": f"halton2d_L{args.levels}", "n_points": N, "levels": args.levels,
                    "nnz": nnz_d + nnz_l, "kernel": "wendland_3_1", "neighbours_per_row": 40,
                    "target": "fourier32_seed1000", "parallelism": "single_gpu"},
-        "fast_form": {"name": "mixed FP32/FP64-refined, block forward substitution", "cg_rtol": rt_fast,
+        "fast_form": {"name": "mixed FP32/FP64-refined, block forward substitution"
+                      + (", learned warm start" if learned and learned.get("used_in_fast_form") else ""),
+                      "cg_rtol": rt_fast,
                       "time_to_1e-8_ms": round(fast_ms, 3), "steps": steps},
         "plain_fp64_jacobi": {"cg_rtol": rt_plain, "time_to_1e-8_ms": round(plain_ms, 3),
                               "rel_residual": plain_rel, "sweeps": h.levels,
@@ -245,6 +382,8 @@ def main():
         "speedup_vs_plain_fp64": round(plain_ms / fast_ms, 3),
         "spmv": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
                  for k, v in spmv.items()},
+        "batched": bt,
+        "learned": learned,
         "spmv_GBps": round(dom["GBps"], 1),
         "spmv_widths": widths,
         "roofline": {"bound": "hbm", "achieved": round(dom["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -207,13 +207,13 @@ mskm_status mskm_apply_internal(mskm_ctx* ctx, const mskm_hier* h, int32_t op, i
                                 int32_t repeats, float* avg_ms);
 
 /* Autotuner: times every CSR SpMV variant -- lanes per row 4, 8, 16, 32, 64,
- * each with per-entry loads and with 16-byte loads (variant codes w and
- * w + 1000) -- for each operator (DIAG, LOWER, FULL) and each stored
- * precision on this hierarchy's own blocks (`repeats` >= 1 timed launches
- * per variant) and keeps the fastest for later apply / solve calls.
- * times_ms (nullable, host, [3][2][10]) receives the mean ms per launch of
- * every [op][precision][variant] (order 4..64 then 4+1000..64+1000; 0 where
- * a precision is not stored).
+ * each with per-entry loads, 16-byte loads and 16-byte non-temporal loads
+ * (variant codes w, w + 1000, w + 2000) -- for each operator (DIAG, LOWER,
+ * FULL) and each stored precision on this hierarchy's own blocks (`repeats`
+ * >= 1 timed launches per variant) and keeps the fastest for later apply /
+ * solve calls. times_ms (nullable, host, [3][2][15]) receives the mean ms
+ * per launch of every [op][precision][variant] in that order (0 where a
+ * precision is not stored).
  * The choice is also remembered by the context: hierarchies created later
  * on it with the same dimension, level count, point count and nonzero
  * counts start with the tuned widths. */
@@ -281,6 +281,56 @@ mskm_status mskm_residual(mskm_ctx* ctx, const mskm_hier* h, const double* alpha
  * query: [nq][dim]; out: [nq][nrhs]. */
 mskm_status mskm_evaluate(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, int32_t nrhs, const double* query,
                           int64_t nq, double* out, int32_t flags);
+
+/* --------------------------------------------------------- learned warm start
+ *
+ * Not part of the paper (its CG starts from zero): a per-point network that
+ * predicts each level's CG solution from that level's right-hand side b.
+ * For point i of level l, with n_1..n_16 its 16 nearest other points of the
+ * level (exact, squared FP64 distance, ties by input index; padded with i on
+ * levels of fewer than 17 points):
+ *   s_i  = sqrt(mean of b^2 over {i, n_1..n_16})
+ *   feat = [b_i/s, (b_{n_m}/s, (x_{n_m} - x_i)/delta_l) for m = 1..16],
+ *          zero-padded to a multiple of 8 (56 values in 2-D, 72 in 3-D)
+ *   x0_i = s_i * (w2 . relu(W1 feat + b1) + b2), 64 hidden units; x0_i = 0
+ *          where s_i = 0.
+ * The first layer runs on BF16 MFMA with FP32 accumulation. CG starts from
+ * x0 and remains the judge: a level with ||b - A x0|| >= ||b|| restarts from
+ * zero (counted in mskm_report.warm_fallbacks). */
+typedef struct {
+  const mskm_hier* h;  /* hierarchy whose solves generate the training pairs */
+  const double* f;     /* [N][nrhs] training right-hand sides (input order) */
+  int32_t nrhs;        /* >= 1 */
+  int64_t samples;     /* per-point (stencil -> correction / s) samples drawn, spread over the rhs */
+  int32_t steps;       /* Adam steps, mini-batch 128 */
+  float lr;            /* Adam step size (e.g. 1e-3) */
+  uint64_t seed;       /* initial weights and sample positions */
+  double cg_rtol;      /* tolerance of the plain FP64 solves that produce the pairs */
+  int32_t flags;       /* MSKM_IO_DEVICE: f is a device pointer */
+} mskm_train_desc;
+
+/* Trains a network on pairs the method itself generates: each rhs is solved
+ * by the plain FP64 sequential algorithm; level l contributes the pair
+ * (b_l = f_l - sum_{k<l} B_{l,k} alpha_k, alpha_l). Sample points are drawn
+ * uniformly over all points (SplitMix64(seed)). loss_log (nullable, host)
+ * receives the mini-batch MSE (before the update) of steps 0, 50, 100, ...:
+ * ceil(steps / 50) floats. */
+mskm_status mskm_mlp_train(mskm_ctx* ctx, const mskm_train_desc* desc, mskm_mlp** out, float* loss_log);
+mskm_status mskm_mlp_destroy(mskm_mlp* m);
+
+/* Versioned weight blob (little endian): "MSKMMLP1", int32 dim, int32 F,
+ * int32 hidden (64), then W1, b1, w2, b2 as float32. blob == NULL: *size
+ * receives the byte count. */
+mskm_status mskm_mlp_save(const mskm_mlp* m, void* blob, size_t* size);
+mskm_status mskm_mlp_load(mskm_ctx* ctx, const void* blob, size_t size, mskm_mlp** out);
+
+/* x0 = network prediction for b on every level (b, x0: [N] input order). */
+mskm_status mskm_mlp_predict(mskm_ctx* ctx, const mskm_hier* h, const mskm_mlp* m, const double* b, double* x0,
+                             int32_t flags);
+
+/* The 16 nearest same-level points of every point of `level`, as indices
+ * within the level's input order: out [n][16] (host). */
+mskm_status mskm_knn_export(mskm_ctx* ctx, const mskm_hier* h, int32_t level, int32_t* out);
 
 #ifdef __cplusplus
 }

@@ -40,6 +40,7 @@ EXPORTED = [
     "mskm_export_block", "mskm_export_rows", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
     "mskm_autotune", "mskm_spmv_width",
     "mskm_solve_opts_default", "mskm_solve", "mskm_residual", "mskm_evaluate",
+    "mskm_mlp_train", "mskm_mlp_destroy", "mskm_mlp_save", "mskm_mlp_load", "mskm_mlp_predict", "mskm_knn_export",
 ]
 
 
@@ -83,6 +84,12 @@ class Report(C.Structure):
                 ("solve_ms", C.c_double), ("warm_fallbacks", C.c_int32)]
 
 
+class TrainDesc(C.Structure):
+    _fields_ = [("h", C.c_void_p), ("f", C.c_void_p), ("nrhs", C.c_int32), ("samples", C.c_int64),
+                ("steps", C.c_int32), ("lr", C.c_float), ("seed", C.c_uint64), ("cg_rtol", C.c_double),
+                ("flags", C.c_int32)]
+
+
 _lib = None
 
 
@@ -117,6 +124,12 @@ def lib():
     L.mskm_solve.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(Report)]
     L.mskm_residual.argtypes = [vp, vp, vp, vp, i32, dp, i32]
     L.mskm_evaluate.argtypes = [vp, vp, vp, i32, vp, i64, vp, i32]
+    L.mskm_mlp_train.argtypes = [vp, C.POINTER(TrainDesc), C.POINTER(vp), C.POINTER(C.c_float)]
+    L.mskm_mlp_destroy.argtypes = [vp]
+    L.mskm_mlp_save.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+    L.mskm_mlp_load.argtypes = [vp, vp, C.c_size_t, C.POINTER(vp)]
+    L.mskm_mlp_predict.argtypes = [vp, vp, vp, vp, vp, i32]
+    L.mskm_knn_export.argtypes = [vp, vp, i32, vp]
     for name in EXPORTED:
         if name not in ("mskm_last_error", "mskm_abi_version", "mskm_solve_opts_default"):
             getattr(L, name).restype = i32
@@ -292,15 +305,15 @@ def mskm_apply_internal(ctx, h, op: int, x, y, prec: int = MSKM_PREC_FP64, repea
     return float(ms.value)
 
 
-TUNE_VARIANTS = [4, 8, 16, 32, 64, 1004, 1008, 1016, 1032, 1064]
+TUNE_VARIANTS = [4, 8, 16, 32, 64, 1004, 1008, 1016, 1032, 1064, 2004, 2008, 2016, 2032, 2064]
 
 
 def mskm_autotune(ctx, h, repeats: int = 5) -> np.ndarray:
     """Pick the fastest SpMV variant per operator/precision; returns the
-    [3][2][10] table of mean ms per launch (op, precision, TUNE_VARIANTS)."""
-    t = np.zeros(60, dtype=np.float32)
+    [3][2][15] table of mean ms per launch (op, precision, TUNE_VARIANTS)."""
+    t = np.zeros(3 * 2 * len(TUNE_VARIANTS), dtype=np.float32)
     _check(lib().mskm_autotune(ctx, h, repeats, t.ctypes.data_as(C.POINTER(C.c_float))), "mskm_autotune")
-    return t.reshape(3, 2, 10)
+    return t.reshape(3, 2, len(TUNE_VARIANTS))
 
 
 def mskm_spmv_width(h, op: int, prec: int = MSKM_PREC_FP64) -> int:
@@ -367,3 +380,61 @@ def mskm_evaluate(ctx, h, alpha, query, out, nrhs: int = 1) -> None:
         raise ValueError("alpha, query and out must all be host or all be device arrays")
     nq = int(query.shape[0])
     _check(lib().mskm_evaluate(ctx, h, ap, nrhs, qp, nq, op, MSKM_IO_DEVICE if ad else 0), "mskm_evaluate")
+
+
+# ------------------------------------------------------- learned warm start
+
+def mskm_mlp_train(ctx, h, f, nrhs: int, samples: int = 20000, steps: int = 2000, lr: float = 1e-3,
+                   seed: int = 5000, cg_rtol: float = 1e-10):
+    """Train the warm-start network on pairs from plain solves of f [N][nrhs];
+    returns (mlp handle, loss log every 50 steps)."""
+    fp, fd = _ptr(f, np.float64)
+    d = TrainDesc(h.value if isinstance(h, C.c_void_p) else h, fp.value, nrhs, samples, steps, lr, seed, cg_rtol,
+                  MSKM_IO_DEVICE if fd else 0)
+    out = C.c_void_p()
+    log = np.zeros((steps + 49) // 50, dtype=np.float32)
+    _check(lib().mskm_mlp_train(ctx, C.byref(d), C.byref(out), log.ctypes.data_as(C.POINTER(C.c_float))),
+           "mskm_mlp_train")
+    return out, log
+
+
+def mskm_mlp_destroy(m) -> None:
+    lib().mskm_mlp_destroy(m)
+
+
+def mskm_mlp_save(m) -> bytes:
+    n = C.c_size_t()
+    _check(lib().mskm_mlp_save(m, None, C.byref(n)), "mskm_mlp_save (size)")
+    buf = C.create_string_buffer(n.value)
+    _check(lib().mskm_mlp_save(m, buf, C.byref(n)), "mskm_mlp_save")
+    return buf.raw[: n.value]
+
+
+def mskm_mlp_load(ctx, blob: bytes):
+    out = C.c_void_p()
+    buf = C.create_string_buffer(blob, len(blob))
+    _check(lib().mskm_mlp_load(ctx, buf, len(blob), C.byref(out)), "mskm_mlp_load")
+    return out
+
+
+def mlp_blob(dim: int, W1: np.ndarray, b1: np.ndarray, w2: np.ndarray, b2: float) -> bytes:
+    """Weight blob in the library's MSKMMLP1 layout."""
+    F = W1.shape[1]
+    hdr = np.array([dim, F, W1.shape[0]], dtype=np.int32).tobytes()
+    body = np.concatenate([W1.ravel(), b1, w2, [b2]]).astype(np.float32).tobytes()
+    return b"MSKMMLP1" + hdr + body
+
+
+def mskm_mlp_predict(ctx, h, m, b, x0) -> None:
+    bp, bd = _ptr(b, np.float64)
+    xp, xd = _ptr(x0, np.float64)
+    if bd != xd:
+        raise ValueError("b and x0 must both be host or both be device arrays")
+    _check(lib().mskm_mlp_predict(ctx, h, m, bp, xp, MSKM_IO_DEVICE if bd else 0), "mskm_mlp_predict")
+
+
+def mskm_knn_export(ctx, h, level: int) -> np.ndarray:
+    n = int(mskm_hier_level_info(h, level)["n"])
+    out = np.zeros((max(n, 1), 16), dtype=np.int32)
+    _check(lib().mskm_knn_export(ctx, h, level, C.c_void_p(out.ctypes.data)), "mskm_knn_export")
+    return out[:n]

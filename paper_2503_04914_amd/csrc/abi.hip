@@ -372,4 +372,97 @@ mskm_status mskm_evaluate(mskm_ctx* ctx, const mskm_hier* h, const double* alpha
   return mskm::evaluate(const_cast<mskm_hier*>(h), alpha, nrhs, query, nq, out, (flags & MSKM_IO_DEVICE) != 0);
 }
 
+mskm_status mskm_mlp_train(mskm_ctx* ctx, const mskm_train_desc* d, mskm_mlp** out, float* loss_log) {
+  if (!valid_ctx(ctx) || !d || !out || !d->h || !d->f) return fail(MSKM_EINVAL, "mskm_mlp_train: NULL argument");
+  *out = nullptr;
+  if (d->nrhs < 1 || d->samples < 1 || d->steps < 1 || !(d->lr > 0.0f) || !(d->cg_rtol > 0.0 && d->cg_rtol < 1.0))
+    return fail(MSKM_EINVAL, "mskm_mlp_train: nrhs, samples, steps, lr and cg_rtol must be positive");
+  mskm_hier* h = const_cast<mskm_hier*>(d->h);
+  if (!h->diag.val) return fail(MSKM_ESTATE, "training pairs need FP64 values (MSKM_STORE_FP64)");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  mskm_mlp* m = nullptr;
+  MSKM_TRY(mskm::mlp_new(h->dim, d->seed, &m));
+  std::vector<double*> rhs, alpha;
+  mskm_status st = mskm::train_pairs(h, d->f, d->nrhs, (d->flags & MSKM_IO_DEVICE) != 0, d->cg_rtol, &rhs, &alpha);
+  std::vector<float> log;
+  if (st == MSKM_OK) st = mskm::mlp_train_device(h, m, rhs, alpha, d->samples, d->steps, d->lr, d->seed, &log);
+  for (double* p : rhs) (void)hipFree(p);
+  for (double* p : alpha) (void)hipFree(p);
+  if (st != MSKM_OK) {
+    delete m;
+    return st;
+  }
+  if (loss_log) std::memcpy(loss_log, log.data(), log.size() * sizeof(float));
+  *out = m;
+  return MSKM_OK;
+}
+
+mskm_status mskm_mlp_destroy(mskm_mlp* m) {
+  delete m;
+  return MSKM_OK;
+}
+
+mskm_status mskm_mlp_save(const mskm_mlp* m, void* blob, size_t* size) {
+  if (!m || !size) return fail(MSKM_EINVAL, "mskm_mlp_save: NULL argument");
+  const size_t need = 8 + 3 * 4 + m->params.size() * 4;
+  if (!blob) {
+    *size = need;
+    return MSKM_OK;
+  }
+  if (*size < need) return fail(MSKM_EINVAL, "mskm_mlp_save: blob too small");
+  char* p = static_cast<char*>(blob);
+  std::memcpy(p, "MSKMMLP1", 8);
+  const int32_t hdr[3] = {m->dim, m->F, 64};
+  std::memcpy(p + 8, hdr, 12);
+  std::memcpy(p + 20, m->params.data(), m->params.size() * 4);
+  *size = need;
+  return MSKM_OK;
+}
+
+mskm_status mskm_mlp_load(mskm_ctx* ctx, const void* blob, size_t size, mskm_mlp** out) {
+  if (!valid_ctx(ctx) || !blob || !out) return fail(MSKM_EINVAL, "mskm_mlp_load: NULL argument");
+  *out = nullptr;
+  const char* p = static_cast<const char*>(blob);
+  if (size < 20 || std::memcmp(p, "MSKMMLP1", 8) != 0) return fail(MSKM_EINVAL, "not an MSKMMLP1 blob");
+  int32_t hdr[3];
+  std::memcpy(hdr, p + 8, 12);
+  if ((hdr[0] != 2 && hdr[0] != 3) || hdr[2] != 64 || hdr[1] != ((1 + 16 * (1 + hdr[0])) + 7) / 8 * 8)
+    return fail(MSKM_EINVAL, "unsupported network shape");
+  const size_t P = (size_t)64 * hdr[1] + 2 * 64 + 1;
+  if (size < 20 + P * 4) return fail(MSKM_EINVAL, "truncated blob");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  mskm_mlp* m = nullptr;
+  MSKM_TRY(mskm::mlp_new(hdr[0], 0, &m));
+  std::memcpy(m->params.data(), p + 20, P * 4);
+  for (float v : m->params)
+    if (!std::isfinite(v)) {
+      delete m;
+      return fail(MSKM_EINVAL, "non-finite weight");
+    }
+  mskm_status st = mskm::mlp_upload(m);
+  if (st != MSKM_OK) {
+    delete m;
+    return st;
+  }
+  *out = m;
+  return MSKM_OK;
+}
+
+mskm_status mskm_mlp_predict(mskm_ctx* ctx, const mskm_hier* hc, const mskm_mlp* m, const double* b, double* x0,
+                             int32_t flags) {
+  if (!valid_ctx(ctx) || !hc || !m || !b || !x0) return fail(MSKM_EINVAL, "mskm_mlp_predict: NULL argument");
+  mskm_hier* h = const_cast<mskm_hier*>(hc);
+  if (m->dim != h->dim) return fail(MSKM_EINVAL, "network and hierarchy dimensions differ");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::mlp_predict_all(h, m, b, x0, (flags & MSKM_IO_DEVICE) != 0);
+}
+
+mskm_status mskm_knn_export(mskm_ctx* ctx, const mskm_hier* hc, int32_t level, int32_t* out) {
+  if (!valid_ctx(ctx) || !hc || !out) return fail(MSKM_EINVAL, "mskm_knn_export: NULL argument");
+  if (level < 0 || level >= hc->L) return fail(MSKM_EINVAL, "level out of range");
+  mskm_hier* h = const_cast<mskm_hier*>(hc);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::knn_export(h, level, out);
+}
+
 }  // extern "C"

@@ -28,8 +28,8 @@ namespace mskm {
 constexpr int kMaxLevels = 4096;  // levels of one hierarchy object (all groups of a batch)
 constexpr int kBlock = 256;  // threads per block of every streaming / SpMV kernel
 constexpr int kCsrPad = 16;  // tail pad (entries) of CSR column and value arrays
-constexpr int kVecFlag = 1000;  // SpMV variant code: lanes per row + kVecFlag = 16-byte loads
-constexpr int kTuneVariants = 10;  // widths 4..64, scalar and 16-byte loads
+constexpr int kVecFlag = 1000;  // SpMV variant code: lanes per row (+1000: 16-byte loads, +2000: also non-temporal)
+constexpr int kTuneVariants = 15;  // widths 4..64 x {per-entry, 16-byte, 16-byte non-temporal} loads
 
 // Per-level descriptor read by the kernels (all fields uniform per wave).
 struct DevLevel {
@@ -89,6 +89,19 @@ struct mskm_ctx {
   size_t pinned_bytes = 0;
 };
 
+// Learned warm start network (learned.hip).
+struct mskm_mlp {
+  int32_t dim = 2, F = 56;         // point dimension, padded feature count
+  std::vector<float> params;       // W1 [64][F], b1 [64], w2 [64], b2
+  float* d_params = nullptr;       // device copy (FP32)
+  short* d_w1b = nullptr;          // device W1 in bfloat16
+  int64_t samples = 0;             // training samples used
+  ~mskm_mlp() {
+    (void)hipFree(d_params);
+    (void)hipFree(d_w1b);
+  }
+};
+
 struct mskm_hier {
   mskm_ctx* ctx = nullptr;
   int32_t dim = 0, L = 0;
@@ -114,6 +127,7 @@ struct mskm_hier {
   int64_t device_bytes = 0;
   double assemble_ms = 0.0;
   std::vector<void*> allocs;            // everything to free
+  int32_t* knn = nullptr;               // [N][16] same-level nearest neighbours (learned warm start)
   void* solve_ws = nullptr;             // solver workspace (solve.hip), created on first solve
   void (*solve_ws_free)(void*) = nullptr;
 };
@@ -177,6 +191,20 @@ mskm_status apply_internal(mskm_hier* h, int op, int prec, const void* x, void* 
 mskm_status autotune(mskm_hier* h, int repeats, float* times_out);
 mskm_status solve(mskm_hier* h, const double* f, int nrhs, const mskm_solve_opts* o, double* alpha,
                   mskm_report* rep);
+// learned.hip
+mskm_status ensure_knn(mskm_hier* h);
+mskm_status mlp_new(int dim, uint64_t seed, mskm_mlp** out);
+mskm_status mlp_upload(mskm_mlp* m);
+template <typename TX>
+mskm_status mlp_predict_rows(mskm_hier* h, const mskm_mlp* m, int l, const TX* b, TX* x0);
+mskm_status mlp_train_device(mskm_hier* h, mskm_mlp* m, const std::vector<double*>& rhs_int,
+                             const std::vector<double*>& alpha_int, int64_t samples, int steps, float lr, uint64_t seed,
+                             std::vector<float>* loss_log);
+mskm_status mlp_predict_all(mskm_hier* h, const mskm_mlp* m, const double* b, double* x0, bool io_dev);
+mskm_status knn_export(mskm_hier* h, int level, int32_t* out);
+mskm_status train_pairs(mskm_hier* h, const double* f, int nrhs, bool io_dev, double cg_rtol,
+                        std::vector<double*>* rhs_int, std::vector<double*>* alpha_int);
+
 // solve_mr.hip: many right-hand sides in the same launches (2 <= nrhs <= 512)
 bool mr_supported(int nrhs);
 mskm_status solve_multi(mskm_hier* h, const double* f, int nrhs, const mskm_solve_opts* o, double* alpha,

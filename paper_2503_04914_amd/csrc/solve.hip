@@ -68,7 +68,7 @@ __device__ __forceinline__ TA csr_row_dot(const int64_t* __restrict__ rp, const 
 // starting from the row start rounded down to a multiple of V; entries
 // outside the row are masked. Value and column arrays carry a tail pad of
 // kCsrPad entries, so the rounded loads never leave their allocation.
-template <int G, typename TV, typename TX, typename TA>
+template <int G, typename TV, typename TX, typename TA, bool NT = false>
 __device__ __forceinline__ TA csr_row_dot_v(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                             const TV* __restrict__ val, const TX* __restrict__ x, int64_t row,
                                             int gl) {
@@ -78,13 +78,36 @@ __device__ __forceinline__ TA csr_row_dot_v(const int64_t* __restrict__ rp, cons
   for (int64_t k = (s & ~(int64_t)(V - 1)) + (int64_t)gl * V; k < e; k += (int64_t)G * V) {
     TV v[V];
     int32_t c[V];
+    // NT: the matrix streams are read once per SpMV; non-temporal loads keep
+    // them from displacing the gathered x entries in the caches
     if constexpr (V == 2) {
-      const double2 vv = *reinterpret_cast<const double2*>(val + k);
-      const int2 cc = *reinterpret_cast<const int2*>(col + k);
+      double2 vv;
+      int2 cc;
+      if constexpr (NT) {
+        typedef double nd2 __attribute__((ext_vector_type(2)));
+        typedef int ni2 __attribute__((ext_vector_type(2)));
+        const nd2 a = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(val + k));
+        const ni2 b = __builtin_nontemporal_load(reinterpret_cast<const ni2*>(col + k));
+        vv.x = a.x; vv.y = a.y; cc.x = b.x; cc.y = b.y;
+      } else {
+        vv = *reinterpret_cast<const double2*>(val + k);
+        cc = *reinterpret_cast<const int2*>(col + k);
+      }
       v[0] = vv.x; v[1] = vv.y; c[0] = cc.x; c[1] = cc.y;
     } else {
-      const float4 vv = *reinterpret_cast<const float4*>(val + k);
-      const int4 cc = *reinterpret_cast<const int4*>(col + k);
+      float4 vv;
+      int4 cc;
+      if constexpr (NT) {
+        typedef float nf4 __attribute__((ext_vector_type(4)));
+        typedef int ni4 __attribute__((ext_vector_type(4)));
+        const nf4 a = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(val + k));
+        const ni4 b = __builtin_nontemporal_load(reinterpret_cast<const ni4*>(col + k));
+        vv.x = a.x; vv.y = a.y; vv.z = a.z; vv.w = a.w;
+        cc.x = b.x; cc.y = b.y; cc.z = b.z; cc.w = b.w;
+      } else {
+        vv = *reinterpret_cast<const float4*>(val + k);
+        cc = *reinterpret_cast<const int4*>(col + k);
+      }
       v[0] = vv.x; v[1] = vv.y; v[2] = vv.z; v[3] = vv.w;
       c[0] = cc.x; c[1] = cc.y; c[2] = cc.z; c[3] = cc.w;
     }
@@ -111,7 +134,7 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-template <int G, typename TV, typename TX, typename TA>
+template <int G, typename TV, typename TX, typename TA, bool NT = false>
 __global__ void __launch_bounds__(kBlock)
     k_spmv_v(const int64_t* __restrict__ rp1, const int32_t* __restrict__ c1, const TV* __restrict__ v1,
              const int64_t* __restrict__ rp2, const int32_t* __restrict__ c2, const TV* __restrict__ v2,
@@ -119,8 +142,8 @@ __global__ void __launch_bounds__(kBlock)
   const int gl = threadIdx.x % G;
   const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
   for (int64_t i = r0 + (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
-    TA acc = csr_row_dot_v<G, TV, TX, TA>(rp1, c1, v1, x, i, gl);
-    if (rp2) acc += csr_row_dot_v<G, TV, TX, TA>(rp2, c2, v2, x, i, gl);
+    TA acc = csr_row_dot_v<G, TV, TX, TA, NT>(rp1, c1, v1, x, i, gl);
+    if (rp2) acc += csr_row_dot_v<G, TV, TX, TA, NT>(rp2, c2, v2, x, i, gl);
     if (gl == 0) y[i] = (TX)((b ? (TA)b[i] : (TA)0) + sign * acc);
   }
 }
@@ -503,6 +526,7 @@ struct CgStats {
   int64_t iters_total = 0;
   int32_t last_iters[kMaxLevels] = {};
   bool capped = false;
+  int32_t warm_fallbacks = 0;
 };
 
 // K CG iterations (4 kernels each) on levels lo..hi, starting at an even
@@ -559,7 +583,7 @@ static mskm_status chunk_graph(mskm_hier* h, SolveWS& W, const TV* dval, int lo,
 // each chunk and stops when every level has stopped.
 template <typename TV, typename TX>
 static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::vector<char>& on, const TX* b, TX* x,
-                          double rtol, int maxit, bool warm, int K, CgStats* cs) {
+                          double rtol, int maxit, bool warm, int K, CgStats* cs, const mskm_mlp* mlp = nullptr) {
   hipStream_t s = h->ctx->stream;
   const WorkTable& ws = h->wt_spmv;
   int lo = 0, hi = h->L - 1;
@@ -577,11 +601,42 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
   MSKM_HIP_TRY(hipMemcpyAsync(W.st, W.h_st, h->L * sizeof(CgLevel), hipMemcpyHostToDevice, s));
   const int nlev = hi - lo + 1;
   const int sb0 = ws.h_lev_begin[lo], sbn = ws.h_lev_begin[hi + 1] - sb0;
-  const int G = h->spmv_g[MSKM_OP_DIAG][sizeof(TX) == 4 ? 1 : 0];
+  int G = h->spmv_g[MSKM_OP_DIAG][sizeof(TX) == 4 ? 1 : 0];
+  if (G >= 2 * kVecFlag) G -= kVecFlag;  // CG SpMV: 16-byte loads (no non-temporal variant)
+  if (mlp) {  // learned warm start x0 = MLP(b) on every participating level
+    for (int l = lo; l <= hi; ++l)
+      if (on[l]) MSKM_TRY(mlp_predict_rows<TX>(h, mlp, l, b, x));
+    warm = true;
+  }
   if (sbn > 0)
     hipLaunchKernelGGL((k_cg_init<kGDiag, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, h->diag.rowptr, h->diag.col,
                        dval, b, x, (TX*)W.r, (TX*)W.p0, W.st, warm ? 1 : 0, W.part_s, W.part_s2, sb0);
   hipLaunchKernelGGL(k_cg_red_init, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.part_s2, W.st);
+  if (mlp) {  // CG judges the warm start: ||b - A x0|| >= ||b|| restarts that level from zero
+    MSKM_HIP_TRY(hipMemcpyAsync(W.h_st, W.st, h->L * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
+    MSKM_HIP_TRY(hipStreamSynchronize(s));
+    bool again = false;
+    for (int l = lo; l <= hi; ++l) {
+      const CgLevel& S = W.h_st[l];
+      if (on[l] && S.bb > 0.0 && !(S.rr < S.bb)) {
+        MSKM_HIP_TRY(hipMemsetAsync(x + h->h_off[l], 0, (h->h_off[l + 1] - h->h_off[l]) * sizeof(TX), s));
+        cs->warm_fallbacks += 1;
+        again = true;
+      }
+    }
+    if (again) {
+      for (int l = 0; l < h->L; ++l) {
+        W.h_st[l].done = 1;
+        W.h_st[l].iters = 0;
+      }
+      MSKM_HIP_TRY(hipMemcpyAsync(W.st, W.h_st, h->L * sizeof(CgLevel), hipMemcpyHostToDevice, s));
+      if (sbn > 0)
+        hipLaunchKernelGGL((k_cg_init<kGDiag, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, h->diag.rowptr, h->diag.col,
+                           dval, b, x, (TX*)W.r, (TX*)W.p0, W.st, 1, W.part_s, W.part_s2, sb0);
+      hipLaunchKernelGGL(k_cg_red_init, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.part_s2,
+                         W.st);
+    }
+  }
   hipGraphExec_t exec = nullptr;
   MSKM_TRY((chunk_graph<TV, TX>(h, W, dval, lo, hi, x, K, G, &exec)));
   for (int it = 0; it < maxit; it += K) {
@@ -626,6 +681,7 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
   const int L = h->L;
   TX* beta = (TX*)W.beta;
   TX* t = (TX*)W.t;
+  const mskm_mlp* mlp = o->precond == MSKM_PRECOND_LEARNED ? o->mlp : nullptr;
   const int maxit = o->max_cg_iters > 0 ? o->max_cg_iters : 20000;
   int K = o->check_every > 0 ? o->check_every : 8;
   K += K & 1;  // even chunk length
@@ -640,7 +696,7 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
       lower_update<TV, TX>(h, lval, alpha, f, beta, h->h_off[l0], h->h_off[l1]);
       std::fill(on.begin(), on.end(), 0);
       for (int l = l0; l < l1; ++l) on[l] = 1;
-      MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, false, K, cs)));
+      MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, false, K, cs, mlp)));
     }
     *sweeps_done = 0;
     return MSKM_OK;
@@ -659,7 +715,7 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
   }
   if (o->warm_start) MSKM_HIP_TRY(hipMemcpyAsync(alpha, t, N * sizeof(TX), hipMemcpyDeviceToDevice, s));
   std::fill(on.begin(), on.end(), 1);
-  MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, o->warm_start != 0, K, cs)));
+  MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, o->warm_start != 0, K, cs, mlp)));
   return MSKM_OK;
 }
 
@@ -885,6 +941,10 @@ static void spmv_launch(hipStream_t s, int G, const Csr* A1, const T* v1, const 
   case GG + kVecFlag:                                                                                          \
     hipLaunchKernelGGL((k_spmv_v<GG, T, T, T>), dim3(nblk(r1 - r0, kBlock / GG)), dim3(kBlock), 0, s,          \
                        A1->rowptr, A1->col, v1, rp2, c2, v2, x, b, y, sign, r0, r1);                            \
+    break;                                                                                                     \
+  case GG + 2 * kVecFlag:                                                                                      \
+    hipLaunchKernelGGL((k_spmv_v<GG, T, T, T, true>), dim3(nblk(r1 - r0, kBlock / GG)), dim3(kBlock), 0, s,    \
+                       A1->rowptr, A1->col, v1, rp2, c2, v2, x, b, y, sign, r0, r1);                            \
     break;
   switch (G) {
     MSKM_SPMV_CASE(4)
@@ -933,8 +993,21 @@ mskm_status apply_internal(mskm_hier* h, int op, int prec, const void* x, void* 
 // width on the hierarchy's own matrices (scratch vectors, `repeats` launches
 // each after one warm-up) and keep the fastest.
 mskm_status autotune(mskm_hier* h, int repeats, float* times_out) {
-  static const int widths[] = {4, 8, 16, 32, 64, 4 + kVecFlag, 8 + kVecFlag, 16 + kVecFlag, 32 + kVecFlag,
-                               64 + kVecFlag};
+  static const int widths[] = {4,
+                               8,
+                               16,
+                               32,
+                               64,
+                               4 + kVecFlag,
+                               8 + kVecFlag,
+                               16 + kVecFlag,
+                               32 + kVecFlag,
+                               64 + kVecFlag,
+                               4 + 2 * kVecFlag,
+                               8 + 2 * kVecFlag,
+                               16 + 2 * kVecFlag,
+                               32 + 2 * kVecFlag,
+                               64 + 2 * kVecFlag};
   double* x = nullptr;
   double* y = nullptr;
   MSKM_TRY(dalloc(&x, h->N));
@@ -1078,9 +1151,42 @@ mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_o
     for (int l = 0; l < std::min(h->L, 64); ++l) rep->cg_iters_last[l] = cs.last_iters[l];  // first 64 levels
     rep->rel_residual = worst_rel;
     rep->solve_ms = ms;
+    rep->warm_fallbacks = cs.warm_fallbacks;
   }
   MSKM_HIP_TRY(hipGetLastError());
   return enoconv ? MSKM_ENOCONV : MSKM_OK;
+}
+
+// Training pairs for the learned warm start: for each right-hand side a
+// plain FP64 sequential solve gives alpha; each level's own rhs is then
+// beta = f - (T - D) alpha (the residual the sequential algorithm hands to
+// that level), so (beta_l, alpha_l) is one (rhs -> correction) pair per level.
+mskm_status train_pairs(mskm_hier* h, const double* f, int nrhs, bool io_dev, double cg_rtol,
+                        std::vector<double*>* rhs_int, std::vector<double*>* alpha_int) {
+  hipStream_t s = h->ctx->stream;
+  const int64_t N = h->N;
+  DevBuf F;
+  MSKM_TRY(stage_in(s, f, (size_t)N * nrhs, io_dev, F));
+  SolveWS* Wp = nullptr;
+  MSKM_TRY(get_ws(h, &Wp));
+  mskm_solve_opts o;
+  mskm_solve_opts_default(&o);
+  o.algorithm = MSKM_ALG_SEQUENTIAL;
+  o.cg_rtol = cg_rtol;
+  for (int r = 0; r < nrhs; ++r) {
+    double *bi = nullptr, *ai = nullptr;
+    MSKM_TRY(dalloc(&bi, N));
+    rhs_int->push_back(bi);
+    MSKM_TRY(dalloc(&ai, N));
+    alpha_int->push_back(ai);
+    hipLaunchKernelGGL(k_to_internal<double>, dim3(nblk(N)), dim3(kBlock), 0, s, F.p, h->perm, Wp->fi, N, nrhs, r);
+    CgStats cs;
+    int sw = 0;
+    MSKM_TRY((solve_internal<double, double>(h, *Wp, h->diag.val, h->lower.val, Wp->fi, ai, &o, &sw, &cs)));
+    lower_update<double, double>(h, h->lower.val, ai, Wp->fi, bi, 0, N);
+  }
+  MSKM_HIP_TRY(hipStreamSynchronize(s));
+  return MSKM_OK;
 }
 
 mskm_status residual(mskm_hier* h, const double* alpha, const double* f, int nrhs, double* rel_out, bool io_dev) {
