@@ -56,6 +56,15 @@ def spmv_bytes(nnz: int, n: int, nrowptr: int, sval: int, sx: int) -> int:
     return nnz * (sval + 4) + nrowptr * (n + 1) * 8 + n * sx + n * sx
 
 
+def spmv_kernel_name(code: int, t: str) -> str:
+    """Kernel that a SpMV variant code launches (lanes per row + 1000 for
+    16-byte loads, + 2000 for non-temporal 16-byte loads)."""
+    g, kind = code % 1000, code // 1000
+    if kind == 0:
+        return f"k_spmv<{g},{t}>"
+    return f"k_spmv_v<{g},{t}{',nontemporal' if kind == 2 else ''}>"
+
+
 def calibrate(m, ctx, hd, f_dev, alpha_dev, base_opts: dict, label: str):
     """Loosest CG tolerance of the ladder whose solution verifies <= 1e-8
     by the independent FP64 residual."""
@@ -156,6 +165,72 @@ def batched(m, ctx, hd, h, pts_dev, dev, fast_opts, rt_fast, nrhs, count):
     return out
 
 
+def uniform3d(m, ctx, dev, args):
+    """The 3-D mixed-precision workload: 5 prefix-nested levels of a seeded
+    uniform stream (512 .. 2,097,152 points, about 60 neighbours per row).
+    Fast form (FP32 values and accumulation, FP64 dots and residual
+    refinement) against the plain FP64 Jacobi+CG baseline, both to 1e-8, the
+    fast form's coefficient error against a tight FP64 solve, and the FP32
+    full-T SpMV bandwidth."""
+    import torch
+
+    import synth
+
+    h3 = synth.uniform3d_hierarchy(5)
+    f3 = torch.from_numpy(synth.fourier_target(2001, dim=3)(h3.points)).to(dev)
+    p3 = torch.from_numpy(h3.points).to(dev)
+    a3 = torch.zeros_like(f3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hd3 = m.mskm_hier_create(ctx, p3, h3.offsets, h3.delta, fp64=True, fp32=True)
+    torch.cuda.synchronize()
+    t_asm = (time.perf_counter() - t0) * 1e3
+    st = m.mskm_hier_stats_get(hd3)
+    log("uniform3d hierarchy", st)
+    m.mskm_autotune(ctx, hd3, repeats=3)
+    fast_opts = dict(precision=m.MSKM_PREC_FP32, algorithm=m.MSKM_ALG_SEQUENTIAL, target_rel_residual=TARGET,
+                     max_refine=8)
+    plain_opts = dict(precision=m.MSKM_PREC_FP64, algorithm=m.MSKM_ALG_MONOLITHIC)
+    out = {"workload": "uniform3d_L5", "n_points": st["n_total"], "nnz": st["nnz_diag"] + st["nnz_lower"],
+           "assemble_fp64_fp32_ms": round(t_asm, 2)}
+    for label, opts in (("fast", fast_opts), ("plain_fp64_jacobi", plain_opts)):
+        rt = calibrate(m, ctx, hd3, f3, a3, opts, f"uniform3d {label}")
+        o = m.solve_opts(cg_rtol=rt, **opts)
+        ts = []
+        for _ in range(3):
+            r = m.mskm_solve(ctx, hd3, f3, a3, o)
+            ts.append(r.report["solve_ms"])
+        rel = float(m.mskm_residual(ctx, hd3, a3, f3)[0])
+        out[label] = {"cg_rtol": rt, "time_to_1e-8_ms": round(float(np.median(ts)), 3), "rel_residual": rel,
+                      "cg_iters_total": r.report["cg_iters_total"], "status": r.status}
+        if label == "fast":
+            a_fast = a3.clone()
+    # coefficient error of the fast form against a tight FP64 solve
+    a_ref = torch.zeros_like(f3)
+    m.mskm_solve(ctx, hd3, f3, a_ref, m.solve_opts(cg_rtol=1e-13, precision=m.MSKM_PREC_FP64,
+                                                   algorithm=m.MSKM_ALG_SEQUENTIAL))
+    errs = []
+    for l in range(h3.levels):
+        sl = slice(int(h3.offsets[l]), int(h3.offsets[l + 1]))
+        errs.append(float(torch.linalg.norm(a_fast[sl] - a_ref[sl]) / torch.linalg.norm(a_ref[sl])))
+    out["fast"]["coef_rel_err_vs_fp64_per_level"] = errs
+    out["speedup_vs_plain_fp64"] = round(out["plain_fp64_jacobi"]["time_to_1e-8_ms"] / out["fast"]["time_to_1e-8_ms"],
+                                         3)
+    N3 = st["n_total"]
+    x32 = torch.randn(N3, dtype=torch.float32, device=dev)
+    y32 = torch.empty_like(x32)
+    m.mskm_apply_internal(ctx, hd3, m.MSKM_OP_FULL, x32, y32, prec=m.MSKM_PREC_FP32, repeats=2)
+    ms = m.mskm_apply_internal(ctx, hd3, m.MSKM_OP_FULL, x32, y32, prec=m.MSKM_PREC_FP32, repeats=args.spmv_repeats)
+    b = spmv_bytes(out["nnz"], N3, 2, 4, 4)
+    out["spmv_full_fp32"] = {"ms": round(ms, 4), "bytes": b, "GBps": round(b / ms / 1e6, 1),
+                             "variant": m.mskm_spmv_width(hd3, m.MSKM_OP_FULL, m.MSKM_PREC_FP32)}
+    log("uniform3d", out)
+    m.mskm_hier_destroy(hd3)
+    del p3, f3, a3, a_ref, a_fast, x32, y32
+    torch.cuda.empty_cache()
+    return out
+
+
 def train_warm_start(m, ctx, args):
     """Train the warm-start network on (rhs -> correction) pairs from plain
     solves of a 6-level Halton hierarchy with random Fourier targets."""
@@ -192,9 +267,12 @@ def main():
     ap.add_argument("--train-samples", type=int, default=10000)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D mixed-precision workload")
     ap.add_argument("--spmv-only", action="store_true",
-                    help="assemble, autotune, then only time the FP64 full-T SpMV and a 1 GiB device copy "
+                    help="assemble, autotune, then only time the FP64 full-T SpMV and a 1 GiB streaming copy kernel "
                          "(the counter-collection runs)")
+    ap.add_argument("--spmv-variant", type=int, default=0,
+                    help="with --spmv-only: pin this SpMV variant code instead of autotuning")
     ap.add_argument("--batch-count", type=int, default=64, help="hierarchies of the batched solve (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -223,7 +301,10 @@ def main():
     hd = m.mskm_hier_create(ctx, pts_dev, h.offsets, h.delta, fp64=True, fp32=True)
     if args.spmv_only:
         st = m.mskm_hier_stats_get(hd)
-        m.mskm_autotune(ctx, hd, repeats=3)
+        if args.spmv_variant:
+            m.mskm_set_spmv_width(hd, m.MSKM_OP_FULL, m.MSKM_PREC_FP64, args.spmv_variant)
+        else:
+            m.mskm_autotune(ctx, hd, repeats=3)
         x = torch.randn(N, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
         ms = m.mskm_apply_internal(ctx, hd, m.MSKM_OP_FULL, x, y, repeats=args.spmv_repeats)
@@ -233,7 +314,7 @@ def main():
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(args.spmv_repeats):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)  # a plain streaming kernel: reads 1 GiB, writes 1 GiB
         e1.record()
         torch.cuda.synchronize()
         b = spmv_bytes(st["nnz_diag"] + st["nnz_lower"], N, 2, 8, 8)
@@ -352,6 +433,7 @@ def main():
     log("spmv", spmv)
     bt = batched(m, ctx, hd, h, pts_dev, dev, fast_opts, rt_fast, args.rhs, args.batch_count)
     m.mskm_hier_destroy(hd)
+    u3 = None if args.no_3d else uniform3d(m, ctx, dev, args)
     m.mskm_destroy(ctx)
 
     dom = spmv["full_fp64"]
@@ -384,11 +466,12 @@ def main():
                  for k, v in spmv.items()},
         "batched": bt,
         "learned": learned,
+        "uniform3d_mixed": u3,
         "spmv_GBps": round(dom["GBps"], 1),
         "spmv_widths": widths,
         "roofline": {"bound": "hbm", "achieved": round(dom["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_spmv<32,double> (T = D + lower, FP64 values)"},
+                     "kernel": spmv_kernel_name(widths["full_fp64"], "double") + " (T = D + lower, FP64 values)"},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 1 thread)")

@@ -207,13 +207,17 @@ mskm_status mskm_apply_internal(mskm_ctx* ctx, const mskm_hier* h, int32_t op, i
                                 int32_t repeats, float* avg_ms);
 
 /* Autotuner: times every CSR SpMV variant -- lanes per row 4, 8, 16, 32, 64,
- * each with per-entry loads, 16-byte loads and 16-byte non-temporal loads
- * (variant codes w, w + 1000, w + 2000) -- for each operator (DIAG, LOWER,
- * FULL) and each stored precision on this hierarchy's own blocks (`repeats`
- * >= 1 timed launches per variant) and keeps the fastest for later apply /
- * solve calls. times_ms (nullable, host, [3][2][15]) receives the mean ms
- * per launch of every [op][precision][variant] in that order (0 where a
- * precision is not stored).
+ * each with per-entry loads, 16-byte loads, 16-byte non-temporal loads, and
+ * with entry values recomputed in the kernel from the points (the stored
+ * column structure, phi evaluated in the operator's precision) (variant
+ * codes w, w + 1000, w + 2000, w + 3000), and for DIAG also the sliced
+ * (SELL, 64-row slices, one row per lane) copy of the diagonal blocks (code
+ * 4064) -- for each operator (DIAG, LOWER, FULL) and each stored precision
+ * on this hierarchy's own blocks (`repeats` >= 1 timed launches per variant)
+ * and keeps the fastest for later apply / solve calls (the CG products use
+ * the DIAG choice). times_ms (nullable, host, [3][2][21]) receives the mean
+ * ms per launch of every [op][precision][variant] in that order (0 where a
+ * precision is not stored or a variant does not apply).
  * The choice is also remembered by the context: hierarchies created later
  * on it with the same dimension, level count, point count and nonzero
  * counts start with the tuned widths. */
@@ -221,6 +225,12 @@ mskm_status mskm_autotune(mskm_ctx* ctx, mskm_hier* h, int32_t repeats, float* t
 
 /* Current SpMV variant code for op (MSKM_OP_*) and prec (MSKM_PREC_*). */
 mskm_status mskm_spmv_width(const mskm_hier* h, int32_t op, int32_t prec, int32_t* width);
+
+/* Pins the SpMV variant of op / prec to `width`, one of the autotuner's
+ * codes (4, 8, 16, 32, 64, plus 0, 1000, 2000 or 3000; 4064 for DIAG), e.g. a choice saved from
+ * an earlier autotune. Results do not depend on the variant beyond FP
+ * summation order. MSKM_EINVAL for an unknown op, precision or code. */
+mskm_status mskm_set_spmv_width(mskm_hier* h, int32_t op, int32_t prec, int32_t width);
 
 /* ------------------------------------------------------------------ solve */
 

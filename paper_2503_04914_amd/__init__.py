@@ -38,7 +38,7 @@ EXPORTED = [
     "mskm_hier_create", "mskm_hier_create_batch", "mskm_hier_destroy", "mskm_hier_stats_get", "mskm_hier_offsets",
     "mskm_hier_level_info",
     "mskm_export_block", "mskm_export_rows", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
-    "mskm_autotune", "mskm_spmv_width",
+    "mskm_autotune", "mskm_spmv_width", "mskm_set_spmv_width",
     "mskm_solve_opts_default", "mskm_solve", "mskm_residual", "mskm_evaluate",
     "mskm_mlp_train", "mskm_mlp_destroy", "mskm_mlp_save", "mskm_mlp_load", "mskm_mlp_predict", "mskm_knn_export",
 ]
@@ -119,6 +119,7 @@ def lib():
     L.mskm_apply_internal.argtypes = [vp, vp, i32, i32, vp, vp, i32, C.POINTER(C.c_float)]
     L.mskm_autotune.argtypes = [vp, vp, i32, C.POINTER(C.c_float)]
     L.mskm_spmv_width.argtypes = [vp, i32, i32, C.POINTER(i32)]
+    L.mskm_set_spmv_width.argtypes = [vp, i32, i32, i32]
     L.mskm_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
     L.mskm_solve_opts_default.restype = None
     L.mskm_solve.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(Report)]
@@ -305,12 +306,14 @@ def mskm_apply_internal(ctx, h, op: int, x, y, prec: int = MSKM_PREC_FP64, repea
     return float(ms.value)
 
 
-TUNE_VARIANTS = [4, 8, 16, 32, 64, 1004, 1008, 1016, 1032, 1064, 2004, 2008, 2016, 2032, 2064]
+TUNE_VARIANTS = [4, 8, 16, 32, 64, 1004, 1008, 1016, 1032, 1064, 2004, 2008, 2016, 2032, 2064,
+                 3004, 3008, 3016, 3032, 3064, 4064]
+SELL_CODE = 4064  # sliced copy of the diagonal blocks (MSKM_OP_DIAG only)
 
 
 def mskm_autotune(ctx, h, repeats: int = 5) -> np.ndarray:
     """Pick the fastest SpMV variant per operator/precision; returns the
-    [3][2][15] table of mean ms per launch (op, precision, TUNE_VARIANTS)."""
+    [3][2][len(TUNE_VARIANTS)] table of mean ms per launch (op, precision, variant)."""
     t = np.zeros(3 * 2 * len(TUNE_VARIANTS), dtype=np.float32)
     _check(lib().mskm_autotune(ctx, h, repeats, t.ctypes.data_as(C.POINTER(C.c_float))), "mskm_autotune")
     return t.reshape(3, 2, len(TUNE_VARIANTS))
@@ -320,6 +323,10 @@ def mskm_spmv_width(h, op: int, prec: int = MSKM_PREC_FP64) -> int:
     w = C.c_int32()
     _check(lib().mskm_spmv_width(h, op, prec, C.byref(w)), "mskm_spmv_width")
     return int(w.value)
+
+
+def mskm_set_spmv_width(h, op: int, prec: int, width: int) -> None:
+    _check(lib().mskm_set_spmv_width(h, op, prec, width), "mskm_set_spmv_width")
 
 
 def mskm_solve_opts_default() -> SolveOpts:

@@ -313,6 +313,20 @@ mskm_status mskm_spmv_width(const mskm_hier* h, int32_t op, int32_t prec, int32_
   return MSKM_OK;
 }
 
+mskm_status mskm_set_spmv_width(mskm_hier* h, int32_t op, int32_t prec, int32_t width) {
+  if (!h) return fail(MSKM_EINVAL, "mskm_set_spmv_width: NULL hierarchy");
+  if (op < MSKM_OP_DIAG || op > MSKM_OP_FULL || (prec != MSKM_PREC_FP64 && prec != MSKM_PREC_FP32))
+    return fail(MSKM_EINVAL, "unknown op or precision");
+  const int g = width % mskm::kVecFlag, kind = width / mskm::kVecFlag;
+  if (width == mskm::kSellCode) {
+    if (op != MSKM_OP_DIAG) return fail(MSKM_EINVAL, "mskm_set_spmv_width: the SELL variant serves MSKM_OP_DIAG only");
+  } else if (width < 0 || kind > 3 || (g != 4 && g != 8 && g != 16 && g != 32 && g != 64)) {
+    return fail(MSKM_EINVAL, "mskm_set_spmv_width: unknown variant code " + std::to_string(width));
+  }
+  h->spmv_g[op][prec] = width;
+  return MSKM_OK;
+}
+
 void mskm_solve_opts_default(mskm_solve_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));

@@ -368,6 +368,29 @@ static unsigned grid_for(int64_t n, int per_block) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 30));
 }
 
+// Record of internal point i: {x, y, z (0 in 2-D), 1/delta of its level};
+// the level is found by binary search over the level offsets.
+__global__ void __launch_bounds__(kBlock) k_point_records(int dim, int L, const DevLevel* __restrict__ lev,
+                                                          const double* __restrict__ xs, int64_t N,
+                                                          double* __restrict__ rec) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= N) return;
+  int lo = 0, hi = L - 1;  // last level with off <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (lev[mid].off <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  double4 r;
+  r.x = xs[i];
+  r.y = xs[N + i];
+  r.z = dim == 3 ? xs[2 * N + i] : 0.0;
+  r.w = lev[lo].inv_delta;
+  reinterpret_cast<double4*>(rec)[i] = r;
+}
+
+static mskm_status build_sell(mskm_hier* h, bool want64, bool want32);
+
 mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, bool want32) {
   hipStream_t s = h->ctx->stream;
   const int L = h->L, dim = h->dim;
@@ -487,6 +510,11 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
                        key, cs64, tmp, h->perm, h->iperm, h->xs, N);
   }
 
+  // point records for the SpMV variants that recompute entry values
+  MSKM_TRY(halloc(h, &h->prec, (size_t)4 * N));
+  hipLaunchKernelGGL(k_point_records, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, dim, L, h->d_lev, h->xs, N,
+                     h->prec);
+
   // 4. count pass
   int64_t *cnt_d = nullptr, *cnt_l = nullptr;
   MSKM_TRY(dalloc(&cnt_d, N + 1));
@@ -533,11 +561,145 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
                        h->cell_start, h->xs, N, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32,
                        h->lower.rowptr, h->lower.col, h->lower.val, h->lower.val32);
   }
+  MSKM_TRY(build_sell(h, want64, want32));
   MSKM_HIP_TRY(hipEventRecord(h->ctx->ev1, s));
   MSKM_HIP_TRY(hipEventSynchronize(h->ctx->ev1));
   float ms = 0.f;
   MSKM_HIP_TRY(hipEventElapsedTime(&ms, h->ctx->ev0, h->ctx->ev1));
   h->assemble_ms = ms;
+  MSKM_HIP_TRY(hipGetLastError());
+  return MSKM_OK;
+}
+
+// ------------------------------------------------------------------ SELL
+
+// One block per window {row0, cnt, slot0}: rank of each row by (length
+// descending, row ascending) among the window's rows, written as the row of
+// slot slot0 + rank; slots past the window's rows up to its last full slice
+// get -1.
+__global__ void __launch_bounds__(kSellWin) k_sell_sort(const int64_t* __restrict__ win,
+                                                        const int64_t* __restrict__ rp, int32_t* __restrict__ rows) {
+  __shared__ int32_t len[kSellWin];
+  const int64_t row0 = win[3 * blockIdx.x], cnt = win[3 * blockIdx.x + 1], slot0 = win[3 * blockIdx.x + 2];
+  const int t = threadIdx.x;
+  len[t] = t < cnt ? (int32_t)(rp[row0 + t + 1] - rp[row0 + t]) : -1;
+  __syncthreads();
+  if (t < cnt) {
+    const int32_t me = len[t];
+    int rank = 0;
+    for (int u = 0; u < cnt; ++u) {
+      const int32_t o = len[u];
+      rank += (o > me) || (o == me && u < t);
+    }
+    rows[slot0 + rank] = (int32_t)(row0 + t);
+  } else if (t < (cnt + kSellC - 1) / kSellC * kSellC) {
+    rows[slot0 + t] = -1;
+  }
+}
+
+// Width (in entries, w_s * kSellC) of every slice: its first slot holds its
+// longest row. Entry nslices is 0 (scan sentinel).
+__global__ void __launch_bounds__(kBlock) k_sell_width(int64_t nslices, const int32_t* __restrict__ rows,
+                                                       const int64_t* __restrict__ rp, int64_t* __restrict__ w) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (s > nslices) return;
+  if (s == nslices) {
+    w[s] = 0;
+    return;
+  }
+  const int32_t r = rows[s * kSellC];
+  w[s] = r >= 0 ? (rp[r + 1] - rp[r]) * kSellC : 0;
+}
+
+// One wave per slice: copy the CSR rows into the slot-interleaved layout.
+__global__ void __launch_bounds__(kBlock) k_sell_fill(int64_t nslices, const int32_t* __restrict__ rows,
+                                                      const int64_t* __restrict__ sptr, const int64_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                      const float* __restrict__ val32, int32_t* __restrict__ scol,
+                                                      double* __restrict__ sval, float* __restrict__ sval32) {
+  const int64_t s = (int64_t)blockIdx.x * (kBlock / kSellC) + threadIdx.x / kSellC;
+  if (s >= nslices) return;
+  const int t = threadIdx.x % kSellC;
+  const int32_t row = rows[s * kSellC + t];
+  const int64_t e0 = sptr[s], w = (sptr[s + 1] - e0) / kSellC;
+  const int64_t b = row >= 0 ? rp[row] : 0;
+  const int64_t len = row >= 0 ? rp[row + 1] - b : 0;
+  const int32_t pad_col = row >= 0 ? row : 0;
+  for (int64_t k = 0; k < w; ++k) {
+    const int64_t d = e0 + k * kSellC + t;
+    const bool in = k < len;
+    scol[d] = in ? col[b + k] : pad_col;
+    if (sval) sval[d] = in ? val[b + k] : 0.0;
+    if (sval32) sval32[d] = in ? val32[b + k] : 0.0f;
+  }
+}
+
+static mskm_status build_sell(mskm_hier* h, bool want64, bool want32) {
+  hipStream_t s = h->ctx->stream;
+  Sell& S = h->sell;
+  const int L = h->L;
+  S.h_slice_begin.assign(L + 1, 0);
+  std::vector<int64_t> win;  // {row0, cnt, slot0} per window
+  for (int l = 0; l < L; ++l) {
+    const int64_t a = h->h_off[l], n = h->h_off[l + 1] - a;
+    S.h_slice_begin[l + 1] = S.h_slice_begin[l] + (n + kSellC - 1) / kSellC;
+    for (int64_t w = 0; w < n; w += kSellWin) {
+      win.push_back(a + w);
+      win.push_back(std::min<int64_t>(kSellWin, n - w));
+      win.push_back(S.h_slice_begin[l] * kSellC + w);
+    }
+  }
+  S.nslices = S.h_slice_begin[L];
+  const int64_t nw = (int64_t)win.size() / 3;
+  MSKM_TRY(halloc(h, &S.rows, (size_t)S.nslices * kSellC));
+  MSKM_TRY(halloc(h, &S.sptr, (size_t)S.nslices + 1));
+  int64_t *d_win = nullptr, *d_w = nullptr;
+  MSKM_TRY(dalloc(&d_win, win.size()));
+  MSKM_TRY(dalloc(&d_w, (size_t)S.nslices + 1));
+  MSKM_HIP_TRY(hipMemcpyAsync(d_win, win.data(), win.size() * 8, hipMemcpyHostToDevice, s));
+  if (nw > 0) hipLaunchKernelGGL(k_sell_sort, dim3((unsigned)nw), dim3(kSellWin), 0, s, d_win, h->diag.rowptr, S.rows);
+  hipLaunchKernelGGL(k_sell_width, dim3(grid_for(S.nslices + 1, kBlock)), dim3(kBlock), 0, s, S.nslices, S.rows,
+                     h->diag.rowptr, d_w);
+  MSKM_TRY(exclusive_scan_i64(s, d_w, S.sptr, S.nslices + 1));
+  MSKM_HIP_TRY(hipMemcpyAsync(&S.entries, S.sptr + S.nslices, 8, hipMemcpyDeviceToHost, s));
+  MSKM_HIP_TRY(hipStreamSynchronize(s));
+  (void)hipFree(d_win);
+  (void)hipFree(d_w);
+  MSKM_TRY(halloc(h, &S.col, (size_t)S.entries));
+  if (want64) MSKM_TRY(halloc(h, &S.val, (size_t)S.entries));
+  if (want32) MSKM_TRY(halloc(h, &S.val32, (size_t)S.entries));
+  if (S.nslices > 0)
+    hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(S.nslices, kBlock / kSellC)), dim3(kBlock), 0, s, S.nslices, S.rows,
+                       S.sptr, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, S.col, S.val, S.val32);
+  // launch table: blocks of 4 slices (one wave each) within each level
+  WorkTable& wt = h->wt_sell;
+  std::vector<int32_t> lev;
+  std::vector<int64_t> r0, r1;
+  wt.h_lev_begin.assign(L + 1, 0);
+  const int per = kBlock / kSellC;
+  for (int l = 0; l < L; ++l) {
+    wt.h_lev_begin[l] = (int32_t)lev.size();
+    for (int64_t a = S.h_slice_begin[l]; a < S.h_slice_begin[l + 1]; a += per) {
+      lev.push_back(l);
+      r0.push_back(a);
+      r1.push_back(std::min<int64_t>(a + per, S.h_slice_begin[l + 1]));
+    }
+  }
+  wt.h_lev_begin[L] = (int32_t)lev.size();
+  if (lev.size() > (size_t)INT32_MAX) return fail(MSKM_ELIMIT, "SELL table too large");
+  wt.nblocks = (int32_t)lev.size();
+  wt.rows_per_block = per;
+  MSKM_TRY(halloc(h, &wt.lev, lev.size()));
+  MSKM_TRY(halloc(h, &wt.row0, r0.size()));
+  MSKM_TRY(halloc(h, &wt.row1, r1.size()));
+  MSKM_TRY(halloc(h, &wt.lev_begin, wt.h_lev_begin.size()));
+  if (!lev.empty()) {
+    MSKM_HIP_TRY(hipMemcpyAsync(wt.lev, lev.data(), lev.size() * 4, hipMemcpyHostToDevice, s));
+    MSKM_HIP_TRY(hipMemcpyAsync(wt.row0, r0.data(), r0.size() * 8, hipMemcpyHostToDevice, s));
+    MSKM_HIP_TRY(hipMemcpyAsync(wt.row1, r1.data(), r1.size() * 8, hipMemcpyHostToDevice, s));
+  }
+  MSKM_HIP_TRY(hipMemcpyAsync(wt.lev_begin, wt.h_lev_begin.data(), wt.h_lev_begin.size() * 4, hipMemcpyHostToDevice,
+                              s));
   MSKM_HIP_TRY(hipGetLastError());
   return MSKM_OK;
 }

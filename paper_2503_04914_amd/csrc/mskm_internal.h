@@ -28,8 +28,14 @@ namespace mskm {
 constexpr int kMaxLevels = 4096;  // levels of one hierarchy object (all groups of a batch)
 constexpr int kBlock = 256;  // threads per block of every streaming / SpMV kernel
 constexpr int kCsrPad = 16;  // tail pad (entries) of CSR column and value arrays
-constexpr int kVecFlag = 1000;  // SpMV variant code: lanes per row (+1000: 16-byte loads, +2000: also non-temporal)
-constexpr int kTuneVariants = 15;  // widths 4..64 x {per-entry, 16-byte, 16-byte non-temporal} loads
+// SpMV variant code: lanes per row G, plus 1000: 16-byte value/column loads,
+// 2000: the same non-temporal, 3000: values recomputed from point records;
+// kSellCode: the sliced copy of the diagonal blocks (one row per lane)
+constexpr int kVecFlag = 1000;
+constexpr int kSellCode = 4064;
+constexpr int kTuneVariants = 21;  // widths 4..64 x the four kinds, then SELL (diagonal operator only)
+constexpr int kSellC = 64;         // SELL slice height: one wave, one row per lane
+constexpr int kSellWin = 1024;     // rows are sorted by length within windows of this many rows
 
 // Per-level descriptor read by the kernels (all fields uniform per wave).
 struct DevLevel {
@@ -57,6 +63,22 @@ struct WorkTable {
   int64_t* row1 = nullptr;    // device [nblocks]
   int32_t* lev_begin = nullptr;  // device [L+1]
   std::vector<int32_t> h_lev_begin;
+};
+
+// Sliced-ELL copy of the diagonal blocks. Each level's rows are cut into
+// windows of kSellWin rows (from the level start), sorted by row length
+// (descending, ties by row) inside the window, and dealt into slices of
+// kSellC slots; slice s stores its width w_s = longest row of the slice and
+// entry k of slot t at sptr[s] + k * kSellC + t (shorter rows padded with
+// value 0 and their own row as column).
+struct Sell {
+  int64_t nslices = 0, entries = 0;
+  int64_t* sptr = nullptr;   // [nslices + 1]
+  int32_t* rows = nullptr;   // [nslices * kSellC] internal row of each slot, -1 for an empty slot
+  int32_t* col = nullptr;    // [entries]
+  double* val = nullptr;     // [entries] FP64 values (null when not stored)
+  float* val32 = nullptr;    // [entries] FP32 values (null when not stored)
+  std::vector<int64_t> h_slice_begin;  // [L+1] first slice of each level
 };
 
 struct Csr {
@@ -117,12 +139,15 @@ struct mskm_hier {
   std::vector<mskm::DevLevel> h_lev;    // [L]
   mskm::DevLevel* d_lev = nullptr;      // device [L]
   double* xs = nullptr;                 // device [dim][N] SoA, internal order
+  double* prec = nullptr;               // device [N][4] point records {x, y, z or 0, 1/delta of its level}
   int32_t* perm = nullptr;              // device [N] internal -> input
   int32_t* iperm = nullptr;             // device [N] input -> internal
   int32_t* cell_start = nullptr;        // device, all levels' tables
   mskm::Csr diag, lower;
   mskm::WorkTable wt_spmv;              // per-level one-pass SpMV blocks (CG phase 1)
   mskm::WorkTable wt_vec;               // per-level streaming blocks (CG phase 3)
+  mskm::Sell sell;                      // sliced copy of the diagonal blocks
+  mskm::WorkTable wt_sell;              // per-level blocks of 4 slices ("rows" are slices)
   int32_t spmv_g[3][2] = {{8, 8}, {32, 32}, {32, 32}};  // lanes per row [op][FP64, FP32]
   int64_t device_bytes = 0;
   double assemble_ms = 0.0;

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(kBlock)
            const TX* __restrict__ x, const TX* __restrict__ b, TX* __restrict__ y, TA sign, int64_t r0, int64_t r1) {
   const int gl = threadIdx.x % G;
   const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
-  for (int64_t i = r0 + (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
+  for (int64_t i = r0 + (int64_t)xcd_block_id(gridDim.x) * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
     TA acc = csr_row_dot<G, TV, TX, TA>(rp1, c1, v1, x, i, gl);
     if (rp2) acc += csr_row_dot<G, TV, TX, TA>(rp2, c2, v2, x, i, gl);
     if (gl == 0) y[i] = (TX)((b ? (TA)b[i] : (TA)0) + sign * acc);
@@ -141,11 +141,89 @@ __global__ void __launch_bounds__(kBlock)
              const TX* __restrict__ x, const TX* __restrict__ b, TX* __restrict__ y, TA sign, int64_t r0, int64_t r1) {
   const int gl = threadIdx.x % G;
   const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
-  for (int64_t i = r0 + (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
+  for (int64_t i = r0 + (int64_t)xcd_block_id(gridDim.x) * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
     TA acc = csr_row_dot_v<G, TV, TX, TA, NT>(rp1, c1, v1, x, i, gl);
     if (rp2) acc += csr_row_dot_v<G, TV, TX, TA, NT>(rp2, c2, v2, x, i, gl);
     if (gl == 0) y[i] = (TX)((b ? (TA)b[i] : (TA)0) + sign * acc);
   }
+}
+
+// Entry value recomputed from the point records: phi_{3,1}(sqrt(d2) / delta)
+// with 1/delta of the column point's level. The FP64 form differs from the
+// stored value only by the rounding of the reciprocal; the FP32 form takes
+// the root and the polynomial in single precision (for FP32 operators).
+template <typename TA>
+__device__ __forceinline__ TA phi_rec(double d2, double inv_delta);
+template <>
+__device__ __forceinline__ double phi_rec<double>(double d2, double inv_delta) {
+  const double r = sqrt(d2) * inv_delta;
+  double t = 1.0 - r;
+  t = t > 0.0 ? t : 0.0;
+  const double t2 = t * t;
+  return t2 * t2 * (4.0 * r + 1.0);
+}
+template <>
+__device__ __forceinline__ float phi_rec<float>(double d2, double inv_delta) {
+  return phi31_f(sqrtf((float)d2) * (float)inv_delta);
+}
+
+// Row dot with values recomputed from the records: only the column stream
+// is read from HBM (16-byte loads of 4 columns from the row start rounded
+// down to a multiple of 4, entries outside the row masked; the column array
+// carries a tail pad of kCsrPad entries); the records and x are gathered
+// through the caches. The structure is the stored one, so it stays exact.
+template <int G, int DIM, typename TX, typename TA>
+__device__ __forceinline__ TA rec_row_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                          const double4* __restrict__ rec, const TX* __restrict__ x, int64_t row,
+                                          int gl, const double4 me) {
+  const int64_t s = rp[row], e = rp[row + 1];
+  TA acc = 0;
+  for (int64_t k = (s & ~(int64_t)3) + (int64_t)gl * 4; k < e; k += (int64_t)G * 4) {
+    const int4 cc = *reinterpret_cast<const int4*>(col + k);
+    const int32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k + u >= s && k + u < e) {
+        const double4 q = rec[c[u]];
+        const double d2 = sqdist(DIM, me.x, me.y, me.z, q.x, q.y, q.z);
+        acc += phi_rec<TA>(d2, q.w) * (TA)x[c[u]];
+      }
+  }
+  return group_sum<G>(acc);
+}
+
+// y = b + sign * (A1 + A2) x with recomputed values (variant code G + 3000).
+template <int G, int DIM, typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_spmv_rec(const int64_t* __restrict__ rp1, const int32_t* __restrict__ c1, const int64_t* __restrict__ rp2,
+               const int32_t* __restrict__ c2, const double4* __restrict__ rec, const T* __restrict__ x,
+               const T* __restrict__ b, T* __restrict__ y, T sign, int64_t r0, int64_t r1) {
+  const int gl = threadIdx.x % G;
+  const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
+  for (int64_t i = r0 + (int64_t)xcd_block_id(gridDim.x) * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
+    const double4 me = rec[i];
+    T acc = rec_row_dot<G, DIM, T, T>(rp1, c1, rec, x, i, gl, me);
+    if (rp2) acc += rec_row_dot<G, DIM, T, T>(rp2, c2, rec, x, i, gl, me);
+    if (gl == 0) y[i] = (b ? b[i] : (T)0) + sign * acc;
+  }
+}
+
+// y = b + sign * A_diag x from the sliced copy: one wave per slice, one row
+// per lane, the slice's entries read slot-interleaved (fully coalesced).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_spmv_sell(int64_t nslices, const int64_t* __restrict__ sptr, const int32_t* __restrict__ rows,
+                const int32_t* __restrict__ col, const T* __restrict__ val, const T* __restrict__ x,
+                const T* __restrict__ b, T* __restrict__ y, T sign) {
+  const int64_t sl = (int64_t)xcd_block_id(gridDim.x) * (kBlock / kSellC) + threadIdx.x / kSellC;
+  if (sl >= nslices) return;
+  const int t = threadIdx.x % kSellC;
+  const int64_t e0 = sptr[sl], e1 = sptr[sl + 1];
+  T acc = 0;
+#pragma unroll 4
+  for (int64_t d = e0 + t; d < e1; d += kSellC) acc += val[d] * x[col[d]];
+  const int32_t row = rows[sl * kSellC + t];
+  if (row >= 0) y[row] = (b ? b[row] : (T)0) + sign * acc;
 }
 
 // --------------------------------------------------------------------- CG
@@ -343,6 +421,57 @@ __global__ void __launch_bounds__(kBlock)
   block_partial(s, sm, pqp, blk);
 }
 
+// q = A p with recomputed values (variant code G + 3000); partial p.q per block.
+template <int G, int DIM, typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_cg_spmv1_rec(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                   const double4* __restrict__ rec, const TX* __restrict__ p, TX* __restrict__ q,
+                   const CgLevel* __restrict__ st, double* __restrict__ pqp) {
+  __shared__ double sm[kBlock / kWave];
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (st[l].done) return;
+  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
+  const int gl = threadIdx.x % G;
+  double s = 0.0;
+  for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
+    const TX acc = rec_row_dot<G, DIM, TX, TX>(rp, col, rec, p, i, gl, rec[i]);
+    if (gl == 0) {
+      q[i] = acc;
+      s += (double)p[i] * (double)acc;
+    }
+  }
+  block_partial(s, sm, pqp, blk);
+}
+
+// q = A p from the sliced copy (variant kSellCode): blocks of 4 slices of
+// one level; partial p.q per block.
+template <typename TV, typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_cg_spmv1_sell(const WorkTable wt, int base, const int64_t* __restrict__ sptr, const int32_t* __restrict__ rows,
+                    const int32_t* __restrict__ col, const TV* __restrict__ val, const TX* __restrict__ p,
+                    TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ pqp) {
+  __shared__ double sm[kBlock / kWave];
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (st[l].done) return;
+  const int64_t sl = wt.row0[blk] + threadIdx.x / kSellC;
+  const int t = threadIdx.x % kSellC;
+  double s = 0.0;
+  if (sl < wt.row1[blk]) {
+    const int64_t e0 = sptr[sl], e1 = sptr[sl + 1];
+    TX acc = 0;
+#pragma unroll 4
+    for (int64_t d = e0 + t; d < e1; d += kSellC) acc += (TX)val[d] * p[col[d]];
+    const int32_t row = rows[sl * kSellC + t];
+    if (row >= 0) {
+      q[row] = acc;
+      s = (double)p[row] * (double)acc;
+    }
+  }
+  block_partial(s, sm, pqp, blk);
+}
+
 // One block per level: alpha = rr / p.q.
 __global__ void __launch_bounds__(kRedBlock) k_cg_red_a(int lev0, const int32_t* __restrict__ lev_begin,
                                                      const double* __restrict__ pqp, CgLevel* __restrict__ st) {
@@ -438,7 +567,29 @@ static void launch_cg_spmv(hipStream_t s, int code, const WorkTable& wt, int bas
 
 template <typename TV, typename TX>
 static void launch_cg_spmv1(hipStream_t s, int code, const WorkTable& wt, int base, int nb, const Csr& A,
-                            const TV* val, const TX* p, TX* q, const CgLevel* st, double* pqp) {
+                            const TV* val, const TX* p, TX* q, const CgLevel* st, double* pqp, const double* rec,
+                            int dim) {
+  if (code >= 3 * kVecFlag) {
+    const double4* r4 = reinterpret_cast<const double4*>(rec);
+#define MSKM_CGREC_CASE(GG)                                                                                   \
+  case GG:                                                                                                   \
+    if (dim == 3)                                                                                            \
+      hipLaunchKernelGGL((k_cg_spmv1_rec<GG, 3, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
+                         r4, p, q, st, pqp);                                                                 \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_cg_spmv1_rec<GG, 2, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
+                         r4, p, q, st, pqp);                                                                 \
+    return;
+    switch (code - 3 * kVecFlag) {
+      MSKM_CGREC_CASE(4)
+      MSKM_CGREC_CASE(8)
+      MSKM_CGREC_CASE(16)
+      MSKM_CGREC_CASE(32)
+      default:
+        MSKM_CGREC_CASE(64)
+    }
+#undef MSKM_CGREC_CASE
+  }
 #define MSKM_CGSPMV1_CASE(GG)                                                                                    \
   case GG:                                                                                                      \
     hipLaunchKernelGGL((k_cg_spmv1<GG, false, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
@@ -505,7 +656,7 @@ static mskm_status get_ws(mskm_hier* h, SolveWS** out) {
     if (st == MSKM_OK) st = dalloc(v, N);
   if (st == MSKM_OK) st = dalloc(&w->f32, N);
   if (st == MSKM_OK) st = dalloc(&w->a32, N);
-  if (st == MSKM_OK) st = dalloc(&w->part_s, (size_t)h->wt_spmv.nblocks);
+  if (st == MSKM_OK) st = dalloc(&w->part_s, (size_t)std::max(h->wt_spmv.nblocks, h->wt_sell.nblocks));
   if (st == MSKM_OK) st = dalloc(&w->part_s2, h->wt_spmv.nblocks);
   if (st == MSKM_OK) st = dalloc(&w->part_v, h->wt_vec.nblocks);
   if (st == MSKM_OK) st = dalloc(&w->st, h->L);
@@ -520,6 +671,17 @@ static mskm_status get_ws(mskm_hier* h, SolveWS** out) {
   h->solve_ws_free = free_solve_ws;
   *out = w;
   return MSKM_OK;
+}
+
+template <typename TV>
+static const TV* sell_values(const Sell& S);
+template <>
+const double* sell_values<double>(const Sell& S) {
+  return S.val;
+}
+template <>
+const float* sell_values<float>(const Sell& S) {
+  return S.val32;
 }
 
 struct CgStats {
@@ -539,14 +701,25 @@ static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int 
   const int nlev = hi - lo + 1;
   const int sb0 = ws.h_lev_begin[lo], sbn = ws.h_lev_begin[hi + 1] - sb0;
   const int vb0 = wv.h_lev_begin[lo], vbn = wv.h_lev_begin[hi + 1] - vb0;
+  const WorkTable& wc = h->wt_sell;
+  const int cb0 = wc.h_lev_begin[lo], cbn = wc.h_lev_begin[hi + 1] - cb0;
   TX* p[2] = {(TX*)W.p0, (TX*)W.p1};
   TX* r = (TX*)W.r;
   TX* q = (TX*)W.q;
   for (int it = 0; it < K; ++it) {
     // direction update (beta = 0 on the first iteration after the init, p0 = 0 there)
     if (vbn > 0) hipLaunchKernelGGL(k_cg_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, r, p[0], W.st);
-    if (sbn > 0) launch_cg_spmv1<TV, TX>(s, G, ws, sb0, sbn, h->diag, dval, p[0], q, W.st, W.part_s);
-    hipLaunchKernelGGL(k_cg_red_a, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.st);
+    if (G == kSellCode) {
+      const TV* sv = sell_values<TV>(h->sell);
+      if (cbn > 0)
+        hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX>), dim3(cbn), dim3(kBlock), 0, s, wc, cb0, h->sell.sptr,
+                           h->sell.rows, h->sell.col, sv, p[0], q, W.st, W.part_s);
+      hipLaunchKernelGGL(k_cg_red_a, dim3(nlev), dim3(kRedBlock), 0, s, lo, wc.lev_begin, W.part_s, W.st);
+    } else {
+      if (sbn > 0)
+        launch_cg_spmv1<TV, TX>(s, G, ws, sb0, sbn, h->diag, dval, p[0], q, W.st, W.part_s, h->prec, h->dim);
+      hipLaunchKernelGGL(k_cg_red_a, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.st);
+    }
     if (vbn > 0)
       hipLaunchKernelGGL(k_cg_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p[0], q, W.st, W.part_v);
     hipLaunchKernelGGL(k_cg_red_b, dim3(nlev), dim3(kRedBlock), 0, s, lo, wv.lev_begin, W.part_v, W.st);
@@ -602,7 +775,7 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
   const int nlev = hi - lo + 1;
   const int sb0 = ws.h_lev_begin[lo], sbn = ws.h_lev_begin[hi + 1] - sb0;
   int G = h->spmv_g[MSKM_OP_DIAG][sizeof(TX) == 4 ? 1 : 0];
-  if (G >= 2 * kVecFlag) G -= kVecFlag;  // CG SpMV: 16-byte loads (no non-temporal variant)
+  if (G >= 2 * kVecFlag && G < 3 * kVecFlag) G -= kVecFlag;  // CG SpMV: 16-byte loads (no non-temporal variant)
   if (mlp) {  // learned warm start x0 = MLP(b) on every participating level
     for (int l = lo; l <= hi; ++l)
       if (on[l]) MSKM_TRY(mlp_predict_rows<TX>(h, mlp, l, b, x));
@@ -667,7 +840,7 @@ static void spmv_launch(hipStream_t s, int G, const Csr* A1, const T* v1, const 
 template <typename TV, typename TX>
 static void lower_update(mskm_hier* h, const TV* lval, const TX* t, const TX* f, TX* beta, int64_t r0, int64_t r1) {
   spmv_launch<TX>(h->ctx->stream, h->spmv_g[MSKM_OP_LOWER][sizeof(TX) == 4 ? 1 : 0], &h->lower, lval, nullptr,
-                  nullptr, t, f, beta, (TX)-1, r0, r1);
+                  nullptr, t, f, beta, (TX)-1, r0, r1, h->prec, h->dim);
 }
 
 // alpha = T^-1 f in the internal order: monolithic (Jacobi sweeps on T' with
@@ -754,43 +927,25 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Same with FP64 values recomputed from the coordinates (when only FP32 values
-// are stored): v = phi(sqrt(d2)/delta_j). A row of level k holds columns of
-// its hierarchy's levels first(k) .. k in ascending order; the level of a
-// column follows by walking that chain (each lane's columns ascend).
-template <int G>
-__device__ __forceinline__ double row_dot_recompute(int dim, const DevLevel* __restrict__ lev, int j0,
-                                                    const double* __restrict__ xs, int64_t N,
-                                                    const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                    const double* __restrict__ a, int64_t i, int gl) {
-  const double px = xs[i], py = xs[N + i], pz = dim == 3 ? xs[2 * N + i] : 0.0;
-  double acc = 0.0;
-  int j = j0;
-  for (int64_t k = rp[i] + gl; k < rp[i + 1]; k += G) {
-    const int64_t c = col[k];
-    while (c >= lev[j].off + lev[j].n && lev[j].next >= 0) j = lev[j].next;
-    const double d2 = sqdist(dim, px, py, pz, xs[c], xs[N + c], dim == 3 ? xs[2 * N + c] : 0.0);
-    acc += phi31_d2(d2, lev[j].delta) * a[c];
-  }
-  return group_sum<G>(acc);
-}
-
+// Same with FP64 values recomputed from the point records (when only FP32
+// values are stored): v = phi(sqrt(d2) * (1/delta_j)) over the stored
+// structure, 16-byte column loads.
+template <int DIM>
 __global__ void __launch_bounds__(kBlock)
-    k_residual_recompute(const WorkTable wt, int dim, const DevLevel* __restrict__ lev, const double* __restrict__ xs,
-                         int64_t N, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
-                         const int64_t* __restrict__ lrp, const int32_t* __restrict__ lc,
-                         const double* __restrict__ a, const double* __restrict__ f, double* __restrict__ part,
-                         double* __restrict__ rout) {
+    k_residual_rec(const WorkTable wt, const double4* __restrict__ rec, const int64_t* __restrict__ drp,
+                   const int32_t* __restrict__ dc, const int64_t* __restrict__ lrp, const int32_t* __restrict__ lc,
+                   const double* __restrict__ a, const double* __restrict__ f, double* __restrict__ part,
+                   double* __restrict__ rout) {
   constexpr int G = 16;
   __shared__ double sm[kBlock / kWave];
   const int blk = xcd_block_id(gridDim.x);
-  const int l = wt.lev[blk];
   const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
   const int gl = threadIdx.x % G;
   double srr = 0.0, sff = 0.0;
   for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
-    double acc = row_dot_recompute<G>(dim, lev, l, xs, N, drp, dc, a, i, gl);
-    acc += row_dot_recompute<G>(dim, lev, lev[l].first, xs, N, lrp, lc, a, i, gl);
+    const double4 me = rec[i];
+    double acc = rec_row_dot<G, DIM, double, double>(drp, dc, rec, a, i, gl, me);
+    acc += rec_row_dot<G, DIM, double, double>(lrp, lc, rec, a, i, gl, me);
     if (gl == 0) {
       const double ri = f[i] - acc;
       if (rout) rout[i] = ri;
@@ -806,21 +961,48 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// Residual of a = 0: r = f (partials of f.f twice).
+__global__ void __launch_bounds__(kBlock)
+    k_residual_zero(const WorkTable wt, const double* __restrict__ f, double* __restrict__ part,
+                    double* __restrict__ rout) {
+  __shared__ double sm[kBlock / kWave];
+  const int blk = xcd_block_id(gridDim.x);
+  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
+  double sff = 0.0;
+  for (int64_t i = row0 + threadIdx.x; i < row1; i += kBlock) {
+    const double fi = f[i];
+    if (rout) rout[i] = fi;
+    sff += fi * fi;
+  }
+  sff = block_sum(sff, sm);
+  if (threadIdx.x == 0) {
+    part[2 * blk] = sff;
+    part[2 * blk + 1] = sff;
+  }
+}
+
 // ||f - T a|| / ||f|| per group (rel_groups, host [ngroups]) and the maximum
 // over groups (*rel), internal order device vectors. rout (nullable)
 // receives r. FP64 values are used when stored, else recomputed.
 static mskm_status residual_internal(mskm_hier* h, const double* a, const double* f, double* rel, double* rout,
-                                     double* rel_groups = nullptr) {
+                                     double* rel_groups = nullptr, bool a_zero = false) {
   hipStream_t s = h->ctx->stream;
   const WorkTable& wt = h->wt_spmv;
   double* part = nullptr;
   MSKM_TRY(dalloc(&part, 2 * (size_t)wt.nblocks));
-  if (h->diag.val && h->lower.val) {
+  if (a_zero) {
+    hipLaunchKernelGGL(k_residual_zero, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, f, part, rout);
+  } else if (h->diag.val && h->lower.val) {
     hipLaunchKernelGGL(k_residual64, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->diag.rowptr, h->diag.col,
                        h->diag.val, h->lower.rowptr, h->lower.col, h->lower.val, a, f, part, rout);
   } else {
-    hipLaunchKernelGGL(k_residual_recompute, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->dim, h->d_lev, h->xs, h->N,
-                       h->diag.rowptr, h->diag.col, h->lower.rowptr, h->lower.col, a, f, part, rout);
+    const double4* r4 = reinterpret_cast<const double4*>(h->prec);
+    if (h->dim == 3)
+      hipLaunchKernelGGL(k_residual_rec<3>, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, r4, h->diag.rowptr, h->diag.col,
+                         h->lower.rowptr, h->lower.col, a, f, part, rout);
+    else
+      hipLaunchKernelGGL(k_residual_rec<2>, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, r4, h->diag.rowptr, h->diag.col,
+                         h->lower.rowptr, h->lower.col, a, f, part, rout);
   }
   std::vector<double> hp(2 * (size_t)wt.nblocks);
   hipError_t e = hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, s);
@@ -929,10 +1111,31 @@ mskm_status stage_out_copy(hipStream_t s, double* dst, size_t n, bool io_dev, De
 // G chosen at run time among the compiled widths.
 template <typename T>
 static void spmv_launch(hipStream_t s, int G, const Csr* A1, const T* v1, const Csr* A2, const T* v2, const T* x,
-                        const T* b, T* y, T sign, int64_t r0, int64_t r1) {
+                        const T* b, T* y, T sign, int64_t r0, int64_t r1, const double* rec, int dim) {
   if (r1 <= r0) return;
   const int64_t* rp2 = A2 ? A2->rowptr : nullptr;
   const int32_t* c2 = A2 ? A2->col : nullptr;
+  if (G >= 3 * kVecFlag) {
+    const double4* r4 = reinterpret_cast<const double4*>(rec);
+#define MSKM_REC_CASE(GG)                                                                                          \
+  case GG:                                                                                                        \
+    if (dim == 3)                                                                                                 \
+      hipLaunchKernelGGL((k_spmv_rec<GG, 3, T>), dim3(nblk(r1 - r0, kBlock / GG)), dim3(kBlock), 0, s, A1->rowptr, \
+                         A1->col, rp2, c2, r4, x, b, y, sign, r0, r1);                                            \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_spmv_rec<GG, 2, T>), dim3(nblk(r1 - r0, kBlock / GG)), dim3(kBlock), 0, s, A1->rowptr, \
+                         A1->col, rp2, c2, r4, x, b, y, sign, r0, r1);                                            \
+    return;
+    switch (G - 3 * kVecFlag) {
+      MSKM_REC_CASE(4)
+      MSKM_REC_CASE(8)
+      MSKM_REC_CASE(16)
+      MSKM_REC_CASE(32)
+      default:
+        MSKM_REC_CASE(64)
+    }
+#undef MSKM_REC_CASE
+  }
 #define MSKM_SPMV_CASE(GG)                                                                                      \
   case GG:                                                                                                     \
     hipLaunchKernelGGL((k_spmv<GG, T, T, T>), dim3(nblk(r1 - r0, kBlock / GG)), dim3(kBlock), 0, s, A1->rowptr, \
@@ -965,7 +1168,14 @@ static void launch_apply(mskm_hier* h, int op, const T* v1, const T* v2, const T
   const Csr* A1 = op == MSKM_OP_LOWER ? &h->lower : &h->diag;
   const Csr* A2 = op == MSKM_OP_FULL ? &h->lower : nullptr;
   const int G = h->spmv_g[op][sizeof(T) == 4 ? 1 : 0];
-  spmv_launch<T>(h->ctx->stream, G, A1, v1, A2, v2, x, (const T*)nullptr, y, (T)1, 0, h->N);
+  if (G == kSellCode) {  // diagonal operator only
+    if (h->sell.nslices > 0)
+      hipLaunchKernelGGL(k_spmv_sell<T>, dim3(nblk(h->sell.nslices, kBlock / kSellC)), dim3(kBlock), 0,
+                         h->ctx->stream, h->sell.nslices, h->sell.sptr, h->sell.rows, h->sell.col,
+                         sell_values<T>(h->sell), x, (const T*)nullptr, y, (T)1);
+    return;
+  }
+  spmv_launch<T>(h->ctx->stream, G, A1, v1, A2, v2, x, (const T*)nullptr, y, (T)1, 0, h->N, h->prec, h->dim);
 }
 
 mskm_status apply_internal(mskm_hier* h, int op, int prec, const void* x, void* y, int repeats, float* avg_ms) {
@@ -993,21 +1203,8 @@ mskm_status apply_internal(mskm_hier* h, int op, int prec, const void* x, void* 
 // width on the hierarchy's own matrices (scratch vectors, `repeats` launches
 // each after one warm-up) and keep the fastest.
 mskm_status autotune(mskm_hier* h, int repeats, float* times_out) {
-  static const int widths[] = {4,
-                               8,
-                               16,
-                               32,
-                               64,
-                               4 + kVecFlag,
-                               8 + kVecFlag,
-                               16 + kVecFlag,
-                               32 + kVecFlag,
-                               64 + kVecFlag,
-                               4 + 2 * kVecFlag,
-                               8 + 2 * kVecFlag,
-                               16 + 2 * kVecFlag,
-                               32 + 2 * kVecFlag,
-                               64 + 2 * kVecFlag};
+  static const int widths[kTuneVariants] = {4,    8,    16,   32,   64,   1004, 1008, 1016, 1032, 1064, 2004,
+                                            2008, 2016, 2032, 2064, 3004, 3008, 3016, 3032, 3064, kSellCode};
   double* x = nullptr;
   double* y = nullptr;
   MSKM_TRY(dalloc(&x, h->N));
@@ -1021,6 +1218,10 @@ mskm_status autotune(mskm_hier* h, int repeats, float* times_out) {
       float best = 1e30f;
       int bestg = h->spmv_g[op][prec];
       for (int wi = 0; wi < kTuneVariants && st == MSKM_OK; ++wi) {
+        if (widths[wi] == kSellCode && op != MSKM_OP_DIAG) {  // the sliced copy holds the diagonal blocks only
+          if (times_out) times_out[(op * 2 + prec) * kTuneVariants + wi] = 0.f;
+          continue;
+        }
         h->spmv_g[op][prec] = widths[wi];
         float ms = 0.f;
         st = apply_internal(h, op, prec, x, y, 1, nullptr);
@@ -1117,7 +1318,7 @@ mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_o
       MSKM_HIP_TRY(hipMemsetAsync(ai, 0, N * 8, s));
       refine = 0;
       for (;;) {
-        MSKM_TRY(residual_internal(h, ai, fi, &rel, W.res));
+        MSKM_TRY(residual_internal(h, ai, fi, &rel, W.res, nullptr, refine == 0));  // alpha = 0 at the start
         if (rel <= o->target_rel_residual || refine >= maxref) break;
         hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(N)), dim3(kBlock), 0, s, (const double*)W.res, W.f32,
                            N);

@@ -102,6 +102,63 @@ def test_spmv_fp64_and_fp32(mod, ctx, name):
         assert _rel(y32, ref) <= 1e-5, op  # FP32 values, FP32 accumulation
 
 
+@pytest.mark.parametrize("name", ["halton5", "uniform3d3"])
+def test_every_spmv_variant(mod, ctx, name):
+    """Each of the autotuner's SpMV variants, pinned explicitly, against the
+    oracle's products (the variants differ only in summation order)."""
+    h, f, blk, hd, _ = _setup(mod, ctx, name)
+    x = np.random.default_rng(4).standard_normal(h.n_total)
+    D = [blk.mat(l, l) for l in range(h.levels)]
+    off = h.offsets
+    yd = np.concatenate([D[l] @ x[off[l]:off[l + 1]] for l in range(h.levels)])
+    yl = ms.lower_matrix(blk) @ x
+    saved = {(op, pr): mod.mskm_spmv_width(hd, op, pr) for op in range(3) for pr in range(2)}
+    try:
+        for code in mod.TUNE_VARIANTS:
+            for op, ref in ((mod.MSKM_OP_DIAG, yd), (mod.MSKM_OP_LOWER, yl), (mod.MSKM_OP_FULL, yd + yl)):
+                if code == mod.SELL_CODE and op != mod.MSKM_OP_DIAG:
+                    with pytest.raises(mod.MskmError):  # the sliced copy holds the diagonal blocks only
+                        mod.mskm_set_spmv_width(hd, op, 0, code)
+                    continue
+                for pr, tol in ((mod.MSKM_PREC_FP64, 1e-14), (mod.MSKM_PREC_FP32, 1e-5)):
+                    mod.mskm_set_spmv_width(hd, op, pr, code)
+                    y = np.zeros_like(x)
+                    mod.mskm_apply(ctx, hd, op, x, y, prec=pr)
+                    assert _rel(y, ref) <= tol, (code, op, pr)
+        for bad in (0, 3, 65, 1005, 4004, -4):
+            with pytest.raises(mod.MskmError):
+                mod.mskm_set_spmv_width(hd, 0, 0, bad)
+    finally:
+        for (op, pr), w in saved.items():
+            mod.mskm_set_spmv_width(hd, op, pr, w)
+
+
+@pytest.mark.parametrize("name", ["halton5", "uniform3d3"])
+@pytest.mark.parametrize("code", [3008, 3016, 4064])
+def test_solve_with_variant(mod, ctx, name, code):
+    """Solves whose CG products run on the recomputed-value or the sliced
+    (SELL) variant, and whose lower-block products recompute the values,
+    still match the oracle (FP64 and mixed)."""
+    h, f, blk, hd, a_ref = _setup(mod, ctx, name)
+    saved = {(op, pr): mod.mskm_spmv_width(hd, op, pr) for op in range(3) for pr in range(2)}
+    try:
+        for op in range(3):
+            for pr in range(2):
+                mod.mskm_set_spmv_width(hd, op, pr, code if op == 0 or code != mod.SELL_CODE else 3016)
+        for prec, bar in ((mod.MSKM_PREC_FP64, 1e-10), (mod.MSKM_PREC_FP32, 1e-8)):
+            alpha = np.zeros_like(f)
+            o = mod.solve_opts(precision=prec, cg_rtol=1e-14 if prec == mod.MSKM_PREC_FP64 else 1e-5,
+                               target_rel_residual=1e-13, max_refine=20, max_cg_iters=20000)
+            res = mod.mskm_solve(ctx, hd, f, alpha, o)
+            assert res.status == mod.MSKM_OK, res.report
+            for l in range(h.levels):
+                sl = slice(h.offsets[l], h.offsets[l + 1])
+                assert _rel(alpha[sl], a_ref[sl]) <= bar, (prec, l, _rel(alpha[sl], a_ref[sl]))
+    finally:
+        for (op, pr), w in saved.items():
+            mod.mskm_set_spmv_width(hd, op, pr, w)
+
+
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("alg", ["monolithic", "sequential", "monolithic_warm"])
 def test_solve_fp64(mod, ctx, name, alg):
@@ -132,6 +189,31 @@ def test_solve_mixed_refined(mod, ctx, name):
         sl = slice(h.offsets[l], h.offsets[l + 1])
         assert _rel(alpha[sl], a_ref[sl]) <= 1e-8, (l, _rel(alpha[sl], a_ref[sl]))
     assert oracle.residual(blk, alpha, f)[0] <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["grid4", "halton5", "uniform3d3"])
+def test_fp32_only_hierarchy(mod, ctx, name):
+    """A hierarchy that stores only FP32 values: its FP64 residual recomputes
+    the entries from the points, and the mixed solve still reaches the
+    oracle's coefficients."""
+    h, f, blk, _, a_ref = _setup(mod, ctx, name)
+    hd = mod.mskm_hier_create(ctx, h.points, h.offsets, h.delta, fp64=False, fp32=True)
+    try:
+        a = a_ref + 1e-6 * np.random.default_rng(21).standard_normal(a_ref.shape)
+        rel = mod.mskm_residual(ctx, hd, a, f)[0]
+        assert rel == pytest.approx(oracle.residual(blk, a, f)[0], rel=1e-9)
+        assert mod.mskm_residual(ctx, hd, np.zeros_like(f), f)[0] == pytest.approx(1.0, rel=1e-14)
+        alpha = np.zeros_like(f)
+        res = mod.mskm_solve(ctx, hd, f, alpha, mod.solve_opts(precision=mod.MSKM_PREC_FP32, cg_rtol=1e-6,
+                                                               target_rel_residual=1e-13, max_refine=20))
+        assert res.status == mod.MSKM_OK, res.report
+        for l in range(h.levels):
+            sl = slice(h.offsets[l], h.offsets[l + 1])
+            assert _rel(alpha[sl], a_ref[sl]) <= 1e-8, (l, _rel(alpha[sl], a_ref[sl]))
+        with pytest.raises(mod.MskmError):  # FP64 solves need the FP64 values
+            mod.mskm_solve(ctx, hd, f, alpha, mod.solve_opts(precision=mod.MSKM_PREC_FP64))
+    finally:
+        mod.mskm_hier_destroy(hd)
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -222,7 +304,9 @@ def test_autotune_keeps_results(mod, ctx):
     y0 = np.zeros_like(x)
     mod.mskm_apply(ctx, hd, mod.MSKM_OP_FULL, x, y0)
     t = mod.mskm_autotune(ctx, hd, repeats=2)
-    assert t.shape == (3, 2, len(mod.TUNE_VARIANTS)) and np.all(t > 0)
+    assert t.shape == (3, 2, len(mod.TUNE_VARIANTS))
+    sell = mod.TUNE_VARIANTS.index(mod.SELL_CODE)
+    assert np.all(np.delete(t, sell, axis=2) > 0) and np.all(t[0, :, sell] > 0) and np.all(t[1:, :, sell] == 0)
     for op in range(3):
         for pr in range(2):
             assert mod.mskm_spmv_width(hd, op, pr) in mod.TUNE_VARIANTS
