@@ -573,32 +573,17 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
 
 // ------------------------------------------------------------------ SELL
 
-// One block per window {row0, cnt, slot0}: rank of each row by (length
-// descending, row ascending) among the window's rows, written as the row of
-// slot slot0 + rank; slots past the window's rows up to its last full slice
-// get -1.
-__global__ void __launch_bounds__(kSellWin) k_sell_sort(const int64_t* __restrict__ win,
-                                                        const int64_t* __restrict__ rp, int32_t* __restrict__ rows) {
-  __shared__ int32_t len[kSellWin];
-  const int64_t row0 = win[3 * blockIdx.x], cnt = win[3 * blockIdx.x + 1], slot0 = win[3 * blockIdx.x + 2];
-  const int t = threadIdx.x;
-  len[t] = t < cnt ? (int32_t)(rp[row0 + t + 1] - rp[row0 + t]) : -1;
-  __syncthreads();
-  if (t < cnt) {
-    const int32_t me = len[t];
-    int rank = 0;
-    for (int u = 0; u < cnt; ++u) {
-      const int32_t o = len[u];
-      rank += (o > me) || (o == me && u < t);
-    }
-    rows[slot0 + rank] = (int32_t)(row0 + t);
-  } else if (t < (cnt + kSellC - 1) / kSellC * kSellC) {
-    rows[slot0 + t] = -1;
-  }
+// Row of every slot: slot t of the level's slices holds row off + t, or -1
+// past the level's last row.
+__global__ void __launch_bounds__(kBlock) k_sell_rows(int64_t off, int64_t n, int64_t slot0, int64_t nslots,
+                                                      int32_t* __restrict__ rows) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nslots) return;
+  rows[slot0 + t] = t < n ? (int32_t)(off + t) : -1;
 }
 
-// Width (in entries, w_s * kSellC) of every slice: its first slot holds its
-// longest row. Entry nslices is 0 (scan sentinel).
+// Width (in entries, w_s * kSellC) of every slice: its longest row times
+// kSellC. Entry nslices is 0 (scan sentinel).
 __global__ void __launch_bounds__(kBlock) k_sell_width(int64_t nslices, const int32_t* __restrict__ rows,
                                                        const int64_t* __restrict__ rp, int64_t* __restrict__ w) {
   const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -607,8 +592,12 @@ __global__ void __launch_bounds__(kBlock) k_sell_width(int64_t nslices, const in
     w[s] = 0;
     return;
   }
-  const int32_t r = rows[s * kSellC];
-  w[s] = r >= 0 ? (rp[r + 1] - rp[r]) * kSellC : 0;
+  int64_t m = 0;
+  for (int t = 0; t < kSellC; ++t) {
+    const int32_t r = rows[s * kSellC + t];
+    if (r >= 0) m = max(m, rp[r + 1] - rp[r]);
+  }
+  w[s] = m * kSellC;
 }
 
 // One wave per slice: copy the CSR rows into the slot-interleaved layout.
@@ -639,31 +628,24 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32) {
   Sell& S = h->sell;
   const int L = h->L;
   S.h_slice_begin.assign(L + 1, 0);
-  std::vector<int64_t> win;  // {row0, cnt, slot0} per window
-  for (int l = 0; l < L; ++l) {
-    const int64_t a = h->h_off[l], n = h->h_off[l + 1] - a;
-    S.h_slice_begin[l + 1] = S.h_slice_begin[l] + (n + kSellC - 1) / kSellC;
-    for (int64_t w = 0; w < n; w += kSellWin) {
-      win.push_back(a + w);
-      win.push_back(std::min<int64_t>(kSellWin, n - w));
-      win.push_back(S.h_slice_begin[l] * kSellC + w);
-    }
-  }
+  for (int l = 0; l < L; ++l)
+    S.h_slice_begin[l + 1] = S.h_slice_begin[l] + (h->h_off[l + 1] - h->h_off[l] + kSellC - 1) / kSellC;
   S.nslices = S.h_slice_begin[L];
-  const int64_t nw = (int64_t)win.size() / 3;
   MSKM_TRY(halloc(h, &S.rows, (size_t)S.nslices * kSellC));
   MSKM_TRY(halloc(h, &S.sptr, (size_t)S.nslices + 1));
-  int64_t *d_win = nullptr, *d_w = nullptr;
-  MSKM_TRY(dalloc(&d_win, win.size()));
+  for (int l = 0; l < L; ++l) {
+    const int64_t nslots = (S.h_slice_begin[l + 1] - S.h_slice_begin[l]) * kSellC;
+    if (nslots > 0)
+      hipLaunchKernelGGL(k_sell_rows, dim3(grid_for(nslots, kBlock)), dim3(kBlock), 0, s, h->h_off[l],
+                         h->h_off[l + 1] - h->h_off[l], S.h_slice_begin[l] * kSellC, nslots, S.rows);
+  }
+  int64_t* d_w = nullptr;
   MSKM_TRY(dalloc(&d_w, (size_t)S.nslices + 1));
-  MSKM_HIP_TRY(hipMemcpyAsync(d_win, win.data(), win.size() * 8, hipMemcpyHostToDevice, s));
-  if (nw > 0) hipLaunchKernelGGL(k_sell_sort, dim3((unsigned)nw), dim3(kSellWin), 0, s, d_win, h->diag.rowptr, S.rows);
   hipLaunchKernelGGL(k_sell_width, dim3(grid_for(S.nslices + 1, kBlock)), dim3(kBlock), 0, s, S.nslices, S.rows,
                      h->diag.rowptr, d_w);
   MSKM_TRY(exclusive_scan_i64(s, d_w, S.sptr, S.nslices + 1));
   MSKM_HIP_TRY(hipMemcpyAsync(&S.entries, S.sptr + S.nslices, 8, hipMemcpyDeviceToHost, s));
   MSKM_HIP_TRY(hipStreamSynchronize(s));
-  (void)hipFree(d_win);
   (void)hipFree(d_w);
   MSKM_TRY(halloc(h, &S.col, (size_t)S.entries));
   if (want64) MSKM_TRY(halloc(h, &S.val, (size_t)S.entries));

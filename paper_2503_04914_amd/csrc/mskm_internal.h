@@ -35,7 +35,6 @@ constexpr int kVecFlag = 1000;
 constexpr int kSellCode = 4064;
 constexpr int kTuneVariants = 21;  // widths 4..64 x the four kinds, then SELL (diagonal operator only)
 constexpr int kSellC = 64;         // SELL slice height: one wave, one row per lane
-constexpr int kSellWin = 1024;     // rows are sorted by length within windows of this many rows
 
 // Per-level descriptor read by the kernels (all fields uniform per wave).
 struct DevLevel {
@@ -65,12 +64,13 @@ struct WorkTable {
   std::vector<int32_t> h_lev_begin;
 };
 
-// Sliced-ELL copy of the diagonal blocks. Each level's rows are cut into
-// windows of kSellWin rows (from the level start), sorted by row length
-// (descending, ties by row) inside the window, and dealt into slices of
-// kSellC slots; slice s stores its width w_s = longest row of the slice and
-// entry k of slot t at sptr[s] + k * kSellC + t (shorter rows padded with
-// value 0 and their own row as column).
+// Sliced-ELL copy of the diagonal blocks. Each level's rows, in the internal
+// (cell) order, are cut into slices of kSellC consecutive rows from the level
+// start; slice s stores its width w_s = longest row of the slice and entry k
+// of slot t at sptr[s] + k * kSellC + t (shorter rows padded with value 0
+// and their own row as column). Rows are not reordered by length: keeping
+// neighbouring rows together keeps the gathers of one load instruction on
+// few cache lines, which measures faster than the padding it saves.
 struct Sell {
   int64_t nslices = 0, entries = 0;
   int64_t* sptr = nullptr;   // [nslices + 1]

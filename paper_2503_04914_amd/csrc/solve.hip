@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(kBlock)
            const TX* __restrict__ x, const TX* __restrict__ b, TX* __restrict__ y, TA sign, int64_t r0, int64_t r1) {
   const int gl = threadIdx.x % G;
   const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
-  for (int64_t i = r0 + (int64_t)xcd_block_id(gridDim.x) * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
+  for (int64_t i = r0 + (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
     TA acc = csr_row_dot<G, TV, TX, TA>(rp1, c1, v1, x, i, gl);
     if (rp2) acc += csr_row_dot<G, TV, TX, TA>(rp2, c2, v2, x, i, gl);
     if (gl == 0) y[i] = (TX)((b ? (TA)b[i] : (TA)0) + sign * acc);
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(kBlock)
              const TX* __restrict__ x, const TX* __restrict__ b, TX* __restrict__ y, TA sign, int64_t r0, int64_t r1) {
   const int gl = threadIdx.x % G;
   const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
-  for (int64_t i = r0 + (int64_t)xcd_block_id(gridDim.x) * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
+  for (int64_t i = r0 + (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
     TA acc = csr_row_dot_v<G, TV, TX, TA, NT>(rp1, c1, v1, x, i, gl);
     if (rp2) acc += csr_row_dot_v<G, TV, TX, TA, NT>(rp2, c2, v2, x, i, gl);
     if (gl == 0) y[i] = (TX)((b ? (TA)b[i] : (TA)0) + sign * acc);
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(kBlock)
                const T* __restrict__ b, T* __restrict__ y, T sign, int64_t r0, int64_t r1) {
   const int gl = threadIdx.x % G;
   const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
-  for (int64_t i = r0 + (int64_t)xcd_block_id(gridDim.x) * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
+  for (int64_t i = r0 + (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; i < r1; i += groups) {
     const double4 me = rec[i];
     T acc = rec_row_dot<G, DIM, T, T>(rp1, c1, rec, x, i, gl, me);
     if (rp2) acc += rec_row_dot<G, DIM, T, T>(rp2, c2, rec, x, i, gl, me);
@@ -229,14 +229,22 @@ __global__ void __launch_bounds__(kBlock)
 // --------------------------------------------------------------------- CG
 //
 // Conjugate gradients on A_l x_l = b_l for every participating level l, all
-// levels in each launch. Four kernels per iteration, no grid-wide fences:
-//   spmv   (iteration i): p_new = r + beta p_old for the block's rows and
-//          q = A p_new, gathering r and p_old (q_i = sum_j a_ij (r_j + beta
-//          p_old_j)); partial p_new.q per block.
-//   red_a  one block per level: alpha = rr / sum(partials).
-//   update x += alpha p_new; r -= alpha q; partial r.r per block.
+// levels in each launch, no grid-wide fences. Textbook form (Theorem cg),
+// five kernels per iteration:
+//   dir    p = r + beta p
+//   spmv   q = A p; partial p.q per block
+//   red_a  one block per level: alpha = rr / sum(partials)
+//   update x += alpha p; r -= alpha q; partial r.r per block
 //   red_b  one block per level: rr_new, stop test ||r|| <= rtol ||b|| or the
 //          iteration cap, beta = rr_new / rr.
+// Single-reduction form (Chronopoulos and Gear's rearrangement, the same
+// iterates in exact arithmetic), three kernels per iteration, used for the
+// FP32 inner solves of the mixed path (the FP64 outer refinement bounds the
+// effect of its different rounding):
+//   spmv   q = A r; partials r.q and r.r per block
+//   red    one block per level: gamma = r.r, stop test, beta = gamma /
+//          gamma_prev, alpha = gamma / (r.q - beta gamma / alpha_prev)
+//   update p = r + beta p; s = q + beta s (= A p); x += alpha p; r -= alpha s.
 // The per-level scalars are written only by the reduce kernels and read by the
 // big kernels of the next phase; the kernel boundaries order and publish them.
 // Partial sums are reduced in block order: the result is deterministic.
@@ -254,6 +262,8 @@ struct CgLevel {
   int32_t done;   // stopped (converged, capped or broken down)
   int32_t capped; // stopped by the cap or by non-finite data
   int32_t pad;
+  double rr_prev;   // single-reduction form: r.r and step of the previous iteration
+  double alpha_prev;
 };
 
 constexpr int kRedBlock = 1024;  // threads of the per-level reduce kernels
@@ -278,7 +288,7 @@ __global__ void __launch_bounds__(kBlock)
     k_cg_init(const WorkTable wt, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
               const TV* __restrict__ val, const TX* __restrict__ b, TX* __restrict__ x, TX* __restrict__ r,
               TX* __restrict__ p0, const CgLevel* __restrict__ st, int warm, double* __restrict__ bbp,
-              double* __restrict__ rrp, int base) {
+              double* __restrict__ rrp, int base, TX* __restrict__ s0) {
   __shared__ double sm[kBlock / kWave];
   const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
@@ -295,6 +305,7 @@ __global__ void __launch_bounds__(kBlock)
         if (!warm) x[i] = (TX)0;
         r[i] = (TX)ri;
         p0[i] = (TX)0;
+        if (s0) s0[i] = (TX)0;
         sb += bi * bi;
         sr += (double)(TX)ri * (double)(TX)ri;
       }
@@ -320,66 +331,13 @@ __global__ void __launch_bounds__(kRedBlock) k_cg_red_init(int lev0, const int32
     S.beta = 0.0;
     S.iters = 0;
     S.capped = 0;
+    S.rr_prev = 0.0;
+    S.alpha_prev = 0.0;
     const bool finite = isfinite(bb) && isfinite(rr);
     const bool conv = finite && !(rr > S.rtol2 * bb);
     S.capped = S.on && !conv && (!finite || S.maxit <= 0);
     S.done = !S.on || conv || S.capped;
   }
-}
-
-// spmv phase: p_new = r + beta p_old; q = A p_new; partial p_new.q per block.
-// Launched over the table blocks [base, base + gridDim.x) of the
-// participating levels. VEC: 16-byte value/column loads (as csr_row_dot_v).
-template <int G, bool VEC, typename TV, typename TX>
-__global__ void __launch_bounds__(kBlock)
-    k_cg_spmv(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-              const TV* __restrict__ val, const TX* __restrict__ r, const TX* __restrict__ p_old,
-              TX* __restrict__ p_new, TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ pqp) {
-  __shared__ double sm[kBlock / kWave];
-  const int blk = base + xcd_block_id(gridDim.x);
-  const int l = wt.lev[blk];
-  if (st[l].done) return;
-  const TX beta = (TX)st[l].beta;
-  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
-  const int gl = threadIdx.x % G;
-  double s = 0.0;
-  for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
-    const int64_t ks = rp[i], ke = rp[i + 1];
-    TX acc = 0;
-    if constexpr (VEC) {
-      constexpr int V = 16 / sizeof(TV);
-      for (int64_t k = (ks & ~(int64_t)(V - 1)) + (int64_t)gl * V; k < ke; k += (int64_t)G * V) {
-        TV v[V];
-        int32_t c[V];
-        if constexpr (V == 2) {
-          const double2 vv = *reinterpret_cast<const double2*>(val + k);
-          const int2 cc = *reinterpret_cast<const int2*>(col + k);
-          v[0] = vv.x; v[1] = vv.y; c[0] = cc.x; c[1] = cc.y;
-        } else {
-          const float4 vv = *reinterpret_cast<const float4*>(val + k);
-          const int4 cc = *reinterpret_cast<const int4*>(col + k);
-          v[0] = vv.x; v[1] = vv.y; v[2] = vv.z; v[3] = vv.w;
-          c[0] = cc.x; c[1] = cc.y; c[2] = cc.z; c[3] = cc.w;
-        }
-#pragma unroll
-        for (int u = 0; u < V; ++u)
-          if (k + u >= ks && k + u < ke) acc += (TX)v[u] * (r[c[u]] + beta * p_old[c[u]]);
-      }
-    } else {
-      for (int64_t k = ks + gl; k < ke; k += G) {
-        const int32_t j = col[k];
-        acc += (TX)val[k] * (r[j] + beta * p_old[j]);
-      }
-    }
-    acc = group_sum<G>(acc);
-    if (gl == 0) {
-      const TX pn = r[i] + beta * p_old[i];
-      p_new[i] = pn;
-      q[i] = acc;
-      s += (double)pn * (double)acc;
-    }
-  }
-  block_partial(s, sm, pqp, blk);
 }
 
 // direction phase: p = r + beta p on the rows of not-stopped levels.
@@ -399,14 +357,14 @@ template <int G, bool VEC, typename TV, typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_cg_spmv1(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                const TV* __restrict__ val, const TX* __restrict__ p, TX* __restrict__ q,
-               const CgLevel* __restrict__ st, double* __restrict__ pqp) {
+               const CgLevel* __restrict__ st, double* __restrict__ pqp, double* __restrict__ ppp) {
   __shared__ double sm[kBlock / kWave];
   const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
   if (st[l].done) return;
   const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
   const int gl = threadIdx.x % G;
-  double s = 0.0;
+  double s = 0.0, s2 = 0.0;
   for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
     TX acc;
     if constexpr (VEC)
@@ -416,9 +374,11 @@ __global__ void __launch_bounds__(kBlock)
     if (gl == 0) {
       q[i] = acc;
       s += (double)p[i] * (double)acc;
+      s2 += (double)p[i] * (double)p[i];
     }
   }
   block_partial(s, sm, pqp, blk);
+  if (ppp) block_partial(s2, sm, ppp, blk);
 }
 
 // q = A p with recomputed values (variant code G + 3000); partial p.q per block.
@@ -426,22 +386,24 @@ template <int G, int DIM, typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_cg_spmv1_rec(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                    const double4* __restrict__ rec, const TX* __restrict__ p, TX* __restrict__ q,
-                   const CgLevel* __restrict__ st, double* __restrict__ pqp) {
+                   const CgLevel* __restrict__ st, double* __restrict__ pqp, double* __restrict__ ppp) {
   __shared__ double sm[kBlock / kWave];
   const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
   if (st[l].done) return;
   const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
   const int gl = threadIdx.x % G;
-  double s = 0.0;
+  double s = 0.0, s2 = 0.0;
   for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
     const TX acc = rec_row_dot<G, DIM, TX, TX>(rp, col, rec, p, i, gl, rec[i]);
     if (gl == 0) {
       q[i] = acc;
       s += (double)p[i] * (double)acc;
+      s2 += (double)p[i] * (double)p[i];
     }
   }
   block_partial(s, sm, pqp, blk);
+  if (ppp) block_partial(s2, sm, ppp, blk);
 }
 
 // q = A p from the sliced copy (variant kSellCode): blocks of 4 slices of
@@ -450,14 +412,14 @@ template <typename TV, typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_cg_spmv1_sell(const WorkTable wt, int base, const int64_t* __restrict__ sptr, const int32_t* __restrict__ rows,
                     const int32_t* __restrict__ col, const TV* __restrict__ val, const TX* __restrict__ p,
-                    TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ pqp) {
+                    TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ pqp, double* __restrict__ ppp) {
   __shared__ double sm[kBlock / kWave];
   const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
   if (st[l].done) return;
   const int64_t sl = wt.row0[blk] + threadIdx.x / kSellC;
   const int t = threadIdx.x % kSellC;
-  double s = 0.0;
+  double s = 0.0, s2 = 0.0;
   if (sl < wt.row1[blk]) {
     const int64_t e0 = sptr[sl], e1 = sptr[sl + 1];
     TX acc = 0;
@@ -467,9 +429,11 @@ __global__ void __launch_bounds__(kBlock)
     if (row >= 0) {
       q[row] = acc;
       s = (double)p[row] * (double)acc;
+      s2 = (double)p[row] * (double)p[row];
     }
   }
   block_partial(s, sm, pqp, blk);
+  if (ppp) block_partial(s2, sm, ppp, blk);
 }
 
 // One block per level: alpha = rr / p.q.
@@ -536,49 +500,84 @@ __global__ void __launch_bounds__(kRedBlock) k_cg_red_b(int lev0, const int32_t*
   }
 }
 
+// Single-reduction form, one block per level: gamma = r.r (stop test before
+// the update), delta = r.q, then beta and alpha.
+__global__ void __launch_bounds__(kRedBlock) k_cg1_red(int lev0, const int32_t* __restrict__ lev_begin,
+                                                    const double* __restrict__ rqp, const double* __restrict__ rrp,
+                                                    CgLevel* __restrict__ st) {
+  __shared__ double sm[kRedBlock / kWave];
+  const int l = lev0 + blockIdx.x;
+  if (st[l].done) return;
+  const double rq = block_range_sum(rqp, lev_begin[l], lev_begin[l + 1], sm);
+  const double rr = block_range_sum(rrp, lev_begin[l], lev_begin[l + 1], sm);
+  if (threadIdx.x == 0) {
+    CgLevel& S = st[l];
+    S.rr = rr;
+    const bool finite = isfinite(rr) && isfinite(rq);
+    if (finite && !(rr > S.rtol2 * S.bb)) {
+      S.done = 1;
+      return;
+    }
+    if (!finite || S.iters >= S.maxit) {
+      S.done = 1;
+      S.capped = 1;
+      return;
+    }
+    const double beta = S.iters == 0 ? 0.0 : rr / S.rr_prev;
+    const double den = S.iters == 0 ? rq : rq - beta * rr / S.alpha_prev;
+    if (!(den > 0.0) || !isfinite(den)) {  // cannot happen for SPD A and r != 0
+      S.done = 1;
+      S.capped = 1;
+      return;
+    }
+    S.beta = beta;
+    S.alpha = rr / den;
+    S.rr_prev = rr;
+    S.alpha_prev = S.alpha;
+    S.iters += 1;
+  }
+}
+
+// Single-reduction form: p = r + beta p; s = q + beta s; x += alpha p;
+// r -= alpha s.
+template <typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_cg1_update(const WorkTable wt, int base, TX* __restrict__ x, TX* __restrict__ r, TX* __restrict__ p,
+                 TX* __restrict__ sv, const TX* __restrict__ q, const CgLevel* __restrict__ st) {
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (st[l].done) return;
+  const double alpha = st[l].alpha;
+  const TX beta = (TX)st[l].beta;
+  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
+  for (int64_t i = row0 + threadIdx.x; i < row1; i += kBlock) {
+    const TX pi = r[i] + beta * p[i];
+    const TX si = q[i] + beta * sv[i];
+    p[i] = pi;
+    sv[i] = si;
+    x[i] = (TX)((double)x[i] + alpha * (double)pi);
+    r[i] = (TX)((double)r[i] - alpha * (double)si);
+  }
+}
+
 // ---------------------------------------------------------- solver driver
 
 constexpr int kGDiag = 8;  // lanes per row of the CG init kernel (diagonal rows hold 40-60 entries)
 
 template <typename TV, typename TX>
-static void launch_cg_spmv(hipStream_t s, int code, const WorkTable& wt, int base, int nb, const Csr& A,
-                           const TV* val, const TX* r, const TX* p_old, TX* p_new, TX* q, const CgLevel* st,
-                           double* pqp) {
-#define MSKM_CGSPMV_CASE(GG)                                                                                    \
-  case GG:                                                                                                     \
-    hipLaunchKernelGGL((k_cg_spmv<GG, false, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
-                       val, r, p_old, p_new, q, st, pqp);                                                       \
-    break;                                                                                                     \
-  case GG + kVecFlag:                                                                                          \
-    hipLaunchKernelGGL((k_cg_spmv<GG, true, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col,  \
-                       val, r, p_old, p_new, q, st, pqp);                                                       \
-    break;
-  switch (code) {
-    MSKM_CGSPMV_CASE(4)
-    MSKM_CGSPMV_CASE(8)
-    MSKM_CGSPMV_CASE(16)
-    MSKM_CGSPMV_CASE(32)
-    default:
-      hipLaunchKernelGGL((k_cg_spmv<8, false, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col,
-                         val, r, p_old, p_new, q, st, pqp);
-  }
-#undef MSKM_CGSPMV_CASE
-}
-
-template <typename TV, typename TX>
 static void launch_cg_spmv1(hipStream_t s, int code, const WorkTable& wt, int base, int nb, const Csr& A,
                             const TV* val, const TX* p, TX* q, const CgLevel* st, double* pqp, const double* rec,
-                            int dim) {
+                            int dim, double* ppp) {
   if (code >= 3 * kVecFlag) {
     const double4* r4 = reinterpret_cast<const double4*>(rec);
 #define MSKM_CGREC_CASE(GG)                                                                                   \
   case GG:                                                                                                   \
     if (dim == 3)                                                                                            \
       hipLaunchKernelGGL((k_cg_spmv1_rec<GG, 3, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
-                         r4, p, q, st, pqp);                                                                 \
+                         r4, p, q, st, pqp, ppp);                                                                 \
     else                                                                                                     \
       hipLaunchKernelGGL((k_cg_spmv1_rec<GG, 2, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
-                         r4, p, q, st, pqp);                                                                 \
+                         r4, p, q, st, pqp, ppp);                                                                 \
     return;
     switch (code - 3 * kVecFlag) {
       MSKM_CGREC_CASE(4)
@@ -593,11 +592,11 @@ static void launch_cg_spmv1(hipStream_t s, int code, const WorkTable& wt, int ba
 #define MSKM_CGSPMV1_CASE(GG)                                                                                    \
   case GG:                                                                                                      \
     hipLaunchKernelGGL((k_cg_spmv1<GG, false, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
-                       val, p, q, st, pqp);                                                                     \
+                       val, p, q, st, pqp, ppp);                                                                     \
     break;                                                                                                      \
   case GG + kVecFlag:                                                                                           \
     hipLaunchKernelGGL((k_cg_spmv1<GG, true, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col,  \
-                       val, p, q, st, pqp);                                                                     \
+                       val, p, q, st, pqp, ppp);                                                                     \
     break;
   switch (code) {
     MSKM_CGSPMV1_CASE(4)
@@ -606,7 +605,7 @@ static void launch_cg_spmv1(hipStream_t s, int code, const WorkTable& wt, int ba
     MSKM_CGSPMV1_CASE(32)
     default:
       hipLaunchKernelGGL((k_cg_spmv1<8, false, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col,
-                         val, p, q, st, pqp);
+                         val, p, q, st, pqp, ppp);
   }
 #undef MSKM_CGSPMV1_CASE
 }
@@ -623,6 +622,9 @@ struct SolveWS {
   double *part_s = nullptr, *part_s2 = nullptr, *part_v = nullptr;
   CgLevel* st = nullptr;
   CgLevel* h_st = nullptr;  // pinned
+  CgLevel* h_chk[2] = {nullptr, nullptr};  // pinned state copies of the two chunks in flight
+  hipEvent_t ev_chk[2] = {nullptr, nullptr};
+  hipEvent_t pending = nullptr;  // copy of a speculative chunk still in flight (null: none)
   struct Graph {
     int tx;
     const void* val;
@@ -637,7 +639,12 @@ struct SolveWS {
     for (void* p : {(void*)beta, (void*)t, (void*)r, (void*)p0, (void*)p1, (void*)q, (void*)fi, (void*)ai,
                     (void*)res, (void*)f32, (void*)a32, (void*)part_s, (void*)part_s2, (void*)part_v, (void*)st})
       (void)hipFree(p);
+    if (pending) (void)hipEventSynchronize(pending);
+    for (hipEvent_t e : ev_chk)
+      if (e) (void)hipEventDestroy(e);
     if (h_st) (void)hipHostFree(h_st);
+    for (CgLevel* c : h_chk)
+      if (c) (void)hipHostFree(c);
   }
 };
 
@@ -657,12 +664,19 @@ static mskm_status get_ws(mskm_hier* h, SolveWS** out) {
   if (st == MSKM_OK) st = dalloc(&w->f32, N);
   if (st == MSKM_OK) st = dalloc(&w->a32, N);
   if (st == MSKM_OK) st = dalloc(&w->part_s, (size_t)std::max(h->wt_spmv.nblocks, h->wt_sell.nblocks));
-  if (st == MSKM_OK) st = dalloc(&w->part_s2, h->wt_spmv.nblocks);
+  if (st == MSKM_OK) st = dalloc(&w->part_s2, (size_t)std::max(h->wt_spmv.nblocks, h->wt_sell.nblocks));
   if (st == MSKM_OK) st = dalloc(&w->part_v, h->wt_vec.nblocks);
   if (st == MSKM_OK) st = dalloc(&w->st, h->L);
   if (st == MSKM_OK &&
       hipHostMalloc(reinterpret_cast<void**>(&w->h_st), h->L * sizeof(CgLevel), hipHostMallocDefault) != hipSuccess)
     st = fail(MSKM_ENOMEM, "pinned state allocation");
+  for (int k = 0; k < 2 && st == MSKM_OK; ++k) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&w->h_chk[k]), h->L * sizeof(CgLevel), hipHostMallocDefault) !=
+        hipSuccess)
+      st = fail(MSKM_ENOMEM, "pinned state allocation");
+    else if (hipEventCreateWithFlags(&w->ev_chk[k], hipEventDisableTiming) != hipSuccess)
+      st = fail(MSKM_EDEVICE, "event creation");
+  }
   if (st != MSKM_OK) {
     delete w;
     return st;
@@ -691,46 +705,54 @@ struct CgStats {
   int32_t warm_fallbacks = 0;
 };
 
-// K CG iterations (4 kernels each) on levels lo..hi, starting at an even
-// iteration index; K is even, so every chunk sees the same buffer parity.
+// K CG iterations on levels lo..hi (textbook form, or the single-reduction
+// form when one1 is set).
 template <typename TV, typename TX>
-static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int hi, TX* x, int K, int G) {
+static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int hi, TX* x, int K, int G, bool one1) {
   hipStream_t s = h->ctx->stream;
   const WorkTable& ws = h->wt_spmv;
   const WorkTable& wv = h->wt_vec;
-  const int nlev = hi - lo + 1;
-  const int sb0 = ws.h_lev_begin[lo], sbn = ws.h_lev_begin[hi + 1] - sb0;
-  const int vb0 = wv.h_lev_begin[lo], vbn = wv.h_lev_begin[hi + 1] - vb0;
   const WorkTable& wc = h->wt_sell;
-  const int cb0 = wc.h_lev_begin[lo], cbn = wc.h_lev_begin[hi + 1] - cb0;
-  TX* p[2] = {(TX*)W.p0, (TX*)W.p1};
+  const bool sell = G == kSellCode;
+  const WorkTable& wq = sell ? wc : ws;  // table of the product kernel (and of its partials)
+  const int nlev = hi - lo + 1;
+  const int qb0 = wq.h_lev_begin[lo], qbn = wq.h_lev_begin[hi + 1] - qb0;
+  const int vb0 = wv.h_lev_begin[lo], vbn = wv.h_lev_begin[hi + 1] - vb0;
+  TX* p = (TX*)W.p0;
+  TX* sv = (TX*)W.p1;
   TX* r = (TX*)W.r;
   TX* q = (TX*)W.q;
+  // q = A v with partials v.q (and v.v when pp is set)
+  auto product = [&](const TX* v, double* pp) {
+    if (qbn <= 0) return;
+    if (sell)
+      hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX>), dim3(qbn), dim3(kBlock), 0, s, wc, qb0, h->sell.sptr, h->sell.rows,
+                         h->sell.col, sell_values<TV>(h->sell), v, q, W.st, W.part_s, pp);
+    else
+      launch_cg_spmv1<TV, TX>(s, G, ws, qb0, qbn, h->diag, dval, v, q, W.st, W.part_s, h->prec, h->dim, pp);
+  };
   for (int it = 0; it < K; ++it) {
-    // direction update (beta = 0 on the first iteration after the init, p0 = 0 there)
-    if (vbn > 0) hipLaunchKernelGGL(k_cg_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, r, p[0], W.st);
-    if (G == kSellCode) {
-      const TV* sv = sell_values<TV>(h->sell);
-      if (cbn > 0)
-        hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX>), dim3(cbn), dim3(kBlock), 0, s, wc, cb0, h->sell.sptr,
-                           h->sell.rows, h->sell.col, sv, p[0], q, W.st, W.part_s);
-      hipLaunchKernelGGL(k_cg_red_a, dim3(nlev), dim3(kRedBlock), 0, s, lo, wc.lev_begin, W.part_s, W.st);
+    if (one1) {
+      product(r, W.part_s2);
+      hipLaunchKernelGGL(k_cg1_red, dim3(nlev), dim3(kRedBlock), 0, s, lo, wq.lev_begin, W.part_s, W.part_s2, W.st);
+      if (vbn > 0) hipLaunchKernelGGL(k_cg1_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p, sv, q, W.st);
     } else {
-      if (sbn > 0)
-        launch_cg_spmv1<TV, TX>(s, G, ws, sb0, sbn, h->diag, dval, p[0], q, W.st, W.part_s, h->prec, h->dim);
-      hipLaunchKernelGGL(k_cg_red_a, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.st);
+      // direction update (beta = 0 on the first iteration after the init, p = 0 there)
+      if (vbn > 0) hipLaunchKernelGGL(k_cg_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, r, p, W.st);
+      product(p, nullptr);
+      hipLaunchKernelGGL(k_cg_red_a, dim3(nlev), dim3(kRedBlock), 0, s, lo, wq.lev_begin, W.part_s, W.st);
+      if (vbn > 0)
+        hipLaunchKernelGGL(k_cg_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p, q, W.st, W.part_v);
+      hipLaunchKernelGGL(k_cg_red_b, dim3(nlev), dim3(kRedBlock), 0, s, lo, wv.lev_begin, W.part_v, W.st);
     }
-    if (vbn > 0)
-      hipLaunchKernelGGL(k_cg_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p[0], q, W.st, W.part_v);
-    hipLaunchKernelGGL(k_cg_red_b, dim3(nlev), dim3(kRedBlock), 0, s, lo, wv.lev_begin, W.part_v, W.st);
   }
 }
 
 // Instantiated graph of one chunk (captured on first use).
 template <typename TV, typename TX>
 static mskm_status chunk_graph(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int hi, TX* x, int K, int G,
-                               hipGraphExec_t* out) {
-  const int tx = (int)sizeof(TX);
+                               bool one1, hipGraphExec_t* out) {
+  const int tx = (int)sizeof(TX) + (one1 ? 100 : 0);
   for (const auto& g : W.graphs)
     if (g.tx == tx && g.val == dval && g.lo == lo && g.hi == hi && g.x == x && g.K == K && g.G == G) {
       *out = g.exec;
@@ -739,7 +761,7 @@ static mskm_status chunk_graph(mskm_hier* h, SolveWS& W, const TV* dval, int lo,
   hipStream_t s = h->ctx->stream;
   hipGraph_t graph = nullptr;
   MSKM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  enqueue_chunk<TV, TX>(h, W, dval, lo, hi, x, K, G);
+  enqueue_chunk<TV, TX>(h, W, dval, lo, hi, x, K, G, one1);
   MSKM_HIP_TRY(hipStreamEndCapture(s, &graph));
   hipGraphExec_t exec = nullptr;
   const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -763,6 +785,10 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
   while (lo < h->L && !on[lo]) ++lo;
   while (hi >= 0 && !on[hi]) --hi;
   if (lo > hi) return MSKM_OK;
+  if (W.pending) {  // the previous run's speculative chunk copy lands in h_chk
+    MSKM_HIP_TRY(hipEventSynchronize(W.pending));
+    W.pending = nullptr;
+  }
   for (int l = 0; l < h->L; ++l) {
     CgLevel& S = W.h_st[l];
     std::memset(&S, 0, sizeof(S));
@@ -781,9 +807,10 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
       if (on[l]) MSKM_TRY(mlp_predict_rows<TX>(h, mlp, l, b, x));
     warm = true;
   }
+  const bool one1 = sizeof(TX) == 4;  // FP32 inner solves: single-reduction form
   if (sbn > 0)
     hipLaunchKernelGGL((k_cg_init<kGDiag, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, h->diag.rowptr, h->diag.col,
-                       dval, b, x, (TX*)W.r, (TX*)W.p0, W.st, warm ? 1 : 0, W.part_s, W.part_s2, sb0);
+                       dval, b, x, (TX*)W.r, (TX*)W.p0, W.st, warm ? 1 : 0, W.part_s, W.part_s2, sb0, (TX*)W.p1);
   hipLaunchKernelGGL(k_cg_red_init, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.part_s2, W.st);
   if (mlp) {  // CG judges the warm start: ||b - A x0|| >= ||b|| restarts that level from zero
     MSKM_HIP_TRY(hipMemcpyAsync(W.h_st, W.st, h->L * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
@@ -805,25 +832,42 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
       MSKM_HIP_TRY(hipMemcpyAsync(W.st, W.h_st, h->L * sizeof(CgLevel), hipMemcpyHostToDevice, s));
       if (sbn > 0)
         hipLaunchKernelGGL((k_cg_init<kGDiag, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, h->diag.rowptr, h->diag.col,
-                           dval, b, x, (TX*)W.r, (TX*)W.p0, W.st, 1, W.part_s, W.part_s2, sb0);
+                           dval, b, x, (TX*)W.r, (TX*)W.p0, W.st, 1, W.part_s, W.part_s2, sb0, (TX*)W.p1);
       hipLaunchKernelGGL(k_cg_red_init, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.part_s2,
                          W.st);
     }
   }
   hipGraphExec_t exec = nullptr;
-  MSKM_TRY((chunk_graph<TV, TX>(h, W, dval, lo, hi, x, K, G, &exec)));
-  for (int it = 0; it < maxit; it += K) {
+  MSKM_TRY((chunk_graph<TV, TX>(h, W, dval, lo, hi, x, K, G, one1, &exec)));
+  // Two chunks in flight: chunk k+1 is queued before the host reads chunk
+  // k's state, so the device does not idle during the check. Iterations of
+  // stopped levels are no-ops, so a speculative chunk changes nothing.
+  const int max_chunks = (maxit + K - 1) / K;
+  int launched = 0, checked = 0;
+  auto launch = [&]() -> mskm_status {
+    const int slot = launched & 1;
     MSKM_HIP_TRY(hipGraphLaunch(exec, s));
-    MSKM_HIP_TRY(hipMemcpyAsync(W.h_st, W.st, h->L * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
-    MSKM_HIP_TRY(hipStreamSynchronize(s));
+    MSKM_HIP_TRY(hipMemcpyAsync(W.h_chk[slot], W.st, h->L * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
+    MSKM_HIP_TRY(hipEventRecord(W.ev_chk[slot], s));
+    ++launched;
+    return MSKM_OK;
+  };
+  MSKM_TRY(launch());
+  while (checked < launched) {
+    if (launched < max_chunks) MSKM_TRY(launch());
+    MSKM_HIP_TRY(hipEventSynchronize(W.ev_chk[checked & 1]));
+    const CgLevel* c = W.h_chk[checked & 1];
+    ++checked;
     bool any = false;
-    for (int l = lo; l <= hi; ++l) any |= W.h_st[l].done == 0;
+    for (int l = lo; l <= hi; ++l) any |= c[l].done == 0;
     if (!any) break;
   }
+  if (launched > checked) W.pending = W.ev_chk[(launched - 1) & 1];
+  const CgLevel* fin = W.h_chk[(checked - 1) & 1];
   MSKM_HIP_TRY(hipGetLastError());
   for (int l = lo; l <= hi; ++l) {
     if (!on[l]) continue;
-    const CgLevel& o = W.h_st[l];
+    const CgLevel& o = fin[l];
     cs->iters_total += o.iters;
     if (l < kMaxLevels) cs->last_iters[l] = o.iters;
     if (o.capped || !o.done) cs->capped = true;
