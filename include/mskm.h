@@ -235,7 +235,13 @@ mskm_status mskm_set_spmv_width(mskm_hier* h, int32_t op, int32_t prec, int32_t 
 /* ------------------------------------------------------------------ solve */
 
 enum { MSKM_ALG_MONOLITHIC = 0, MSKM_ALG_SEQUENTIAL = 1 };
-enum { MSKM_PRECOND_NONE = 0, MSKM_PRECOND_LEARNED = 1 };
+/* MSKM_PRECOND_LEARNED: the network's prediction as each level's CG start.
+ * MSKM_PRECOND_BLOCK_JACOBI: CG on A_l preconditioned by the dense inverses
+ * of A_l's diagonal blocks over the cells of the level's grid (cells of more
+ * than 32 points cut into chunks); built at the first such solve and kept
+ * with the hierarchy. Both are build extensions (the paper's CG is plain);
+ * the solution they converge to is the same. */
+enum { MSKM_PRECOND_NONE = 0, MSKM_PRECOND_LEARNED = 1, MSKM_PRECOND_BLOCK_JACOBI = 2 };
 
 typedef struct mskm_mlp mskm_mlp;
 
@@ -250,7 +256,7 @@ typedef struct {
   int32_t warm_start;     /* 1: CG of sweep m starts from sweep m-1's solution */
   double target_rel_residual; /* mixed path: stop refining when ||f-T alpha||/||f|| <= this */
   int32_t max_refine;     /* mixed path: cap on refinement steps; <= 0 means 10 */
-  int32_t precond;        /* MSKM_PRECOND_NONE or MSKM_PRECOND_LEARNED (warm start) */
+  int32_t precond;        /* MSKM_PRECOND_NONE, _LEARNED (warm start) or _BLOCK_JACOBI */
   const mskm_mlp* mlp;    /* network for MSKM_PRECOND_LEARNED */
   int32_t check_every;    /* CG convergence poll interval; <= 0 means 8 */
   int32_t flags;          /* MSKM_IO_DEVICE */

@@ -31,7 +31,7 @@ MSKM_IO_DEVICE = 1
 MSKM_OP_DIAG, MSKM_OP_LOWER, MSKM_OP_FULL = 0, 1, 2
 MSKM_PREC_FP64, MSKM_PREC_FP32 = 0, 1
 MSKM_ALG_MONOLITHIC, MSKM_ALG_SEQUENTIAL = 0, 1
-MSKM_PRECOND_NONE, MSKM_PRECOND_LEARNED = 0, 1
+MSKM_PRECOND_NONE, MSKM_PRECOND_LEARNED, MSKM_PRECOND_BLOCK_JACOBI = 0, 1, 2
 
 EXPORTED = [
     "mskm_create", "mskm_destroy", "mskm_last_error", "mskm_abi_version",

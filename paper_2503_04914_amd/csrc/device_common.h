@@ -103,4 +103,21 @@ __device__ __forceinline__ int cell_coord(double x, double lo, double inv_cell, 
   return (int)q;
 }
 
+// Row i of the block-Jacobi product u = M^-1 r: the row of its block's
+// dense inverse times the block's entries of r, which the caller staged in
+// rs (rs[k] = r[row0 + k] for the rows of its workgroup of whole blocks).
+template <typename TX>
+__device__ __forceinline__ TX bj_row(int64_t i, int64_t row0, const TX* rs, const int64_t* __restrict__ start,
+                                     const int32_t* __restrict__ of_row, const int64_t* __restrict__ off,
+                                     const TX* __restrict__ inv) {
+  const int32_t b = of_row[i];
+  const int64_t a = start[b];
+  const int m = (int)(start[b + 1] - a);
+  const TX* Mi = inv + off[b] + (i - a) * m;
+  const TX* rb = rs + (a - row0);
+  TX acc = 0;
+  for (int j = 0; j < m; ++j) acc += Mi[j] * rb[j];
+  return acc;
+}
+
 }  // namespace mskm

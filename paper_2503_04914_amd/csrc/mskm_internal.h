@@ -81,6 +81,22 @@ struct Sell {
   std::vector<int64_t> h_slice_begin;  // [L+1] first slice of each level
 };
 
+// Block-Jacobi preconditioner: the diagonal blocks of A_l restricted to each
+// cell of the level's grid (cells hold consecutive internal rows; cells of
+// more than kBjMax rows are cut into near-equal chunks), inverted densely.
+constexpr int kBjMax = 32;         // largest block
+constexpr int kBjGroupRows = 1024; // rows of one workgroup of whole blocks
+struct BlockJacobi {
+  bool built = false;
+  int64_t nblocks = 0, nvals = 0;
+  int64_t* start = nullptr;   // [nblocks + 1] first internal row of each block (blocks tile every level)
+  int64_t* off = nullptr;     // [nblocks + 1] offset of each block's m x m inverse (row-major)
+  int32_t* of_row = nullptr;  // [N] block of each internal row
+  double* inv = nullptr;      // [nvals] FP64 inverses
+  float* inv32 = nullptr;     // [nvals] FP32 copies
+  WorkTable wt;               // per-level workgroups of whole blocks (<= kBjGroupRows rows)
+};
+
 struct Csr {
   int64_t nnz = 0;
   int64_t* rowptr = nullptr;  // [N+1]
@@ -148,6 +164,7 @@ struct mskm_hier {
   mskm::WorkTable wt_vec;               // per-level streaming blocks (CG phase 3)
   mskm::Sell sell;                      // sliced copy of the diagonal blocks
   mskm::WorkTable wt_sell;              // per-level blocks of 4 slices ("rows" are slices)
+  mskm::BlockJacobi bj;                 // cell block-Jacobi preconditioner (built at its first use)
   int32_t spmv_g[3][2] = {{8, 8}, {32, 32}, {32, 32}};  // lanes per row [op][FP64, FP32]
   int64_t device_bytes = 0;
   double assemble_ms = 0.0;
@@ -209,6 +226,10 @@ mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, i
 // Rows of each level split into blocks of max(min_rows, n_l / max_blocks) rows,
 // so that no level has more than max_blocks blocks.
 mskm_status build_work_table(mskm_hier* h, WorkTable* wt, int min_rows, int max_blocks_per_level);
+// precond.hip
+mskm_status build_block_jacobi(mskm_hier* h);
+template <typename TX>
+void launch_bj_apply(mskm_hier* h, int lo, int hi, const TX* r, TX* u);
 
 // solve.hip
 mskm_status apply_op(mskm_hier* h, int op, int prec, const double* x_in, int nrhs, double* y_in, bool io_dev);

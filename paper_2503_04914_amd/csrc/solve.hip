@@ -352,19 +352,21 @@ __global__ void __launch_bounds__(kBlock) k_cg_dir(const WorkTable wt, int base,
   for (int64_t i = row0 + threadIdx.x; i < row1; i += kBlock) p[i] = r[i] + beta * p[i];
 }
 
-// spmv phase after a separate direction update: q = A p; partial p.q per block.
+// Product phase: q = A p with per-block partials p.q (pqp) and, when given,
+// p.rv (ppp; p.p without rv) and rv.rv (p3).
 template <int G, bool VEC, typename TV, typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_cg_spmv1(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                const TV* __restrict__ val, const TX* __restrict__ p, TX* __restrict__ q,
-               const CgLevel* __restrict__ st, double* __restrict__ pqp, double* __restrict__ ppp) {
+               const CgLevel* __restrict__ st, double* __restrict__ pqp, double* __restrict__ ppp,
+               const TX* __restrict__ rv, double* __restrict__ p3) {
   __shared__ double sm[kBlock / kWave];
   const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
   if (st[l].done) return;
   const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
   const int gl = threadIdx.x % G;
-  double s = 0.0, s2 = 0.0;
+  double s = 0.0, s2 = 0.0, s3 = 0.0;
   for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
     TX acc;
     if constexpr (VEC)
@@ -373,53 +375,61 @@ __global__ void __launch_bounds__(kBlock)
       acc = csr_row_dot<G, TV, TX, TX>(rp, col, val, p, i, gl);
     if (gl == 0) {
       q[i] = acc;
-      s += (double)p[i] * (double)acc;
-      s2 += (double)p[i] * (double)p[i];
+      const double vi = (double)p[i], wi = rv ? (double)rv[i] : vi;
+      s += vi * (double)acc;
+      s2 += vi * wi;
+      s3 += wi * wi;
     }
   }
   block_partial(s, sm, pqp, blk);
   if (ppp) block_partial(s2, sm, ppp, blk);
+  if (p3) block_partial(s3, sm, p3, blk);
 }
 
-// q = A p with recomputed values (variant code G + 3000); partial p.q per block.
+// The same with recomputed values (variant code G + 3000).
 template <int G, int DIM, typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_cg_spmv1_rec(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                    const double4* __restrict__ rec, const TX* __restrict__ p, TX* __restrict__ q,
-                   const CgLevel* __restrict__ st, double* __restrict__ pqp, double* __restrict__ ppp) {
+                       const CgLevel* __restrict__ st, double* __restrict__ pqp, double* __restrict__ ppp,
+                   const TX* __restrict__ rv, double* __restrict__ p3) {
   __shared__ double sm[kBlock / kWave];
   const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
   if (st[l].done) return;
   const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
   const int gl = threadIdx.x % G;
-  double s = 0.0, s2 = 0.0;
+  double s = 0.0, s2 = 0.0, s3 = 0.0;
   for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
     const TX acc = rec_row_dot<G, DIM, TX, TX>(rp, col, rec, p, i, gl, rec[i]);
     if (gl == 0) {
       q[i] = acc;
-      s += (double)p[i] * (double)acc;
-      s2 += (double)p[i] * (double)p[i];
+      const double vi = (double)p[i], wi = rv ? (double)rv[i] : vi;
+      s += vi * (double)acc;
+      s2 += vi * wi;
+      s3 += wi * wi;
     }
   }
   block_partial(s, sm, pqp, blk);
   if (ppp) block_partial(s2, sm, ppp, blk);
+  if (p3) block_partial(s3, sm, p3, blk);
 }
 
-// q = A p from the sliced copy (variant kSellCode): blocks of 4 slices of
-// one level; partial p.q per block.
+// The same from the sliced copy (variant kSellCode): blocks of 4 slices of
+// one level.
 template <typename TV, typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_cg_spmv1_sell(const WorkTable wt, int base, const int64_t* __restrict__ sptr, const int32_t* __restrict__ rows,
                     const int32_t* __restrict__ col, const TV* __restrict__ val, const TX* __restrict__ p,
-                    TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ pqp, double* __restrict__ ppp) {
+                    TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ pqp,
+                    double* __restrict__ ppp, const TX* __restrict__ rv, double* __restrict__ p3) {
   __shared__ double sm[kBlock / kWave];
   const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
   if (st[l].done) return;
   const int64_t sl = wt.row0[blk] + threadIdx.x / kSellC;
   const int t = threadIdx.x % kSellC;
-  double s = 0.0, s2 = 0.0;
+  double s = 0.0, s2 = 0.0, s3 = 0.0;
   if (sl < wt.row1[blk]) {
     const int64_t e0 = sptr[sl], e1 = sptr[sl + 1];
     TX acc = 0;
@@ -428,12 +438,15 @@ __global__ void __launch_bounds__(kBlock)
     const int32_t row = rows[sl * kSellC + t];
     if (row >= 0) {
       q[row] = acc;
-      s = (double)p[row] * (double)acc;
-      s2 = (double)p[row] * (double)p[row];
+      const double vi = (double)p[row], wi = rv ? (double)rv[row] : vi;
+      s = vi * (double)acc;
+      s2 = vi * wi;
+      s3 = wi * wi;
     }
   }
   block_partial(s, sm, pqp, blk);
   if (ppp) block_partial(s2, sm, ppp, blk);
+  if (p3) block_partial(s3, sm, p3, blk);
 }
 
 // One block per level: alpha = rr / p.q.
@@ -500,64 +513,136 @@ __global__ void __launch_bounds__(kRedBlock) k_cg_red_b(int lev0, const int32_t*
   }
 }
 
-// Single-reduction form, one block per level: gamma = r.r (stop test before
-// the update), delta = r.q, then beta and alpha.
+// Single-reduction step decision on the level's sums: gamma = r.z (z = r, or
+// M^-1 r when preconditioned), delta = z.A z, rr = r.r. Stops on rr before
+// the update; else beta = gamma / gamma_prev, alpha = gamma / (delta - beta
+// gamma / alpha_prev). Returns true when the update is to be applied.
+__device__ __forceinline__ bool cg1_decide(CgLevel& S, double gamma, double delta, double rr) {
+  S.rr = rr;
+  const bool finite = isfinite(rr) && isfinite(gamma) && isfinite(delta);
+  if (finite && !(rr > S.rtol2 * S.bb)) {
+    S.done = 1;
+    return false;
+  }
+  if (!finite || S.iters >= S.maxit) {
+    S.done = 1;
+    S.capped = 1;
+    return false;
+  }
+  const double beta = S.iters == 0 ? 0.0 : gamma / S.rr_prev;
+  const double den = S.iters == 0 ? delta : delta - beta * gamma / S.alpha_prev;
+  if (!(den > 0.0) || !isfinite(den) || !(gamma > 0.0)) {  // cannot happen for SPD A (and M) and r != 0
+    S.done = 1;
+    S.capped = 1;
+    return false;
+  }
+  S.beta = beta;
+  S.alpha = gamma / den;
+  S.rr_prev = gamma;
+  S.alpha_prev = S.alpha;
+  S.iters += 1;
+  return true;
+}
+
+// Single-reduction form, one block per level: the sums of the product's
+// partials (dq: z.A z, gp: r.z, rp: r.r, null when z = r) and the decision.
 __global__ void __launch_bounds__(kRedBlock) k_cg1_red(int lev0, const int32_t* __restrict__ lev_begin,
-                                                    const double* __restrict__ rqp, const double* __restrict__ rrp,
-                                                    CgLevel* __restrict__ st) {
+                                                    const double* __restrict__ dq, const double* __restrict__ gp,
+                                                    const double* __restrict__ rp, CgLevel* __restrict__ st) {
   __shared__ double sm[kRedBlock / kWave];
   const int l = lev0 + blockIdx.x;
   if (st[l].done) return;
-  const double rq = block_range_sum(rqp, lev_begin[l], lev_begin[l + 1], sm);
-  const double rr = block_range_sum(rrp, lev_begin[l], lev_begin[l + 1], sm);
-  if (threadIdx.x == 0) {
-    CgLevel& S = st[l];
-    S.rr = rr;
-    const bool finite = isfinite(rr) && isfinite(rq);
-    if (finite && !(rr > S.rtol2 * S.bb)) {
-      S.done = 1;
-      return;
-    }
-    if (!finite || S.iters >= S.maxit) {
-      S.done = 1;
-      S.capped = 1;
-      return;
-    }
-    const double beta = S.iters == 0 ? 0.0 : rr / S.rr_prev;
-    const double den = S.iters == 0 ? rq : rq - beta * rr / S.alpha_prev;
-    if (!(den > 0.0) || !isfinite(den)) {  // cannot happen for SPD A and r != 0
-      S.done = 1;
-      S.capped = 1;
-      return;
-    }
-    S.beta = beta;
-    S.alpha = rr / den;
-    S.rr_prev = rr;
-    S.alpha_prev = S.alpha;
-    S.iters += 1;
-  }
+  const double delta = block_range_sum(dq, lev_begin[l], lev_begin[l + 1], sm);
+  const double gamma = block_range_sum(gp, lev_begin[l], lev_begin[l + 1], sm);
+  const double rr = rp ? block_range_sum(rp, lev_begin[l], lev_begin[l + 1], sm) : gamma;
+  if (threadIdx.x == 0) cg1_decide(st[l], gamma, delta, rr);
 }
 
-// Single-reduction form: p = r + beta p; s = q + beta s; x += alpha p;
-// r -= alpha s.
+// Preconditioner arguments of the single-reduction update (PC form).
 template <typename TX>
-__global__ void __launch_bounds__(kBlock)
-    k_cg1_update(const WorkTable wt, int base, TX* __restrict__ x, TX* __restrict__ r, TX* __restrict__ p,
-                 TX* __restrict__ sv, const TX* __restrict__ q, const CgLevel* __restrict__ st) {
-  const int blk = base + xcd_block_id(gridDim.x);
-  const int l = wt.lev[blk];
-  if (st[l].done) return;
-  const double alpha = st[l].alpha;
-  const TX beta = (TX)st[l].beta;
-  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
+struct PcArgs {
+  const int64_t* start;
+  const int32_t* of_row;
+  const int64_t* off;
+  const TX* inv;
+  TX* z;  // z = M^-1 r
+};
+
+// Single-reduction update on the block's rows: p = z + beta p; s = q + beta s
+// (= A p); x += alpha p; r -= alpha s; then (PC) z = M^-1 r for the block's
+// rows, the block being a workgroup of whole preconditioner blocks.
+template <typename TX, bool PC>
+__device__ __forceinline__ void cg1_rows(int64_t row0, int64_t row1, double alpha, TX beta, TX* __restrict__ x,
+                                         TX* __restrict__ r, TX* __restrict__ p, TX* __restrict__ sv,
+                                         const TX* __restrict__ q, const PcArgs<TX>& pc, TX* rs) {
   for (int64_t i = row0 + threadIdx.x; i < row1; i += kBlock) {
-    const TX pi = r[i] + beta * p[i];
+    const TX zi = PC ? pc.z[i] : r[i];
+    const TX pi = zi + beta * p[i];
     const TX si = q[i] + beta * sv[i];
     p[i] = pi;
     sv[i] = si;
     x[i] = (TX)((double)x[i] + alpha * (double)pi);
-    r[i] = (TX)((double)r[i] - alpha * (double)si);
+    const TX ri = (TX)((double)r[i] - alpha * (double)si);
+    r[i] = ri;
+    if constexpr (PC) rs[i - row0] = ri;
   }
+  if constexpr (PC) {
+    __syncthreads();
+    for (int64_t i = row0 + threadIdx.x; i < row1; i += kBlock)
+      pc.z[i] = bj_row<TX>(i, row0, rs, pc.start, pc.of_row, pc.off, pc.inv);
+  }
+}
+
+// Single-reduction update with the decision taken by k_cg1_red.
+template <typename TX, bool PC>
+__global__ void __launch_bounds__(kBlock)
+    k_cg1_update(const WorkTable wt, int base, TX* __restrict__ x, TX* __restrict__ r, TX* __restrict__ p,
+                 TX* __restrict__ sv, const TX* __restrict__ q, const CgLevel* __restrict__ st, const PcArgs<TX> pc) {
+  __shared__ TX rs[PC ? kBjGroupRows : 1];
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (st[l].done) return;
+  cg1_rows<TX, PC>(wt.row0[blk], wt.row1[blk], st[l].alpha, (TX)st[l].beta, x, r, p, sv, q, pc, rs);
+}
+
+// Single-reduction form with the reduction folded into the update: every
+// block of a level sums that level's partials itself (same order in every
+// block, so all blocks take the same decision), thread 0 of the level's first
+// block publishes the new state. The state is double-buffered by iteration
+// parity (read cur, write next), so no block reads a state another block of
+// the same launch writes.
+constexpr int kFusedMaxPartials = 1024;  // larger levels use the separate reduce kernel
+
+template <typename TX, bool PC>
+__global__ void __launch_bounds__(kBlock)
+    k_cg1_step(const WorkTable wt, int base, const int32_t* __restrict__ qlev_begin, const double* __restrict__ dq,
+               const double* __restrict__ gp, const double* __restrict__ rp, TX* __restrict__ x, TX* __restrict__ r,
+               TX* __restrict__ p, TX* __restrict__ sv, const TX* __restrict__ q, const CgLevel* __restrict__ cur,
+               CgLevel* __restrict__ next, const PcArgs<TX> pc) {
+  __shared__ double sm[kBlock / kWave];
+  __shared__ double coef[2];
+  __shared__ int go;
+  __shared__ TX rs[PC ? kBjGroupRows : 1];
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  const bool writer = blk == wt.lev_begin[l];
+  if (cur[l].done) {
+    if (writer && threadIdx.x == 0) next[l] = cur[l];
+    return;
+  }
+  const double delta = block_range_sum(dq, qlev_begin[l], qlev_begin[l + 1], sm);
+  const double gamma = block_range_sum(gp, qlev_begin[l], qlev_begin[l + 1], sm);
+  const double rr = rp ? block_range_sum(rp, qlev_begin[l], qlev_begin[l + 1], sm) : gamma;
+  if (threadIdx.x == 0) {
+    CgLevel S = cur[l];
+    go = cg1_decide(S, gamma, delta, rr) ? 1 : 0;
+    if (writer) next[l] = S;
+    coef[0] = S.alpha;
+    coef[1] = S.beta;
+  }
+  __syncthreads();
+  if (!go) return;
+  cg1_rows<TX, PC>(wt.row0[blk], wt.row1[blk], coef[0], (TX)coef[1], x, r, p, sv, q, pc, rs);
 }
 
 // ---------------------------------------------------------- solver driver
@@ -567,17 +652,17 @@ constexpr int kGDiag = 8;  // lanes per row of the CG init kernel (diagonal rows
 template <typename TV, typename TX>
 static void launch_cg_spmv1(hipStream_t s, int code, const WorkTable& wt, int base, int nb, const Csr& A,
                             const TV* val, const TX* p, TX* q, const CgLevel* st, double* pqp, const double* rec,
-                            int dim, double* ppp) {
+                            int dim, double* ppp, const TX* rv, double* p3) {
   if (code >= 3 * kVecFlag) {
     const double4* r4 = reinterpret_cast<const double4*>(rec);
 #define MSKM_CGREC_CASE(GG)                                                                                   \
   case GG:                                                                                                   \
     if (dim == 3)                                                                                            \
       hipLaunchKernelGGL((k_cg_spmv1_rec<GG, 3, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
-                         r4, p, q, st, pqp, ppp);                                                                 \
+                         r4, p, q, st, pqp, ppp, rv, p3);                                                                 \
     else                                                                                                     \
       hipLaunchKernelGGL((k_cg_spmv1_rec<GG, 2, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
-                         r4, p, q, st, pqp, ppp);                                                                 \
+                         r4, p, q, st, pqp, ppp, rv, p3);                                                                 \
     return;
     switch (code - 3 * kVecFlag) {
       MSKM_CGREC_CASE(4)
@@ -592,11 +677,11 @@ static void launch_cg_spmv1(hipStream_t s, int code, const WorkTable& wt, int ba
 #define MSKM_CGSPMV1_CASE(GG)                                                                                    \
   case GG:                                                                                                      \
     hipLaunchKernelGGL((k_cg_spmv1<GG, false, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col, \
-                       val, p, q, st, pqp, ppp);                                                                     \
+                       val, p, q, st, pqp, ppp, rv, p3);                                                                     \
     break;                                                                                                      \
   case GG + kVecFlag:                                                                                           \
     hipLaunchKernelGGL((k_cg_spmv1<GG, true, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col,  \
-                       val, p, q, st, pqp, ppp);                                                                     \
+                       val, p, q, st, pqp, ppp, rv, p3);                                                                     \
     break;
   switch (code) {
     MSKM_CGSPMV1_CASE(4)
@@ -605,7 +690,7 @@ static void launch_cg_spmv1(hipStream_t s, int code, const WorkTable& wt, int ba
     MSKM_CGSPMV1_CASE(32)
     default:
       hipLaunchKernelGGL((k_cg_spmv1<8, false, TV, TX>), dim3(nb), dim3(kBlock), 0, s, wt, base, A.rowptr, A.col,
-                         val, p, q, st, pqp, ppp);
+                         val, p, q, st, pqp, ppp, rv, p3);
   }
 #undef MSKM_CGSPMV1_CASE
 }
@@ -619,7 +704,8 @@ struct SolveWS {
   double *beta = nullptr, *t = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
   double *fi = nullptr, *ai = nullptr, *res = nullptr;  // FP64 f, alpha, residual (internal order)
   float *f32 = nullptr, *a32 = nullptr;                 // FP32 rhs and correction (mixed path)
-  double *part_s = nullptr, *part_s2 = nullptr, *part_v = nullptr;
+  double *part_s = nullptr, *part_s2 = nullptr, *part_s3 = nullptr, *part_v = nullptr;
+  double* z = nullptr;  // preconditioned residual M^-1 r (block-Jacobi form)
   CgLevel* st = nullptr;
   CgLevel* h_st = nullptr;  // pinned
   CgLevel* h_chk[2] = {nullptr, nullptr};  // pinned state copies of the two chunks in flight
@@ -637,7 +723,8 @@ struct SolveWS {
   ~SolveWS() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
     for (void* p : {(void*)beta, (void*)t, (void*)r, (void*)p0, (void*)p1, (void*)q, (void*)fi, (void*)ai,
-                    (void*)res, (void*)f32, (void*)a32, (void*)part_s, (void*)part_s2, (void*)part_v, (void*)st})
+                    (void*)res, (void*)f32, (void*)a32, (void*)part_s, (void*)part_s2, (void*)part_s3, (void*)part_v,
+                    (void*)st, (void*)z})
       (void)hipFree(p);
     if (pending) (void)hipEventSynchronize(pending);
     for (hipEvent_t e : ev_chk)
@@ -659,14 +746,15 @@ static mskm_status get_ws(mskm_hier* h, SolveWS** out) {
   if (!w) return fail(MSKM_ENOMEM, "workspace allocation");
   const size_t N = (size_t)h->N;
   mskm_status st = MSKM_OK;
-  for (double** v : {&w->beta, &w->t, &w->r, &w->p0, &w->p1, &w->q, &w->fi, &w->ai, &w->res})
+  for (double** v : {&w->beta, &w->t, &w->r, &w->p0, &w->p1, &w->q, &w->fi, &w->ai, &w->res, &w->z})
     if (st == MSKM_OK) st = dalloc(v, N);
   if (st == MSKM_OK) st = dalloc(&w->f32, N);
   if (st == MSKM_OK) st = dalloc(&w->a32, N);
   if (st == MSKM_OK) st = dalloc(&w->part_s, (size_t)std::max(h->wt_spmv.nblocks, h->wt_sell.nblocks));
   if (st == MSKM_OK) st = dalloc(&w->part_s2, (size_t)std::max(h->wt_spmv.nblocks, h->wt_sell.nblocks));
+  if (st == MSKM_OK) st = dalloc(&w->part_s3, (size_t)std::max(h->wt_spmv.nblocks, h->wt_sell.nblocks));
   if (st == MSKM_OK) st = dalloc(&w->part_v, h->wt_vec.nblocks);
-  if (st == MSKM_OK) st = dalloc(&w->st, h->L);
+  if (st == MSKM_OK) st = dalloc(&w->st, 2 * (size_t)h->L);  // two parities (fused single-reduction form)
   if (st == MSKM_OK &&
       hipHostMalloc(reinterpret_cast<void**>(&w->h_st), h->L * sizeof(CgLevel), hipHostMallocDefault) != hipSuccess)
     st = fail(MSKM_ENOMEM, "pinned state allocation");
@@ -705,13 +793,27 @@ struct CgStats {
   int32_t warm_fallbacks = 0;
 };
 
-// K CG iterations on levels lo..hi (textbook form, or the single-reduction
-// form when one1 is set).
+// CG forms: textbook (five kernels per iteration), single-reduction (two or
+// three), single-reduction with the cell block-Jacobi preconditioner.
+enum CgForm { kCgTextbook = 0, kCgOneRed = 1, kCgOneRedBj = 2 };
+
+template <typename TX>
+static PcArgs<TX> pc_args(mskm_hier* h, SolveWS& W) {
+  PcArgs<TX> a{h->bj.start, h->bj.of_row, h->bj.off, nullptr, (TX*)W.z};
+  if constexpr (sizeof(TX) == 8)
+    a.inv = h->bj.inv;
+  else
+    a.inv = h->bj.inv32;
+  return a;
+}
+
+// K CG iterations of the given form on levels lo..hi.
 template <typename TV, typename TX>
-static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int hi, TX* x, int K, int G, bool one1) {
+static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int hi, TX* x, int K, int G, int form) {
   hipStream_t s = h->ctx->stream;
   const WorkTable& ws = h->wt_spmv;
-  const WorkTable& wv = h->wt_vec;
+  const bool pcf = form == kCgOneRedBj;
+  const WorkTable& wv = pcf ? h->bj.wt : h->wt_vec;  // vector table (whole preconditioner blocks when pcf)
   const WorkTable& wc = h->wt_sell;
   const bool sell = G == kSellCode;
   const WorkTable& wq = sell ? wc : ws;  // table of the product kernel (and of its partials)
@@ -722,24 +824,53 @@ static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int 
   TX* sv = (TX*)W.p1;
   TX* r = (TX*)W.r;
   TX* q = (TX*)W.q;
-  // q = A v with partials v.q (and v.v when pp is set)
-  auto product = [&](const TX* v, double* pp) {
+  const PcArgs<TX> pc = pc_args<TX>(h, W);
+  // q = A v with partials v.q, v.rv (v.v without rv) when pp, rv.rv when p3
+  auto product = [&](const TX* v, double* pp, const TX* rv, double* p3, const CgLevel* st) {
     if (qbn <= 0) return;
     if (sell)
       hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX>), dim3(qbn), dim3(kBlock), 0, s, wc, qb0, h->sell.sptr, h->sell.rows,
-                         h->sell.col, sell_values<TV>(h->sell), v, q, W.st, W.part_s, pp);
+                         h->sell.col, sell_values<TV>(h->sell), v, q, st, W.part_s, pp, rv, p3);
     else
-      launch_cg_spmv1<TV, TX>(s, G, ws, qb0, qbn, h->diag, dval, v, q, W.st, W.part_s, h->prec, h->dim, pp);
+      launch_cg_spmv1<TV, TX>(s, G, ws, qb0, qbn, h->diag, dval, v, q, st, W.part_s, h->prec, h->dim, pp, rv, p3);
   };
+  // fold the reduction into the update when every level's partials are few
+  int maxpart = 0;
+  for (int l = lo; l <= hi; ++l) maxpart = std::max(maxpart, wq.h_lev_begin[l + 1] - wq.h_lev_begin[l]);
+  const bool fused = form != kCgTextbook && maxpart <= kFusedMaxPartials;
+  // single-reduction product: of z (= M^-1 r) with r.z and r.r partials, or of r with r.r
+  const TX* zv = pcf ? pc.z : r;
+  const TX* rv = pcf ? r : nullptr;
+  double* p3 = pcf ? W.part_s3 : nullptr;
   for (int it = 0; it < K; ++it) {
-    if (one1) {
-      product(r, W.part_s2);
-      hipLaunchKernelGGL(k_cg1_red, dim3(nlev), dim3(kRedBlock), 0, s, lo, wq.lev_begin, W.part_s, W.part_s2, W.st);
-      if (vbn > 0) hipLaunchKernelGGL(k_cg1_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p, sv, q, W.st);
+    if (form != kCgTextbook && fused) {
+      CgLevel* cur = W.st + (size_t)(it & 1) * h->L;
+      CgLevel* nxt = W.st + (size_t)((it + 1) & 1) * h->L;
+      product(zv, W.part_s2, rv, p3, cur);
+      if (vbn > 0) {
+        if (pcf)
+          hipLaunchKernelGGL((k_cg1_step<TX, true>), dim3(vbn), dim3(kBlock), 0, s, wv, vb0, wq.lev_begin, W.part_s,
+                             W.part_s2, p3, x, r, p, sv, q, cur, nxt, pc);
+        else
+          hipLaunchKernelGGL((k_cg1_step<TX, false>), dim3(vbn), dim3(kBlock), 0, s, wv, vb0, wq.lev_begin, W.part_s,
+                             W.part_s2, p3, x, r, p, sv, q, cur, nxt, pc);
+      }
+    } else if (form != kCgTextbook) {
+      product(zv, W.part_s2, rv, p3, W.st);
+      hipLaunchKernelGGL(k_cg1_red, dim3(nlev), dim3(kRedBlock), 0, s, lo, wq.lev_begin, W.part_s, W.part_s2, p3,
+                         W.st);
+      if (vbn > 0) {
+        if (pcf)
+          hipLaunchKernelGGL((k_cg1_update<TX, true>), dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p, sv, q, W.st,
+                             pc);
+        else
+          hipLaunchKernelGGL((k_cg1_update<TX, false>), dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p, sv, q, W.st,
+                             pc);
+      }
     } else {
       // direction update (beta = 0 on the first iteration after the init, p = 0 there)
       if (vbn > 0) hipLaunchKernelGGL(k_cg_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, r, p, W.st);
-      product(p, nullptr);
+      product(p, nullptr, nullptr, nullptr, W.st);
       hipLaunchKernelGGL(k_cg_red_a, dim3(nlev), dim3(kRedBlock), 0, s, lo, wq.lev_begin, W.part_s, W.st);
       if (vbn > 0)
         hipLaunchKernelGGL(k_cg_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p, q, W.st, W.part_v);
@@ -751,8 +882,8 @@ static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int 
 // Instantiated graph of one chunk (captured on first use).
 template <typename TV, typename TX>
 static mskm_status chunk_graph(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int hi, TX* x, int K, int G,
-                               bool one1, hipGraphExec_t* out) {
-  const int tx = (int)sizeof(TX) + (one1 ? 100 : 0);
+                               int form, hipGraphExec_t* out) {
+  const int tx = (int)sizeof(TX) + 100 * form;
   for (const auto& g : W.graphs)
     if (g.tx == tx && g.val == dval && g.lo == lo && g.hi == hi && g.x == x && g.K == K && g.G == G) {
       *out = g.exec;
@@ -761,7 +892,7 @@ static mskm_status chunk_graph(mskm_hier* h, SolveWS& W, const TV* dval, int lo,
   hipStream_t s = h->ctx->stream;
   hipGraph_t graph = nullptr;
   MSKM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  enqueue_chunk<TV, TX>(h, W, dval, lo, hi, x, K, G, one1);
+  enqueue_chunk<TV, TX>(h, W, dval, lo, hi, x, K, G, form);
   MSKM_HIP_TRY(hipStreamEndCapture(s, &graph));
   hipGraphExec_t exec = nullptr;
   const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -778,7 +909,7 @@ static mskm_status chunk_graph(mskm_hier* h, SolveWS& W, const TV* dval, int lo,
 // each chunk and stops when every level has stopped.
 template <typename TV, typename TX>
 static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::vector<char>& on, const TX* b, TX* x,
-                          double rtol, int maxit, bool warm, int K, CgStats* cs, const mskm_mlp* mlp = nullptr) {
+                          double rtol, int maxit, bool warm, int K, CgStats* cs, const mskm_mlp* mlp, bool bj) {
   hipStream_t s = h->ctx->stream;
   const WorkTable& ws = h->wt_spmv;
   int lo = 0, hi = h->L - 1;
@@ -807,11 +938,14 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
       if (on[l]) MSKM_TRY(mlp_predict_rows<TX>(h, mlp, l, b, x));
     warm = true;
   }
-  const bool one1 = sizeof(TX) == 4;  // FP32 inner solves: single-reduction form
+  // form: preconditioned single-reduction when asked; the single-reduction
+  // form for the FP32 inner solves; the textbook form otherwise
+  const int form = bj ? kCgOneRedBj : sizeof(TX) == 4 ? kCgOneRed : kCgTextbook;
   if (sbn > 0)
     hipLaunchKernelGGL((k_cg_init<kGDiag, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, h->diag.rowptr, h->diag.col,
                        dval, b, x, (TX*)W.r, (TX*)W.p0, W.st, warm ? 1 : 0, W.part_s, W.part_s2, sb0, (TX*)W.p1);
   hipLaunchKernelGGL(k_cg_red_init, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.part_s2, W.st);
+  if (bj) launch_bj_apply<TX>(h, lo, hi, (const TX*)W.r, (TX*)W.z);
   if (mlp) {  // CG judges the warm start: ||b - A x0|| >= ||b|| restarts that level from zero
     MSKM_HIP_TRY(hipMemcpyAsync(W.h_st, W.st, h->L * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
     MSKM_HIP_TRY(hipStreamSynchronize(s));
@@ -835,10 +969,11 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
                            dval, b, x, (TX*)W.r, (TX*)W.p0, W.st, 1, W.part_s, W.part_s2, sb0, (TX*)W.p1);
       hipLaunchKernelGGL(k_cg_red_init, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.part_s2,
                          W.st);
+      if (bj) launch_bj_apply<TX>(h, lo, hi, (const TX*)W.r, (TX*)W.z);
     }
   }
   hipGraphExec_t exec = nullptr;
-  MSKM_TRY((chunk_graph<TV, TX>(h, W, dval, lo, hi, x, K, G, one1, &exec)));
+  MSKM_TRY((chunk_graph<TV, TX>(h, W, dval, lo, hi, x, K, G, form, &exec)));
   // Two chunks in flight: chunk k+1 is queued before the host reads chunk
   // k's state, so the device does not idle during the check. Iterations of
   // stopped levels are no-ops, so a speculative chunk changes nothing.
@@ -899,6 +1034,7 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
   TX* beta = (TX*)W.beta;
   TX* t = (TX*)W.t;
   const mskm_mlp* mlp = o->precond == MSKM_PRECOND_LEARNED ? o->mlp : nullptr;
+  const bool bj = o->precond == MSKM_PRECOND_BLOCK_JACOBI;
   const int maxit = o->max_cg_iters > 0 ? o->max_cg_iters : 20000;
   int K = o->check_every > 0 ? o->check_every : 8;
   K += K & 1;  // even chunk length
@@ -913,7 +1049,7 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
       lower_update<TV, TX>(h, lval, alpha, f, beta, h->h_off[l0], h->h_off[l1]);
       std::fill(on.begin(), on.end(), 0);
       for (int l = l0; l < l1; ++l) on[l] = 1;
-      MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, false, K, cs, mlp)));
+      MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, false, K, cs, mlp, bj)));
     }
     *sweeps_done = 0;
     return MSKM_OK;
@@ -926,13 +1062,14 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
   MSKM_HIP_TRY(hipMemsetAsync(t, 0, N * sizeof(TX), s));
   for (int l = 0; l < L; ++l) on[l] = h->h_next[l] >= 0;  // every level below its hierarchy's top
   for (int sw = 0; sw < S && Lmax > 1; ++sw) {
-    MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, t, o->cg_rtol, maxit, o->warm_start != 0 && sw > 0, K, cs)));
+    MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, t, o->cg_rtol, maxit, o->warm_start != 0 && sw > 0, K, cs,
+                             nullptr, bj)));
     lower_update<TV, TX>(h, lval, t, f, beta, 0, N);
     *sweeps_done = sw + 1;
   }
   if (o->warm_start) MSKM_HIP_TRY(hipMemcpyAsync(alpha, t, N * sizeof(TX), hipMemcpyDeviceToDevice, s));
   std::fill(on.begin(), on.end(), 1);
-  MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, o->warm_start != 0, K, cs, mlp)));
+  MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, o->warm_start != 0, K, cs, mlp, bj)));
   return MSKM_OK;
 }
 
@@ -1337,6 +1474,7 @@ mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_o
   const bool io_dev = (o->flags & MSKM_IO_DEVICE) != 0;
   const bool mixed = o->precision == MSKM_PREC_FP32;
   if (mixed ? !h->diag.val32 : !h->diag.val) return fail(MSKM_ESTATE, "requested precision's values are not stored");
+  if (o->precond == MSKM_PRECOND_BLOCK_JACOBI) MSKM_TRY(build_block_jacobi(h));
   DevBuf F, A;
   MSKM_TRY(stage_in(s, f_in, (size_t)N * nrhs, io_dev, F));
   MSKM_TRY(stage_out_alloc(alpha_out, (size_t)N * nrhs, io_dev, A));
