@@ -34,8 +34,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the roofline kernel: rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch) of `bench.py --spmv-only --spmv-op diag
+# --spmv-prec fp32 --spmv-variant 4064`, each scaled by the factor that makes
+# the same counter read 1 GiB for the 1 GiB streaming copy kernel of those
+# runs. Only valid for that kernel on that workload (None: not measured).
+PMC_TRAFFIC = {
+    ("halton2d_L8", "k_spmv_sell<float>"): {"fetch_kib": 247464.125, "fetch_scale": 1048576 / 524299.0,
+                                           "write_kib": 5461.25, "write_scale": 1048576 / 1048606.4},
+}
 TARGET = 1e-8
-RTOL_LADDER = [1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12]
+RTOL_LADDER = [3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12]
 
 
 def log(*a):
@@ -62,29 +71,39 @@ def spmv_kernel_name(code: int, t: str) -> str:
     g, kind = code % 1000, code // 1000
     if kind == 0:
         return f"k_spmv<{g},{t}>"
+    if kind == 3:
+        return f"k_spmv_rec<{g},{t}>"
+    if kind == 4:
+        return f"k_spmv_sell<{t}>"
     return f"k_spmv_v<{g},{t}{',nontemporal' if kind == 2 else ''}>"
 
 
 def calibrate(m, ctx, hd, f_dev, alpha_dev, base_opts: dict, label: str):
-    """Loosest CG tolerance of the ladder whose solution verifies <= 1e-8
-    by the independent FP64 residual."""
-    best = None
+    """Fastest inner CG tolerance of the ladder whose solution verifies the
+    target by the independent FP64 residual, with a 20% margin (other
+    SpMV variants round differently). The time is not monotone in the
+    tolerance (a looser one can need another refinement round), so up to
+    four passing tolerances are timed, from the loosest."""
+    passing = []
     for rt in RTOL_LADDER:
         o = m.solve_opts(cg_rtol=rt, **base_opts)
+        m.mskm_solve(ctx, hd, f_dev, alpha_dev, o)  # first call: graphs and preconditioner set up
         res = m.mskm_solve(ctx, hd, f_dev, alpha_dev, o)
         rel = float(m.mskm_residual(ctx, hd, alpha_dev, f_dev)[0])
         log(f"calibrate {label}: rtol={rt:g} rel={rel:.3e} ms={res.report['solve_ms']:.1f} status={res.status}")
-        if res.status >= 0 and rel <= TARGET:
-            best = rt
-            break
-    if best is None:
+        if res.status >= 0 and rel <= 0.8 * TARGET:
+            passing.append((res.report["solve_ms"], rt))
+            if len(passing) == 4:
+                break
+    if not passing:
         raise RuntimeError(f"{label}: no tolerance in the ladder reaches {TARGET}")
-    return best
+    return min(passing)[1]
 
 
 def cpu_baseline(levels_sample: int, rtol: float):
     """The oracle as it stands, single-threaded, on the first levels of the
-    same hierarchy: assembly + Jacobi/CG solve (the paper's algorithms)."""
+    same hierarchy: assembly + the paper's Jacobi/CG solve (L sweeps) to the
+    same 1e-8 relative residual."""
     import oracle
     import synth
     from oracle import multiscale as ms
@@ -106,8 +125,9 @@ def cpu_baseline(levels_sample: int, rtol: float):
         if ctxm is not None:
             ctxm.__exit__(None, None, None)
     rel = oracle.residual(blk, a, f)[0]
+    nnz = sum(blk.nnz(k, j) for k in range(h.levels) for j in range(k + 1))
     return {"assemble_ms": (t1 - t0) * 1e3, "solve_ms": (t2 - t1) * 1e3, "rel_residual": rel,
-            "n_points": h.n_total, "levels": h.levels}
+            "n_points": h.n_total, "levels": h.levels, "nnz": nnz}
 
 
 def batched(m, ctx, hd, h, pts_dev, dev, fast_opts, rt_fast, nrhs, count):
@@ -268,12 +288,16 @@ def main():
     ap.add_argument("--train-samples", type=int, default=10000)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--fast-rtol", type=float, default=0.0,
+                    help="inner CG tolerance of the fast form (default: calibrated, the fastest that verifies 1e-8)")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D mixed-precision workload")
     ap.add_argument("--spmv-only", action="store_true",
-                    help="assemble, autotune, then only time the FP64 full-T SpMV and a 1 GiB streaming copy kernel "
+                    help="assemble, autotune, then only time one SpMV operator and a 1 GiB streaming copy kernel "
                          "(the counter-collection runs)")
     ap.add_argument("--spmv-variant", type=int, default=0,
                     help="with --spmv-only: pin this SpMV variant code instead of autotuning")
+    ap.add_argument("--spmv-op", choices=("diag", "lower", "full"), default="diag", help="with --spmv-only")
+    ap.add_argument("--spmv-prec", choices=("fp32", "fp64"), default="fp32", help="with --spmv-only")
     ap.add_argument("--batch-count", type=int, default=64, help="hierarchies of the batched solve (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -302,15 +326,20 @@ def main():
     hd = m.mskm_hier_create(ctx, pts_dev, h.offsets, h.delta, fp64=True, fp32=True)
     if args.spmv_only:
         st = m.mskm_hier_stats_get(hd)
+        op = {"diag": m.MSKM_OP_DIAG, "lower": m.MSKM_OP_LOWER, "full": m.MSKM_OP_FULL}[args.spmv_op]
+        prec = m.MSKM_PREC_FP32 if args.spmv_prec == "fp32" else m.MSKM_PREC_FP64
         if args.spmv_variant:
-            m.mskm_set_spmv_width(hd, m.MSKM_OP_FULL, m.MSKM_PREC_FP64, args.spmv_variant)
+            m.mskm_set_spmv_width(hd, op, prec, args.spmv_variant)
         else:
             m.mskm_autotune(ctx, hd, repeats=3)
-        x = torch.randn(N, dtype=torch.float64, device=dev)
+        dt = torch.float32 if prec == m.MSKM_PREC_FP32 else torch.float64
+        x = torch.randn(N, dtype=dt, device=dev)
         y = torch.empty_like(x)
-        ms = m.mskm_apply_internal(ctx, hd, m.MSKM_OP_FULL, x, y, repeats=args.spmv_repeats)
+        m.mskm_apply_internal(ctx, hd, op, x, y, prec=prec, repeats=2)
+        ms = m.mskm_apply_internal(ctx, hd, op, x, y, prec=prec, repeats=args.spmv_repeats)
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
         dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -318,9 +347,12 @@ def main():
             torch.mul(src, 1.0, out=dst)  # a plain streaming kernel: reads 1 GiB, writes 1 GiB
         e1.record()
         torch.cuda.synchronize()
-        b = spmv_bytes(st["nnz_diag"] + st["nnz_lower"], N, 2, 8, 8)
-        print(json.dumps({"spmv_full_fp64_ms": ms, "spmv_bytes": b, "spmv_GBps": b / ms / 1e6,
-                          "variant": m.mskm_spmv_width(hd, m.MSKM_OP_FULL, 0),
+        nnz = {"diag": st["nnz_diag"], "lower": st["nnz_lower"], "full": st["nnz_diag"] + st["nnz_lower"]}[args.spmv_op]
+        sv = 4 if prec == m.MSKM_PREC_FP32 else 8
+        b = spmv_bytes(nnz, N, 2 if args.spmv_op == "full" else 1, sv, sv)
+        code = m.mskm_spmv_width(hd, op, prec)
+        print(json.dumps({"op": args.spmv_op, "prec": args.spmv_prec, "ms": ms, "bytes": b, "GBps": b / ms / 1e6,
+                          "variant": code, "kernel": spmv_kernel_name(code, "float" if sv == 4 else "double"),
                           "copy_bytes_each_way": 1 << 30, "copy_ms": e0.elapsed_time(e1) / args.spmv_repeats}))
         m.mskm_hier_destroy(hd)
         m.mskm_destroy(ctx)
@@ -334,7 +366,7 @@ def main():
     fast_opts = dict(precision=m.MSKM_PREC_FP32, algorithm=m.MSKM_ALG_SEQUENTIAL, target_rel_residual=TARGET,
                      max_refine=8, precond=m.MSKM_PRECOND_BLOCK_JACOBI)
     plain_opts = dict(precision=m.MSKM_PREC_FP64, algorithm=m.MSKM_ALG_MONOLITHIC)
-    rt_fast = calibrate(m, ctx, hd, f_dev, alpha_dev, fast_opts, "fast")
+    rt_fast = args.fast_rtol or calibrate(m, ctx, hd, f_dev, alpha_dev, fast_opts, "fast")
     learned = None
     if not args.no_learned:
         net, tinfo = train_warm_start(m, ctx, args)
@@ -442,7 +474,12 @@ def main():
     u3 = None if args.no_3d else uniform3d(m, ctx, dev, args)
     m.mskm_destroy(ctx)
 
-    dom = spmv["full_fp64"]
+    # dominant kernel of the timed step: the CG products on the diagonal blocks (FP32)
+    dom = spmv["diag_fp32"]
+    dom_kernel = spmv_kernel_name(widths["diag_fp32"], "float")
+    pmc = PMC_TRAFFIC.get((f"halton2d_L{args.levels}", dom_kernel))
+    traffic = None if pmc is None else int(pmc["fetch_kib"] * pmc["fetch_scale"] * 1024
+                                           + pmc["write_kib"] * pmc["write_scale"] * 1024)
     out = {
         "metric": "time-to-1e-8 rel. residual + kernel SpMV GB/s, plain FP64 vs mixed/learned",
         "value": round(fast_ms, 3),
@@ -477,18 +514,21 @@ def main():
         "spmv_GBps": round(dom["GBps"], 1),
         "spmv_widths": widths,
         "roofline": {"bound": "hbm", "achieved": round(dom["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(dom["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": spmv_kernel_name(widths["full_fp64"], "double") + " (T = D + lower, FP64 values)"},
+                     "frac": round(dom["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": dom_kernel + " (D, the diagonal blocks of all levels, FP32 values: the CG products)",
+                     "algorithmic_bytes": dom["bytes"], "ms": round(dom["ms"], 5)},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 1 thread)")
-        cb = cpu_baseline(args.cpu_levels, rt_plain)
-        out["cpu_baseline"] = {"value": round(cb["assemble_ms"] + cb["solve_ms"], 1), "unit": "ms", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"first {cb['levels']} of the {args.levels} Halton levels "
-                                         f"({cb['n_points']} points): assembly + {cb['levels']} Jacobi sweeps with "
-                                         f"CG rtol {rt_plain:g}; rel residual {cb['rel_residual']:.2e}",
-                               "assemble_ms": round(cb["assemble_ms"], 1), "solve_ms": round(cb["solve_ms"], 1)}
+        cb = cpu_baseline(args.cpu_levels, 1e-7)
+        scale = (nnz_d + nnz_l) / cb["nnz"]
+        out["cpu_baseline"] = {
+            "value": round(cb["solve_ms"] * scale, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"first {cb['levels']} of the {args.levels} Halton levels ({cb['n_points']} points, "
+                      f"{cb['nnz']} nonzeros): the oracle's Jacobi sweeps ({cb['levels']}) with CG rtol 1e-7 to "
+                      f"rel. residual {cb['rel_residual']:.2e}, single thread; value = the sample's solve time "
+                      f"x {scale:.1f} (nonzero ratio of the full workload, linear extrapolation)",
+            "sample_solve_ms": round(cb["solve_ms"], 1), "sample_assemble_ms": round(cb["assemble_ms"], 1)}
     print(json.dumps(out), flush=True)
 
 

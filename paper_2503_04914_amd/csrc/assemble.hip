@@ -600,26 +600,45 @@ __global__ void __launch_bounds__(kBlock) k_sell_width(int64_t nslices, const in
   w[s] = m * kSellC;
 }
 
-// One wave per slice: copy the CSR rows into the slot-interleaved layout.
-__global__ void __launch_bounds__(kBlock) k_sell_fill(int64_t nslices, const int32_t* __restrict__ rows,
-                                                      const int64_t* __restrict__ sptr, const int64_t* __restrict__ rp,
-                                                      const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                      const float* __restrict__ val32, int32_t* __restrict__ scol,
-                                                      double* __restrict__ sval, float* __restrict__ sval32) {
-  const int64_t s = (int64_t)blockIdx.x * (kBlock / kSellC) + threadIdx.x / kSellC;
-  if (s >= nslices) return;
-  const int t = threadIdx.x % kSellC;
+// One wave (workgroup) per slice: copy the CSR rows into the slot-interleaved
+// layout through LDS tiles of 16 entries x 64 slots: the loads read 4 rows x
+// 16 consecutive entries per instruction, the stores write one entry of all
+// 64 slots (contiguous).
+constexpr int kSellTile = 16;
+__global__ void __launch_bounds__(kSellC)
+    k_sell_fill(int64_t nslices, const int32_t* __restrict__ rows, const int64_t* __restrict__ sptr,
+                const int64_t* __restrict__ rp, const int32_t* __restrict__ col, const double* __restrict__ val,
+                const float* __restrict__ val32, int32_t* __restrict__ scol, double* __restrict__ sval,
+                float* __restrict__ sval32) {
+  __shared__ int32_t tc[kSellTile][kSellC + 1];
+  __shared__ double tv[kSellTile][kSellC + 1];
+  __shared__ float tf[kSellTile][kSellC + 1];
+  const int64_t s = blockIdx.x;
+  const int t = threadIdx.x;
   const int32_t row = rows[s * kSellC + t];
-  const int64_t e0 = sptr[s], w = (sptr[s + 1] - e0) / kSellC;
   const int64_t b = row >= 0 ? rp[row] : 0;
   const int64_t len = row >= 0 ? rp[row + 1] - b : 0;
-  const int32_t pad_col = row >= 0 ? row : 0;
-  for (int64_t k = 0; k < w; ++k) {
-    const int64_t d = e0 + k * kSellC + t;
-    const bool in = k < len;
-    scol[d] = in ? col[b + k] : pad_col;
-    if (sval) sval[d] = in ? val[b + k] : 0.0;
-    if (sval32) sval32[d] = in ? val32[b + k] : 0.0f;
+  const int64_t e0 = sptr[s], w = (sptr[s + 1] - e0) / kSellC;
+  constexpr int kRowsPerPass = kSellC / kSellTile;  // 4
+  for (int64_t k0 = 0; k0 < w; k0 += kSellTile) {
+    for (int j = 0; j < kSellTile; ++j) {
+      const int rr = j * kRowsPerPass + t / kSellTile, kk = t % kSellTile;
+      const int64_t brr = __shfl(b, rr, kSellC), lrr = __shfl(len, rr, kSellC);
+      const int32_t rowrr = __shfl(row, rr, kSellC);
+      const int64_t k = k0 + kk;
+      const bool in = k < lrr;
+      tc[kk][rr] = in ? col[brr + k] : (rowrr >= 0 ? rowrr : 0);
+      if (val) tv[kk][rr] = in ? val[brr + k] : 0.0;
+      if (val32) tf[kk][rr] = in ? val32[brr + k] : 0.0f;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kSellTile && k0 + kk < w; ++kk) {
+      const int64_t d = e0 + (k0 + kk) * kSellC + t;
+      scol[d] = tc[kk][t];
+      if (sval) sval[d] = tv[kk][t];
+      if (sval32) sval32[d] = tf[kk][t];
+    }
+    __syncthreads();
   }
 }
 
@@ -651,8 +670,8 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32) {
   if (want64) MSKM_TRY(halloc(h, &S.val, (size_t)S.entries));
   if (want32) MSKM_TRY(halloc(h, &S.val32, (size_t)S.entries));
   if (S.nslices > 0)
-    hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(S.nslices, kBlock / kSellC)), dim3(kBlock), 0, s, S.nslices, S.rows,
-                       S.sptr, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, S.col, S.val, S.val32);
+    hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)S.nslices), dim3(kSellC), 0, s, S.nslices, S.rows, S.sptr,
+                       h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, S.col, S.val, S.val32);
   // launch table: blocks of 4 slices (one wave each) within each level
   WorkTable& wt = h->wt_sell;
   std::vector<int32_t> lev;
