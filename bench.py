@@ -80,10 +80,11 @@ def spmv_kernel_name(code: int, t: str) -> str:
 
 def calibrate(m, ctx, hd, f_dev, alpha_dev, base_opts: dict, label: str):
     """Fastest inner CG tolerance of the ladder whose solution verifies the
-    target by the independent FP64 residual, with a 20% margin (other
-    SpMV variants round differently). The time is not monotone in the
-    tolerance (a looser one can need another refinement round), so up to
-    four passing tolerances are timed, from the loosest."""
+    target by the independent FP64 residual, with a 5% margin (the timed
+    steps' FP32-only hierarchies compute that residual by another kernel,
+    rounding differently in the last digits). The time is not monotone in
+    the tolerance (a looser one can need another refinement round), so up
+    to four passing tolerances are timed, from the loosest."""
     passing = []
     for rt in RTOL_LADDER:
         o = m.solve_opts(cg_rtol=rt, **base_opts)
@@ -91,7 +92,7 @@ def calibrate(m, ctx, hd, f_dev, alpha_dev, base_opts: dict, label: str):
         res = m.mskm_solve(ctx, hd, f_dev, alpha_dev, o)
         rel = float(m.mskm_residual(ctx, hd, alpha_dev, f_dev)[0])
         log(f"calibrate {label}: rtol={rt:g} rel={rel:.3e} ms={res.report['solve_ms']:.1f} status={res.status}")
-        if res.status >= 0 and rel <= 0.8 * TARGET:
+        if res.status >= 0 and rel <= 0.95 * TARGET:
             passing.append((res.report["solve_ms"], rt))
             if len(passing) == 4:
                 break
