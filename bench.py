@@ -143,8 +143,8 @@ def batched(m, ctx, hd, h, pts_dev, dev, fast_opts, rt_fast, nrhs, count):
         log(f"batched: {nrhs} right-hand sides")
         F = torch.stack([synth.fourier_target(3000 + r).torch_eval(pts_dev) for r in range(nrhs)], dim=1).contiguous()
         A = torch.zeros_like(F)
-        # several right-hand sides per launch: plain CG (no per-rhs preconditioner)
-        o = m.solve_opts(cg_rtol=rt_fast, **dict(fast_opts, precond=m.MSKM_PRECOND_NONE, mlp=None))
+        # several right-hand sides per launch (block-Jacobi preconditioned CG, no learned warm start)
+        o = m.solve_opts(cg_rtol=rt_fast, **dict(fast_opts, precond=m.MSKM_PRECOND_BLOCK_JACOBI, mlp=None))
         m.mskm_solve(ctx, hd, F, A, o, nrhs=nrhs)  # warm-up (allocations, code objects)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -360,8 +360,8 @@ mskm_status mskm_solve(mskm_ctx* ctx, const mskm_hier* h, const double* f, int32
   if (o.precond == MSKM_PRECOND_LEARNED && !o.mlp) return fail(MSKM_EINVAL, "learned warm start needs an mlp");
   if (o.precond != MSKM_PRECOND_NONE && o.precond != MSKM_PRECOND_LEARNED && o.precond != MSKM_PRECOND_BLOCK_JACOBI)
     return fail(MSKM_EINVAL, "unknown precond");
-  if (nrhs > 1 && o.precond != MSKM_PRECOND_NONE)
-    return fail(MSKM_EINVAL, "solves of several right-hand sides take no warm start or preconditioner");
+  if (nrhs > 1 && o.precond == MSKM_PRECOND_LEARNED)
+    return fail(MSKM_EINVAL, "solves of several right-hand sides take no learned warm start");
   if (!(o.flags & MSKM_IO_DEVICE)) {
     for (int64_t i = 0; i < h->N * (int64_t)nrhs; ++i)
       if (!std::isfinite(f[i])) return fail(MSKM_EINVAL, "non-finite right-hand side");

@@ -32,6 +32,7 @@ static MrCfg mr_cfg(int R) {
 // Per-(level, rhs) CG state (index l * R + r).
 struct MrState {
   double rtol2, bb, rr, alpha, beta;
+  double rz;  // r.z with z = M^-1 r (preconditioned), else r.r
   int32_t maxit, on, iters, done, capped, pad;
 };
 
@@ -109,6 +110,29 @@ __device__ __forceinline__ void mr_block_partial(const double* acc, const MrCfg&
 
 constexpr int kMrLds = kBlock * kMaxRPerLane;  // doubles of LDS for block partials
 
+// Reductions over a level's per-block partials part[b][R]: one block of
+// kMrRedThreads threads per (level, chunk of 64 right-hand sides); thread
+// (k, r) sums the partials b = lev_begin + k, k + kMrRedLanes, ... of rhs r,
+// then the kMrRedLanes sums of each rhs are added in LDS in a fixed order
+// (deterministic).
+constexpr int kMrRedLanes = 16;
+constexpr int kMrRedThreads = 64 * kMrRedLanes;
+
+__device__ __forceinline__ double mr_level_sum(const double* __restrict__ part, int b0, int b1, int R, int r,
+                                               double* sm) {
+  const int k = threadIdx.x / 64, rl = threadIdx.x % 64;
+  double v = 0.0;
+  if (r < R)
+    for (int b = b0 + k; b < b1; b += kMrRedLanes) v += part[(size_t)b * R + r];
+  sm[k * 64 + rl] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (k == 0)
+    for (int q = 0; q < kMrRedLanes; ++q) t += sm[q * 64 + rl];
+  __syncthreads();
+  return t;  // valid in the threads with k == 0
+}
+
 // init: X = 0, Rv = B, P = 0; partials of b.b and r.r per rhs.
 template <typename TX>
 __global__ void __launch_bounds__(kBlock)
@@ -135,28 +159,41 @@ __global__ void __launch_bounds__(kBlock)
   mr_block_partial(acc, c, sm, bbp, blk);
 }
 
-// One block per level, threads over rhs: initial state (r = b, so rr = bb).
-__global__ void __launch_bounds__(kBlock) k_mr_red_init(int lev0, const int32_t* __restrict__ lev_begin,
-                                                        const double* __restrict__ bbp, MrState* __restrict__ st,
-                                                        int32_t* __restrict__ lev_done, MrCfg c) {
-  __shared__ int any;
+// Initial state (r = b, so rr = bb); grid (levels, rhs chunks of 64). The
+// level's done flag is set by the host-visible all-stopped test of red_b.
+__global__ void __launch_bounds__(kMrRedThreads) k_mr_red_init(int lev0, const int32_t* __restrict__ lev_begin,
+                                                               const double* __restrict__ bbp,
+                                                               const int32_t* __restrict__ zlev_begin,
+                                                               const double* __restrict__ rzp,
+                                                               MrState* __restrict__ st, MrCfg c) {
+  __shared__ double sm[kMrRedThreads];
   const int l = lev0 + blockIdx.x;
-  if (threadIdx.x == 0) any = 0;
-  __syncthreads();
-  for (int r = threadIdx.x; r < c.R; r += kBlock) {
-    double bb = 0.0;
-    for (int b = lev_begin[l]; b < lev_begin[l + 1]; ++b) bb += bbp[(size_t)b * c.R + r];
+  const int r = blockIdx.y * 64 + (int)(threadIdx.x % 64);
+  const double bb = mr_level_sum(bbp, lev_begin[l], lev_begin[l + 1], c.R, r, sm);
+  const double rz = rzp ? mr_level_sum(rzp, zlev_begin[l], zlev_begin[l + 1], c.R, r, sm) : bb;
+  if (threadIdx.x < 64 && r < c.R) {
     MrState& S = st[(size_t)l * c.R + r];
     S.bb = bb;
     S.rr = bb;
+    S.rz = rz;
     S.alpha = S.beta = 0.0;
     S.iters = 0;
     const bool finite = isfinite(bb);
     const bool conv = finite && !(bb > S.rtol2 * bb);
     S.capped = S.on && !conv && (!finite || S.maxit <= 0);
     S.done = !S.on || conv || S.capped;
-    if (!S.done) any = 1;
   }
+}
+
+// lev_done[l] = every system of level l has stopped (one block per level).
+__global__ void __launch_bounds__(kBlock) k_mr_lev_done(int lev0, const MrState* __restrict__ st,
+                                                        int32_t* __restrict__ lev_done, MrCfg c) {
+  __shared__ int any;
+  const int l = lev0 + blockIdx.x;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < c.R; r += kBlock)
+    if (!st[(size_t)l * c.R + r].done) any = 1;
   __syncthreads();
   if (threadIdx.x == 0) lev_done[l] = !any;
 }
@@ -166,6 +203,7 @@ template <typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_mr_dir(const WorkTable wt, int base, const TX* __restrict__ r, TX* __restrict__ p,
              const MrState* __restrict__ st, const int32_t* __restrict__ lev_done, MrCfg c) {
+  // r here is the direction's source: the residual, or z = M^-1 r when preconditioned
   const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
   if (lev_done[l]) return;
@@ -216,18 +254,20 @@ __global__ void __launch_bounds__(kBlock)
   mr_block_partial(part, c, sm, pqp, blk);
 }
 
-__global__ void __launch_bounds__(kBlock) k_mr_red_a(int lev0, const int32_t* __restrict__ lev_begin,
-                                                     const double* __restrict__ pqp, MrState* __restrict__ st,
-                                                     const int32_t* __restrict__ lev_done, MrCfg c) {
+// alpha = rr / p.q per system; grid (levels, rhs chunks of 64).
+__global__ void __launch_bounds__(kMrRedThreads) k_mr_red_a(int lev0, const int32_t* __restrict__ lev_begin,
+                                                            const double* __restrict__ pqp, MrState* __restrict__ st,
+                                                            const int32_t* __restrict__ lev_done, MrCfg c) {
+  __shared__ double sm[kMrRedThreads];
   const int l = lev0 + blockIdx.x;
   if (lev_done[l]) return;
-  for (int r = threadIdx.x; r < c.R; r += kBlock) {
+  const int r = blockIdx.y * 64 + (int)(threadIdx.x % 64);
+  const double pq = mr_level_sum(pqp, lev_begin[l], lev_begin[l + 1], c.R, r, sm);
+  if (threadIdx.x < 64 && r < c.R) {
     MrState& S = st[(size_t)l * c.R + r];
-    if (S.done) continue;
-    double pq = 0.0;
-    for (int b = lev_begin[l]; b < lev_begin[l + 1]; ++b) pq += pqp[(size_t)b * c.R + r];
+    if (S.done) return;
     if (pq > 0.0 && isfinite(pq)) {
-      S.alpha = S.rr / pq;
+      S.alpha = S.rz / pq;
     } else {
       S.alpha = 0.0;
       S.done = 1;
@@ -265,35 +305,84 @@ __global__ void __launch_bounds__(kBlock)
   mr_block_partial(acc, c, sm, rrp, blk);
 }
 
-__global__ void __launch_bounds__(kBlock) k_mr_red_b(int lev0, const int32_t* __restrict__ lev_begin,
-                                                     const double* __restrict__ rrp, MrState* __restrict__ st,
-                                                     int32_t* __restrict__ lev_done, MrCfg c) {
-  __shared__ int any;
+// rr_new, stop test, beta per system; grid (levels, rhs chunks of 64).
+__global__ void __launch_bounds__(kMrRedThreads) k_mr_red_b(int lev0, const int32_t* __restrict__ lev_begin,
+                                                            const double* __restrict__ rrp,
+                                                            const int32_t* __restrict__ zlev_begin,
+                                                            const double* __restrict__ rzp, MrState* __restrict__ st,
+                                                            const int32_t* __restrict__ lev_done, MrCfg c) {
+  __shared__ double sm[kMrRedThreads];
   const int l = lev0 + blockIdx.x;
   if (lev_done[l]) return;
-  if (threadIdx.x == 0) any = 0;
-  __syncthreads();
-  for (int r = threadIdx.x; r < c.R; r += kBlock) {
+  const int r = blockIdx.y * 64 + (int)(threadIdx.x % 64);
+  const double rr = mr_level_sum(rrp, lev_begin[l], lev_begin[l + 1], c.R, r, sm);
+  const double rz = rzp ? mr_level_sum(rzp, zlev_begin[l], zlev_begin[l + 1], c.R, r, sm) : rr;
+  if (threadIdx.x < 64 && r < c.R) {
     MrState& S = st[(size_t)l * c.R + r];
-    if (!S.done) {
-      double rr = 0.0;
-      for (int b = lev_begin[l]; b < lev_begin[l + 1]; ++b) rr += rrp[(size_t)b * c.R + r];
-      S.iters += 1;
-      const double old = S.rr;
-      S.rr = rr;
-      if (isfinite(rr) && !(rr > S.rtol2 * S.bb)) {
-        S.done = 1;
-      } else if (!isfinite(rr) || S.iters >= S.maxit) {
-        S.done = 1;
-        S.capped = 1;
-      } else {
-        S.beta = rr / old;
-      }
+    if (S.done) return;
+    S.iters += 1;
+    const double old = S.rz;
+    S.rr = rr;
+    S.rz = rz;
+    if (isfinite(rr) && !(rr > S.rtol2 * S.bb)) {
+      S.done = 1;
+    } else if (!isfinite(rr) || !isfinite(rz) || S.iters >= S.maxit) {
+      S.done = 1;
+      S.capped = 1;
+    } else {
+      S.beta = rz / old;
     }
-    if (!S.done) any = 1;
   }
+}
+
+// Block-Jacobi product for many right-hand sides: z[i][:] = M^-1 r over the
+// workgroups of whole blocks (grid: groups x chunks of 64 rhs). Wave w of a
+// workgroup takes blocks w, w + 4, ... of its group; lane t holds rhs
+// chunk*64 + t, keeps the block's m entries of r in registers and forms its
+// m entries of z (each r value is read once per block). Partial r.z per
+// (group, rhs).
+template <typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_mr_bj_apply(const WorkTable wt, int base, const int64_t* __restrict__ start, const int32_t* __restrict__ of_row,
+                  const int64_t* __restrict__ off, const TX* __restrict__ inv, const TX* __restrict__ rv,
+                  TX* __restrict__ z, const int32_t* __restrict__ lev_done, double* __restrict__ rzp, MrCfg c) {
+  __shared__ double sm[kBlock];
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (lev_done && lev_done[l]) return;
+  const int t = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int rr = blockIdx.y * 64 + t;
+  const bool on = rr < c.R;
+  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
+  const int32_t bfirst = of_row[row0], blast = of_row[row1 - 1];
+  double acc = 0.0;
+  for (int32_t b = bfirst + w; b <= blast; b += kBlock / 64) {
+    const int64_t a = start[b];
+    const int m = (int)(start[b + 1] - a);
+    const TX* Mb = inv + off[b];
+    TX x[kBjMax];
+#pragma unroll
+    for (int j = 0; j < kBjMax; ++j) x[j] = (on && j < m) ? rv[(a + j) * c.R + rr] : (TX)0;
+    for (int i = 0; i < m; ++i) {
+      TX zi = 0;
+#pragma unroll
+      for (int j = 0; j < kBjMax; ++j)
+        if (j < m) zi += Mb[(int64_t)i * m + j] * x[j];
+      if (on) z[(a + i) * c.R + rr] = zi;
+      TX xi = 0;
+#pragma unroll
+      for (int j = 0; j < kBjMax; ++j)
+        if (j == i) xi = x[j];
+      acc += (double)xi * (double)zi;
+    }
+  }
+  sm[w * 64 + t] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) lev_done[l] = !any;
+  if (w == 0 && on) {
+    double s = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) s += sm[q * 64 + t];
+    rzp[(size_t)blk * c.R + rr] = s;
+  }
 }
 
 // FP64 residual per rhs over the level-aligned SpMV table: partials
@@ -349,6 +438,28 @@ __global__ void __launch_bounds__(kBlock)
   mr_block_partial(pff, c, sm, ffp, blk);
 }
 
+// Residual of a = 0 (r = f): partials of f.f for both sums.
+__global__ void __launch_bounds__(kBlock)
+    k_mr_residual_zero(const WorkTable wt, const double* __restrict__ f, double* __restrict__ rout,
+                       double* __restrict__ rrp, double* __restrict__ ffp, MrCfg c) {
+  __shared__ double sm[kMrLds];
+  const int blk = xcd_block_id(gridDim.x);
+  const int gl = threadIdx.x % c.LR;
+  double pff[kMaxRPerLane];
+  for (int m = 0; m < kMaxRPerLane; ++m) pff[m] = 0.0;
+  for (int64_t i = wt.row0[blk] + threadIdx.x / c.LR; i < wt.row1[blk]; i += kBlock / c.LR) {
+    for (int m = 0; m < c.RM; ++m) {
+      const int r = gl + m * c.LR;
+      if (r >= c.R) continue;
+      const double fi = f[i * c.R + r];
+      if (rout) rout[i * c.R + r] = fi;
+      pff[m] += fi * fi;
+    }
+  }
+  mr_block_partial(pff, c, sm, rrp, blk);
+  mr_block_partial(pff, c, sm, ffp, blk);
+}
+
 __global__ void __launch_bounds__(kBlock) k_mr_axpy(const float* __restrict__ d, double* __restrict__ a, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) a[i] += (double)d[i];
@@ -369,13 +480,15 @@ struct MrWS {
   size_t NR = 0;
   double *fi = nullptr, *ai = nullptr, *res = nullptr;
   void *beta = nullptr, *t = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *f32 = nullptr, *a32 = nullptr;
-  double *part_s = nullptr, *part_v = nullptr, *part_v2 = nullptr;
+  void* z = nullptr;  // M^-1 r (block-Jacobi form)
+  double *part_s = nullptr, *part_v = nullptr, *part_v2 = nullptr, *part_z = nullptr;
+  bool pc = false;
   MrState* st = nullptr;
   int32_t* lev_done = nullptr;
   int32_t* h_lev_done = nullptr;
   ~MrWS() {
-    for (void* v : {(void*)fi, (void*)ai, (void*)res, beta, t, r, p, q, f32, a32, (void*)part_s, (void*)part_v,
-                    (void*)part_v2, (void*)st, (void*)lev_done})
+    for (void* v : {(void*)fi, (void*)ai, (void*)res, beta, t, r, p, q, f32, a32, z, (void*)part_s, (void*)part_v,
+                    (void*)part_v2, (void*)part_z, (void*)st, (void*)lev_done})
       (void)hipFree(v);
     if (h_lev_done) (void)hipHostFree(h_lev_done);
   }
@@ -417,21 +530,48 @@ mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>
   TX* r = (TX*)W.r;
   TX* p = (TX*)W.p;
   TX* q = (TX*)W.q;
+  TX* z = (TX*)W.z;
+  const bool pc = W.pc;
+  const BlockJacobi& B = h->bj;
+  const int zb0 = pc ? B.wt.h_lev_begin[lo] : 0, zbn = pc ? B.wt.h_lev_begin[hi + 1] - zb0 : 0;
+  const TX* inv = nullptr;
+  if (pc) {
+    if constexpr (sizeof(TX) == 8)
+      inv = B.inv;
+    else
+      inv = B.inv32;
+  }
+  const dim3 zgrid(std::max(zbn, 1), (c.R + 63) / 64);
+  auto bj_apply = [&](const int32_t* ld) {
+    if (zbn > 0)
+      hipLaunchKernelGGL(k_mr_bj_apply<TX>, zgrid, dim3(kBlock), 0, s, B.wt, zb0, B.start, B.of_row, B.off, inv,
+                         (const TX*)r, z, ld, W.part_z, c);
+  };
+  const int32_t* zlb = pc ? B.wt.lev_begin : nullptr;
+  double* rzp = pc ? W.part_z : nullptr;
   if (vbn > 0)
     hipLaunchKernelGGL(k_mr_init<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, b, x, r, p, W.st, W.part_v, c);
-  hipLaunchKernelGGL(k_mr_red_init, dim3(nlev), dim3(kBlock), 0, s, lo, wv.lev_begin, W.part_v, W.st, W.lev_done, c);
+  if (pc) bj_apply(nullptr);
+  const dim3 rgrid(nlev, (c.R + 63) / 64);
+  hipLaunchKernelGGL(k_mr_red_init, rgrid, dim3(kMrRedThreads), 0, s, lo, wv.lev_begin, W.part_v, zlb, rzp, W.st, c);
+  hipLaunchKernelGGL(k_mr_lev_done, dim3(nlev), dim3(kBlock), 0, s, lo, W.st, W.lev_done, c);
   for (int it = 0; it < maxit; it += K) {
     for (int kk = 0; kk < K; ++kk) {
       if (vbn > 0)
-        hipLaunchKernelGGL(k_mr_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, r, p, W.st, W.lev_done, c);
+        hipLaunchKernelGGL(k_mr_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, pc ? (const TX*)z : (const TX*)r, p,
+                           W.st, W.lev_done, c);
       if (sbn > 0)
         hipLaunchKernelGGL((k_mr_cg_spmm<TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, h->diag.rowptr, h->diag.col,
                            dval, p, q, W.lev_done, W.part_s, c);
-      hipLaunchKernelGGL(k_mr_red_a, dim3(nlev), dim3(kBlock), 0, s, lo, ws.lev_begin, W.part_s, W.st, W.lev_done, c);
+      hipLaunchKernelGGL(k_mr_red_a, rgrid, dim3(kMrRedThreads), 0, s, lo, ws.lev_begin, W.part_s, W.st, W.lev_done,
+                         c);
       if (vbn > 0)
         hipLaunchKernelGGL(k_mr_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, p, q, W.st, W.lev_done,
                            W.part_v, c);
-      hipLaunchKernelGGL(k_mr_red_b, dim3(nlev), dim3(kBlock), 0, s, lo, wv.lev_begin, W.part_v, W.st, W.lev_done, c);
+      if (pc) bj_apply(W.lev_done);
+      hipLaunchKernelGGL(k_mr_red_b, rgrid, dim3(kMrRedThreads), 0, s, lo, wv.lev_begin, W.part_v, zlb, rzp, W.st,
+                         W.lev_done, c);
+      hipLaunchKernelGGL(k_mr_lev_done, dim3(nlev), dim3(kBlock), 0, s, lo, W.st, W.lev_done, c);
     }
     MSKM_HIP_TRY(hipMemcpyAsync(W.h_lev_done, W.lev_done, h->L * 4, hipMemcpyDeviceToHost, s));
     MSKM_HIP_TRY(hipStreamSynchronize(s));
@@ -503,13 +643,17 @@ mskm_status mr_solve_internal(mskm_hier* h, MrWS& W, const TV* dval, const TV* l
 }
 
 // Per-rhs, per-group relative residuals (host rel[R][ngroups]); rout nullable.
-mskm_status mr_residual(mskm_hier* h, MrWS& W, const double* a, const double* f, double* rout, std::vector<double>& rel) {
+mskm_status mr_residual(mskm_hier* h, MrWS& W, const double* a, const double* f, double* rout, std::vector<double>& rel,
+                        bool a_zero = false) {
   hipStream_t s = h->ctx->stream;
   const MrCfg c = W.c;
   const WorkTable& wt = h->wt_spmv;
-  hipLaunchKernelGGL(k_mr_residual, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->dim, h->d_lev, h->xs, h->N,
-                     h->diag.rowptr, h->diag.col, h->diag.val, h->lower.rowptr, h->lower.col, h->lower.val, a, f, rout,
-                     W.part_s, W.part_v2, c);
+  if (a_zero)
+    hipLaunchKernelGGL(k_mr_residual_zero, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, f, rout, W.part_s, W.part_v2, c);
+  else
+    hipLaunchKernelGGL(k_mr_residual, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->dim, h->d_lev, h->xs, h->N,
+                       h->diag.rowptr, h->diag.col, h->diag.val, h->lower.rowptr, h->lower.col, h->lower.val, a, f,
+                       rout, W.part_s, W.part_v2, c);
   std::vector<double> prr((size_t)wt.nblocks * c.R), pff((size_t)wt.nblocks * c.R);
   MSKM_HIP_TRY(hipMemcpyAsync(prr.data(), W.part_s, prr.size() * 8, hipMemcpyDeviceToHost, s));
   MSKM_HIP_TRY(hipMemcpyAsync(pff.data(), W.part_v2, pff.size() * 8, hipMemcpyDeviceToHost, s));
@@ -546,7 +690,10 @@ mskm_status solve_multi(mskm_hier* h, const double* f_in, int nrhs, const mskm_s
   for (double** v : {&W.fi, &W.ai}) MSKM_TRY(dalloc(v, NR));
   if (mixed) MSKM_TRY(dalloc(&W.res, NR));
   const size_t xs = mixed ? 4 : 8;
+  W.pc = o->precond == MSKM_PRECOND_BLOCK_JACOBI;
+  if (W.pc) MSKM_TRY(build_block_jacobi(h));
   for (void** v : {&W.beta, &W.t, &W.r, &W.p, &W.q}) MSKM_TRY(dalloc(reinterpret_cast<char**>(v), NR * xs));
+  if (W.pc) MSKM_TRY(dalloc(reinterpret_cast<char**>(&W.z), NR * xs));
   if (mixed) {
     MSKM_TRY(dalloc(reinterpret_cast<float**>(&W.f32), NR));
     MSKM_TRY(dalloc(reinterpret_cast<float**>(&W.a32), NR));
@@ -555,6 +702,7 @@ mskm_status solve_multi(mskm_hier* h, const double* f_in, int nrhs, const mskm_s
   MSKM_TRY(dalloc(&W.part_s, nbp));
   MSKM_TRY(dalloc(&W.part_v, nbp));
   MSKM_TRY(dalloc(&W.part_v2, nbp));
+  if (W.pc) MSKM_TRY(dalloc(&W.part_z, (size_t)std::max(h->bj.wt.nblocks, 1) * nrhs));
   MSKM_TRY(dalloc(&W.st, (size_t)h->L * nrhs));
   MSKM_TRY(dalloc(&W.lev_done, h->L));
   MSKM_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&W.h_lev_done), h->L * 4, hipHostMallocDefault));
@@ -580,7 +728,7 @@ mskm_status solve_multi(mskm_hier* h, const double* f_in, int nrhs, const mskm_s
     const int maxref = o->max_refine > 0 ? o->max_refine : 10;
     MSKM_HIP_TRY(hipMemsetAsync(W.ai, 0, NR * 8, s));
     for (;;) {
-      st = mr_residual(h, W, W.ai, W.fi, W.res, rel);
+      st = mr_residual(h, W, W.ai, W.fi, W.res, rel, refine == 0);  // alpha = 0 at the start
       if (st != MSKM_OK) break;
       const double worst = *std::max_element(rel.begin(), rel.end());
       if (worst <= o->target_rel_residual || refine >= maxref) break;

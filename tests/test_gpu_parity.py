@@ -234,12 +234,12 @@ def test_block_jacobi_needs_fewer_iterations(mod, ctx):
     assert its[mod.MSKM_PRECOND_BLOCK_JACOBI] < 0.7 * its[mod.MSKM_PRECOND_NONE], its
 
 
-def test_several_rhs_reject_preconditioner(mod, ctx):
+def test_several_rhs_reject_learned_warm_start(mod, ctx):
     h, f, blk, hd, _ = _setup(mod, ctx, "grid4")
     F = np.ascontiguousarray(np.stack([f, 2 * f], axis=1))
     A = np.zeros_like(F)
-    with pytest.raises(mod.MskmError):
-        mod.mskm_solve(ctx, hd, F, A, mod.solve_opts(precond=mod.MSKM_PRECOND_BLOCK_JACOBI), nrhs=2)
+    with pytest.raises(mod.MskmError):  # no network given either: rejected before anything runs
+        mod.mskm_solve(ctx, hd, F, A, mod.solve_opts(precond=mod.MSKM_PRECOND_LEARNED), nrhs=2)
 
 
 @pytest.mark.parametrize("name", ["grid4", "halton5", "uniform3d3"])
