@@ -62,11 +62,13 @@ def test_batch_layout_and_structure(batch):
 
 @pytest.mark.parametrize("alg", ["sequential", "monolithic"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batch_solve(batch, alg, prec):
+@pytest.mark.parametrize("pc", ["plain", "block_jacobi"])
+def test_batch_solve(batch, alg, prec, pc):
     m, ctx, hs, hd, refs = batch
     f = np.concatenate([f for _, f in hs])
     alpha = np.zeros_like(f)
-    kw = dict(algorithm=m.MSKM_ALG_SEQUENTIAL if alg == "sequential" else m.MSKM_ALG_MONOLITHIC)
+    kw = dict(algorithm=m.MSKM_ALG_SEQUENTIAL if alg == "sequential" else m.MSKM_ALG_MONOLITHIC,
+              precond=m.MSKM_PRECOND_BLOCK_JACOBI if pc == "block_jacobi" else m.MSKM_PRECOND_NONE)
     if prec == "fp64":
         kw.update(cg_rtol=1e-14)
         bar = 1e-10
