@@ -236,94 +236,307 @@ __device__ __forceinline__ void for_each_range(int dim, const DevLevel& L, const
   }
 }
 
-// One wave per row. Count pass: cnt_d[i] = |{n in level k : d2 < delta_k^2}|,
-// cnt_l[i] = sum_{j<k} |{n in level j : d2 < delta_j^2}|.
-__global__ void __launch_bounds__(kBlock) k_nbr_count(int dim, int k, const DevLevel* __restrict__ lev,
-                                                      const int32_t* __restrict__ cs_all,
-                                                      const double* __restrict__ xs, int64_t N,
-                                                      int64_t* __restrict__ cnt_d, int64_t* __restrict__ cnt_l) {
-  const int lane = threadIdx.x % kWave;
-  const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+// Neighbour search on LDS-staged cell tiles: a tile is 64 consecutive rows
+// of level k; rows in the internal (cell) order are spatial neighbours. For
+// every level j of the rows' hierarchy, from the coarsest up to k:
+//   * the union of the rows' 3^d neighbour cells in level j's grid is
+//     bounded by a box of cell rows; each box row is one contiguous range of
+//     level j's points;
+//   * when the box holds at most kTileCap points they are staged in LDS
+//     (coalesced copies) and the candidates are read from there, else from
+//     global memory (same arithmetic, same order);
+//   * a row's candidates are its own 3^d cells' points in ascending index
+//     order, so its columns come out ascending (canonical CSR).
+// COUNT (one row per lane, no writes but the two counts): cnt_d[i] = hits on
+// level k, cnt_l[i] = hits on the coarser levels. FILL (one row per wave
+// step, ballot compaction): the hits with their phi values at the row's
+// CSR positions, as contiguous runs.
+constexpr int kTileCap = 768;    // staged points per level
+constexpr int kMaxBoxRows = 64;  // cell rows of a stageable box (one lane each)
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const T u = __shfl_xor(v, o, kWave);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const T u = __shfl_xor(v, o, kWave);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(kWave)
+    k_nbr_tile_count(int k, const DevLevel* __restrict__ lev, const int32_t* __restrict__ cs_all,
+                     const double* __restrict__ xs, int64_t N, int64_t* __restrict__ cnt_d,
+                     int64_t* __restrict__ cnt_l) {
+  __shared__ double sx[kTileCap], sy[kTileCap], sz[DIM == 3 ? kTileCap : 1];
+  __shared__ int64_t box_a[kMaxBoxRows];
+  __shared__ int32_t box_o[kMaxBoxRows];
   const DevLevel Lk = lev[k];
+  const int lane = threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * kWave + lane;
+  const bool act = r < Lk.n;
+  const int64_t i = Lk.off + (act ? r : 0);
   const double* X = xs;
   const double* Y = xs + N;
   const double* Z = xs + 2 * N;
-  for (int64_t r = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; r < Lk.n; r += waves) {
-    const int64_t i = Lk.off + r;
-    const double px = X[i], py = Y[i], pz = dim == 3 ? Z[i] : 0.0;
-    int64_t lower = 0, diag = 0;
-    // this hierarchy's levels from the coarsest up to k (ascending index)
-    for (int j = Lk.first;; j = lev[j].next) {
-      const DevLevel Lj = lev[j];
-      int64_t c = 0;
-      for_each_range(dim, Lj, cs_all, px, py, pz, [&](int64_t a, int64_t b) {
-        for (int64_t t = a + lane; t - lane < b; t += kWave) {
-          bool hit = false;
-          if (t < b) hit = sqdist(dim, px, py, pz, X[t], Y[t], dim == 3 ? Z[t] : 0.0) < Lj.d2max;
-          c += __popcll(__ballot(hit));
-        }
-      });
-      if (j == k) {
-        diag = c;
-        break;
+  const double px = X[i], py = Y[i], pz = DIM == 3 ? Z[i] : 0.0;
+  int64_t nd = 0, nl = 0;
+  for (int j = Lk.first;; j = lev[j].next) {
+    const DevLevel Lj = lev[j];
+    const bool is_diag = j == k;
+    const int cx = cell_coord(px, Lj.lo[0], Lj.inv_cell, Lj.nc[0]);
+    const int cy = cell_coord(py, Lj.lo[1], Lj.inv_cell, Lj.nc[1]);
+    const int cz = DIM == 3 ? cell_coord(pz, Lj.lo[2], Lj.inv_cell, Lj.nc[2]) : 0;
+    const int x0 = max(cx - 1, 0), x1 = min(cx + 1, Lj.nc[0] - 1);
+    const int y0 = max(cy - 1, 0), y1 = min(cy + 1, Lj.nc[1] - 1);
+    const int z0 = DIM == 3 ? max(cz - 1, 0) : 0, z1 = DIM == 3 ? min(cz + 1, Lj.nc[2] - 1) : 0;
+    // the tile's box of cell rows (inactive lanes do not widen it)
+    const int BX0 = wave_min(act ? x0 : INT32_MAX), BX1 = wave_max(act ? x1 : -1);
+    const int BY0 = wave_min(act ? y0 : INT32_MAX), BY1 = wave_max(act ? y1 : -1);
+    const int BZ0 = wave_min(act ? z0 : INT32_MAX), BZ1 = wave_max(act ? z1 : -1);
+    const int ny = BY1 - BY0 + 1;
+    const int nrows = ny * (BZ1 - BZ0 + 1);
+    const int32_t* cs = cs_all + Lj.cs_off;
+    const bool boxed = nrows >= 1 && nrows <= kMaxBoxRows;
+    bool staged = false;
+    if (boxed) {
+      int64_t a = 0, len = 0;
+      if (lane < nrows) {
+        const int yy = BY0 + lane % ny, zz = BZ0 + lane / ny;
+        const int rk = (zz * Lj.nc[1] + yy) * Lj.nc[0];
+        a = cs[rk + BX0];
+        len = cs[rk + BX1 + 1] - a;
       }
-      lower += c;
+      // exclusive scan of the box rows' lengths
+      int64_t incl = len;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t u = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += u;
+      }
+      const int64_t total = __shfl(incl, kWave - 1, kWave);
+      if (lane < nrows) {
+        box_a[lane] = a;
+        box_o[lane] = (int32_t)(incl - len);
+      }
+      staged = total <= kTileCap;
+      __syncthreads();
+      if (staged) {
+        for (int q = 0; q < nrows; ++q) {
+          const int64_t qa = box_a[q];
+          const int32_t qo = box_o[q];
+          const int32_t qn = (q + 1 < nrows ? box_o[q + 1] : (int32_t)total) - qo;
+          for (int t = lane; t < qn; t += kWave) {
+            sx[qo + t] = X[qa + t];
+            sy[qo + t] = Y[qa + t];
+            if (DIM == 3) sz[qo + t] = Z[qa + t];
+          }
+        }
+      }
+      __syncthreads();
     }
-    if (lane == 0) {
-      cnt_d[i] = diag;
-      cnt_l[i] = lower;
+    if (act) {
+      int64_t hits = 0;
+      for (int zz = z0; zz <= z1; ++zz)
+        for (int yy = y0; yy <= y1; ++yy) {
+          const int rk = (zz * Lj.nc[1] + yy) * Lj.nc[0];
+          const int64_t a = cs[rk + x0], b = cs[rk + x1 + 1];
+          // LDS slot of point t: its box row starts at box_a with offset box_o
+          int64_t shift = 0;
+          if (staged) {
+            const int q = (zz - BZ0) * ny + (yy - BY0);
+            shift = (int64_t)box_o[q] - box_a[q];
+          }
+          for (int64_t t = a; t < b; ++t) {
+            double qx, qy, qz = 0.0;
+            if (staged) {
+              qx = sx[t + shift];
+              qy = sy[t + shift];
+              if (DIM == 3) qz = sz[t + shift];
+            } else {
+              qx = X[t];
+              qy = Y[t];
+              if (DIM == 3) qz = Z[t];
+            }
+            hits += sqdist(DIM, px, py, pz, qx, qy, qz) < Lj.d2max;
+          }
+        }
+      if (is_diag) nd = hits;
+      else nl += hits;
     }
+    if (boxed) __syncthreads();  // before the next level reuses the LDS
+    if (is_diag) break;
+  }
+  if (act) {
+    cnt_d[i] = nd;
+    cnt_l[i] = nl;
   }
 }
 
-// Fill pass: same traversal, each hit written at rowptr[i] + (hits so far).
-__global__ void __launch_bounds__(kBlock) k_nbr_fill(int dim, int k, const DevLevel* __restrict__ lev,
-                                                     const int32_t* __restrict__ cs_all,
-                                                     const double* __restrict__ xs, int64_t N,
-                                                     const int64_t* __restrict__ dptr, int32_t* __restrict__ dcol,
-                                                     double* __restrict__ dval, float* __restrict__ dval32,
-                                                     const int64_t* __restrict__ lptr, int32_t* __restrict__ lcol,
-                                                     double* __restrict__ lval, float* __restrict__ lval32) {
-  const int lane = threadIdx.x % kWave;
-  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-  const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+// Fill pass on the same staged tiles, four waves per tile: wave w fills rows
+// w, w + 4, ... of the tile, one row at a time; for each row the lanes test
+// 64 candidates per step and the hits are compacted with a ballot prefix
+// count, so each row's columns and values are written as contiguous,
+// coalesced runs in ascending order. The first wave computes the box.
+constexpr int kFillWaves = 4;
+
+template <int DIM>
+__global__ void __launch_bounds__(kFillWaves * kWave)
+    k_nbr_tile_fill(int k, const DevLevel* __restrict__ lev, const int32_t* __restrict__ cs_all,
+                    const double* __restrict__ xs, int64_t N, const int64_t* __restrict__ dptr,
+                    int32_t* __restrict__ dcol, double* __restrict__ dval, float* __restrict__ dval32,
+                    const int64_t* __restrict__ lptr, int32_t* __restrict__ lcol, double* __restrict__ lval,
+                    float* __restrict__ lval32) {
+  __shared__ double sx[kTileCap], sy[kTileCap], sz[DIM == 3 ? kTileCap : 1];
+  __shared__ int64_t box_a[kMaxBoxRows];
+  __shared__ int32_t box_o[kMaxBoxRows];
+  __shared__ int box[7];         // X0, X1, Y0, Y1, Z0, Z1, staged
+  __shared__ int64_t lpos_s[kWave];  // next lower-block position of each row of the tile
   const DevLevel Lk = lev[k];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t tile0 = (int64_t)blockIdx.x * kWave;
+  const int nrow_tile = (int)min<int64_t>(kWave, Lk.n - tile0);
   const double* X = xs;
   const double* Y = xs + N;
   const double* Z = xs + 2 * N;
-  for (int64_t r = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; r < Lk.n; r += waves) {
-    const int64_t i = Lk.off + r;
-    const double px = X[i], py = Y[i], pz = dim == 3 ? Z[i] : 0.0;
-    int64_t lpos = lptr[i];
-    for (int j = Lk.first;; j = lev[j].next) {
-      const DevLevel Lj = lev[j];
-      const bool is_diag = j == k;
-      int64_t pos = is_diag ? dptr[i] : lpos;
-      int32_t* col = is_diag ? dcol : lcol;
-      double* val = is_diag ? dval : lval;
-      float* val32 = is_diag ? dval32 : lval32;
-      for_each_range(dim, Lj, cs_all, px, py, pz, [&](int64_t a, int64_t b) {
-        for (int64_t t = a + lane; t - lane < b; t += kWave) {
-          bool hit = false;
-          double d2 = 0.0;
-          if (t < b) {
-            d2 = sqdist(dim, px, py, pz, X[t], Y[t], dim == 3 ? Z[t] : 0.0);
-            hit = d2 < Lj.d2max;
-          }
-          const uint64_t m = __ballot(hit);
-          if (hit) {
-            const int64_t p = pos + __popcll(m & below);
-            col[p] = (int32_t)t;
-            const double v = phi31_d2(d2, Lj.delta);
-            if (val) val[p] = v;
-            if (val32) val32[p] = (float)v;
-          }
-          pos += __popcll(m);
+  if (threadIdx.x < nrow_tile) lpos_s[threadIdx.x] = lptr[Lk.off + tile0 + threadIdx.x];
+  for (int j = Lk.first;; j = lev[j].next) {
+    const DevLevel Lj = lev[j];
+    const bool is_diag = j == k;
+    const int32_t* cs = cs_all + Lj.cs_off;
+    if (w == 0) {  // the tile's box of cell rows, and its candidate count
+      const bool act = lane < nrow_tile;
+      const int64_t i = Lk.off + tile0 + (act ? lane : 0);
+      const double px = X[i], py = Y[i], pz = DIM == 3 ? Z[i] : 0.0;
+      const int cx = cell_coord(px, Lj.lo[0], Lj.inv_cell, Lj.nc[0]);
+      const int cy = cell_coord(py, Lj.lo[1], Lj.inv_cell, Lj.nc[1]);
+      const int cz = DIM == 3 ? cell_coord(pz, Lj.lo[2], Lj.inv_cell, Lj.nc[2]) : 0;
+      const int BX0 = wave_min(act ? max(cx - 1, 0) : INT32_MAX);
+      const int BX1 = wave_max(act ? min(cx + 1, Lj.nc[0] - 1) : -1);
+      const int BY0 = wave_min(act ? max(cy - 1, 0) : INT32_MAX);
+      const int BY1 = wave_max(act ? min(cy + 1, Lj.nc[1] - 1) : -1);
+      const int BZ0 = DIM == 3 ? wave_min(act ? max(cz - 1, 0) : INT32_MAX) : 0;
+      const int BZ1 = DIM == 3 ? wave_max(act ? min(cz + 1, Lj.nc[2] - 1) : -1) : 0;
+      const int ny = BY1 - BY0 + 1;
+      const int nrows = ny * (BZ1 - BZ0 + 1);
+      int staged = 0;
+      if (nrows >= 1 && nrows <= kMaxBoxRows) {
+        int64_t a = 0, len = 0;
+        if (lane < nrows) {
+          const int yy = BY0 + lane % ny, zz = BZ0 + lane / ny;
+          const int rk = (zz * Lj.nc[1] + yy) * Lj.nc[0];
+          a = cs[rk + BX0];
+          len = cs[rk + BX1 + 1] - a;
         }
-      });
-      if (is_diag) break;
-      lpos = pos;
+        int64_t incl = len;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const int64_t u = __shfl_up(incl, o, kWave);
+          if (lane >= o) incl += u;
+        }
+        const int64_t total = __shfl(incl, kWave - 1, kWave);
+        if (lane < nrows) {
+          box_a[lane] = a;
+          box_o[lane] = (int32_t)(incl - len);
+        }
+        staged = total <= kTileCap ? (int)total + 1 : 0;  // total + 1 when staged
+      }
+      if (lane == 0) {
+        box[0] = BX0;
+        box[1] = BX1;
+        box[2] = BY0;
+        box[3] = BY1;
+        box[4] = BZ0;
+        box[5] = BZ1;
+        box[6] = staged;
+      }
     }
+    __syncthreads();
+    const int BY0 = box[2], BZ0 = box[4];
+    const int ny = box[3] - BY0 + 1;
+    const int nrows = ny * (box[5] - BZ0 + 1);
+    const bool staged = box[6] > 0;
+    if (staged) {
+      const int32_t total = box[6] - 1;
+      for (int q = 0; q < nrows; ++q) {
+        const int64_t qa = box_a[q];
+        const int32_t qo = box_o[q];
+        const int32_t qn = (q + 1 < nrows ? box_o[q + 1] : total) - qo;
+        for (int t = threadIdx.x; t < qn; t += kFillWaves * kWave) {
+          sx[qo + t] = X[qa + t];
+          sy[qo + t] = Y[qa + t];
+          if (DIM == 3) sz[qo + t] = Z[qa + t];
+        }
+      }
+    }
+    __syncthreads();
+    int32_t* col = is_diag ? dcol : lcol;
+    double* val = is_diag ? dval : lval;
+    float* val32 = is_diag ? dval32 : lval32;
+    for (int q = w; q < nrow_tile; q += kFillWaves) {
+      const int64_t i = Lk.off + tile0 + q;
+      const double qx = X[i], qy = Y[i], qz = DIM == 3 ? Z[i] : 0.0;
+      const int cx = cell_coord(qx, Lj.lo[0], Lj.inv_cell, Lj.nc[0]);
+      const int cy = cell_coord(qy, Lj.lo[1], Lj.inv_cell, Lj.nc[1]);
+      const int cz = DIM == 3 ? cell_coord(qz, Lj.lo[2], Lj.inv_cell, Lj.nc[2]) : 0;
+      const int qx0 = max(cx - 1, 0), qx1 = min(cx + 1, Lj.nc[0] - 1);
+      const int qy0 = max(cy - 1, 0), qy1 = min(cy + 1, Lj.nc[1] - 1);
+      const int qz0 = DIM == 3 ? max(cz - 1, 0) : 0, qz1 = DIM == 3 ? min(cz + 1, Lj.nc[2] - 1) : 0;
+      const int64_t pos = is_diag ? dptr[i] : lpos_s[q];
+      int64_t nh = 0;
+      for (int zz = qz0; zz <= qz1; ++zz)
+        for (int yy = qy0; yy <= qy1; ++yy) {
+          const int rk = (zz * Lj.nc[1] + yy) * Lj.nc[0];
+          const int64_t a = cs[rk + qx0], b = cs[rk + qx1 + 1];
+          int64_t shift = 0;
+          if (staged) {
+            const int bq = (zz - BZ0) * ny + (yy - BY0);
+            shift = (int64_t)box_o[bq] - box_a[bq];
+          }
+          for (int64_t t0 = a; t0 < b; t0 += kWave) {
+            const int64_t t = t0 + lane;
+            bool hit = false;
+            double d2 = 0.0;
+            if (t < b) {
+              double cxv, cyv, czv = 0.0;
+              if (staged) {
+                cxv = sx[t + shift];
+                cyv = sy[t + shift];
+                if (DIM == 3) czv = sz[t + shift];
+              } else {
+                cxv = X[t];
+                cyv = Y[t];
+                if (DIM == 3) czv = Z[t];
+              }
+              d2 = sqdist(DIM, qx, qy, qz, cxv, cyv, czv);
+              hit = d2 < Lj.d2max;
+            }
+            const uint64_t m = __ballot(hit);
+            if (hit) {
+              const int64_t pp = pos + nh + __popcll(m & below);
+              col[pp] = (int32_t)t;
+              const double v = phi31_d2(d2, Lj.delta);
+              if (val) val[pp] = v;
+              if (val32) val32[pp] = (float)v;
+            }
+            nh += __popcll(m);
+          }
+        }
+      if (!is_diag && lane == 0) lpos_s[q] = pos + nh;
+    }
+    __syncthreads();  // before the next level reuses the LDS and the box
+    if (is_diag) break;
   }
 }
 
@@ -521,12 +734,15 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   MSKM_TRY(dalloc(&cnt_l, N + 1));
   MSKM_HIP_TRY(hipMemsetAsync(cnt_d + N, 0, 8, s));
   MSKM_HIP_TRY(hipMemsetAsync(cnt_l + N, 0, 8, s));
-  const int rows_per_block = kBlock / kWave;
   for (int k = 0; k < L; ++k) {
     const int64_t n = h->h_lev[k].n;
     if (n == 0) continue;
-    hipLaunchKernelGGL(k_nbr_count, dim3(grid_for(n, rows_per_block)), dim3(kBlock), 0, s, dim, k, h->d_lev,
-                       h->cell_start, h->xs, N, cnt_d, cnt_l);
+    if (dim == 3)
+      hipLaunchKernelGGL(k_nbr_tile_count<3>, dim3(grid_for(n, kWave)), dim3(kWave), 0, s, k, h->d_lev, h->cell_start,
+                         h->xs, N, cnt_d, cnt_l);
+    else
+      hipLaunchKernelGGL(k_nbr_tile_count<2>, dim3(grid_for(n, kWave)), dim3(kWave), 0, s, k, h->d_lev, h->cell_start,
+                         h->xs, N, cnt_d, cnt_l);
   }
   MSKM_TRY(halloc(h, &h->diag.rowptr, N + 1));
   MSKM_TRY(halloc(h, &h->lower.rowptr, N + 1));
@@ -557,9 +773,14 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   for (int k = 0; k < L; ++k) {
     const int64_t n = h->h_lev[k].n;
     if (n == 0) continue;
-    hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(n, rows_per_block)), dim3(kBlock), 0, s, dim, k, h->d_lev,
-                       h->cell_start, h->xs, N, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32,
-                       h->lower.rowptr, h->lower.col, h->lower.val, h->lower.val32);
+    if (dim == 3)
+      hipLaunchKernelGGL(k_nbr_tile_fill<3>, dim3(grid_for(n, kWave)), dim3(kFillWaves * kWave), 0, s, k, h->d_lev,
+                         h->cell_start, h->xs, N, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, h->lower.rowptr,
+                         h->lower.col, h->lower.val, h->lower.val32);
+    else
+      hipLaunchKernelGGL(k_nbr_tile_fill<2>, dim3(grid_for(n, kWave)), dim3(kFillWaves * kWave), 0, s, k, h->d_lev,
+                         h->cell_start, h->xs, N, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, h->lower.rowptr,
+                         h->lower.col, h->lower.val, h->lower.val32);
   }
   MSKM_TRY(build_sell(h, want64, want32));
   MSKM_HIP_TRY(hipEventRecord(h->ctx->ev1, s));
