@@ -495,44 +495,80 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
       const int qz0 = DIM == 3 ? max(cz - 1, 0) : 0, qz1 = DIM == 3 ? min(cz + 1, Lj.nc[2] - 1) : 0;
       const int64_t pos = is_diag ? dptr[i] : lpos_s[q];
       int64_t nh = 0;
-      for (int zz = qz0; zz <= qz1; ++zz)
-        for (int yy = qy0; yy <= qy1; ++yy) {
-          const int rk = (zz * Lj.nc[1] + yy) * Lj.nc[0];
-          const int64_t a = cs[rk + qx0], b = cs[rk + qx1 + 1];
-          int64_t shift = 0;
+      // one candidate step: 64 lanes test candidates, hits compacted in order
+      auto step = [&](int64_t t, int64_t sh, bool valid) {
+        bool hit = false;
+        double d2 = 0.0;
+        if (valid) {
+          double cxv, cyv, czv = 0.0;
           if (staged) {
-            const int bq = (zz - BZ0) * ny + (yy - BY0);
-            shift = (int64_t)box_o[bq] - box_a[bq];
+            cxv = sx[t + sh];
+            cyv = sy[t + sh];
+            if (DIM == 3) czv = sz[t + sh];
+          } else {
+            cxv = X[t];
+            cyv = Y[t];
+            if (DIM == 3) czv = Z[t];
           }
-          for (int64_t t0 = a; t0 < b; t0 += kWave) {
-            const int64_t t = t0 + lane;
-            bool hit = false;
-            double d2 = 0.0;
-            if (t < b) {
-              double cxv, cyv, czv = 0.0;
-              if (staged) {
-                cxv = sx[t + shift];
-                cyv = sy[t + shift];
-                if (DIM == 3) czv = sz[t + shift];
-              } else {
-                cxv = X[t];
-                cyv = Y[t];
-                if (DIM == 3) czv = Z[t];
-              }
-              d2 = sqdist(DIM, qx, qy, qz, cxv, cyv, czv);
-              hit = d2 < Lj.d2max;
-            }
-            const uint64_t m = __ballot(hit);
-            if (hit) {
-              const int64_t pp = pos + nh + __popcll(m & below);
-              col[pp] = (int32_t)t;
-              const double v = phi31_d2(d2, Lj.delta);
-              if (val) val[pp] = v;
-              if (val32) val32[pp] = (float)v;
-            }
-            nh += __popcll(m);
+          d2 = sqdist(DIM, qx, qy, qz, cxv, cyv, czv);
+          hit = d2 < Lj.d2max;
+        }
+        const uint64_t m = __ballot(hit);
+        if (hit) {
+          const int64_t pp = pos + nh + __popcll(m & below);
+          col[pp] = (int32_t)t;
+          const double v = phi31_d2(d2, Lj.delta);
+          if (val) val[pp] = v;
+          if (val32) val32[pp] = (float)v;
+        }
+        nh += __popcll(m);
+      };
+      if constexpr (DIM == 2) {
+        // the row's 3 cell-row ranges taken as one concatenated candidate list,
+        // so that the steps of 64 lanes are full (ascending across the ranges)
+        int64_t ra[3] = {0, 0, 0}, rs[3] = {0, 0, 0}, rl[3] = {0, 0, 0};
+        int nr = 0;
+        for (int yy = qy0; yy <= qy1; ++yy, ++nr) {
+          const int rk = yy * Lj.nc[0];
+          const int64_t a = cs[rk + qx0], b = cs[rk + qx1 + 1];
+          const int64_t sh = staged ? (int64_t)box_o[yy - BY0] - box_a[yy - BY0] : 0;
+          if (nr == 0) {
+            ra[0] = a; rs[0] = sh; rl[0] = b - a;
+          } else if (nr == 1) {
+            ra[1] = a; rs[1] = sh; rl[1] = b - a;
+          } else {
+            ra[2] = a; rs[2] = sh; rl[2] = b - a;
           }
         }
+        const int64_t total = rl[0] + rl[1] + rl[2];
+        for (int64_t c0 = 0; c0 < total; c0 += kWave) {
+          const int64_t c = c0 + lane;
+          int64_t t, sh;
+          if (c < rl[0]) {
+            t = ra[0] + c;
+            sh = rs[0];
+          } else if (c < rl[0] + rl[1]) {
+            t = ra[1] + (c - rl[0]);
+            sh = rs[1];
+          } else {
+            t = ra[2] + (c - rl[0] - rl[1]);
+            sh = rs[2];
+          }
+          step(t, sh, c < total);
+        }
+      } else {
+        for (int zz = qz0; zz <= qz1; ++zz)
+          for (int yy = qy0; yy <= qy1; ++yy) {
+            const int rk = (zz * Lj.nc[1] + yy) * Lj.nc[0];
+            const int64_t a = cs[rk + qx0], b = cs[rk + qx1 + 1];
+            int64_t sh = 0;
+            if (staged) {
+              const int bq = (zz - BZ0) * ny + (yy - BY0);
+              sh = (int64_t)box_o[bq] - box_a[bq];
+            }
+            for (int64_t t0 = a; t0 < b; t0 += kWave) step(t0 + lane, sh, t0 + lane < b);
+          }
+      }
       if (!is_diag && lane == 0) lpos_s[q] = pos + nh;
     }
     __syncthreads();  // before the next level reuses the LDS and the box
