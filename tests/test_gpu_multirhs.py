@@ -93,6 +93,26 @@ def test_multi_rhs_block_jacobi(env, name, R, prec):
     assert iters[m.MSKM_PRECOND_BLOCK_JACOBI] < iters[m.MSKM_PRECOND_NONE], iters
 
 
+@pytest.mark.parametrize("R", [64, 100])
+def test_multi_rhs_mixed_wide_2d(env, R):
+    """Mixed precision, block-Jacobi preconditioned, with R >= 64 (several
+    right-hand sides per lane) on a 2-D hierarchy."""
+    m, ctx, get = env
+    h, blk, hd = get("halton5")
+    F = _targets(h, R, 3400)
+    A = np.zeros_like(F)
+    o = m.solve_opts(precision=m.MSKM_PREC_FP32, algorithm=m.MSKM_ALG_SEQUENTIAL, cg_rtol=1e-5,
+                     target_rel_residual=1e-13, max_refine=20, precond=m.MSKM_PRECOND_BLOCK_JACOBI)
+    res = m.mskm_solve(ctx, hd, F, A, o, nrhs=R)
+    assert res.status == m.MSKM_OK, res.report
+    for r in (0, 1, R // 2, R - 1):
+        ref = oracle.sequential_solve(blk, F[:, r])
+        for l in range(h.levels):
+            sl = slice(h.offsets[l], h.offsets[l + 1])
+            err = np.linalg.norm(A[sl, r] - ref[sl]) / np.linalg.norm(ref[sl])
+            assert err <= 1e-8, (r, l, err)
+
+
 def test_multi_rhs_mixed_matches_single(env):
     m, ctx, get = env
     h, blk, hd = get("halton5")
