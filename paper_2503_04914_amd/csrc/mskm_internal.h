@@ -86,6 +86,7 @@ struct Sell {
 // more than kBjMax rows are cut into near-equal chunks), inverted densely.
 constexpr int kBjMax = 32;         // largest block
 constexpr int kBjGroupRows = 1024; // rows of one workgroup of whole blocks
+constexpr int kBjGroupStep = kBjGroupRows - kBjMax + 1;  // window of block starts of one workgroup
 struct BlockJacobi {
   bool built = false;
   int64_t nblocks = 0, nvals = 0;

@@ -4,7 +4,6 @@
 // interact strongly (the cell side is about delta), so the dense inverses of
 // these small diagonal blocks remove much of the local ill-conditioning of
 // A_l at the cost of about m reads per row (m = rows of the row's block).
-#include <algorithm>
 #include <vector>
 
 #include "device_common.h"
@@ -12,28 +11,39 @@
 namespace mskm {
 
 // One 64-thread workgroup per block: the dense m x m principal submatrix of
-// the block's rows from the diagonal CSR rows, inverted in place by
-// Gauss-Jordan elimination without pivoting (the block is SPD), in FP64,
-// then symmetrized and stored. A non-positive or non-finite pivot (a block
-// too ill-conditioned for this) stores the identity: that block is then left
-// unpreconditioned.
+// the block's rows, gathered from the diagonal CSR rows (the block's rows are
+// consecutive, so their entries form one contiguous run that the wave reads
+// coalesced; each entry finds its row among the block's m + 1 row pointers),
+// inverted in place by Gauss-Jordan elimination without pivoting (the block
+// is SPD), in FP64, then symmetrized and stored. A non-positive or
+// non-finite pivot (a block too ill-conditioned for this) stores the
+// identity: that block is then left unpreconditioned.
 __global__ void __launch_bounds__(kWave)
     k_bj_invert(const int64_t* __restrict__ start, const int64_t* __restrict__ off, const int64_t* __restrict__ rp,
                 const int32_t* __restrict__ col, const double* __restrict__ val, const float* __restrict__ val32,
                 double* __restrict__ inv, float* __restrict__ inv32) {
   __shared__ double M[kBjMax][kBjMax + 1];
   __shared__ double F[kBjMax];
+  __shared__ int64_t rps[kBjMax + 1];
   const int64_t b = blockIdx.x;
   const int64_t a = start[b];
   const int m = (int)(start[b + 1] - a);
   const int t = threadIdx.x;
-  if (t < m)
-    for (int i = 0; i < m; ++i) M[i][t] = 0.0;
+  for (int k = t; k < kBjMax * (kBjMax + 1); k += kWave) (&M[0][0])[k] = 0.0;
+  if (t <= m) rps[t] = rp[a + t];
   __syncthreads();
-  if (t < m) {
-    for (int64_t k = rp[a + t]; k < rp[a + t + 1]; ++k) {
-      const int64_t c = col[k];
-      if (c >= a && c < a + m) M[t][c - a] = val ? val[k] : (double)val32[k];
+  for (int64_t k = rps[0] + t; k < rps[m]; k += kWave) {
+    const int64_t c = col[k];
+    if (c >= a && c < a + m) {
+      int lo = 0, hi = m - 1;  // the row of entry k: the last i with rps[i] <= k
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rps[mid] <= k)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      M[lo][c - a] = val ? val[k] : (double)val32[k];
     }
   }
   __syncthreads();
@@ -53,22 +63,83 @@ __global__ void __launch_bounds__(kWave)
     __syncthreads();
   }
   const int64_t o = off[b];
-  if (t < m) {
-    for (int j = 0; j < m; ++j) {
-      double v = 0.5 * (M[t][j] + M[j][t]);
-      if (bad || !isfinite(v)) v = t == j ? 1.0 : 0.0;
-      if (inv) inv[o + (int64_t)t * m + j] = v;
-      if (inv32) inv32[o + (int64_t)t * m + j] = (float)v;
-    }
+  for (int q = t; q < m * m; q += kWave) {
+    const int i = q / m, j = q - i * m;
+    double v = 0.5 * (M[i][j] + M[j][i]);
+    if (bad || !isfinite(v)) v = i == j ? 1.0 : 0.0;
+    if (inv) inv[o + q] = v;
+    if (inv32) inv32[o + q] = (float)v;
   }
 }
 
-// of_row[r] = b for the rows of block b.
-__global__ void __launch_bounds__(kBlock) k_bj_rows(int64_t nb, const int64_t* __restrict__ start,
-                                                    int32_t* __restrict__ of_row) {
+// Blocks of cell-table slot k: the cell's rows cut into ceil(count / kBjMax)
+// near-equal chunks. cell_start is one array over all levels; each level's
+// table ends in the level's end row, which is also the next level's first
+// row, so those closing slots count zero rows. nch[nslots] = 0 closes the
+// scan.
+__global__ void __launch_bounds__(kBlock)
+    k_bj_cell_chunks(const int32_t* __restrict__ cs, int64_t nslots, int64_t* __restrict__ nch) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k > nslots) return;
+  nch[k] = k < nslots ? (cs[k + 1] - cs[k] + kBjMax - 1) / kBjMax : 0;
+}
+
+// Block tables from the exclusive scan bbase of the chunk counts: the first
+// row of each block, its m^2 (scanned next into the inverse offsets) and the
+// block of every row; the closing entries start[nb] = N and msq[nb] = 0.
+__global__ void __launch_bounds__(kBlock)
+    k_bj_blocks(const int32_t* __restrict__ cs, int64_t nslots, const int64_t* __restrict__ bbase,
+                int64_t* __restrict__ start, int64_t* __restrict__ msq, int32_t* __restrict__ of_row) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k > nslots) return;
+  if (k == nslots) {
+    start[bbase[k]] = cs[k];
+    msq[bbase[k]] = 0;
+    return;
+  }
+  const int64_t a = cs[k], e = cs[k + 1], nc = bbase[k + 1] - bbase[k];
+  for (int64_t q = 0; q < nc; ++q) {
+    const int64_t ca = a + (e - a) * q / nc, ce = a + (e - a) * (q + 1) / nc;
+    const int64_t b = bbase[k] + q;
+    start[b] = ca;
+    msq[b] = (ce - ca) * (ce - ca);
+    for (int64_t r = ca; r < ce; ++r) of_row[r] = (int32_t)b;
+  }
+}
+
+// Workgroups of whole blocks: within a level, the blocks whose first row
+// falls in one window of kBjGroupStep rows (windows counted from the level's
+// first row) form one group, so a group spans at most kBjGroupStep - 1 +
+// kBjMax = kBjGroupRows rows. Any window of at least kBjMax rows holds a
+// block start (blocks have at most kBjMax rows); a shorter last window is
+// merged into the one before it (at most kBjGroupStep + kBjMax - 1 rows).
+// gbase = first group of each level, its window count gbase[l+1] - gbase[l].
+__global__ void __launch_bounds__(kBlock)
+    k_bj_groups(int64_t nb, const int64_t* __restrict__ start, const DevLevel* __restrict__ lev, int L,
+                const int32_t* __restrict__ gbase, int32_t* __restrict__ glev, int64_t* __restrict__ row0,
+                int64_t* __restrict__ row1) {
   const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (b >= nb) return;
-  for (int64_t r = start[b]; r < start[b + 1]; ++r) of_row[r] = (int32_t)b;
+  const int64_t s = start[b], e = start[b + 1];
+  int lo = 0, hi = L - 1;  // the level holding row s: the last with off <= s (an empty level shares its
+                          // offset with the next level, so the last such level is never empty)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (lev[mid].off <= s)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int64_t l0 = lev[lo].off, l1 = l0 + lev[lo].n;
+  const int64_t nw = gbase[lo + 1] - gbase[lo];
+  const int64_t w = min((s - l0) / kBjGroupStep, nw - 1);
+  const int64_t w0 = l0 + w * kBjGroupStep, w1 = w == nw - 1 ? l1 : w0 + kBjGroupStep;
+  const int g = gbase[lo] + (int)w;
+  if (b == 0 || start[b - 1] < w0) {
+    row0[g] = s;
+    glev[g] = lo;
+  }
+  if (e >= w1 || e == l1) row1[g] = e;
 }
 
 // u = M^-1 r over workgroups of whole blocks (r staged in LDS).
@@ -107,82 +178,71 @@ mskm_status build_block_jacobi(mskm_hier* h) {
   hipStream_t s = h->ctx->stream;
   const int L = h->L;
   const DevLevel& last = h->h_lev[L - 1];
-  const int64_t cs_total = (int64_t)last.cs_off + last.ncell_tot + 1;
-  std::vector<int32_t> cs((size_t)cs_total);
-  MSKM_HIP_TRY(hipMemcpyAsync(cs.data(), h->cell_start, cs.size() * 4, hipMemcpyDeviceToHost, s));
-  MSKM_HIP_TRY(hipStreamSynchronize(s));
-  // blocks = cells (cut into near-equal chunks of <= kBjMax rows); groups =
-  // runs of whole blocks of one level with <= kBjGroupRows rows
-  std::vector<int64_t> start, off;
-  std::vector<int32_t> glev;
-  std::vector<int64_t> g0, g1;
-  B.wt.h_lev_begin.assign(L + 1, 0);
-  int64_t nv = 0;
-  for (int l = 0; l < L; ++l) {
-    B.wt.h_lev_begin[l] = (int32_t)glev.size();
-    const DevLevel& D = h->h_lev[l];
-    int64_t ga = -1, ge = -1;
-    for (int c = 0; c < D.ncell_tot; ++c) {
-      const int64_t a = cs[(size_t)D.cs_off + c], e = cs[(size_t)D.cs_off + c + 1];
-      if (e <= a) continue;
-      const int64_t nch = (e - a + kBjMax - 1) / kBjMax;
-      for (int64_t q = 0; q < nch; ++q) {
-        const int64_t ca = a + (e - a) * q / nch, ce = a + (e - a) * (q + 1) / nch;
-        start.push_back(ca);
-        off.push_back(nv);
-        nv += (ce - ca) * (ce - ca);
-        if (ga >= 0 && ce - ga > kBjGroupRows) {
-          glev.push_back(l);
-          g0.push_back(ga);
-          g1.push_back(ge);
-          ga = -1;
-        }
-        if (ga < 0) ga = ca;
-        ge = ce;
-      }
+  // blocks = cells cut into near-equal chunks of <= kBjMax rows, built on the
+  // device from the cell tables; sized first by an upper bound (one block per
+  // cell slot plus one per kBjMax rows), the exact counts read back once
+  const int64_t nslots = (int64_t)last.cs_off + last.ncell_tot;
+  const int64_t nb_max = nslots + h->N / kBjMax + 1;
+  int64_t *nch = nullptr, *bbase = nullptr, *msq = nullptr;
+  mskm_status st = dalloc(&nch, (size_t)nslots + 1);
+  if (st == MSKM_OK) st = dalloc(&bbase, (size_t)nslots + 1);
+  if (st == MSKM_OK) st = dalloc(&msq, (size_t)nb_max + 1);
+  if (st == MSKM_OK) st = halloc(h, &B.start, (size_t)nb_max + 1);
+  if (st == MSKM_OK) st = halloc(h, &B.off, (size_t)nb_max + 1);
+  if (st == MSKM_OK) st = halloc(h, &B.of_row, (size_t)h->N);
+  int64_t counts[2] = {0, 0};
+  if (st == MSKM_OK) {
+    const unsigned gs = (unsigned)((nslots + kBlock) / kBlock);
+    hipLaunchKernelGGL(k_bj_cell_chunks, dim3(gs), dim3(kBlock), 0, s, h->cell_start, nslots, nch);
+    st = exclusive_scan_i64(s, nch, bbase, nslots + 1);
+    if (st == MSKM_OK) {
+      if (hipMemsetAsync(msq, 0, ((size_t)nb_max + 1) * 8, s) != hipSuccess) st = fail(MSKM_EDEVICE, "memset");
+      hipLaunchKernelGGL(k_bj_blocks, dim3(gs), dim3(kBlock), 0, s, h->cell_start, nslots, bbase, B.start, msq,
+                         B.of_row);
     }
-    if (ga >= 0) {
-      glev.push_back(l);
-      g0.push_back(ga);
-      g1.push_back(ge);
-    }
-    if (ge >= 0 && ge != h->h_off[l + 1]) return fail(MSKM_EDEVICE, "block-Jacobi blocks do not tile a level");
+    if (st == MSKM_OK) st = exclusive_scan_i64(s, msq, B.off, nb_max + 1);
+    if (st == MSKM_OK && (hipMemcpyAsync(&counts[0], bbase + nslots, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                          hipMemcpyAsync(&counts[1], B.off + nb_max, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                          hipStreamSynchronize(s) != hipSuccess))
+      st = fail(MSKM_EDEVICE, "block-Jacobi counts");
   }
-  B.wt.h_lev_begin[L] = (int32_t)glev.size();
-  start.push_back(h->N);
-  off.push_back(nv);
-  B.nblocks = (int64_t)start.size() - 1;
-  B.nvals = nv;
-  if (glev.size() > (size_t)INT32_MAX || B.nblocks > (int64_t)INT32_MAX)
-    return fail(MSKM_ELIMIT, "block-Jacobi tables too large");
-  MSKM_TRY(halloc(h, &B.start, start.size()));
-  MSKM_TRY(halloc(h, &B.off, off.size()));
-  MSKM_TRY(halloc(h, &B.of_row, (size_t)h->N));
-  MSKM_HIP_TRY(hipMemcpyAsync(B.start, start.data(), start.size() * 8, hipMemcpyHostToDevice, s));
-  MSKM_HIP_TRY(hipMemcpyAsync(B.off, off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
-  if (h->diag.val) MSKM_TRY(halloc(h, &B.inv, (size_t)nv));
-  if (h->diag.val32) MSKM_TRY(halloc(h, &B.inv32, (size_t)nv));
-  if (B.nblocks > 0) {
-    hipLaunchKernelGGL(k_bj_rows, dim3((unsigned)((B.nblocks + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, B.nblocks,
-                       B.start, B.of_row);
+  (void)hipFree(nch);
+  (void)hipFree(bbase);
+  (void)hipFree(msq);
+  MSKM_TRY(st);
+  B.nblocks = counts[0];
+  B.nvals = counts[1];
+  if (B.nblocks > (int64_t)INT32_MAX) return fail(MSKM_ELIMIT, "block-Jacobi tables too large");
+  if (h->diag.val) MSKM_TRY(halloc(h, &B.inv, (size_t)B.nvals));
+  if (h->diag.val32) MSKM_TRY(halloc(h, &B.inv32, (size_t)B.nvals));
+  if (B.nblocks > 0)
     hipLaunchKernelGGL(k_bj_invert, dim3((unsigned)B.nblocks), dim3(kWave), 0, s, B.start, B.off, h->diag.rowptr,
                        h->diag.col, h->diag.val, h->diag.val32, B.inv, B.inv32);
-  }
+  // workgroups of whole blocks: one per window of kBjGroupStep rows, a last
+  // window shorter than kBjMax merged into the one before
   WorkTable& wt = B.wt;
-  wt.nblocks = (int32_t)glev.size();
-  wt.rows_per_block = kBjGroupRows;
-  MSKM_TRY(halloc(h, &wt.lev, glev.size()));
-  MSKM_TRY(halloc(h, &wt.row0, g0.size()));
-  MSKM_TRY(halloc(h, &wt.row1, g1.size()));
-  MSKM_TRY(halloc(h, &wt.lev_begin, wt.h_lev_begin.size()));
-  if (!glev.empty()) {
-    MSKM_HIP_TRY(hipMemcpyAsync(wt.lev, glev.data(), glev.size() * 4, hipMemcpyHostToDevice, s));
-    MSKM_HIP_TRY(hipMemcpyAsync(wt.row0, g0.data(), g0.size() * 8, hipMemcpyHostToDevice, s));
-    MSKM_HIP_TRY(hipMemcpyAsync(wt.row1, g1.data(), g1.size() * 8, hipMemcpyHostToDevice, s));
+  wt.h_lev_begin.assign(L + 1, 0);
+  int64_t ng = 0;
+  for (int l = 0; l < L; ++l) {
+    wt.h_lev_begin[l] = (int32_t)ng;
+    const int64_t n = h->h_lev[l].n;
+    int64_t nw = (n + kBjGroupStep - 1) / kBjGroupStep;
+    if (nw > 1 && n - (nw - 1) * kBjGroupStep < kBjMax) --nw;
+    ng += nw;
+    if (ng > (int64_t)INT32_MAX) return fail(MSKM_ELIMIT, "block-Jacobi tables too large");
   }
+  wt.h_lev_begin[L] = (int32_t)ng;
+  wt.nblocks = (int32_t)ng;
+  wt.rows_per_block = kBjGroupRows;
+  MSKM_TRY(halloc(h, &wt.lev, (size_t)ng));
+  MSKM_TRY(halloc(h, &wt.row0, (size_t)ng));
+  MSKM_TRY(halloc(h, &wt.row1, (size_t)ng));
+  MSKM_TRY(halloc(h, &wt.lev_begin, wt.h_lev_begin.size()));
   MSKM_HIP_TRY(hipMemcpyAsync(wt.lev_begin, wt.h_lev_begin.data(), wt.h_lev_begin.size() * 4, hipMemcpyHostToDevice,
                               s));
-  MSKM_HIP_TRY(hipStreamSynchronize(s));
+  if (B.nblocks > 0)
+    hipLaunchKernelGGL(k_bj_groups, dim3((unsigned)((B.nblocks + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       B.nblocks, B.start, h->d_lev, L, wt.lev_begin, wt.lev, wt.row0, wt.row1);
   MSKM_HIP_TRY(hipGetLastError());
   B.built = true;
   return MSKM_OK;

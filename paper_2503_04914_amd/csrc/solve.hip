@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -649,6 +650,181 @@ __global__ void __launch_bounds__(kBlock)
   cg1_rows<TX, PC>(wt.row0[blk], wt.row1[blk], coef[0], (TX)coef[1], x, r, p, sv, q, pc, rs);
 }
 
+// Small levels: the whole CG solve of a level in one workgroup (one
+// workgroup per level, levels lev0 + blockIdx.x), in the single-reduction
+// form and with the decision rule of the kernels above (cg1_decide), so a
+// level stops after the same test. The phases are separated by workgroup
+// barriers instead of launches, so no launch and no host check sits between
+// iterations. The level's vectors live in LDS (its diagonal block couples
+// only rows of the level); thread t owns row t (n <= kWgThreads) in the
+// vector phases, the product spreads each row over a group of lanes, and the
+// row bounds and preconditioner block of each row are read once, so an
+// iteration reads from memory only the matrix entries and the inverse rows.
+// x0 = 0; the final state goes to st[l], the solution to x.
+constexpr int kWgSolveRows = 1024;  // largest level solved by one workgroup
+constexpr int kWgThreads = 1024;
+
+// G lanes per row in the product, R rows per group of G lanes (R kWgThreads / G >= n).
+template <typename TV, typename TX, bool PC, int G, int R>
+__global__ void __launch_bounds__(kWgThreads)
+    k_cg_level_wg(int lev0, const DevLevel* __restrict__ lev, const int64_t* __restrict__ rp,
+                  const int32_t* __restrict__ col, const TV* __restrict__ val, const TX* __restrict__ b,
+                  TX* __restrict__ x, CgLevel* __restrict__ st, double rtol2, int maxit, const PcArgs<TX> pc) {
+  constexpr int kW = kWgThreads / kWave;
+  __shared__ double sm[3 * kW];
+  __shared__ double coef[2];
+  __shared__ int go;
+  __shared__ TX xs[kWgSolveRows], rs[kWgSolveRows], ps[kWgSolveRows], ss[kWgSolveRows], qs[kWgSolveRows];
+  __shared__ TX zs[PC ? kWgSolveRows : 1];
+  const int l = lev0 + blockIdx.x;
+  const int64_t r0 = lev[l].off;
+  const int n = lev[l].n;
+  const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
+  const bool mine = t < n;
+  // sum of three per-thread values over the workgroup, fixed order, in thread 0
+  auto sum3 = [&](double& a, double& c, double& d) {
+    a = wave_sum(a);
+    c = wave_sum(c);
+    d = wave_sum(d);
+    if (lane == 0) {
+      sm[w] = a;
+      sm[kW + w] = c;
+      sm[2 * kW + w] = d;
+    }
+    __syncthreads();
+    if (t == 0) {
+      a = c = d = 0.0;
+      for (int k = 0; k < kW; ++k) {
+        a += sm[k];
+        c += sm[kW + k];
+        d += sm[2 * kW + k];
+      }
+    }
+  };
+  // product layout: group gi of G lanes takes rows gi, gi + ng, ... (at
+  // most R); step j of a row is its entry gl + j G, and one step of all the
+  // group's rows is issued together
+  constexpr int ng = kWgThreads / G;
+  const int gi = t / G, gl = t % G;
+  const int64_t e0 = rp[r0];  // entries of the level's rows relative to its first (fewer than 2^31)
+  const int32_t* cl = col + e0;
+  const TV* vl = val + e0;
+  int kb[R], len[R];
+  int steps = 0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int i = gi + u * ng;
+    kb[u] = 0;
+    len[u] = 0;
+    if (i < n) {
+      kb[u] = (int)(rp[r0 + i] - e0) + gl;
+      const int e = (int)(rp[r0 + i + 1] - e0);
+      len[u] = e > kb[u] ? (e - kb[u] + G - 1) / G : 0;
+    }
+    steps = max(steps, len[u]);
+  }
+  // preconditioner row of row t: its block's first row (level-relative), size and inverse row
+  int ba = 0, bm = 0;
+  const TX* Mi = nullptr;
+  if (PC && mine) {
+    const int32_t bk = pc.of_row[r0 + t];
+    const int64_t a = pc.start[bk];
+    bm = (int)(pc.start[bk + 1] - a);
+    ba = (int)(a - r0);
+    Mi = pc.inv + pc.off[bk] + (r0 + t - a) * bm;
+  }
+  auto bj = [&]() {
+    TX acc = 0;
+    for (int j = 0; j < bm; ++j) acc += Mi[j] * rs[ba + j];
+    return acc;
+  };
+  // r = b, x = p = s = 0; b.b (= r.r)
+  double sb = 0.0, u1 = 0.0, u2 = 0.0;
+  if (mine) {
+    const TX bi = b[r0 + t];
+    xs[t] = (TX)0;
+    rs[t] = bi;
+    ps[t] = (TX)0;
+    ss[t] = (TX)0;
+    sb = (double)bi * (double)bi;
+  }
+  sum3(sb, u1, u2);
+  CgLevel S{};
+  if (t == 0) {
+    S.rtol2 = rtol2;
+    S.maxit = maxit;
+    S.on = 1;
+    S.bb = sb;
+    S.rr = sb;
+    const bool finite = isfinite(sb);
+    const bool conv = finite && !(sb > rtol2 * sb);
+    S.capped = !conv && (!finite || maxit <= 0);
+    S.done = conv || S.capped;
+    go = S.done ? 0 : 1;
+  }
+  __syncthreads();
+  if constexpr (PC) {
+    if (mine) zs[t] = bj();
+    __syncthreads();
+  }
+  const TX* zv = PC ? zs : rs;
+  while (go) {
+    // q = A z with z.q, r.z and r.r
+    TX acc[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) acc[u] = 0;
+    for (int j = 0; j < steps; ++j) {
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+        if (j < len[u]) {
+          const int k = kb[u] + j * G;
+          acc[u] += (TX)vl[k] * zv[cl[k] - r0];
+        }
+    }
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      TX a = acc[u];
+#pragma unroll
+      for (int o = G >> 1; o > 0; o >>= 1) a += __shfl_xor(a, o, G);
+      const int i = gi + u * ng;
+      if (gl == 0 && i < n) {
+        qs[i] = a;
+        const double vi = (double)zv[i], wi = (double)rs[i];
+        s1 += vi * (double)a;
+        s2 += vi * wi;
+        s3 += wi * wi;
+      }
+    }
+    sum3(s1, s2, s3);
+    if (t == 0) {
+      go = cg1_decide(S, s2, s1, PC ? s3 : s2) ? 1 : 0;
+      coef[0] = S.alpha;
+      coef[1] = S.beta;
+    }
+    __syncthreads();
+    if (!go) break;
+    const double alpha = coef[0];
+    const TX beta = (TX)coef[1];
+    if (mine) {
+      const TX zi = zv[t];
+      const TX pi = zi + beta * ps[t];
+      const TX si = qs[t] + beta * ss[t];
+      ps[t] = pi;
+      ss[t] = si;
+      xs[t] = (TX)((double)xs[t] + alpha * (double)pi);
+      rs[t] = (TX)((double)rs[t] - alpha * (double)si);
+    }
+    __syncthreads();
+    if constexpr (PC) {
+      if (mine) zs[t] = bj();
+      __syncthreads();
+    }
+  }
+  if (mine) x[r0 + t] = xs[t];
+  if (t == 0) st[l] = S;
+}
+
 // ---------------------------------------------------------- solver driver
 
 constexpr int kGDiag = 8;  // lanes per row of the CG init kernel (diagonal rows hold 40-60 entries)
@@ -713,6 +889,9 @@ struct SolveWS {
   CgLevel* st = nullptr;
   CgLevel* h_st = nullptr;  // pinned
   CgLevel* h_chk[2] = {nullptr, nullptr};  // pinned state copies of the two chunks in flight
+  CgLevel* h_defer = nullptr;  // pinned final states of levels solved by one workgroup, read at the next flush
+  std::vector<char> deferred;  // levels whose final state waits in h_defer
+  hipEvent_t ev_defer = nullptr;  // after the last copy into h_defer
   hipEvent_t ev_chk[2] = {nullptr, nullptr};
   hipEvent_t pending = nullptr;  // copy of a speculative chunk still in flight (null: none)
   struct Graph {
@@ -724,18 +903,16 @@ struct SolveWS {
     hipGraphExec_t exec;
   };
   std::vector<Graph> graphs;
+  void* arena = nullptr;     // every device buffer above, carved from one allocation
+  CgLevel* pinned = nullptr; // h_st, the two h_chk copies and h_defer, one pinned allocation
   ~SolveWS() {
-    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
-    for (void* p : {(void*)beta, (void*)t, (void*)r, (void*)p0, (void*)p1, (void*)q, (void*)fi, (void*)ai,
-                    (void*)res, (void*)f32, (void*)a32, (void*)part_s, (void*)part_s2, (void*)part_s3, (void*)part_v,
-                    (void*)st, (void*)z})
-      (void)hipFree(p);
     if (pending) (void)hipEventSynchronize(pending);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    (void)hipFree(arena);
     for (hipEvent_t e : ev_chk)
       if (e) (void)hipEventDestroy(e);
-    if (h_st) (void)hipHostFree(h_st);
-    for (CgLevel* c : h_chk)
-      if (c) (void)hipHostFree(c);
+    if (ev_defer) (void)hipEventDestroy(ev_defer);
+    if (pinned) (void)hipHostFree(pinned);
   }
 };
 
@@ -749,26 +926,46 @@ static mskm_status get_ws(mskm_hier* h, SolveWS** out) {
   auto* w = new (std::nothrow) SolveWS();
   if (!w) return fail(MSKM_ENOMEM, "workspace allocation");
   const size_t N = (size_t)h->N;
+  const size_t np = (size_t)std::max(std::max(h->wt_spmv.nblocks, h->wt_sell.nblocks), 1);
+  // one device allocation for all vectors (each 256-byte aligned), one
+  // pinned allocation for the host copies of the level states
+  size_t bytes = 0;
+  auto carve = [&](auto** p, size_t count, char* base) {
+    const size_t sz = (std::max(count, (size_t)1) * sizeof(**p) + 255) & ~(size_t)255;
+    if (base) *p = reinterpret_cast<std::remove_reference_t<decltype(*p)>>(base + bytes);
+    bytes += sz;
+  };
+  auto layout = [&](char* base) {
+    bytes = 0;
+    for (double** v : {&w->beta, &w->t, &w->r, &w->p0, &w->p1, &w->q, &w->fi, &w->ai, &w->res, &w->z})
+      carve(v, N, base);
+    carve(&w->f32, N, base);
+    carve(&w->a32, N, base);
+    for (double** v : {&w->part_s, &w->part_s2, &w->part_s3}) carve(v, np, base);
+    carve(&w->part_v, (size_t)h->wt_vec.nblocks, base);
+    carve(&w->st, 2 * (size_t)h->L, base);  // two parities (fused single-reduction form)
+  };
+  layout(nullptr);
   mskm_status st = MSKM_OK;
-  for (double** v : {&w->beta, &w->t, &w->r, &w->p0, &w->p1, &w->q, &w->fi, &w->ai, &w->res, &w->z})
-    if (st == MSKM_OK) st = dalloc(v, N);
-  if (st == MSKM_OK) st = dalloc(&w->f32, N);
-  if (st == MSKM_OK) st = dalloc(&w->a32, N);
-  if (st == MSKM_OK) st = dalloc(&w->part_s, (size_t)std::max(h->wt_spmv.nblocks, h->wt_sell.nblocks));
-  if (st == MSKM_OK) st = dalloc(&w->part_s2, (size_t)std::max(h->wt_spmv.nblocks, h->wt_sell.nblocks));
-  if (st == MSKM_OK) st = dalloc(&w->part_s3, (size_t)std::max(h->wt_spmv.nblocks, h->wt_sell.nblocks));
-  if (st == MSKM_OK) st = dalloc(&w->part_v, h->wt_vec.nblocks);
-  if (st == MSKM_OK) st = dalloc(&w->st, 2 * (size_t)h->L);  // two parities (fused single-reduction form)
-  if (st == MSKM_OK &&
-      hipHostMalloc(reinterpret_cast<void**>(&w->h_st), h->L * sizeof(CgLevel), hipHostMallocDefault) != hipSuccess)
-    st = fail(MSKM_ENOMEM, "pinned state allocation");
-  for (int k = 0; k < 2 && st == MSKM_OK; ++k) {
-    if (hipHostMalloc(reinterpret_cast<void**>(&w->h_chk[k]), h->L * sizeof(CgLevel), hipHostMallocDefault) !=
-        hipSuccess)
-      st = fail(MSKM_ENOMEM, "pinned state allocation");
-    else if (hipEventCreateWithFlags(&w->ev_chk[k], hipEventDisableTiming) != hipSuccess)
-      st = fail(MSKM_EDEVICE, "event creation");
+  char* base = nullptr;
+  st = dalloc(&base, bytes);
+  if (st == MSKM_OK) {
+    w->arena = base;
+    layout(base);
   }
+  if (st == MSKM_OK && hipHostMalloc(reinterpret_cast<void**>(&w->pinned), 4 * h->L * sizeof(CgLevel),
+                                     hipHostMallocDefault) != hipSuccess)
+    st = fail(MSKM_ENOMEM, "pinned state allocation");
+  if (st == MSKM_OK) {
+    w->h_st = w->pinned;
+    w->h_chk[0] = w->pinned + h->L;
+    w->h_chk[1] = w->pinned + 2 * h->L;
+    w->h_defer = w->pinned + 3 * h->L;
+    w->deferred.assign(h->L, 0);
+  }
+  for (hipEvent_t* e : {&w->ev_chk[0], &w->ev_chk[1], &w->ev_defer})
+    if (st == MSKM_OK && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
+      st = fail(MSKM_EDEVICE, "event creation");
   if (st != MSKM_OK) {
     delete w;
     return st;
@@ -907,19 +1104,82 @@ static mskm_status chunk_graph(mskm_hier* h, SolveWS& W, const TV* dval, int lo,
   return MSKM_OK;
 }
 
+// Adds the final states of the levels solved by one workgroup (copied into
+// h_defer behind their launch) to the statistics; waits for that copy.
+static mskm_status flush_deferred(mskm_hier* h, SolveWS& W, CgStats* cs) {
+  bool any = false;
+  for (char d : W.deferred) any = any || d != 0;
+  if (!any) return MSKM_OK;
+  MSKM_HIP_TRY(hipEventSynchronize(W.ev_defer));
+  for (int l = 0; l < h->L; ++l) {
+    if (!W.deferred[l]) continue;
+    W.deferred[l] = 0;
+    const CgLevel& o = W.h_defer[l];
+    cs->iters_total += o.iters;
+    if (l < kMaxLevels) cs->last_iters[l] = o.iters;
+    if (o.capped || !o.done) cs->capped = true;
+  }
+  return MSKM_OK;
+}
+
 // Per-level CG on A_l x_l = b_l for the levels in `mask` (contiguous bits).
 // x holds x0 if warm, else it is overwritten. Iterations run as replays of a
 // captured chunk of K iterations; the host reads the per-level state after
 // each chunk and stops when every level has stopped.
 template <typename TV, typename TX>
 static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::vector<char>& on, const TX* b, TX* x,
-                          double rtol, int maxit, bool warm, int K, CgStats* cs, const mskm_mlp* mlp, bool bj) {
+                          double rtol, int maxit, bool warm, int K, CgStats* cs, const mskm_mlp* mlp, bool bj,
+                          const std::vector<char>* next_on = nullptr) {
   hipStream_t s = h->ctx->stream;
   const WorkTable& ws = h->wt_spmv;
   int lo = 0, hi = h->L - 1;
   while (lo < h->L && !on[lo]) ++lo;
   while (hi >= 0 && !on[hi]) --hi;
   if (lo > hi) return MSKM_OK;
+  // form: preconditioned single-reduction when asked; the single-reduction
+  // form for the FP32 inner solves; the textbook form otherwise
+  const int form = bj ? kCgOneRedBj : sizeof(TX) == 4 ? kCgOneRed : kCgTextbook;
+  // levels lo..hi all small enough for one workgroup each (and all on)
+  auto all_small = [&](const std::vector<char>& m, int a, int e) {
+    bool ok = form != kCgTextbook && !mlp && !warm;
+    for (int l = a; l <= e && ok; ++l) ok = m[l] && h->h_lev[l].n <= kWgSolveRows;
+    return ok;
+  };
+  if (all_small(on, lo, hi)) {  // one workgroup per level, all iterations in one launch, no host check
+    for (int l = lo; l <= hi; ++l)
+      if (W.deferred[l]) {  // a state of this level still waits in h_defer
+        MSKM_TRY(flush_deferred(h, W, cs));
+        break;
+      }
+    const PcArgs<TX> pc = pc_args<TX>(h, W);
+    int nmax = 0;
+    for (int l = lo; l <= hi; ++l) nmax = std::max(nmax, (int)h->h_lev[l].n);
+    // lanes and rows per product group by level size (measured on 64-, 256- and 1024-row levels)
+    const int shape = nmax <= 64 ? 0 : nmax <= 256 ? 1 : 2;
+#define MSKM_WG_LAUNCH(PCF, GG, RR)                                                                              \
+  hipLaunchKernelGGL((k_cg_level_wg<TV, TX, PCF, GG, RR>), dim3(hi - lo + 1), dim3(kWgThreads), 0, s, lo, h->d_lev, \
+                     h->diag.rowptr, h->diag.col, dval, b, x, W.st, rtol * rtol, maxit, pc)
+    if (bj) {
+      if (shape == 0)
+        MSKM_WG_LAUNCH(true, 16, 1);
+      else if (shape == 1)
+        MSKM_WG_LAUNCH(true, 4, 1);
+      else
+        MSKM_WG_LAUNCH(true, 8, 8);
+    } else {
+      if (shape == 0)
+        MSKM_WG_LAUNCH(false, 16, 1);
+      else if (shape == 1)
+        MSKM_WG_LAUNCH(false, 4, 1);
+      else
+        MSKM_WG_LAUNCH(false, 8, 8);
+    }
+#undef MSKM_WG_LAUNCH
+    MSKM_HIP_TRY(hipMemcpyAsync(W.h_defer + lo, W.st + lo, (hi - lo + 1) * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
+    MSKM_HIP_TRY(hipEventRecord(W.ev_defer, s));
+    for (int l = lo; l <= hi; ++l) W.deferred[l] = 1;
+    return MSKM_OK;
+  }
   if (W.pending) {  // the previous run's speculative chunk copy lands in h_chk
     MSKM_HIP_TRY(hipEventSynchronize(W.pending));
     W.pending = nullptr;
@@ -942,9 +1202,6 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
       if (on[l]) MSKM_TRY(mlp_predict_rows<TX>(h, mlp, l, b, x));
     warm = true;
   }
-  // form: preconditioned single-reduction when asked; the single-reduction
-  // form for the FP32 inner solves; the textbook form otherwise
-  const int form = bj ? kCgOneRedBj : sizeof(TX) == 4 ? kCgOneRed : kCgTextbook;
   if (sbn > 0)
     hipLaunchKernelGGL((k_cg_init<kGDiag, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, h->diag.rowptr, h->diag.col,
                        dval, b, x, (TX*)W.r, (TX*)W.p0, W.st, warm ? 1 : 0, W.part_s, W.part_s2, sb0, (TX*)W.p1);
@@ -992,8 +1249,18 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
     return MSKM_OK;
   };
   MSKM_TRY(launch());
+  bool prepared = next_on == nullptr;
   while (checked < launched) {
     if (launched < max_chunks) MSKM_TRY(launch());
+    if (!prepared) {  // capture the next levels' chunk while this one's two chunks run
+      prepared = true;
+      int nlo = 0, nhi = h->L - 1;
+      while (nlo < h->L && !(*next_on)[nlo]) ++nlo;
+      while (nhi >= 0 && !(*next_on)[nhi]) --nhi;
+      hipGraphExec_t next_exec = nullptr;
+      if (nlo <= nhi && !all_small(*next_on, nlo, nhi))
+        MSKM_TRY((chunk_graph<TV, TX>(h, W, dval, nlo, nhi, x, K, G, form, &next_exec)));
+    }
     MSKM_HIP_TRY(hipEventSynchronize(W.ev_chk[checked & 1]));
     const CgLevel* c = W.h_chk[checked & 1];
     ++checked;
@@ -1048,15 +1315,20 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
     // that depth in the same launches): rhs_l = f_l - sum_{k<l} B_{l,k} alpha_k
     MSKM_HIP_TRY(hipMemsetAsync(alpha, 0, N * sizeof(TX), s));
     const int D = (int)h->h_depth_begin.size() - 1;
+    std::vector<char> next(L, 0);
     for (int d = 0; d < D; ++d) {
       const int l0 = h->h_depth_begin[d], l1 = h->h_depth_begin[d + 1];
       lower_update<TV, TX>(h, lval, alpha, f, beta, h->h_off[l0], h->h_off[l1]);
       std::fill(on.begin(), on.end(), 0);
       for (int l = l0; l < l1; ++l) on[l] = 1;
-      MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, false, K, cs, mlp, bj)));
+      std::fill(next.begin(), next.end(), 0);
+      if (d + 1 < D)
+        for (int l = l1; l < h->h_depth_begin[d + 2]; ++l) next[l] = 1;
+      MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, false, K, cs, mlp, bj,
+                               d + 1 < D ? &next : nullptr)));
     }
     *sweeps_done = 0;
-    return MSKM_OK;
+    return flush_deferred(h, W, cs);
   }
   // monolithic: Jacobi on T' beta = f from beta_0 = f, then D alpha = beta
   int Lmax = 0;
@@ -1074,7 +1346,7 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
   if (o->warm_start) MSKM_HIP_TRY(hipMemcpyAsync(alpha, t, N * sizeof(TX), hipMemcpyDeviceToDevice, s));
   std::fill(on.begin(), on.end(), 1);
   MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, o->warm_start != 0, K, cs, mlp, bj)));
-  return MSKM_OK;
+  return flush_deferred(h, W, cs);
 }
 
 // ------------------------------------------------------------- residual
