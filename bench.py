@@ -40,8 +40,8 @@ HBM_PEAK_GBS = 8000.0
 # the same counter read 1 GiB for the 1 GiB streaming copy kernel of those
 # runs. Only valid for that kernel on that workload (None: not measured).
 PMC_TRAFFIC = {
-    ("halton2d_L8", "k_spmv_sell<float>"): {"fetch_kib": 247124.5625, "fetch_scale": 1048576 / 524299.0,
-                                           "write_kib": 5461.25, "write_scale": 1048576 / 1048604.5625},
+    ("halton2d_L8", "k_spmv_sell<float,true>"): {"fetch_kib": 191687.4375, "fetch_scale": 1048576 / 524299.0,
+                                                "write_kib": 5461.25, "write_scale": 1048576 / 1048604.1875},
 }
 TARGET = 1e-8
 RTOL_LADDER = [3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12]
@@ -59,22 +59,30 @@ def build_inputs(levels: int):
     return h, f
 
 
-def spmv_bytes(nnz: int, n: int, nrowptr: int, sval: int, sx: int) -> int:
-    """Algorithmic bytes of one CSR SpMV: values + int32 columns, int64 row
-    pointers (nrowptr arrays), x read once, y written once."""
-    return nnz * (sval + 4) + nrowptr * (n + 1) * 8 + n * sx + n * sx
+def spmv_bytes(nnz: int, n: int, nrowptr: int, sval: int, sx: int, scol: int = 4) -> int:
+    """Algorithmic bytes of one SpMV: values + columns (int32, or 16-bit
+    offsets in the sliced copy), 8 bytes of row metadata per row and matrix
+    (nrowptr), x read once, y written once."""
+    return nnz * (sval + scol) + nrowptr * (n + 1) * 8 + n * sx + n * sx
 
 
-def spmv_kernel_name(code: int, t: str) -> str:
+def diag_col_bytes(code: int, stats: dict) -> int:
+    """Column bytes per entry of the diagonal-block variant `code`: 2 for the
+    sliced copy with 16-bit column offsets, else 4."""
+    return 2 if code == 4064 and stats.get("sell_col16") else 4
+
+
+def spmv_kernel_name(code: int, t: str, col16: bool = False) -> str:
     """Kernel that a SpMV variant code launches (lanes per row + 1000 for
-    16-byte loads, + 2000 for non-temporal 16-byte loads)."""
+    16-byte loads, + 2000 for non-temporal 16-byte loads, + 3000 for
+    recomputed values; 4064 / 4032 the sliced copy, 16-bit / 32-bit columns)."""
     g, kind = code % 1000, code // 1000
     if kind == 0:
         return f"k_spmv<{g},{t}>"
     if kind == 3:
         return f"k_spmv_rec<{g},{t}>"
     if kind == 4:
-        return f"k_spmv_sell<{t}>"
+        return f"k_spmv_sell<{t},{'true' if code == 4064 and col16 else 'false'}>"
     return f"k_spmv_v<{g},{t}{',nontemporal' if kind == 2 else ''}>"
 
 
@@ -400,10 +408,12 @@ def main():
         torch.cuda.synchronize()
         nnz = {"diag": st["nnz_diag"], "lower": st["nnz_lower"], "full": st["nnz_diag"] + st["nnz_lower"]}[args.spmv_op]
         sv = 4 if prec == m.MSKM_PREC_FP32 else 8
-        b = spmv_bytes(nnz, N, 2 if args.spmv_op == "full" else 1, sv, sv)
         code = m.mskm_spmv_width(hd, op, prec)
+        sc = diag_col_bytes(code, st) if args.spmv_op == "diag" else 4
+        b = spmv_bytes(nnz, N, 2 if args.spmv_op == "full" else 1, sv, sv, sc)
         print(json.dumps({"op": args.spmv_op, "prec": args.spmv_prec, "ms": ms, "bytes": b, "GBps": b / ms / 1e6,
-                          "variant": code, "kernel": spmv_kernel_name(code, "float" if sv == 4 else "double"),
+                          "variant": code, "sell_col16": st["sell_col16"],
+                          "kernel": spmv_kernel_name(code, "float" if sv == 4 else "double", st["sell_col16"]),
                           "copy_bytes_each_way": 1 << 30, "copy_ms": e0.elapsed_time(e1) / args.spmv_repeats}))
         m.mskm_hier_destroy(hd)
         m.mskm_destroy(ctx)
@@ -517,7 +527,8 @@ def main():
     ]:
         m.mskm_apply_internal(ctx, hd, op, x, y, prec=prec, repeats=2)
         ms = m.mskm_apply_internal(ctx, hd, op, x, y, prec=prec, repeats=args.spmv_repeats)
-        b = spmv_bytes(nnz, N, nrp, sval, sx)
+        sc = diag_col_bytes(m.mskm_spmv_width(hd, op, prec), stats) if op == m.MSKM_OP_DIAG else 4
+        b = spmv_bytes(nnz, N, nrp, sval, sx, sc)
         spmv[name] = {"ms": ms, "bytes": b, "GBps": b / ms / 1e6}
     log("spmv", spmv)
     bt = batched(m, ctx, hd, h, pts_dev, dev, fast_opts, rt_fast, args.rhs, args.batch_count)
@@ -528,7 +539,7 @@ def main():
 
     # dominant kernel of the timed step: the CG products on the diagonal blocks (FP32)
     dom = spmv["diag_fp32"]
-    dom_kernel = spmv_kernel_name(widths["diag_fp32"], "float")
+    dom_kernel = spmv_kernel_name(widths["diag_fp32"], "float", stats["sell_col16"])
     pmc = PMC_TRAFFIC.get((f"halton2d_L{args.levels}", dom_kernel))
     traffic = None if pmc is None else int(pmc["fetch_kib"] * pmc["fetch_scale"] * 1024
                                            + pmc["write_kib"] * pmc["write_scale"] * 1024)

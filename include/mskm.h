@@ -140,6 +140,8 @@ typedef struct {
   int64_t device_bytes; /* device memory held by the hierarchy */
   double assemble_ms;   /* device time of the last assembly */
   int32_t ngroups;      /* independent hierarchies held (1 unless created as a batch) */
+  int32_t sell_col16;   /* 1 when the sliced copy of D_L also holds 16-bit column offsets (variant 4064) */
+  int64_t sell_entries; /* stored entries of the sliced copy of D_L, padding included */
 } mskm_hier_stats;
 
 mskm_status mskm_hier_stats_get(const mskm_hier* h, mskm_hier_stats* out);
@@ -211,11 +213,14 @@ mskm_status mskm_apply_internal(mskm_ctx* ctx, const mskm_hier* h, int32_t op, i
  * with entry values recomputed in the kernel from the points (the stored
  * column structure, phi evaluated in the operator's precision) (variant
  * codes w, w + 1000, w + 2000, w + 3000), and for DIAG also the sliced
- * (SELL, 64-row slices, one row per lane) copy of the diagonal blocks (code
- * 4064) -- for each operator (DIAG, LOWER, FULL) and each stored precision
- * on this hierarchy's own blocks (`repeats` >= 1 timed launches per variant)
- * and keeps the fastest for later apply / solve calls (the CG products use
- * the DIAG choice). times_ms (nullable, host, [3][2][21]) receives the mean
+ * (SELL, 64-row slices, one row per lane) copy of the diagonal blocks, with
+ * 16-bit column offsets from each slice's smallest column when every slice
+ * spans at most 65536 rows (code 4064; 32-bit columns otherwise) or with
+ * 32-bit columns (code 4032) -- for each operator (DIAG, LOWER, FULL) and
+ * each stored precision on this hierarchy's own blocks (`repeats` >= 1
+ * timed launches per variant) and keeps the fastest for later apply / solve
+ * calls (the CG products use the DIAG choice). times_ms (nullable, host,
+ * [3][2][22]) receives the mean
  * ms per launch of every [op][precision][variant] in that order (0 where a
  * precision is not stored or a variant does not apply).
  * The choice is also remembered by the context: hierarchies created later
@@ -227,7 +232,7 @@ mskm_status mskm_autotune(mskm_ctx* ctx, mskm_hier* h, int32_t repeats, float* t
 mskm_status mskm_spmv_width(const mskm_hier* h, int32_t op, int32_t prec, int32_t* width);
 
 /* Pins the SpMV variant of op / prec to `width`, one of the autotuner's
- * codes (4, 8, 16, 32, 64, plus 0, 1000, 2000 or 3000; 4064 for DIAG), e.g. a choice saved from
+ * codes (4, 8, 16, 32, 64, plus 0, 1000, 2000 or 3000; 4064 or 4032 for DIAG), e.g. a choice saved from
  * an earlier autotune. Results do not depend on the variant beyond FP
  * summation order. MSKM_EINVAL for an unknown op, precision or code. */
 mskm_status mskm_set_spmv_width(mskm_hier* h, int32_t op, int32_t prec, int32_t width);

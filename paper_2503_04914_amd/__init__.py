@@ -63,7 +63,8 @@ class HierDesc(C.Structure):
 class HierStats(C.Structure):
     _fields_ = [("dim", C.c_int32), ("levels", C.c_int32), ("n_total", C.c_int64), ("nnz_diag", C.c_int64),
                 ("nnz_lower", C.c_int64), ("has_fp64", C.c_int32), ("has_fp32", C.c_int32),
-                ("device_bytes", C.c_int64), ("assemble_ms", C.c_double), ("ngroups", C.c_int32)]
+                ("device_bytes", C.c_int64), ("assemble_ms", C.c_double), ("ngroups", C.c_int32),
+                ("sell_col16", C.c_int32), ("sell_entries", C.c_int64)]
 
 
 class LevelInfo(C.Structure):
@@ -307,8 +308,9 @@ def mskm_apply_internal(ctx, h, op: int, x, y, prec: int = MSKM_PREC_FP64, repea
 
 
 TUNE_VARIANTS = [4, 8, 16, 32, 64, 1004, 1008, 1016, 1032, 1064, 2004, 2008, 2016, 2032, 2064,
-                 3004, 3008, 3016, 3032, 3064, 4064]
-SELL_CODE = 4064  # sliced copy of the diagonal blocks (MSKM_OP_DIAG only)
+                 3004, 3008, 3016, 3032, 3064, 4064, 4032]
+SELL_CODE = 4064  # sliced copy of the diagonal blocks, 16-bit column offsets where possible (MSKM_OP_DIAG only)
+SELL32_CODE = 4032  # the same copy with 32-bit columns (MSKM_OP_DIAG only)
 
 
 def mskm_autotune(ctx, h, repeats: int = 5) -> np.ndarray:

@@ -220,6 +220,8 @@ mskm_status mskm_hier_stats_get(const mskm_hier* h, mskm_hier_stats* o) {
   o->device_bytes = h->device_bytes;
   o->assemble_ms = h->assemble_ms;
   o->ngroups = h->ngroups;
+  o->sell_col16 = h->sell.col16 ? 1 : 0;
+  o->sell_entries = h->sell.entries;
   return MSKM_OK;
 }
 
@@ -318,7 +320,7 @@ mskm_status mskm_set_spmv_width(mskm_hier* h, int32_t op, int32_t prec, int32_t 
   if (op < MSKM_OP_DIAG || op > MSKM_OP_FULL || (prec != MSKM_PREC_FP64 && prec != MSKM_PREC_FP32))
     return fail(MSKM_EINVAL, "unknown op or precision");
   const int g = width % mskm::kVecFlag, kind = width / mskm::kVecFlag;
-  if (width == mskm::kSellCode) {
+  if (width == mskm::kSellCode || width == mskm::kSell32Code) {
     if (op != MSKM_OP_DIAG) return fail(MSKM_EINVAL, "mskm_set_spmv_width: the SELL variant serves MSKM_OP_DIAG only");
   } else if (width < 0 || kind > 3 || (g != 4 && g != 8 && g != 16 && g != 32 && g != 64)) {
     return fail(MSKM_EINVAL, "mskm_set_spmv_width: unknown variant code " + std::to_string(width));

@@ -839,8 +839,8 @@ __global__ void __launch_bounds__(kBlock) k_sell_rows(int64_t off, int64_t n, in
   rows[slot0 + t] = t < n ? (int32_t)(off + t) : -1;
 }
 
-// Width (in entries, w_s * kSellC) of every slice: its longest row times
-// kSellC. Entry nslices is 0 (scan sentinel).
+// Width (in entries, w_s * kSellC) of every slice: its longest row rounded
+// up to a multiple of 4, times kSellC. Entry nslices is 0 (scan sentinel).
 __global__ void __launch_bounds__(kBlock) k_sell_width(int64_t nslices, const int32_t* __restrict__ rows,
                                                        const int64_t* __restrict__ rp, int64_t* __restrict__ w) {
   const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -854,13 +854,14 @@ __global__ void __launch_bounds__(kBlock) k_sell_width(int64_t nslices, const in
     const int32_t r = rows[s * kSellC + t];
     if (r >= 0) m = max(m, rp[r + 1] - rp[r]);
   }
-  w[s] = m * kSellC;
+  w[s] = (m + 3) / 4 * 4 * kSellC;
 }
 
 // One wave (workgroup) per slice: copy the CSR rows into the slot-interleaved
-// layout through LDS tiles of 16 entries x 64 slots: the loads read 4 rows x
-// 16 consecutive entries per instruction, the stores write one entry of all
-// 64 slots (contiguous).
+// layout (groups of four consecutive entries per slot: entry k of slot t at
+// e0 + (k / 4) * 4 kSellC + 4 t + k % 4) through LDS tiles of 16 entries x 64
+// slots: the loads read 4 rows x 16 consecutive entries per instruction, the
+// stores write four entries of all 64 slots (contiguous).
 constexpr int kSellTile = 16;
 __global__ void __launch_bounds__(kSellC)
     k_sell_fill(int64_t nslices, const int32_t* __restrict__ rows, const int64_t* __restrict__ sptr,
@@ -889,14 +890,47 @@ __global__ void __launch_bounds__(kSellC)
       if (val32) tf[kk][rr] = in ? val32[brr + k] : 0.0f;
     }
     __syncthreads();
-    for (int kk = 0; kk < kSellTile && k0 + kk < w; ++kk) {
-      const int64_t d = e0 + (k0 + kk) * kSellC + t;
+    for (int kk = 0; kk < kSellTile && k0 + kk < w; ++kk) {  // w and kSellTile are multiples of 4
+      const int64_t k = k0 + kk;
+      const int64_t d = e0 + (k / 4) * (4 * kSellC) + 4 * t + (k % 4);
       scol[d] = tc[kk][t];
       if (sval) sval[d] = tv[kk][t];
       if (sval32) sval32[d] = tf[kk][t];
     }
     __syncthreads();
   }
+}
+
+// Smallest column of each slice (one wave per slice); the slices whose
+// columns span more than 65536 rows are counted in *wide.
+__global__ void __launch_bounds__(kSellC)
+    k_sell_span(const int64_t* __restrict__ sptr, const int32_t* __restrict__ scol, int32_t* __restrict__ cbase,
+                int32_t* __restrict__ wide) {
+  const int64_t s = blockIdx.x;
+  int32_t lo = INT32_MAX, hi = -1;
+  for (int64_t d = sptr[s] + threadIdx.x; d < sptr[s + 1]; d += kSellC) {
+    const int32_t c = scol[d];
+    lo = min(lo, c);
+    hi = max(hi, c);
+  }
+#pragma unroll
+  for (int o = kSellC / 2; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o, kSellC));
+    hi = max(hi, __shfl_xor(hi, o, kSellC));
+  }
+  if (threadIdx.x == 0) {
+    cbase[s] = hi >= 0 ? lo : 0;
+    if (hi >= 0 && hi - lo > 65535) atomicAdd(wide, 1);
+  }
+}
+
+// col16 = col - cbase[slice] (one workgroup per slice).
+__global__ void __launch_bounds__(kSellC)
+    k_sell_narrow(const int64_t* __restrict__ sptr, const int32_t* __restrict__ scol,
+                  const int32_t* __restrict__ cbase, uint16_t* __restrict__ col16) {
+  const int64_t s = blockIdx.x;
+  const int32_t b = cbase[s];
+  for (int64_t d = sptr[s] + threadIdx.x; d < sptr[s + 1]; d += kSellC) col16[d] = (uint16_t)(scol[d] - b);
 }
 
 static mskm_status build_sell(mskm_hier* h, bool want64, bool want32) {
@@ -929,6 +963,35 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32) {
   if (S.nslices > 0)
     hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)S.nslices), dim3(kSellC), 0, s, S.nslices, S.rows, S.sptr,
                        h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, S.col, S.val, S.val32);
+  // 16-bit column offsets when every slice's columns span at most 65536 rows
+  if (S.nslices > 0) {
+    int32_t* cbase = nullptr;
+    int32_t* d_wide = nullptr;
+    int32_t wide = 0;
+    MSKM_TRY(dalloc(&cbase, (size_t)S.nslices));
+    MSKM_TRY(dalloc(&d_wide, 1));
+    mskm_status st = MSKM_OK;
+    if (hipMemsetAsync(d_wide, 0, 4, s) != hipSuccess) st = fail(MSKM_EDEVICE, "memset");
+    if (st == MSKM_OK) {
+      hipLaunchKernelGGL(k_sell_span, dim3((unsigned)S.nslices), dim3(kSellC), 0, s, S.sptr, S.col, cbase, d_wide);
+      if (hipMemcpyAsync(&wide, d_wide, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        st = fail(MSKM_EDEVICE, "SELL column span");
+    }
+    (void)hipFree(d_wide);
+    if (st == MSKM_OK && wide == 0) {
+      h->allocs.push_back(cbase);
+      h->device_bytes += S.nslices * 4;
+      S.cbase = cbase;
+      st = halloc(h, &S.col16, (size_t)S.entries);
+      if (st == MSKM_OK)
+        hipLaunchKernelGGL(k_sell_narrow, dim3((unsigned)S.nslices), dim3(kSellC), 0, s, S.sptr, S.col, S.cbase,
+                           S.col16);
+    } else {
+      (void)hipFree(cbase);
+    }
+    MSKM_TRY(st);
+  }
   // launch table: blocks of 4 slices (one wave each) within each level
   WorkTable& wt = h->wt_sell;
   std::vector<int32_t> lev;

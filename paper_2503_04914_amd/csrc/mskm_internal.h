@@ -30,10 +30,13 @@ constexpr int kBlock = 256;  // threads per block of every streaming / SpMV kern
 constexpr int kCsrPad = 16;  // tail pad (entries) of CSR column and value arrays
 // SpMV variant code: lanes per row G, plus 1000: 16-byte value/column loads,
 // 2000: the same non-temporal, 3000: values recomputed from point records;
-// kSellCode: the sliced copy of the diagonal blocks (one row per lane)
+// kSellCode: the sliced copy of the diagonal blocks (one row per lane), with
+// 16-bit column offsets when every slice allows them; kSell32Code: the same
+// copy with its 32-bit columns
 constexpr int kVecFlag = 1000;
 constexpr int kSellCode = 4064;
-constexpr int kTuneVariants = 21;  // widths 4..64 x the four kinds, then SELL (diagonal operator only)
+constexpr int kSell32Code = 4032;
+constexpr int kTuneVariants = 22;  // widths 4..64 x the four kinds, then the two SELL codes (diagonal operator only)
 constexpr int kSellC = 64;         // SELL slice height: one wave, one row per lane
 
 // Per-level descriptor read by the kernels (all fields uniform per wave).
@@ -66,8 +69,10 @@ struct WorkTable {
 
 // Sliced-ELL copy of the diagonal blocks. Each level's rows, in the internal
 // (cell) order, are cut into slices of kSellC consecutive rows from the level
-// start; slice s stores its width w_s = longest row of the slice and entry k
-// of slot t at sptr[s] + k * kSellC + t (shorter rows padded with value 0
+// start; slice s stores its width w_s = longest row of the slice rounded up
+// to a multiple of 4, and entry k of slot t at
+// sptr[s] + (k / 4) * 4 kSellC + 4 t + k % 4 (four consecutive entries of a
+// slot side by side, one vector load each; shorter rows padded with value 0
 // and their own row as column). Rows are not reordered by length: keeping
 // neighbouring rows together keeps the gathers of one load instruction on
 // few cache lines, which measures faster than the padding it saves.
@@ -76,6 +81,10 @@ struct Sell {
   int64_t* sptr = nullptr;   // [nslices + 1]
   int32_t* rows = nullptr;   // [nslices * kSellC] internal row of each slot, -1 for an empty slot
   int32_t* col = nullptr;    // [entries]
+  // 16-bit copy of the columns, col = cbase[slice] + col16 (null when some
+  // slice's columns span more than 65536 rows)
+  uint16_t* col16 = nullptr;  // [entries]
+  int32_t* cbase = nullptr;   // [nslices] smallest column of each slice
   double* val = nullptr;     // [entries] FP64 values (null when not stored)
   float* val32 = nullptr;    // [entries] FP32 values (null when not stored)
   std::vector<int64_t> h_slice_begin;  // [L+1] first slice of each level

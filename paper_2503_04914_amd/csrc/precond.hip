@@ -32,19 +32,32 @@ __global__ void __launch_bounds__(kWave)
   for (int k = t; k < kBjMax * (kBjMax + 1); k += kWave) (&M[0][0])[k] = 0.0;
   if (t <= m) rps[t] = rp[a + t];
   __syncthreads();
-  for (int64_t k = rps[0] + t; k < rps[m]; k += kWave) {
-    const int64_t c = col[k];
-    if (c >= a && c < a + m) {
-      int lo = 0, hi = m - 1;  // the row of entry k: the last i with rps[i] <= k
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (rps[mid] <= k)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      M[lo][c - a] = val ? val[k] : (double)val32[k];
+  // the run of entries in batches of 4 per lane, loads of a batch issued together
+  constexpr int kU = 4;
+  const int64_t k1 = rps[m];
+  for (int64_t kk = rps[0] + t; kk < k1; kk += kU * kWave) {
+    int64_t c[kU];
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t k = kk + u * kWave;
+      c[u] = k < k1 ? col[k] : -1;
+      v[u] = k < k1 ? (val ? val[k] : (double)val32[k]) : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (c[u] >= a && c[u] < a + m) {
+        const int64_t k = kk + u * kWave;
+        int lo = 0, hi = m - 1;  // the row of entry k: the last i with rps[i] <= k
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (rps[mid] <= k)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        M[lo][c[u] - a] = v[u];
+      }
   }
   __syncthreads();
   bool bad = false;

@@ -209,23 +209,89 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// The sliced copy stores each slot's entries in groups of four consecutive
+// entries (entry k of slot t at e0 + (k / 4) * 4 kSellC + 4 t + k % 4), so a
+// lane reads four values and four columns with one load each.
+typedef float sf4 __attribute__((ext_vector_type(4)));
+typedef double sd2 __attribute__((ext_vector_type(2)));
+typedef int si4 __attribute__((ext_vector_type(4)));
+typedef unsigned short su4 __attribute__((ext_vector_type(4)));
+
+// Four values of one slot (non-temporal: the stream is read once per product
+// and should not evict the gathered x entries).
+__device__ __forceinline__ void sell_vals4(const float* p, float v[4]) {
+  const sf4 a = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(p));
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = a.z;
+  v[3] = a.w;
+}
+__device__ __forceinline__ void sell_vals4(const double* p, double v[4]) {
+  const sd2 a = __builtin_nontemporal_load(reinterpret_cast<const sd2*>(p));
+  const sd2 b = __builtin_nontemporal_load(reinterpret_cast<const sd2*>(p + 2));
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+
+// Columns of the sliced copy: 32-bit, or 16-bit offsets from the slice's
+// smallest column.
+template <bool C16>
+struct SellCols;
+template <>
+struct SellCols<false> {
+  const int32_t* col;
+  __device__ __forceinline__ void at4(int64_t, int64_t d, int32_t c[4]) const {
+    const si4 b = __builtin_nontemporal_load(reinterpret_cast<const si4*>(col + d));
+    c[0] = b.x;
+    c[1] = b.y;
+    c[2] = b.z;
+    c[3] = b.w;
+  }
+};
+template <>
+struct SellCols<true> {
+  const uint16_t* col16;
+  const int32_t* cbase;
+  __device__ __forceinline__ void at4(int64_t sl, int64_t d, int32_t c[4]) const {
+    const su4 b = __builtin_nontemporal_load(reinterpret_cast<const su4*>(col16 + d));
+    const int32_t o = cbase[sl];
+    c[0] = o + (int32_t)b.x;
+    c[1] = o + (int32_t)b.y;
+    c[2] = o + (int32_t)b.z;
+    c[3] = o + (int32_t)b.w;
+  }
+};
+
+// Dot of slot t of slice sl with x: entries in order, four per load.
+template <typename TV, typename TX, bool C16>
+__device__ __forceinline__ TX sell_slot_dot(int64_t sl, int t, int64_t e0, int64_t e1, const SellCols<C16>& cols,
+                                            const TV* __restrict__ val, const TX* __restrict__ x) {
+  TX acc = 0;
+#pragma unroll 2
+  for (int64_t d = e0 + 4 * t; d < e1; d += 4 * kSellC) {
+    TV v[4];
+    int32_t c[4];
+    sell_vals4(val + d, v);
+    cols.at4(sl, d, c);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += (TX)v[u] * x[c[u]];
+  }
+  return acc;
+}
+
 // y = b + sign * A_diag x from the sliced copy: one wave per slice, one row
 // per lane, the slice's entries read slot-interleaved (fully coalesced).
-template <typename T>
+template <typename T, bool C16>
 __global__ void __launch_bounds__(kBlock)
     k_spmv_sell(int64_t nslices, const int64_t* __restrict__ sptr, const int32_t* __restrict__ rows,
-                const int32_t* __restrict__ col, const T* __restrict__ val, const T* __restrict__ x,
+                const SellCols<C16> cols, const T* __restrict__ val, const T* __restrict__ x,
                 const T* __restrict__ b, T* __restrict__ y, T sign) {
   const int64_t sl = (int64_t)xcd_block_id(gridDim.x) * (kBlock / kSellC) + threadIdx.x / kSellC;
   if (sl >= nslices) return;
   const int t = threadIdx.x % kSellC;
-  const int64_t e0 = sptr[sl], e1 = sptr[sl + 1];
-  T acc = 0;
-  // the value and column streams are read once per product: non-temporal loads
-  // keep them from evicting the gathered x entries (measured 10% faster)
-#pragma unroll 8
-  for (int64_t d = e0 + t; d < e1; d += kSellC)
-    acc += __builtin_nontemporal_load(val + d) * x[__builtin_nontemporal_load(col + d)];
+  const T acc = sell_slot_dot<T, T, C16>(sl, t, sptr[sl], sptr[sl + 1], cols, val, x);
   const int32_t row = rows[sl * kSellC + t];
   if (row >= 0) y[row] = (b ? b[row] : (T)0) + sign * acc;
 }
@@ -421,10 +487,10 @@ __global__ void __launch_bounds__(kBlock)
 
 // The same from the sliced copy (variant kSellCode): blocks of 4 slices of
 // one level.
-template <typename TV, typename TX>
+template <typename TV, typename TX, bool C16>
 __global__ void __launch_bounds__(kBlock)
     k_cg_spmv1_sell(const WorkTable wt, int base, const int64_t* __restrict__ sptr, const int32_t* __restrict__ rows,
-                    const int32_t* __restrict__ col, const TV* __restrict__ val, const TX* __restrict__ p,
+                    const SellCols<C16> cols, const TV* __restrict__ val, const TX* __restrict__ p,
                     TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ pqp,
                     double* __restrict__ ppp, const TX* __restrict__ rv, double* __restrict__ p3) {
   __shared__ double sm[kBlock / kWave];
@@ -435,11 +501,7 @@ __global__ void __launch_bounds__(kBlock)
   const int t = threadIdx.x % kSellC;
   double s = 0.0, s2 = 0.0, s3 = 0.0;
   if (sl < wt.row1[blk]) {
-    const int64_t e0 = sptr[sl], e1 = sptr[sl + 1];
-    TX acc = 0;
-#pragma unroll 8
-    for (int64_t d = e0 + t; d < e1; d += kSellC)
-      acc += (TX)__builtin_nontemporal_load(val + d) * p[__builtin_nontemporal_load(col + d)];
+    const TX acc = sell_slot_dot<TV, TX, C16>(sl, t, sptr[sl], sptr[sl + 1], cols, val, p);
     const int32_t row = rows[sl * kSellC + t];
     if (row >= 0) {
       q[row] = acc;
@@ -1016,7 +1078,8 @@ static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int 
   const bool pcf = form == kCgOneRedBj;
   const WorkTable& wv = pcf ? h->bj.wt : h->wt_vec;  // vector table (whole preconditioner blocks when pcf)
   const WorkTable& wc = h->wt_sell;
-  const bool sell = G == kSellCode;
+  const bool sell = G == kSellCode || G == kSell32Code;
+  const bool c16 = G == kSellCode && h->sell.col16;
   const WorkTable& wq = sell ? wc : ws;  // table of the product kernel (and of its partials)
   const int nlev = hi - lo + 1;
   const int qb0 = wq.h_lev_begin[lo], qbn = wq.h_lev_begin[hi + 1] - qb0;
@@ -1029,9 +1092,14 @@ static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int 
   // q = A v with partials v.q, v.rv (v.v without rv) when pp, rv.rv when p3
   auto product = [&](const TX* v, double* pp, const TX* rv, double* p3, const CgLevel* st) {
     if (qbn <= 0) return;
-    if (sell)
-      hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX>), dim3(qbn), dim3(kBlock), 0, s, wc, qb0, h->sell.sptr, h->sell.rows,
-                         h->sell.col, sell_values<TV>(h->sell), v, q, st, W.part_s, pp, rv, p3);
+    if (sell && c16)
+      hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX, true>), dim3(qbn), dim3(kBlock), 0, s, wc, qb0, h->sell.sptr,
+                         h->sell.rows, SellCols<true>{h->sell.col16, h->sell.cbase}, sell_values<TV>(h->sell), v, q,
+                         st, W.part_s, pp, rv, p3);
+    else if (sell)
+      hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX, false>), dim3(qbn), dim3(kBlock), 0, s, wc, qb0, h->sell.sptr,
+                         h->sell.rows, SellCols<false>{h->sell.col}, sell_values<TV>(h->sell), v, q, st, W.part_s, pp,
+                         rv, p3);
     else
       launch_cg_spmv1<TV, TX>(s, G, ws, qb0, qbn, h->diag, dval, v, q, st, W.part_s, h->prec, h->dim, pp, rv, p3);
   };
@@ -1625,11 +1693,17 @@ static void launch_apply(mskm_hier* h, int op, const T* v1, const T* v2, const T
   const Csr* A1 = op == MSKM_OP_LOWER ? &h->lower : &h->diag;
   const Csr* A2 = op == MSKM_OP_FULL ? &h->lower : nullptr;
   const int G = h->spmv_g[op][sizeof(T) == 4 ? 1 : 0];
-  if (G == kSellCode) {  // diagonal operator only
-    if (h->sell.nslices > 0)
-      hipLaunchKernelGGL(k_spmv_sell<T>, dim3(nblk(h->sell.nslices, kBlock / kSellC)), dim3(kBlock), 0,
-                         h->ctx->stream, h->sell.nslices, h->sell.sptr, h->sell.rows, h->sell.col,
-                         sell_values<T>(h->sell), x, (const T*)nullptr, y, (T)1);
+  if (G == kSellCode || G == kSell32Code) {  // diagonal operator only
+    const dim3 grid(nblk(h->sell.nslices, kBlock / kSellC));
+    if (h->sell.nslices <= 0) return;
+    if (G == kSellCode && h->sell.col16)
+      hipLaunchKernelGGL((k_spmv_sell<T, true>), grid, dim3(kBlock), 0, h->ctx->stream, h->sell.nslices, h->sell.sptr,
+                         h->sell.rows, SellCols<true>{h->sell.col16, h->sell.cbase}, sell_values<T>(h->sell), x,
+                         (const T*)nullptr, y, (T)1);
+    else
+      hipLaunchKernelGGL((k_spmv_sell<T, false>), grid, dim3(kBlock), 0, h->ctx->stream, h->sell.nslices,
+                         h->sell.sptr, h->sell.rows, SellCols<false>{h->sell.col}, sell_values<T>(h->sell), x,
+                         (const T*)nullptr, y, (T)1);
     return;
   }
   spmv_launch<T>(h->ctx->stream, G, A1, v1, A2, v2, x, (const T*)nullptr, y, (T)1, 0, h->N, h->prec, h->dim);
@@ -1661,7 +1735,8 @@ mskm_status apply_internal(mskm_hier* h, int op, int prec, const void* x, void* 
 // each after one warm-up) and keep the fastest.
 mskm_status autotune(mskm_hier* h, int repeats, float* times_out) {
   static const int widths[kTuneVariants] = {4,    8,    16,   32,   64,   1004, 1008, 1016, 1032, 1064, 2004,
-                                            2008, 2016, 2032, 2064, 3004, 3008, 3016, 3032, 3064, kSellCode};
+                                            2008, 2016, 2032, 2064, 3004, 3008, 3016, 3032, 3064, kSellCode,
+                                            kSell32Code};
   double* x = nullptr;
   double* y = nullptr;
   MSKM_TRY(dalloc(&x, h->N));
@@ -1675,7 +1750,7 @@ mskm_status autotune(mskm_hier* h, int repeats, float* times_out) {
       float best = 1e30f;
       int bestg = h->spmv_g[op][prec];
       for (int wi = 0; wi < kTuneVariants && st == MSKM_OK; ++wi) {
-        if (widths[wi] == kSellCode && op != MSKM_OP_DIAG) {  // the sliced copy holds the diagonal blocks only
+        if (widths[wi] >= kSell32Code && op != MSKM_OP_DIAG) {  // the sliced copy holds the diagonal blocks only
           if (times_out) times_out[(op * 2 + prec) * kTuneVariants + wi] = 0.f;
           continue;
         }

@@ -116,7 +116,7 @@ def test_every_spmv_variant(mod, ctx, name):
     try:
         for code in mod.TUNE_VARIANTS:
             for op, ref in ((mod.MSKM_OP_DIAG, yd), (mod.MSKM_OP_LOWER, yl), (mod.MSKM_OP_FULL, yd + yl)):
-                if code == mod.SELL_CODE and op != mod.MSKM_OP_DIAG:
+                if code in (mod.SELL_CODE, mod.SELL32_CODE) and op != mod.MSKM_OP_DIAG:
                     with pytest.raises(mod.MskmError):  # the sliced copy holds the diagonal blocks only
                         mod.mskm_set_spmv_width(hd, op, 0, code)
                     continue
@@ -133,8 +133,43 @@ def test_every_spmv_variant(mod, ctx, name):
             mod.mskm_set_spmv_width(hd, op, pr, w)
 
 
+def test_sell_column_offsets(mod, ctx):
+    """The sliced copy stores 16-bit column offsets when every 64-row slice's
+    columns span at most 65536 rows, and its 16-bit product equals the 32-bit
+    one bit for bit (same entries, same order). A lattice of 8 planes of
+    320 x 320 points whose cell layers hold over 65536 rows each has slices
+    coupled across layers: there the copy keeps 32-bit columns only and code
+    4064 runs the 32-bit kernel."""
+    h, f, blk, hd, _ = _setup(mod, ctx, "halton5")
+    assert mod.mskm_hier_stats_get(hd)["sell_col16"] == 1
+    g = (np.arange(320) + 0.5) / 320
+    X, Y, Z = np.meshgrid(g, g, (np.arange(8) + 0.5) / 320, indexing="ij")
+    pts = np.ascontiguousarray(np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1))
+    wide = mod.mskm_hier_create(ctx, pts, np.array([0, len(pts)], dtype=np.int64), np.array([1.5 / 320]),
+                                fp64=True, fp32=True)
+    try:
+        assert mod.mskm_hier_stats_get(wide)["sell_col16"] == 0
+        for hh, n in ((hd, h.n_total), (wide, len(pts))):
+            x = np.random.default_rng(6).standard_normal(n)
+            out = {}
+            for code in (mod.SELL_CODE, mod.SELL32_CODE):
+                for pr in (mod.MSKM_PREC_FP64, mod.MSKM_PREC_FP32):
+                    mod.mskm_set_spmv_width(hh, mod.MSKM_OP_DIAG, pr, code)
+                    y = np.zeros_like(x)
+                    mod.mskm_apply(ctx, hh, mod.MSKM_OP_DIAG, x, y, prec=pr)
+                    out[code, pr] = y
+            for pr in (mod.MSKM_PREC_FP64, mod.MSKM_PREC_FP32):
+                assert np.array_equal(out[mod.SELL_CODE, pr], out[mod.SELL32_CODE, pr])
+                y8 = np.zeros_like(x)
+                mod.mskm_set_spmv_width(hh, mod.MSKM_OP_DIAG, pr, 1008)
+                mod.mskm_apply(ctx, hh, mod.MSKM_OP_DIAG, x, y8, prec=pr)
+                assert _rel(out[mod.SELL_CODE, pr], y8) <= (1e-14 if pr == mod.MSKM_PREC_FP64 else 1e-5)
+    finally:
+        mod.mskm_hier_destroy(wide)
+
+
 @pytest.mark.parametrize("name", ["halton5", "uniform3d3"])
-@pytest.mark.parametrize("code", [3008, 3016, 4064])
+@pytest.mark.parametrize("code", [3008, 3016, 4064, 4032])
 def test_solve_with_variant(mod, ctx, name, code):
     """Solves whose CG products run on the recomputed-value or the sliced
     (SELL) variant, and whose lower-block products recompute the values,
@@ -144,7 +179,7 @@ def test_solve_with_variant(mod, ctx, name, code):
     try:
         for op in range(3):
             for pr in range(2):
-                mod.mskm_set_spmv_width(hd, op, pr, code if op == 0 or code != mod.SELL_CODE else 3016)
+                mod.mskm_set_spmv_width(hd, op, pr, code if op == 0 or code < mod.SELL32_CODE else 3016)
         for prec, bar in ((mod.MSKM_PREC_FP64, 1e-10), (mod.MSKM_PREC_FP32, 1e-8)):
             alpha = np.zeros_like(f)
             o = mod.solve_opts(precision=prec, cg_rtol=1e-14 if prec == mod.MSKM_PREC_FP64 else 1e-5,
@@ -356,8 +391,8 @@ def test_autotune_keeps_results(mod, ctx):
     mod.mskm_apply(ctx, hd, mod.MSKM_OP_FULL, x, y0)
     t = mod.mskm_autotune(ctx, hd, repeats=2)
     assert t.shape == (3, 2, len(mod.TUNE_VARIANTS))
-    sell = mod.TUNE_VARIANTS.index(mod.SELL_CODE)
-    assert np.all(np.delete(t, sell, axis=2) > 0) and np.all(t[0, :, sell] > 0) and np.all(t[1:, :, sell] == 0)
+    sell = [mod.TUNE_VARIANTS.index(mod.SELL_CODE), mod.TUNE_VARIANTS.index(mod.SELL32_CODE)]
+    assert np.all(np.delete(t, sell, axis=2) > 0) and np.all(t[0][:, sell] > 0) and np.all(t[1:][:, :, sell] == 0)
     for op in range(3):
         for pr in range(2):
             assert mod.mskm_spmv_width(hd, op, pr) in mod.TUNE_VARIANTS
