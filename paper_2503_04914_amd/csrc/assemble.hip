@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
                     const double* __restrict__ xs, int64_t N, const int64_t* __restrict__ dptr,
                     int32_t* __restrict__ dcol, double* __restrict__ dval, float* __restrict__ dval32,
                     const int64_t* __restrict__ lptr, int32_t* __restrict__ lcol, double* __restrict__ lval,
-                    float* __restrict__ lval32) {
+                    float* __restrict__ lval32, float* __restrict__ dlo, float* __restrict__ llo) {
   __shared__ double sx[kTileCap], sy[kTileCap], sz[DIM == 3 ? kTileCap : 1];
   __shared__ int64_t box_a[kMaxBoxRows];
   __shared__ int32_t box_o[kMaxBoxRows];
@@ -484,6 +484,7 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
     int32_t* col = is_diag ? dcol : lcol;
     double* val = is_diag ? dval : lval;
     float* val32 = is_diag ? dval32 : lval32;
+    float* vlo = is_diag ? dlo : llo;
     for (int q = w; q < nrow_tile; q += kFillWaves) {
       const int64_t i = Lk.off + tile0 + q;
       const double qx = X[i], qy = Y[i], qz = DIM == 3 ? Z[i] : 0.0;
@@ -520,6 +521,7 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
           const double v = phi31_d2(d2, Lj.delta);
           if (val) val[pp] = v;
           if (val32) val32[pp] = (float)v;
+          if (vlo) vlo[pp] = (float)(v - (double)(float)v);
         }
         nh += __popcll(m);
       };
@@ -796,15 +798,18 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   (void)hipFree(tmp);
   (void)hipFree(d_off);
 
-  // 5. fill pass
+  // 5. fill pass (FP32-only hierarchies also keep the FP32 rounding remainders)
+  const bool want_lo = want32 && !want64;
   for (Csr* c : {&h->diag, &h->lower}) {
     MSKM_TRY(halloc(h, &c->col, (size_t)c->nnz + kCsrPad));
     if (want64) MSKM_TRY(halloc(h, &c->val, (size_t)c->nnz + kCsrPad));
     if (want32) MSKM_TRY(halloc(h, &c->val32, (size_t)c->nnz + kCsrPad));
+    if (want_lo) MSKM_TRY(halloc(h, &c->val32lo, (size_t)c->nnz + kCsrPad));
     // pads hold finite values (never used: the loads that reach them are masked)
     MSKM_HIP_TRY(hipMemsetAsync(c->col + c->nnz, 0, kCsrPad * 4, s));
     if (want64) MSKM_HIP_TRY(hipMemsetAsync(c->val + c->nnz, 0, kCsrPad * 8, s));
     if (want32) MSKM_HIP_TRY(hipMemsetAsync(c->val32 + c->nnz, 0, kCsrPad * 4, s));
+    if (want_lo) MSKM_HIP_TRY(hipMemsetAsync(c->val32lo + c->nnz, 0, kCsrPad * 4, s));
   }
   for (int k = 0; k < L; ++k) {
     const int64_t n = h->h_lev[k].n;
@@ -812,11 +817,11 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
     if (dim == 3)
       hipLaunchKernelGGL(k_nbr_tile_fill<3>, dim3(grid_for(n, kWave)), dim3(kFillWaves * kWave), 0, s, k, h->d_lev,
                          h->cell_start, h->xs, N, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, h->lower.rowptr,
-                         h->lower.col, h->lower.val, h->lower.val32);
+                         h->lower.col, h->lower.val, h->lower.val32, h->diag.val32lo, h->lower.val32lo);
     else
       hipLaunchKernelGGL(k_nbr_tile_fill<2>, dim3(grid_for(n, kWave)), dim3(kFillWaves * kWave), 0, s, k, h->d_lev,
                          h->cell_start, h->xs, N, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, h->lower.rowptr,
-                         h->lower.col, h->lower.val, h->lower.val32);
+                         h->lower.col, h->lower.val, h->lower.val32, h->diag.val32lo, h->lower.val32lo);
   }
   MSKM_TRY(build_sell(h, want64, want32));
   MSKM_HIP_TRY(hipEventRecord(h->ctx->ev1, s));
@@ -890,12 +895,15 @@ __global__ void __launch_bounds__(kSellC)
       if (val32) tf[kk][rr] = in ? val32[brr + k] : 0.0f;
     }
     __syncthreads();
-    for (int kk = 0; kk < kSellTile && k0 + kk < w; ++kk) {  // w and kSellTile are multiples of 4
-      const int64_t k = k0 + kk;
-      const int64_t d = e0 + (k / 4) * (4 * kSellC) + 4 * t + (k % 4);
-      scol[d] = tc[kk][t];
-      if (sval) sval[d] = tv[kk][t];
-      if (sval32) sval32[d] = tf[kk][t];
+    for (int kk = 0; kk < kSellTile && k0 + kk < w; kk += 4) {  // w and kSellTile are multiples of 4
+      const int64_t d = e0 + ((k0 + kk) / 4) * (4 * kSellC) + 4 * t;  // the slot's four entries, one store each
+      *reinterpret_cast<int4*>(scol + d) = make_int4(tc[kk][t], tc[kk + 1][t], tc[kk + 2][t], tc[kk + 3][t]);
+      if (sval) {
+        *reinterpret_cast<double2*>(sval + d) = make_double2(tv[kk][t], tv[kk + 1][t]);
+        *reinterpret_cast<double2*>(sval + d + 2) = make_double2(tv[kk + 2][t], tv[kk + 3][t]);
+      }
+      if (sval32)
+        *reinterpret_cast<float4*>(sval32 + d) = make_float4(tf[kk][t], tf[kk + 1][t], tf[kk + 2][t], tf[kk + 3][t]);
     }
     __syncthreads();
   }

@@ -113,6 +113,10 @@ struct Csr {
   int32_t* col = nullptr;     // [nnz]
   double* val = nullptr;      // [nnz] FP64 values (optional)
   float* val32 = nullptr;     // [nnz] FP32 values (optional)
+  // [nnz] FP32 remainders v - (double)(float)v, stored with FP32 values when
+  // FP64 values are not: (double)val32 + (double)val32lo reproduces v to
+  // about 2^-48 relative, for the FP64 residual of an FP32-only hierarchy
+  float* val32lo = nullptr;
 };
 
 }  // namespace mskm

@@ -10,20 +10,29 @@
 
 namespace mskm {
 
+// Lane `lane`'s value of v (a wave-uniform lane), for every lane.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int64_t u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffff), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
 // One 64-thread workgroup per block: the dense m x m principal submatrix of
 // the block's rows, gathered from the diagonal CSR rows (the block's rows are
 // consecutive, so their entries form one contiguous run that the wave reads
 // coalesced; each entry finds its row among the block's m + 1 row pointers),
 // inverted in place by Gauss-Jordan elimination without pivoting (the block
-// is SPD), in FP64, then symmetrized and stored. A non-positive or
-// non-finite pivot (a block too ill-conditioned for this) stores the
-// identity: that block is then left unpreconditioned.
+// is SPD), in FP64, then symmetrized and stored. Lane t keeps column t in
+// registers during the elimination; the pivot row is each lane's own entry
+// and the pivot column is read lane by lane. A non-positive or non-finite
+// pivot (a block too ill-conditioned for this) stores the identity: that
+// block is then left unpreconditioned.
 __global__ void __launch_bounds__(kWave)
     k_bj_invert(const int64_t* __restrict__ start, const int64_t* __restrict__ off, const int64_t* __restrict__ rp,
                 const int32_t* __restrict__ col, const double* __restrict__ val, const float* __restrict__ val32,
                 double* __restrict__ inv, float* __restrict__ inv32) {
   __shared__ double M[kBjMax][kBjMax + 1];
-  __shared__ double F[kBjMax];
   __shared__ int64_t rps[kBjMax + 1];
   const int64_t b = blockIdx.x;
   const int64_t a = start[b];
@@ -60,21 +69,30 @@ __global__ void __launch_bounds__(kWave)
       }
   }
   __syncthreads();
+  double cc[kBjMax];  // column t
+#pragma unroll
+  for (int i = 0; i < kBjMax; ++i) cc[i] = M[i][t < kBjMax ? t : 0];
   bool bad = false;
-  for (int k = 0; k < m; ++k) {
-    const double piv = M[k][k];
-    bad = bad || !(piv > 0.0) || !isfinite(piv);
-    double rk = 0.0;
-    if (t < m) {
-      rk = (t == k ? 1.0 : M[k][t]) / piv;
-      F[t] = t == k ? 0.0 : M[t][k];
+#pragma unroll
+  for (int k = 0; k < kBjMax; ++k) {
+    if (k < m) {
+      const double piv = readlane_d(cc[k], k);
+      bad = bad || !(piv > 0.0) || !isfinite(piv);
+      const double rk = (t == k ? 1.0 : cc[k]) / piv;  // row k of the new matrix, entry t
+#pragma unroll
+      for (int i = 0; i < kBjMax; ++i)
+        if (i < m) {
+          const double fi = readlane_d(cc[i], k);  // entry i of the pivot column
+          cc[i] = i == k ? rk : (t == k ? 0.0 : cc[i]) - fi * rk;
+        }
     }
-    __syncthreads();
-    if (t < m) {
-      for (int i = 0; i < m; ++i) M[i][t] = i == k ? rk : (t == k ? 0.0 : M[i][t]) - F[i] * rk;
-    }
-    __syncthreads();
   }
+  __syncthreads();
+  if (t < m)
+#pragma unroll
+    for (int i = 0; i < kBjMax; ++i)
+      if (i < m) M[i][t] = cc[i];
+  __syncthreads();
   const int64_t o = off[b];
   for (int q = t; q < m * m; q += kWave) {
     const int i = q / m, j = q - i * m;

@@ -1452,15 +1452,36 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Same with FP64 values recomputed from the point records (when only FP32
-// values are stored): v = phi(sqrt(d2) * (1/delta_j)) over the stored
-// structure, 16-byte column loads.
-template <int DIM>
+// Same with split values (FP32-only hierarchies): v = (double)hi + (double)lo,
+// the FP32 value and its stored FP32 remainder. Each lane reads four
+// consecutive entries per (non-temporal, 16-byte) load from the row start
+// rounded down to a multiple of 4, entries outside the row masked; the arrays
+// carry a tail pad of kCsrPad entries.
+__device__ __forceinline__ double split_row_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                const float* __restrict__ hi, const float* __restrict__ lo,
+                                                const double* __restrict__ x, int64_t row, int gl) {
+  constexpr int G = 16;
+  const int64_t s = rp[row], e = rp[row + 1];
+  double acc = 0.0;
+  for (int64_t k = (s & ~(int64_t)3) + (int64_t)gl * 4; k < e; k += (int64_t)G * 4) {
+    const sf4 h = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(hi + k));
+    const sf4 l = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(lo + k));
+    const si4 c = __builtin_nontemporal_load(reinterpret_cast<const si4*>(col + k));
+    const float hv[4] = {h.x, h.y, h.z, h.w}, lv[4] = {l.x, l.y, l.z, l.w};
+    const int32_t cv[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k + u >= s && k + u < e) acc += ((double)hv[u] + (double)lv[u]) * x[cv[u]];
+  }
+  return group_sum<G>(acc);
+}
+
 __global__ void __launch_bounds__(kBlock)
-    k_residual_rec(const WorkTable wt, const double4* __restrict__ rec, const int64_t* __restrict__ drp,
-                   const int32_t* __restrict__ dc, const int64_t* __restrict__ lrp, const int32_t* __restrict__ lc,
-                   const double* __restrict__ a, const double* __restrict__ f, double* __restrict__ part,
-                   double* __restrict__ rout) {
+    k_residual_split(const WorkTable wt, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
+                     const float* __restrict__ dh, const float* __restrict__ dl, const int64_t* __restrict__ lrp,
+                     const int32_t* __restrict__ lc, const float* __restrict__ lh, const float* __restrict__ ll,
+                     const double* __restrict__ a, const double* __restrict__ f, double* __restrict__ part,
+                     double* __restrict__ rout) {
   constexpr int G = 16;
   __shared__ double sm[kBlock / kWave];
   const int blk = xcd_block_id(gridDim.x);
@@ -1468,9 +1489,8 @@ __global__ void __launch_bounds__(kBlock)
   const int gl = threadIdx.x % G;
   double srr = 0.0, sff = 0.0;
   for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
-    const double4 me = rec[i];
-    double acc = rec_row_dot<G, DIM, double, double>(drp, dc, rec, a, i, gl, me);
-    acc += rec_row_dot<G, DIM, double, double>(lrp, lc, rec, a, i, gl, me);
+    double acc = split_row_dot(drp, dc, dh, dl, a, i, gl);
+    acc += split_row_dot(lrp, lc, lh, ll, a, i, gl);
     if (gl == 0) {
       const double ri = f[i] - acc;
       if (rout) rout[i] = ri;
@@ -1508,7 +1528,8 @@ __global__ void __launch_bounds__(kBlock)
 
 // ||f - T a|| / ||f|| per group (rel_groups, host [ngroups]) and the maximum
 // over groups (*rel), internal order device vectors. rout (nullable)
-// receives r. FP64 values are used when stored, else recomputed.
+// receives r. FP64 values are used when stored, else the split FP32 values
+// (an FP32-only hierarchy stores the remainders).
 static mskm_status residual_internal(mskm_hier* h, const double* a, const double* f, double* rel, double* rout,
                                      double* rel_groups = nullptr, bool a_zero = false) {
   hipStream_t s = h->ctx->stream;
@@ -1520,14 +1541,10 @@ static mskm_status residual_internal(mskm_hier* h, const double* a, const double
   } else if (h->diag.val && h->lower.val) {
     hipLaunchKernelGGL(k_residual64, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->diag.rowptr, h->diag.col,
                        h->diag.val, h->lower.rowptr, h->lower.col, h->lower.val, a, f, part, rout);
-  } else {
-    const double4* r4 = reinterpret_cast<const double4*>(h->prec);
-    if (h->dim == 3)
-      hipLaunchKernelGGL(k_residual_rec<3>, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, r4, h->diag.rowptr, h->diag.col,
-                         h->lower.rowptr, h->lower.col, a, f, part, rout);
-    else
-      hipLaunchKernelGGL(k_residual_rec<2>, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, r4, h->diag.rowptr, h->diag.col,
-                         h->lower.rowptr, h->lower.col, a, f, part, rout);
+  } else {  // FP32 values and their remainders
+    hipLaunchKernelGGL(k_residual_split, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->diag.rowptr, h->diag.col,
+                       h->diag.val32, h->diag.val32lo, h->lower.rowptr, h->lower.col, h->lower.val32,
+                       h->lower.val32lo, a, f, part, rout);
   }
   std::vector<double> hp(2 * (size_t)wt.nblocks);
   hipError_t e = hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, s);

@@ -386,37 +386,32 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // FP64 residual per rhs over the level-aligned SpMV table: partials
-// rr[blk][r], ff[blk][r]. Values: stored FP64, or recomputed from coordinates.
+// rr[blk][r], ff[blk][r]. Values: stored FP64, else the split FP32 values
+// (hi + remainder; an FP32-only hierarchy stores the remainders).
 __global__ void __launch_bounds__(kBlock)
-    k_mr_residual(const WorkTable wt, int dim, const DevLevel* __restrict__ lev, const double* __restrict__ xs,
-                  int64_t N, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
+    k_mr_residual(const WorkTable wt, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
                   const double* __restrict__ dv, const int64_t* __restrict__ lrp, const int32_t* __restrict__ lc,
-                  const double* __restrict__ lv, const double* __restrict__ a, const double* __restrict__ f,
-                  double* __restrict__ rout, double* __restrict__ rrp, double* __restrict__ ffp, MrCfg c) {
+                  const double* __restrict__ lv, const float* __restrict__ dh, const float* __restrict__ dl,
+                  const float* __restrict__ lh, const float* __restrict__ ll, const double* __restrict__ a,
+                  const double* __restrict__ f, double* __restrict__ rout, double* __restrict__ rrp,
+                  double* __restrict__ ffp, MrCfg c) {
   __shared__ double sm[kMrLds];
   const int blk = xcd_block_id(gridDim.x);
-  const int l = wt.lev[blk];
   const int gl = threadIdx.x % c.LR;
   double prr[kMaxRPerLane], pff[kMaxRPerLane];
   for (int m = 0; m < kMaxRPerLane; ++m) prr[m] = pff[m] = 0.0;
   for (int64_t i = wt.row0[blk] + threadIdx.x / c.LR; i < wt.row1[blk]; i += kBlock / c.LR) {
     double acc[kMaxRPerLane];
     for (int m = 0; m < kMaxRPerLane; ++m) acc[m] = 0.0;
-    const double px = xs[i], py = xs[N + i], pz = dim == 3 ? xs[2 * N + i] : 0.0;
     for (int pass = 0; pass < 2; ++pass) {
       const int64_t* rp = pass == 0 ? drp : lrp;
       const int32_t* col = pass == 0 ? dc : lc;
       const double* val = pass == 0 ? dv : lv;
-      int j = pass == 0 ? l : lev[l].first;
+      const float* vh = pass == 0 ? dh : lh;
+      const float* vl = pass == 0 ? dl : ll;
       for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
         const int64_t cc = col[k];
-        double v;
-        if (val) {
-          v = val[k];
-        } else {
-          while (cc >= lev[j].off + lev[j].n && lev[j].next >= 0) j = lev[j].next;
-          v = phi31_d2(sqdist(dim, px, py, pz, xs[cc], xs[N + cc], dim == 3 ? xs[2 * N + cc] : 0.0), lev[j].delta);
-        }
+        const double v = val ? val[k] : (double)vh[k] + (double)vl[k];
         const double* ar = a + cc * c.R;
         for (int m = 0; m < c.RM; ++m) {
           const int r = gl + m * c.LR;
@@ -651,9 +646,9 @@ mskm_status mr_residual(mskm_hier* h, MrWS& W, const double* a, const double* f,
   if (a_zero)
     hipLaunchKernelGGL(k_mr_residual_zero, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, f, rout, W.part_s, W.part_v2, c);
   else
-    hipLaunchKernelGGL(k_mr_residual, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->dim, h->d_lev, h->xs, h->N,
-                       h->diag.rowptr, h->diag.col, h->diag.val, h->lower.rowptr, h->lower.col, h->lower.val, a, f,
-                       rout, W.part_s, W.part_v2, c);
+    hipLaunchKernelGGL(k_mr_residual, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->diag.rowptr, h->diag.col, h->diag.val, h->lower.rowptr, h->lower.col, h->lower.val,
+                       h->diag.val32, h->diag.val32lo, h->lower.val32, h->lower.val32lo, a, f, rout, W.part_s,
+                       W.part_v2, c);
   std::vector<double> prr((size_t)wt.nblocks * c.R), pff((size_t)wt.nblocks * c.R);
   MSKM_HIP_TRY(hipMemcpyAsync(prr.data(), W.part_s, prr.size() * 8, hipMemcpyDeviceToHost, s));
   MSKM_HIP_TRY(hipMemcpyAsync(pff.data(), W.part_v2, pff.size() * 8, hipMemcpyDeviceToHost, s));

@@ -153,3 +153,30 @@ def test_batch_and_multi_rhs_together(env):
         assert rels.shape == (R * len(hs),) and rels.max() < 1e-12
     finally:
         m.mskm_hier_destroy(hd)
+
+
+@pytest.mark.parametrize("name,R", [("halton5", 3), ("uniform3d3", 70)])
+def test_multi_rhs_fp32_only_hierarchy(env, name, R):
+    """A hierarchy that stores only FP32 values (and their FP32 remainders,
+    which its FP64 residuals use): mixed many-right-hand-side solves still
+    reach the oracle's coefficients, and the residuals match the oracle's."""
+    m, ctx, get = env
+    h, blk, _ = get(name)
+    hd = m.mskm_hier_create(ctx, h.points, h.offsets, h.delta, fp64=False, fp32=True)
+    try:
+        F = _targets(h, R, 3400)
+        A = np.zeros_like(F)
+        o = m.solve_opts(precision=m.MSKM_PREC_FP32, algorithm=m.MSKM_ALG_SEQUENTIAL, cg_rtol=1e-5,
+                         target_rel_residual=1e-13, max_refine=20, precond=m.MSKM_PRECOND_BLOCK_JACOBI)
+        res = m.mskm_solve(ctx, hd, F, A, o, nrhs=R)
+        assert res.status == m.MSKM_OK, res.report
+        rels = m.mskm_residual(ctx, hd, A, F, nrhs=R)
+        for r in (0, R - 1):
+            ref = oracle.sequential_solve(blk, F[:, r])
+            for l in range(h.levels):
+                sl = slice(h.offsets[l], h.offsets[l + 1])
+                err = np.linalg.norm(A[sl, r] - ref[sl]) / np.linalg.norm(ref[sl])
+                assert err <= 1e-8, (r, l, err)
+            assert rels[r] == pytest.approx(oracle.residual(blk, A[:, r], F[:, r])[0], rel=1e-6, abs=1e-15)
+    finally:
+        m.mskm_hier_destroy(hd)

@@ -279,9 +279,9 @@ def test_several_rhs_reject_learned_warm_start(mod, ctx):
 
 @pytest.mark.parametrize("name", ["grid4", "halton5", "uniform3d3"])
 def test_fp32_only_hierarchy(mod, ctx, name):
-    """A hierarchy that stores only FP32 values: its FP64 residual recomputes
-    the entries from the points, and the mixed solve still reaches the
-    oracle's coefficients."""
+    """A hierarchy that stores only FP32 values: its FP64 residual takes each
+    entry as the FP32 value plus its stored FP32 remainder, and the mixed
+    solve still reaches the oracle's coefficients."""
     h, f, blk, _, a_ref = _setup(mod, ctx, name)
     hd = mod.mskm_hier_create(ctx, h.points, h.offsets, h.delta, fp64=False, fp32=True)
     try:
