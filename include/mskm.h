@@ -76,7 +76,9 @@ enum { MSKM_WENDLAND_3_1 = 31 };
 enum {
   MSKM_POINTS_ON_DEVICE = 1 << 0, /* points is a device pointer */
   MSKM_STORE_FP64 = 1 << 1,       /* keep FP64 block values (plain path) */
-  MSKM_STORE_FP32 = 1 << 2        /* keep FP32 block values (mixed path) */
+  MSKM_STORE_FP32 = 1 << 2        /* keep FP32 block values (mixed path); without
+                                     STORE_FP64 also each value's FP32 rounding
+                                     remainder, which the FP64 residual adds back */
 };
 
 /* flags of calls taking vectors */
