@@ -1456,11 +1456,12 @@ __global__ void __launch_bounds__(kBlock)
 // the FP32 value and its stored FP32 remainder. Each lane reads four
 // consecutive entries per (non-temporal, 16-byte) load from the row start
 // rounded down to a multiple of 4, entries outside the row masked; the arrays
-// carry a tail pad of kCsrPad entries.
-__device__ __forceinline__ double split_row_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                const float* __restrict__ hi, const float* __restrict__ lo,
-                                                const double* __restrict__ x, int64_t row, int gl) {
-  constexpr int G = 16;
+// carry a tail pad of kCsrPad entries. Lane gl's share of the row's dot (the
+// caller sums over the G lanes).
+template <int G>
+__device__ __forceinline__ double split_row_part(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                 const float* __restrict__ hi, const float* __restrict__ lo,
+                                                 const double* __restrict__ x, int64_t row, int gl) {
   const int64_t s = rp[row], e = rp[row + 1];
   double acc = 0.0;
   for (int64_t k = (s & ~(int64_t)3) + (int64_t)gl * 4; k < e; k += (int64_t)G * 4) {
@@ -1473,8 +1474,10 @@ __device__ __forceinline__ double split_row_dot(const int64_t* __restrict__ rp, 
     for (int u = 0; u < 4; ++u)
       if (k + u >= s && k + u < e) acc += ((double)hv[u] + (double)lv[u]) * x[cv[u]];
   }
-  return group_sum<G>(acc);
+  return acc;
 }
+
+constexpr int kSplitG = 16;  // lanes per row of the split-value residual
 
 __global__ void __launch_bounds__(kBlock)
     k_residual_split(const WorkTable wt, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
@@ -1482,15 +1485,15 @@ __global__ void __launch_bounds__(kBlock)
                      const int32_t* __restrict__ lc, const float* __restrict__ lh, const float* __restrict__ ll,
                      const double* __restrict__ a, const double* __restrict__ f, double* __restrict__ part,
                      double* __restrict__ rout) {
-  constexpr int G = 16;
+  constexpr int G = kSplitG;
   __shared__ double sm[kBlock / kWave];
   const int blk = xcd_block_id(gridDim.x);
   const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
   const int gl = threadIdx.x % G;
   double srr = 0.0, sff = 0.0;
   for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
-    double acc = split_row_dot(drp, dc, dh, dl, a, i, gl);
-    acc += split_row_dot(lrp, lc, lh, ll, a, i, gl);
+    double acc = split_row_part<G>(lrp, lc, lh, ll, a, i, gl) + split_row_part<G>(drp, dc, dh, dl, a, i, gl);
+    acc = group_sum<G>(acc);
     if (gl == 0) {
       const double ri = f[i] - acc;
       if (rout) rout[i] = ri;

@@ -65,22 +65,41 @@ def test_sampled_rows_bit_exact(setup, k):
         np.testing.assert_allclose(val, oval, rtol=1e-15, atol=0)
 
 
-@pytest.mark.parametrize("form", ["plain_fp64", "mixed_sequential"])
+@pytest.mark.parametrize("form", ["plain_fp64", "mixed_sequential", "fast_form"])
 def test_full_solve(setup, form):
+    """fast_form: the timed configuration of the benchmark (a hierarchy that
+    stores FP32 values and their remainders only, 16-bit sliced products,
+    block-Jacobi preconditioned sequential mixed solve, one workgroup per
+    small level), run to a tighter target so that the coefficients can be
+    compared with the oracle's."""
     m, ctx, h, f, hd, hp, a_prefix = setup
     alpha = np.zeros_like(f)
+    hs = hd
     if form == "plain_fp64":
         o = m.solve_opts(cg_rtol=1e-13, max_cg_iters=20000)
         bar = 1e-10
-    else:
+    elif form == "mixed_sequential":
         o = m.solve_opts(precision=m.MSKM_PREC_FP32, algorithm=m.MSKM_ALG_SEQUENTIAL, cg_rtol=1e-4,
                          target_rel_residual=1e-12, max_refine=12)
         bar = 1e-8
+    else:
+        hs = m.mskm_hier_create(ctx, h.points, h.offsets, h.delta, fp64=False, fp32=True)
+        assert m.mskm_hier_stats_get(hs)["sell_col16"] == 1
+        o = m.solve_opts(precision=m.MSKM_PREC_FP32, algorithm=m.MSKM_ALG_SEQUENTIAL, cg_rtol=1e-4,
+                         target_rel_residual=1e-12, max_refine=12, precond=m.MSKM_PRECOND_BLOCK_JACOBI)
+        bar = 1e-8
     print(f"[fullsize] solve {form}", flush=True)
-    res = m.mskm_solve(ctx, hd, f, alpha, o)
-    assert res.status == m.MSKM_OK, res.report
-    rel = m.mskm_residual(ctx, hd, alpha, f)[0]
+    try:
+        res = m.mskm_solve(ctx, hs, f, alpha, o)
+        assert res.status == m.MSKM_OK, res.report
+        rel = m.mskm_residual(ctx, hs, alpha, f)[0]
+    finally:
+        if hs is not hd:
+            m.mskm_hier_destroy(hs)
     assert rel <= 1e-8
+    # the residual of the FP32-only hierarchy (FP32 values + remainders) against the FP64 one
+    rel64 = m.mskm_residual(ctx, hd, alpha, f)[0]
+    assert rel64 <= 1e-8 and abs(rel64 - rel) <= 1e-11, (rel64, rel)
     # levels 0..PREFIX-1 against the oracle's exact prefix solve
     for l in range(PREFIX):
         sl = slice(hp.offsets[l], hp.offsets[l + 1])
