@@ -70,6 +70,10 @@ mskm_status mskm_destroy(mskm_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   (void)hipEventDestroy(c->ev0);
   (void)hipEventDestroy(c->ev1);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return MSKM_OK;
@@ -201,6 +205,11 @@ mskm_status mskm_hier_destroy(mskm_hier* h) {
     (void)hipSetDevice(h->ctx->device);
     (void)hipStreamSynchronize(h->ctx->stream);
   }
+  for (hipEvent_t e : {h->bj.ev_tables, h->bj.ev_side})
+    if (e) {
+      (void)hipEventSynchronize(e);
+      (void)hipEventDestroy(e);
+    }
   if (h->solve_ws_free) h->solve_ws_free(h->solve_ws);
   for (void* p : h->allocs) (void)hipFree(p);
   delete h;

@@ -105,6 +105,13 @@ struct BlockJacobi {
   double* inv = nullptr;      // [nvals] FP64 inverses
   float* inv32 = nullptr;     // [nvals] FP32 copies
   WorkTable wt;               // per-level workgroups of whole blocks (<= kBjGroupRows rows)
+  // the inverses of the finest depth (levels >= side_level0) are formed on
+  // the context's side stream, after the coarser ones on the main stream;
+  // ev_side marks their end and the main stream waits for it before their
+  // first use (side_pending), so the coarse levels' solves overlap them
+  int side_level0 = INT32_MAX;
+  bool side_pending = false;
+  hipEvent_t ev_tables = nullptr, ev_side = nullptr;
 };
 
 struct Csr {
@@ -136,9 +143,10 @@ struct mskm_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  // pinned host scratch for small readbacks
-  void* pinned = nullptr;
-  size_t pinned_bytes = 0;
+  // second stream (default priority), created at first use: block-Jacobi
+  // inverses of a hierarchy's finest levels are formed there while the main
+  // stream solves the coarse levels
+  hipStream_t side = nullptr;
 };
 
 // Learned warm start network (learned.hip).
@@ -242,6 +250,9 @@ mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, i
 mskm_status build_work_table(mskm_hier* h, WorkTable* wt, int min_rows, int max_blocks_per_level);
 // precond.hip
 mskm_status build_block_jacobi(mskm_hier* h);
+// Orders the main stream after the inverses of levels up to `hi` (a no-op
+// once they are known to be formed).
+mskm_status bj_wait(mskm_hier* h, int hi);
 template <typename TX>
 void launch_bj_apply(mskm_hier* h, int lo, int hi, const TX* r, TX* u);
 

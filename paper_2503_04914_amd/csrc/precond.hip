@@ -29,12 +29,12 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // pivot (a block too ill-conditioned for this) stores the identity: that
 // block is then left unpreconditioned.
 __global__ void __launch_bounds__(kWave)
-    k_bj_invert(const int64_t* __restrict__ start, const int64_t* __restrict__ off, const int64_t* __restrict__ rp,
-                const int32_t* __restrict__ col, const double* __restrict__ val, const float* __restrict__ val32,
-                double* __restrict__ inv, float* __restrict__ inv32) {
+    k_bj_invert(int64_t b0, const int64_t* __restrict__ start, const int64_t* __restrict__ off,
+                const int64_t* __restrict__ rp, const int32_t* __restrict__ col, const double* __restrict__ val,
+                const float* __restrict__ val32, double* __restrict__ inv, float* __restrict__ inv32) {
   __shared__ double M[kBjMax][kBjMax + 1];
   __shared__ int64_t rps[kBjMax + 1];
-  const int64_t b = blockIdx.x;
+  const int64_t b = b0 + blockIdx.x;
   const int64_t a = start[b];
   const int m = (int)(start[b + 1] - a);
   const int t = threadIdx.x;
@@ -221,7 +221,11 @@ mskm_status build_block_jacobi(mskm_hier* h) {
   if (st == MSKM_OK) st = halloc(h, &B.start, (size_t)nb_max + 1);
   if (st == MSKM_OK) st = halloc(h, &B.off, (size_t)nb_max + 1);
   if (st == MSKM_OK) st = halloc(h, &B.of_row, (size_t)h->N);
-  int64_t counts[2] = {0, 0};
+  // the finest depth's blocks are inverted on the side stream (when there are
+  // coarser levels); blocks are numbered level by level, levels depth by depth
+  const int D = (int)h->h_depth_begin.size() - 1;
+  const int side0 = D >= 2 ? h->h_depth_begin[D - 1] : INT32_MAX;
+  int64_t counts[3] = {0, 0, 0};
   if (st == MSKM_OK) {
     const unsigned gs = (unsigned)((nslots + kBlock) / kBlock);
     hipLaunchKernelGGL(k_bj_cell_chunks, dim3(gs), dim3(kBlock), 0, s, h->cell_start, nslots, nch);
@@ -234,6 +238,8 @@ mskm_status build_block_jacobi(mskm_hier* h) {
     if (st == MSKM_OK) st = exclusive_scan_i64(s, msq, B.off, nb_max + 1);
     if (st == MSKM_OK && (hipMemcpyAsync(&counts[0], bbase + nslots, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
                           hipMemcpyAsync(&counts[1], B.off + nb_max, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                          (side0 < L && hipMemcpyAsync(&counts[2], bbase + h->h_lev[side0].cs_off, 8,
+                                                       hipMemcpyDeviceToHost, s) != hipSuccess) ||
                           hipStreamSynchronize(s) != hipSuccess))
       st = fail(MSKM_EDEVICE, "block-Jacobi counts");
   }
@@ -246,9 +252,24 @@ mskm_status build_block_jacobi(mskm_hier* h) {
   if (B.nblocks > (int64_t)INT32_MAX) return fail(MSKM_ELIMIT, "block-Jacobi tables too large");
   if (h->diag.val) MSKM_TRY(halloc(h, &B.inv, (size_t)B.nvals));
   if (h->diag.val32) MSKM_TRY(halloc(h, &B.inv32, (size_t)B.nvals));
-  if (B.nblocks > 0)
-    hipLaunchKernelGGL(k_bj_invert, dim3((unsigned)B.nblocks), dim3(kWave), 0, s, B.start, B.off, h->diag.rowptr,
-                       h->diag.col, h->diag.val, h->diag.val32, B.inv, B.inv32);
+  // blocks [0, nb_main) on the main stream, then [nb_main, nblocks) (the
+  // finest depth's levels) on the side stream
+  const int64_t nb_main = side0 < L ? counts[2] : B.nblocks;
+  if (nb_main > 0)
+    hipLaunchKernelGGL(k_bj_invert, dim3((unsigned)nb_main), dim3(kWave), 0, s, (int64_t)0, B.start, B.off,
+                       h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, B.inv, B.inv32);
+  if (nb_main < B.nblocks) {
+    if (!h->ctx->side) MSKM_HIP_TRY(hipStreamCreateWithFlags(&h->ctx->side, hipStreamNonBlocking));
+    MSKM_HIP_TRY(hipEventCreateWithFlags(&B.ev_tables, hipEventDisableTiming));
+    MSKM_HIP_TRY(hipEventCreateWithFlags(&B.ev_side, hipEventDisableTiming));
+    MSKM_HIP_TRY(hipEventRecord(B.ev_tables, s));
+    MSKM_HIP_TRY(hipStreamWaitEvent(h->ctx->side, B.ev_tables, 0));
+    hipLaunchKernelGGL(k_bj_invert, dim3((unsigned)(B.nblocks - nb_main)), dim3(kWave), 0, h->ctx->side, nb_main,
+                       B.start, B.off, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, B.inv, B.inv32);
+    MSKM_HIP_TRY(hipEventRecord(B.ev_side, h->ctx->side));
+    B.side_level0 = side0;
+    B.side_pending = true;
+  }
   // workgroups of whole blocks: one per window of kBjGroupStep rows, a last
   // window shorter than kBjMax merged into the one before
   WorkTable& wt = B.wt;
@@ -276,6 +297,14 @@ mskm_status build_block_jacobi(mskm_hier* h) {
                        B.nblocks, B.start, h->d_lev, L, wt.lev_begin, wt.lev, wt.row0, wt.row1);
   MSKM_HIP_TRY(hipGetLastError());
   B.built = true;
+  return MSKM_OK;
+}
+
+mskm_status bj_wait(mskm_hier* h, int hi) {
+  BlockJacobi& B = h->bj;
+  if (!B.side_pending || hi < B.side_level0) return MSKM_OK;
+  MSKM_HIP_TRY(hipStreamWaitEvent(h->ctx->stream, B.ev_side, 0));
+  B.side_pending = false;
   return MSKM_OK;
 }
 

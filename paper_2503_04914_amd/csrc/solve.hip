@@ -966,7 +966,9 @@ struct SolveWS {
   };
   std::vector<Graph> graphs;
   void* arena = nullptr;     // every device buffer above, carved from one allocation
-  CgLevel* pinned = nullptr; // h_st, the two h_chk copies and h_defer, one pinned allocation
+  double* part_res = nullptr;    // residual partials (r.r, f.f per block of the SpMV table)
+  double* h_part_res = nullptr;  // pinned copy of them
+  void* pinned = nullptr;  // h_st, the two h_chk copies, h_defer and h_part_res, one pinned allocation
   ~SolveWS() {
     if (pending) (void)hipEventSynchronize(pending);
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
@@ -1005,6 +1007,7 @@ static mskm_status get_ws(mskm_hier* h, SolveWS** out) {
     carve(&w->a32, N, base);
     for (double** v : {&w->part_s, &w->part_s2, &w->part_s3}) carve(v, np, base);
     carve(&w->part_v, (size_t)h->wt_vec.nblocks, base);
+    carve(&w->part_res, 2 * (size_t)h->wt_spmv.nblocks, base);
     carve(&w->st, 2 * (size_t)h->L, base);  // two parities (fused single-reduction form)
   };
   layout(nullptr);
@@ -1015,14 +1018,17 @@ static mskm_status get_ws(mskm_hier* h, SolveWS** out) {
     w->arena = base;
     layout(base);
   }
-  if (st == MSKM_OK && hipHostMalloc(reinterpret_cast<void**>(&w->pinned), 4 * h->L * sizeof(CgLevel),
+  const size_t pin_states = 4 * (size_t)h->L * sizeof(CgLevel);  // a multiple of 8 bytes
+  if (st == MSKM_OK && hipHostMalloc(&w->pinned, pin_states + 2 * (size_t)h->wt_spmv.nblocks * sizeof(double),
                                      hipHostMallocDefault) != hipSuccess)
     st = fail(MSKM_ENOMEM, "pinned state allocation");
   if (st == MSKM_OK) {
-    w->h_st = w->pinned;
-    w->h_chk[0] = w->pinned + h->L;
-    w->h_chk[1] = w->pinned + 2 * h->L;
-    w->h_defer = w->pinned + 3 * h->L;
+    CgLevel* ps = static_cast<CgLevel*>(w->pinned);
+    w->h_st = ps;
+    w->h_chk[0] = ps + h->L;
+    w->h_chk[1] = ps + 2 * h->L;
+    w->h_defer = ps + 3 * h->L;
+    w->h_part_res = reinterpret_cast<double*>(static_cast<char*>(w->pinned) + pin_states);
     w->deferred.assign(h->L, 0);
   }
   for (hipEvent_t* e : {&w->ev_chk[0], &w->ev_chk[1], &w->ev_defer})
@@ -1204,6 +1210,7 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
   while (lo < h->L && !on[lo]) ++lo;
   while (hi >= 0 && !on[hi]) --hi;
   if (lo > hi) return MSKM_OK;
+  if (bj) MSKM_TRY(bj_wait(h, hi));  // the finest levels' inverses may still be forming on the side stream
   // form: preconditioned single-reduction when asked; the single-reduction
   // form for the FP32 inner solves; the textbook form otherwise
   const int form = bj ? kCgOneRedBj : sizeof(TX) == 4 ? kCgOneRed : kCgTextbook;
@@ -1533,12 +1540,11 @@ __global__ void __launch_bounds__(kBlock)
 // over groups (*rel), internal order device vectors. rout (nullable)
 // receives r. FP64 values are used when stored, else the split FP32 values
 // (an FP32-only hierarchy stores the remainders).
-static mskm_status residual_internal(mskm_hier* h, const double* a, const double* f, double* rel, double* rout,
-                                     double* rel_groups = nullptr, bool a_zero = false) {
+static mskm_status residual_internal(mskm_hier* h, SolveWS& W, const double* a, const double* f, double* rel,
+                                     double* rout, double* rel_groups = nullptr, bool a_zero = false) {
   hipStream_t s = h->ctx->stream;
   const WorkTable& wt = h->wt_spmv;
-  double* part = nullptr;
-  MSKM_TRY(dalloc(&part, 2 * (size_t)wt.nblocks));
+  double* part = W.part_res;
   if (a_zero) {
     hipLaunchKernelGGL(k_residual_zero, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, f, part, rout);
   } else if (h->diag.val && h->lower.val) {
@@ -1549,10 +1555,9 @@ static mskm_status residual_internal(mskm_hier* h, const double* a, const double
                        h->diag.val32, h->diag.val32lo, h->lower.rowptr, h->lower.col, h->lower.val32,
                        h->lower.val32lo, a, f, part, rout);
   }
-  std::vector<double> hp(2 * (size_t)wt.nblocks);
-  hipError_t e = hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, s);
+  const double* hp = W.h_part_res;
+  hipError_t e = hipMemcpyAsync(W.h_part_res, part, 2 * (size_t)wt.nblocks * 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(part);
   if (e != hipSuccess) return fail(MSKM_EDEVICE, std::string("residual: ") + hipGetErrorString(e));
   std::vector<double> rr(h->ngroups, 0.0), ff(h->ngroups, 0.0);
   for (int l = 0; l < h->L; ++l) {
@@ -1863,7 +1868,7 @@ mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_o
     double rel = 0.0;
     if (!mixed) {
       MSKM_TRY((solve_internal<double, double>(h, W, h->diag.val, h->lower.val, fi, ai, o, &sweeps_done, &cs)));
-      MSKM_TRY(residual_internal(h, ai, fi, &rel, nullptr));
+      MSKM_TRY(residual_internal(h, W, ai, fi, &rel, nullptr));
     } else {
       // FP64 residual refinement around FP32 inner solves (values, vectors and
       // SpMV accumulation in FP32, dots in FP64)
@@ -1871,7 +1876,7 @@ mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_o
       MSKM_HIP_TRY(hipMemsetAsync(ai, 0, N * 8, s));
       refine = 0;
       for (;;) {
-        MSKM_TRY(residual_internal(h, ai, fi, &rel, W.res, nullptr, refine == 0));  // alpha = 0 at the start
+        MSKM_TRY(residual_internal(h, W, ai, fi, &rel, W.res, nullptr, refine == 0));  // alpha = 0 at the start
         if (rel <= o->target_rel_residual || refine >= maxref) break;
         hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(N)), dim3(kBlock), 0, s, (const double*)W.res, W.f32,
                            N);
@@ -1949,18 +1954,17 @@ mskm_status residual(mskm_hier* h, const double* alpha, const double* f, int nrh
   DevBuf A, F;
   MSKM_TRY(stage_in(s, alpha, (size_t)N * nrhs, io_dev, A));
   MSKM_TRY(stage_in(s, f, (size_t)N * nrhs, io_dev, F));
-  double *ai = nullptr, *fi = nullptr;
-  MSKM_TRY(dalloc(&ai, N));
-  MSKM_TRY(dalloc(&fi, N));
+  SolveWS* Wp = nullptr;  // the solver workspace's internal-order vectors and residual partials
+  MSKM_TRY(get_ws(h, &Wp));
+  double* ai = Wp->ai;
+  double* fi = Wp->fi;
   mskm_status st = MSKM_OK;
   for (int r = 0; r < nrhs && st == MSKM_OK; ++r) {
     hipLaunchKernelGGL(k_to_internal<double>, dim3(nblk(N)), dim3(kBlock), 0, s, A.p, h->perm, ai, N, nrhs, r);
     hipLaunchKernelGGL(k_to_internal<double>, dim3(nblk(N)), dim3(kBlock), 0, s, F.p, h->perm, fi, N, nrhs, r);
     double worst = 0.0;
-    st = residual_internal(h, ai, fi, &worst, nullptr, rel_out + (size_t)r * h->ngroups);
+    st = residual_internal(h, *Wp, ai, fi, &worst, nullptr, rel_out + (size_t)r * h->ngroups);
   }
-  (void)hipFree(ai);
-  (void)hipFree(fi);
   return st;
 }
 
@@ -1972,8 +1976,11 @@ mskm_status evaluate(mskm_hier* h, const double* alpha, int nrhs, const double* 
   MSKM_TRY(stage_in(s, alpha, (size_t)N * nrhs, io_dev, A));
   MSKM_TRY(stage_in(s, query, (size_t)nq * h->dim, io_dev, Q));
   MSKM_TRY(stage_out_alloc(out, (size_t)nq * nrhs, io_dev, O));
-  double* ai = nullptr;
-  MSKM_TRY(dalloc(&ai, N));
+  // internal-order coefficients: the solver workspace's vector when one exists
+  // (no allocation, no implicit device synchronisation), else a scratch vector
+  double* ai = h->solve_ws ? static_cast<SolveWS*>(h->solve_ws)->ai : nullptr;
+  const bool own = ai == nullptr;
+  if (own) MSKM_TRY(dalloc(&ai, N));
   for (int r = 0; r < nrhs; ++r) {
     hipLaunchKernelGGL(k_to_internal<double>, dim3(nblk(N)), dim3(kBlock), 0, s, A.p, h->perm, ai, N, nrhs, r);
     if (nq > 0)
@@ -1981,7 +1988,7 @@ mskm_status evaluate(mskm_hier* h, const double* alpha, int nrhs, const double* 
                          h->cell_start, h->xs, N, ai, Q.p, nq, O.p, nrhs, r);
   }
   mskm_status st = stage_out_copy(s, out, (size_t)nq * nrhs, io_dev, O);
-  (void)hipFree(ai);
+  if (own) (void)hipFree(ai);
   MSKM_HIP_TRY(hipGetLastError());
   return st;
 }

@@ -686,7 +686,10 @@ mskm_status solve_multi(mskm_hier* h, const double* f_in, int nrhs, const mskm_s
   if (mixed) MSKM_TRY(dalloc(&W.res, NR));
   const size_t xs = mixed ? 4 : 8;
   W.pc = o->precond == MSKM_PRECOND_BLOCK_JACOBI;
-  if (W.pc) MSKM_TRY(build_block_jacobi(h));
+  if (W.pc) {
+    MSKM_TRY(build_block_jacobi(h));
+    MSKM_TRY(bj_wait(h, h->L - 1));
+  }
   for (void** v : {&W.beta, &W.t, &W.r, &W.p, &W.q}) MSKM_TRY(dalloc(reinterpret_cast<char**>(v), NR * xs));
   if (W.pc) MSKM_TRY(dalloc(reinterpret_cast<char**>(&W.z), NR * xs));
   if (mixed) {
