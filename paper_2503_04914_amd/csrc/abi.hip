@@ -55,10 +55,13 @@ mskm_status mskm_create(int32_t device, void* hip_stream, mskm_ctx** out) {
     }
     c->own_stream = true;
   }
-  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
-    return fail(MSKM_EDEVICE, "hipEventCreate failed");
+    return fail(MSKM_EDEVICE, "hipEventCreate / hipStreamCreate failed");
   }
   *out = c;
   return MSKM_OK;

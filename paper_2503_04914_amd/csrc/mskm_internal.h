@@ -105,12 +105,15 @@ struct BlockJacobi {
   double* inv = nullptr;      // [nvals] FP64 inverses
   float* inv32 = nullptr;     // [nvals] FP32 copies
   WorkTable wt;               // per-level workgroups of whole blocks (<= kBjGroupRows rows)
-  // the inverses of the finest depth (levels >= side_level0) are formed on
-  // the context's side stream, after the coarser ones on the main stream;
-  // ev_side marks their end and the main stream waits for it before their
-  // first use (side_pending), so the coarse levels' solves overlap them
+  // the inverses of the finest depth (blocks from side_b0, levels >=
+  // side_level0) are formed on the context's side stream, started once the
+  // solve reaches its first chunked (many-workgroup) level, so that they
+  // overlap the latency-bound middle levels rather than the one-workgroup
+  // ones; ev_side marks their end and the main stream waits for it before
+  // their first use (side_pending)
   int side_level0 = INT32_MAX;
-  bool side_pending = false;
+  int64_t side_b0 = 0;
+  bool side_pending = false, side_started = false;
   hipEvent_t ev_tables = nullptr, ev_side = nullptr;
 };
 
@@ -143,9 +146,9 @@ struct mskm_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  // second stream (default priority), created at first use: block-Jacobi
-  // inverses of a hierarchy's finest levels are formed there while the main
-  // stream solves the coarse levels
+  // second stream (default priority): block-Jacobi inverses of a
+  // hierarchy's finest levels are formed there while the main stream solves
+  // the coarser levels
   hipStream_t side = nullptr;
 };
 
@@ -253,6 +256,8 @@ mskm_status build_block_jacobi(mskm_hier* h);
 // Orders the main stream after the inverses of levels up to `hi` (a no-op
 // once they are known to be formed).
 mskm_status bj_wait(mskm_hier* h, int hi);
+// Starts the side-stream inversion of the finest depth's blocks (once).
+mskm_status bj_start_side(mskm_hier* h);
 template <typename TX>
 void launch_bj_apply(mskm_hier* h, int lo, int hi, const TX* r, TX* u);
 

@@ -258,17 +258,11 @@ mskm_status build_block_jacobi(mskm_hier* h) {
   if (nb_main > 0)
     hipLaunchKernelGGL(k_bj_invert, dim3((unsigned)nb_main), dim3(kWave), 0, s, (int64_t)0, B.start, B.off,
                        h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, B.inv, B.inv32);
-  if (nb_main < B.nblocks) {
-    if (!h->ctx->side) MSKM_HIP_TRY(hipStreamCreateWithFlags(&h->ctx->side, hipStreamNonBlocking));
-    MSKM_HIP_TRY(hipEventCreateWithFlags(&B.ev_tables, hipEventDisableTiming));
-    MSKM_HIP_TRY(hipEventCreateWithFlags(&B.ev_side, hipEventDisableTiming));
-    MSKM_HIP_TRY(hipEventRecord(B.ev_tables, s));
-    MSKM_HIP_TRY(hipStreamWaitEvent(h->ctx->side, B.ev_tables, 0));
-    hipLaunchKernelGGL(k_bj_invert, dim3((unsigned)(B.nblocks - nb_main)), dim3(kWave), 0, h->ctx->side, nb_main,
-                       B.start, B.off, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, B.inv, B.inv32);
-    MSKM_HIP_TRY(hipEventRecord(B.ev_side, h->ctx->side));
+  if (nb_main < B.nblocks) {  // started by bj_start_side
+    B.side_b0 = nb_main;
     B.side_level0 = side0;
     B.side_pending = true;
+    B.side_started = false;
   }
   // workgroups of whole blocks: one per window of kBjGroupStep rows, a last
   // window shorter than kBjMax merged into the one before
@@ -300,9 +294,25 @@ mskm_status build_block_jacobi(mskm_hier* h) {
   return MSKM_OK;
 }
 
+mskm_status bj_start_side(mskm_hier* h) {
+  BlockJacobi& B = h->bj;
+  if (!B.side_pending || B.side_started) return MSKM_OK;
+  hipStream_t s = h->ctx->stream;
+  if (!B.ev_tables) MSKM_HIP_TRY(hipEventCreateWithFlags(&B.ev_tables, hipEventDisableTiming));
+  if (!B.ev_side) MSKM_HIP_TRY(hipEventCreateWithFlags(&B.ev_side, hipEventDisableTiming));
+  MSKM_HIP_TRY(hipEventRecord(B.ev_tables, s));
+  MSKM_HIP_TRY(hipStreamWaitEvent(h->ctx->side, B.ev_tables, 0));
+  hipLaunchKernelGGL(k_bj_invert, dim3((unsigned)(B.nblocks - B.side_b0)), dim3(kWave), 0, h->ctx->side, B.side_b0,
+                     B.start, B.off, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, B.inv, B.inv32);
+  MSKM_HIP_TRY(hipEventRecord(B.ev_side, h->ctx->side));
+  B.side_started = true;
+  return MSKM_OK;
+}
+
 mskm_status bj_wait(mskm_hier* h, int hi) {
   BlockJacobi& B = h->bj;
   if (!B.side_pending || hi < B.side_level0) return MSKM_OK;
+  MSKM_TRY(bj_start_side(h));
   MSKM_HIP_TRY(hipStreamWaitEvent(h->ctx->stream, B.ev_side, 0));
   B.side_pending = false;
   return MSKM_OK;

@@ -1253,8 +1253,23 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
     MSKM_HIP_TRY(hipMemcpyAsync(W.h_defer + lo, W.st + lo, (hi - lo + 1) * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
     MSKM_HIP_TRY(hipEventRecord(W.ev_defer, s));
     for (int l = lo; l <= hi; ++l) W.deferred[l] = 1;
+    // capture the next levels' chunk while the workgroups run (when they are chunked)
+    if (next_on) {
+      int nlo = 0, nhi = h->L - 1;
+      while (nlo < h->L && !(*next_on)[nlo]) ++nlo;
+      while (nhi >= 0 && !(*next_on)[nhi]) --nhi;
+      if (nlo <= nhi && !all_small(*next_on, nlo, nhi)) {
+        int Gn = h->spmv_g[MSKM_OP_DIAG][sizeof(TX) == 4 ? 1 : 0];
+        if (Gn >= 2 * kVecFlag && Gn < 3 * kVecFlag) Gn -= kVecFlag;
+        hipGraphExec_t next_exec = nullptr;
+        MSKM_TRY((chunk_graph<TV, TX>(h, W, dval, nlo, nhi, x, K, Gn, form, &next_exec)));
+      }
+    }
     return MSKM_OK;
   }
+  // the first chunked level starts the side-stream inversion of the finest
+  // depth's blocks (its few-block launches leave most of the GPU free)
+  if (bj) MSKM_TRY(bj_start_side(h));
   if (W.pending) {  // the previous run's speculative chunk copy lands in h_chk
     MSKM_HIP_TRY(hipEventSynchronize(W.pending));
     W.pending = nullptr;
