@@ -43,7 +43,6 @@ __global__ void __launch_bounds__(kBlock) k_knn16(int dim, int l, const DevLevel
   if (r >= L.n) return;
   const int64_t i = L.off + r;
   const double px = xs[i], py = xs[N + i], pz = dim == 3 ? xs[2 * N + i] : 0.0;
-  const int32_t pin = perm[i];
   const int cx = cell_coord(px, L.lo[0], L.inv_cell, L.nc[0]);
   const int cy = cell_coord(py, L.lo[1], L.inv_cell, L.nc[1]);
   const int cz = dim == 3 ? cell_coord(pz, L.lo[2], L.inv_cell, L.nc[2]) : 0;
