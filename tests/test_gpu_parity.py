@@ -255,6 +255,42 @@ def test_solve_block_jacobi(mod, ctx, name, alg, diag):
         mod.mskm_set_spmv_width(hd, mod.MSKM_OP_DIAG, 1, saved[1])
 
 
+def test_level_size_boundaries(mod, ctx):
+    """Level sizes at the edges of the launch shapes: 64 / 257 / 1024 rows
+    (solved by one workgroup each, with the three product layouts), 1025 rows
+    (the first chunked size), 2017 = 2 x 993 + 31 rows (the last window of
+    preconditioner blocks merged into the one before) and 2018 rows (not
+    merged). Plain and preconditioned, FP64 and mixed, both algorithms. The
+    near-duplicate level pairs make some levels' right-hand sides tiny and
+    their coefficients sensitive, so every solve is judged by the oracle's
+    monolithic residual of the GPU coefficients (and the coefficients are
+    checked against the oracle's loosely)."""
+    h = synth.halton_hierarchy(sizes=[64, 257, 1024, 1025, 2017, 2018, 3000])
+    f = synth.fourier_target(77)(h.points)
+    blk = ms.assemble(h.points, h.offsets, h.delta)
+    a_ref = oracle.sequential_solve(blk, f)
+    hd = mod.mskm_hier_create(ctx, h.points, h.offsets, h.delta, fp64=True, fp32=True)
+    try:
+        for pc in (mod.MSKM_PRECOND_NONE, mod.MSKM_PRECOND_BLOCK_JACOBI):
+            for algo in (mod.MSKM_ALG_SEQUENTIAL, mod.MSKM_ALG_MONOLITHIC):
+                for prec, bar in ((mod.MSKM_PREC_FP64, 1e-11), (mod.MSKM_PREC_FP32, 1e-12)):
+                    alpha = np.zeros_like(f)
+                    o = mod.solve_opts(precision=prec, algorithm=algo, precond=pc,
+                                       cg_rtol=1e-14 if prec == mod.MSKM_PREC_FP64 else 1e-5,
+                                       target_rel_residual=1e-13, max_refine=20, max_cg_iters=20000)
+                    res = mod.mskm_solve(ctx, hd, f, alpha, o)
+                    assert res.status == mod.MSKM_OK, (pc, algo, prec, res.report)
+                    rel = oracle.residual(blk, alpha, f)[0]
+                    assert rel <= bar, (pc, algo, prec, rel)
+                    for l in range(h.levels):
+                        sl = slice(h.offsets[l], h.offsets[l + 1])
+                        err = _rel(alpha[sl], a_ref[sl])
+                        assert err <= 1e-5, (pc, algo, prec, l, err)
+                    assert all(0 < it < 20000 for it in res.report["cg_iters_last"][:h.levels])
+    finally:
+        mod.mskm_hier_destroy(hd)
+
+
 def test_block_jacobi_needs_fewer_iterations(mod, ctx):
     """On the 3-D case the preconditioned solves take clearly fewer CG
     iterations than the plain ones to the same tolerance."""
