@@ -341,6 +341,21 @@ typedef struct {
 mskm_status mskm_mlp_train(mskm_ctx* ctx, const mskm_train_desc* desc, mskm_mlp** out, float* loss_log);
 mskm_status mskm_mlp_destroy(mskm_mlp* m);
 
+/* Trains network m in place on caller-given samples, with the schedule of
+ * mskm_mlp_train: Adam (Kingma and Ba 2015; beta1 0.9, beta2 0.999, eps
+ * 1e-8) from zero moment estimates on the mean squared error of the network
+ * output (before the s scaling) against y; step b (0-based) takes the rows
+ * (128 b + q) mod ns, q = 0..127. The first layer computes with the
+ * BF16-rounded weights and features that inference uses, and its gradient,
+ * taken at those rounded values, updates the FP32 weights.
+ *   X: [ns][F] FP32 features (F = 56 in 2-D, 72 in 3-D: the layout of the
+ *      definition above), y: [ns] FP32 targets; host pointers, or device
+ *      pointers with MSKM_IO_DEVICE in flags. The caller keeps ownership.
+ *   loss_log: nullable host [steps], each mini-batch's MSE before its update.
+ * MSKM_EINVAL for ns < 1, steps < 1, lr <= 0 or non-finite host inputs. */
+mskm_status mskm_mlp_fit(mskm_ctx* ctx, mskm_mlp* m, const float* X, const float* y, int64_t ns, int32_t steps,
+                         float lr, int32_t flags, float* loss_log);
+
 /* Versioned weight blob (little endian): "MSKMMLP1", int32 dim, int32 F,
  * int32 hidden (64), then W1, b1, w2, b2 as float32. blob == NULL: *size
  * receives the byte count. */

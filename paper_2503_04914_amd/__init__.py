@@ -40,7 +40,7 @@ EXPORTED = [
     "mskm_export_block", "mskm_export_rows", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
     "mskm_autotune", "mskm_spmv_width", "mskm_set_spmv_width",
     "mskm_solve_opts_default", "mskm_solve", "mskm_residual", "mskm_evaluate",
-    "mskm_mlp_train", "mskm_mlp_destroy", "mskm_mlp_save", "mskm_mlp_load", "mskm_mlp_predict", "mskm_knn_export",
+    "mskm_mlp_train", "mskm_mlp_fit", "mskm_mlp_destroy", "mskm_mlp_save", "mskm_mlp_load", "mskm_mlp_predict", "mskm_knn_export",
 ]
 
 
@@ -127,6 +127,7 @@ def lib():
     L.mskm_residual.argtypes = [vp, vp, vp, vp, i32, dp, i32]
     L.mskm_evaluate.argtypes = [vp, vp, vp, i32, vp, i64, vp, i32]
     L.mskm_mlp_train.argtypes = [vp, C.POINTER(TrainDesc), C.POINTER(vp), C.POINTER(C.c_float)]
+    L.mskm_mlp_fit.argtypes = [vp, vp, vp, vp, i64, i32, C.c_float, i32, C.POINTER(C.c_float)]
     L.mskm_mlp_destroy.argtypes = [vp]
     L.mskm_mlp_save.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
     L.mskm_mlp_load.argtypes = [vp, vp, C.c_size_t, C.POINTER(vp)]
@@ -405,6 +406,33 @@ def mskm_mlp_train(ctx, h, f, nrhs: int, samples: int = 20000, steps: int = 2000
     _check(lib().mskm_mlp_train(ctx, C.byref(d), C.byref(out), log.ctypes.data_as(C.POINTER(C.c_float))),
            "mskm_mlp_train")
     return out, log
+
+
+def mskm_mlp_fit(ctx, m, X, y, steps: int, lr: float = 1e-3) -> np.ndarray:
+    """Adam on caller-given samples (X [ns][F] float32, y [ns] float32, numpy
+    or CUDA tensors); updates the network in place and returns the loss of
+    every mini-batch."""
+    if _is_torch(X):
+        import torch
+
+        if X.dtype != torch.float32 or y.dtype != torch.float32 or not (X.is_contiguous() and y.is_contiguous()):
+            raise TypeError("X and y must be contiguous float32 tensors")
+        xp, yp, dev = C.c_void_p(X.data_ptr()), C.c_void_p(y.data_ptr()), X.is_cuda
+        if y.is_cuda != dev:
+            raise ValueError("X and y must both be host or both be device arrays")
+    else:
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        xp, yp, dev = C.c_void_p(X.ctypes.data), C.c_void_p(y.ctypes.data), False
+    log = np.zeros(steps, dtype=np.float32)
+    _check(lib().mskm_mlp_fit(ctx, m, xp, yp, int(X.shape[0]), steps, lr, MSKM_IO_DEVICE if dev else 0,
+                              log.ctypes.data_as(C.POINTER(C.c_float))), "mskm_mlp_fit")
+    return log
+
+
+def mlp_params(m) -> np.ndarray:
+    """Flat FP32 parameters (W1, b1, w2, b2) of a network, from its saved blob."""
+    return np.frombuffer(mskm_mlp_save(m)[20:], dtype=np.float32).copy()
 
 
 def mskm_mlp_destroy(m) -> None:

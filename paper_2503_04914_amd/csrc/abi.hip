@@ -428,6 +428,21 @@ mskm_status mskm_mlp_train(mskm_ctx* ctx, const mskm_train_desc* d, mskm_mlp** o
   return MSKM_OK;
 }
 
+mskm_status mskm_mlp_fit(mskm_ctx* ctx, mskm_mlp* m, const float* X, const float* y, int64_t ns, int32_t steps,
+                         float lr, int32_t flags, float* loss_log) {
+  if (!valid_ctx(ctx) || !m || !X || !y) return fail(MSKM_EINVAL, "mskm_mlp_fit: NULL argument");
+  if (ns < 1 || steps < 1 || !(lr > 0.0f) || !std::isfinite(lr))
+    return fail(MSKM_EINVAL, "mskm_mlp_fit: ns, steps and lr must be positive");
+  if (!(flags & MSKM_IO_DEVICE)) {
+    for (int64_t i = 0; i < ns * (int64_t)m->F; ++i)
+      if (!std::isfinite(X[i])) return fail(MSKM_EINVAL, "mskm_mlp_fit: non-finite feature");
+    for (int64_t i = 0; i < ns; ++i)
+      if (!std::isfinite(y[i])) return fail(MSKM_EINVAL, "mskm_mlp_fit: non-finite target");
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::mlp_fit(ctx, m, X, y, ns, steps, lr, (flags & MSKM_IO_DEVICE) != 0, loss_log);
+}
+
 mskm_status mskm_mlp_destroy(mskm_mlp* m) {
   delete m;
   return MSKM_OK;

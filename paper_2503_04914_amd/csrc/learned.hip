@@ -8,9 +8,11 @@
 //     feat = [b_i/s, (b_{n_m}/s, (x_{n_m} - x_i)/delta_l) for m = 1..16].
 // Inference: the first layer on MFMA (v_mfma_f32_32x32x8_bf16: 32 points x 32
 // hidden units x 8 features per instruction, BF16 operands, FP32
-// accumulation), 32 points per wave. Training: one deterministic block (FP32,
-// Adam) on (rhs stencil -> correction / s) samples drawn from the solver's
-// own sequential solves. CG judges the result: a level whose warm start does
+// accumulation), 32 points per wave. Training: one deterministic block (FP32
+// Adam on the mean squared error, the first layer with the same BF16-rounded
+// weights and features as inference) on (rhs stencil -> correction / s)
+// samples drawn from the solver's own sequential solves, or on samples the
+// caller gives. CG judges the result: a level whose warm start does
 // not reduce ||b - A x0|| below ||b|| restarts from zero.
 #include <algorithm>
 #include <cmath>
@@ -218,10 +220,16 @@ __global__ void __launch_bounds__(kBlock)
   y[k] = s > 0.0 ? (float)((double)alpha[i] / s) : 0.0f;
 }
 
+// float rounded to the nearest bfloat16 (ties to even) and widened back.
+__device__ __forceinline__ float bf16_round(float x) { return __uint_as_float((uint32_t)(uint16_t)to_bf16(x) << 16); }
+
 // Parameters in one FP32 array: W1 [64][F], b1 [64], w2 [64], b2 [1].
 // One block of kTrainB threads runs `steps` Adam steps on mini-batches
-// (sample (step*B + t) mod ns). Every parameter is owned by one thread, every
-// gradient is a fixed-order sum over the batch: the run is deterministic.
+// (sample (step*B + t) mod ns). The first layer computes with BF16-rounded
+// weights and features, as inference on MFMA does; its gradient (taken at
+// the rounded values) updates the FP32 weights. Every parameter is owned by
+// one thread, every gradient is a fixed-order sum over the batch: the run is
+// deterministic.
 __global__ void __launch_bounds__(kTrainB)
     k_mlp_train(int F, const float* __restrict__ X, const float* __restrict__ y, int64_t ns, int steps, float lr,
                 float* __restrict__ params, float* __restrict__ adam_m, float* __restrict__ adam_v,
@@ -242,7 +250,7 @@ __global__ void __launch_bounds__(kTrainB)
   __syncthreads();
   for (int step = 0; step < steps; ++step) {
     const int64_t k = ((int64_t)step * kTrainB + t) % ns;
-    for (int j = 0; j < F; ++j) Xs[t * XS + j] = X[k * F + j];
+    for (int j = 0; j < F; ++j) Xs[t * XS + j] = bf16_round(X[k * F + j]);
     const float target = y[k];
     __syncthreads();
     // forward
@@ -253,7 +261,7 @@ __global__ void __launch_bounds__(kTrainB)
     float out = b2;
     for (int h = 0; h < kHidden; ++h) {
       float a = b1[h];
-      for (int j = 0; j < F; ++j) a += W1[h * F + j] * Xs[t * XS + j];
+      for (int j = 0; j < F; ++j) a += bf16_round(W1[h * F + j]) * Xs[t * XS + j];
       a = fmaxf(a, 0.0f);
       Hs[t * (kHidden + 1) + h] = a;
       out += w2[h] * a;
@@ -445,6 +453,25 @@ mskm_status mlp_new(int dim, uint64_t seed, mskm_mlp** out) {
   return MSKM_OK;
 }
 
+// `steps` Adam steps of k_mlp_train on device samples (X [ns][F], y [ns])
+// from the moments in am / av; the network's host and device parameters
+// (and its BF16 copy of W1) are updated; the mini-batch loss of steps 0,
+// log_every, ... goes to lg.
+static mskm_status run_train(hipStream_t s, mskm_mlp* m, const float* X, const float* y, int64_t ns, int steps,
+                             float lr, float* am, float* av, float* lg, int log_every) {
+  const int F = m->F;
+  const int P = kHidden * F + 2 * kHidden + 1;
+  if (!m->d_params) MSKM_TRY(mlp_upload(m));
+  const size_t lds = sizeof(float) * (P + kTrainB * (F + 1) + 2 * kTrainB * (kHidden + 1) + 2 * kTrainB);
+  MSKM_HIP_TRY(hipFuncSetAttribute((const void*)k_mlp_train, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_mlp_train, dim3(1), dim3(kTrainB), lds, s, F, X, y, ns, steps, lr, m->d_params, am, av, lg,
+                     log_every);
+  MSKM_HIP_TRY(hipGetLastError());
+  MSKM_HIP_TRY(hipStreamSynchronize(s));
+  MSKM_HIP_TRY(hipMemcpy(m->params.data(), m->d_params, P * 4, hipMemcpyDeviceToHost));
+  return mlp_upload(m);
+}
+
 // Train on samples of (level rhs -> correction) pairs from plain FP64
 // sequential solves of the given right-hand sides (internal order rhs in fi).
 mskm_status mlp_train_device(mskm_hier* h, mskm_mlp* m, const std::vector<double*>& rhs_int,
@@ -483,20 +510,43 @@ mskm_status mlp_train_device(mskm_hier* h, mskm_mlp* m, const std::vector<double
                        h->dim, F, h->L, h->d_lev, h->knn, h->xs, h->N, rhs_int[r], alpha_int[r], idx + (int64_t)r * per,
                        per, X + (int64_t)r * per * F, y + (int64_t)r * per);
   }
-  if (!m->d_params) MSKM_TRY(mlp_upload(m));
-  const size_t lds = sizeof(float) * (P + kTrainB * (F + 1) + 2 * kTrainB * (kHidden + 1) + 2 * kTrainB);
-  MSKM_HIP_TRY(hipFuncSetAttribute((const void*)k_mlp_train, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_mlp_train, dim3(1), dim3(kTrainB), lds, s, F, X, y, ns, steps, lr, m->d_params, am, av, lg,
-                     log_every);
-  MSKM_HIP_TRY(hipGetLastError());
-  MSKM_HIP_TRY(hipStreamSynchronize(s));
-  MSKM_HIP_TRY(hipMemcpy(m->params.data(), m->d_params, P * 4, hipMemcpyDeviceToHost));
+  MSKM_TRY(run_train(s, m, X, y, ns, steps, lr, am, av, lg, log_every));
   if (loss_log) {
     loss_log->resize(nlog);
     MSKM_HIP_TRY(hipMemcpy(loss_log->data(), lg, nlog * 4, hipMemcpyDeviceToHost));
   }
   m->samples = ns;
-  MSKM_TRY(mlp_upload(m));
+  return MSKM_OK;
+}
+
+// Adam on caller-given samples: X [ns][F], y [ns] (FP32, host or device).
+mskm_status mlp_fit(mskm_ctx* ctx, mskm_mlp* m, const float* X, const float* y, int64_t ns, int steps, float lr,
+                    bool io_dev, float* loss_log) {
+  hipStream_t s = ctx->stream;
+  const int F = m->F;
+  const int P = kHidden * F + 2 * kHidden + 1;
+  float *Xd = nullptr, *yd = nullptr, *am = nullptr, *av = nullptr, *lg = nullptr;
+  if (!io_dev) {
+    MSKM_TRY(dalloc(&Xd, (size_t)ns * F));
+    MSKM_TRY(dalloc(&yd, ns));
+  }
+  MSKM_TRY(dalloc(&am, P));
+  MSKM_TRY(dalloc(&av, P));
+  MSKM_TRY(dalloc(&lg, steps));
+  struct Free {
+    void* v[5];
+    ~Free() {
+      for (void* p : v) (void)hipFree(p);
+    }
+  } fr{{Xd, yd, am, av, lg}};
+  if (!io_dev) {
+    MSKM_HIP_TRY(hipMemcpyAsync(Xd, X, (size_t)ns * F * 4, hipMemcpyHostToDevice, s));
+    MSKM_HIP_TRY(hipMemcpyAsync(yd, y, (size_t)ns * 4, hipMemcpyHostToDevice, s));
+  }
+  MSKM_HIP_TRY(hipMemsetAsync(am, 0, P * 4, s));
+  MSKM_HIP_TRY(hipMemsetAsync(av, 0, P * 4, s));
+  MSKM_TRY(run_train(s, m, io_dev ? X : Xd, io_dev ? y : yd, ns, steps, lr, am, av, lg, 1));
+  if (loss_log) MSKM_HIP_TRY(hipMemcpy(loss_log, lg, (size_t)steps * 4, hipMemcpyDeviceToHost));
   return MSKM_OK;
 }
 

@@ -276,6 +276,8 @@ mskm_status mlp_predict_rows(mskm_hier* h, const mskm_mlp* m, int l, const TX* b
 mskm_status mlp_train_device(mskm_hier* h, mskm_mlp* m, const std::vector<double*>& rhs_int,
                              const std::vector<double*>& alpha_int, int64_t samples, int steps, float lr, uint64_t seed,
                              std::vector<float>* loss_log);
+mskm_status mlp_fit(mskm_ctx* ctx, mskm_mlp* m, const float* X, const float* y, int64_t ns, int steps, float lr,
+                    bool io_dev, float* loss_log);
 mskm_status mlp_predict_all(mskm_hier* h, const mskm_mlp* m, const double* b, double* x0, bool io_dev);
 mskm_status knn_export(mskm_hier* h, int level, int32_t* out);
 mskm_status train_pairs(mskm_hier* h, const double* f, int nrhs, bool io_dev, double cg_rtol,

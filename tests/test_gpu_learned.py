@@ -3,7 +3,11 @@
 * kNN-16 lists: bit-exact against the oracle's brute force;
 * network inference (BF16 MFMA, FP32 accumulation) against the oracle's
   forward pass with the same BF16 rounding (FP64 accumulation);
-* training: the loss falls; save/load round trip;
+* training: one Adam step on fixed samples against the oracle's FP64
+  gradient and Adam step, parameter by parameter, within the FP32 error
+  bound of the gradient; a 100-step loss trajectory against the oracle's
+  FP64 training run; determinism; the loss falls on pairs from the solver;
+  save/load round trip;
 * solves with the warm start: coefficients still match the oracle (CG is the
   judge), FP64 <= 1e-10.
 """
@@ -107,3 +111,70 @@ def test_train_and_solve(env):
         assert np.linalg.norm(a2 - ref) / np.linalg.norm(ref) <= 1e-8
     finally:
         m.mskm_mlp_destroy(net)
+
+
+def _fit_case(dim, seed, ns):
+    """Random features and a target from a teacher network of the same shape
+    (so the loss can fall far), a random student."""
+    rng = np.random.default_rng(seed)
+    F = ol.feature_count(dim)
+    X = rng.standard_normal((ns, F)).astype(np.float32)
+    T1 = (rng.standard_normal((64, F)) * 0.2).astype(np.float32)
+    t1 = (rng.standard_normal(64) * 0.1).astype(np.float32)
+    t2 = (rng.standard_normal(64) * 0.2).astype(np.float32)
+    y = ol.forward(T1, t1, t2, 0.05, X, np.ones(ns)).astype(np.float32)
+    W1 = (rng.standard_normal((64, F)) * 0.1).astype(np.float32)
+    b1 = (rng.standard_normal(64) * 0.05).astype(np.float32)
+    w2 = (rng.standard_normal(64) * 0.1).astype(np.float32)
+    return X, y, (W1, b1, w2, np.float32(0.01))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fit_one_step_matches_oracle(env, dim):
+    m, ctx, _, _ = env
+    X, y, (W1, b1, w2, b2) = _fit_case(dim, 20 + dim, 300)
+    lr = 1e-3
+    net = m.mskm_mlp_load(ctx, m.mlp_blob(dim, W1, b1, w2, float(b2)))
+    try:
+        log = m.mskm_mlp_fit(ctx, net, X, y, steps=1, lr=lr)
+        got = m.mlp_params(net).astype(np.float64)
+    finally:
+        m.mskm_mlp_destroy(net)
+    rows = ol.batch_rows(0, len(y))
+    loss, g = ol.loss_and_grads(W1, b1, w2, b2, X[rows], y[rows])
+    g = ol.pack(*g)
+    p0 = ol.pack(W1, b1, w2, b2)
+    want, _, _ = ol.adam_update(p0, g, np.zeros_like(p0), np.zeros_like(p0), 1, lr)
+    # first Adam step: -lr g / (|g| + eps); an FP32 gradient within E of g
+    # moves it by at most lr min(2, 2 E / (|g| + eps)); plus the FP32
+    # rounding of the Adam arithmetic and of the updated parameter
+    E = ol.grad_error_bound(W1, b1, w2, b2, X[rows], y[rows])
+    ulp = np.spacing(np.maximum(np.abs(p0), np.abs(want)).astype(np.float32)).astype(np.float64)
+    tol = lr * np.minimum(2.0, 2.0 * E / (np.abs(g) + 1e-8)) + 1e-5 * lr + 2.0 * ulp
+    bad = np.flatnonzero(np.abs(got - want) > tol)
+    assert bad.size == 0, (bad[:10], got[bad[:10]], want[bad[:10]], tol[bad[:10]])
+    assert np.mean(np.abs(got - p0) > 0.5 * lr) > 0.9  # the step is a real one
+    assert log[0] == pytest.approx(loss, rel=1e-5)
+
+
+def test_fit_trajectory_matches_oracle(env):
+    m, ctx, _, _ = env
+    X, y, (W1, b1, w2, b2) = _fit_case(2, 31, 2000)
+    steps, lr = 100, 1e-3
+    net = m.mskm_mlp_load(ctx, m.mlp_blob(2, W1, b1, w2, float(b2)))
+    net2 = m.mskm_mlp_load(ctx, m.mlp_blob(2, W1, b1, w2, float(b2)))
+    try:
+        log = m.mskm_mlp_fit(ctx, net, X, y, steps=steps, lr=lr)
+        log2 = m.mskm_mlp_fit(ctx, net2, X, y, steps=steps, lr=lr)
+        assert np.array_equal(log, log2) and np.array_equal(m.mlp_params(net), m.mlp_params(net2))  # deterministic
+        got = m.mlp_params(net).astype(np.float64)
+    finally:
+        m.mskm_mlp_destroy(net)
+        m.mskm_mlp_destroy(net2)
+    want, ref_log = ol.train(ol.pack(W1, b1, w2, b2), X, y, steps, lr)
+    # FP32 and FP64 runs separate slowly: an FP32 emulation of this loop
+    # (numpy, another summation order) stays within 1.1e-4 of the FP64 losses
+    # and within 6e-7 in median parameter over these 100 steps
+    assert np.all(np.abs(log - ref_log) <= 1e-3 * ref_log), np.max(np.abs(log - ref_log) / ref_log)
+    assert np.mean(ref_log[-10:]) < 0.5 * np.mean(ref_log[:10])
+    assert np.median(np.abs(got - want)) < 1e-2 * lr
