@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define MSKM_ABI_VERSION 1
+#define MSKM_ABI_VERSION 2
 
 typedef int32_t mskm_status;
 enum {
@@ -76,9 +76,13 @@ enum { MSKM_WENDLAND_3_1 = 31 };
 enum {
   MSKM_POINTS_ON_DEVICE = 1 << 0, /* points is a device pointer */
   MSKM_STORE_FP64 = 1 << 1,       /* keep FP64 block values (plain path) */
-  MSKM_STORE_FP32 = 1 << 2        /* keep FP32 block values (mixed path); without
+  MSKM_STORE_FP32 = 1 << 2,       /* keep FP32 block values (mixed path); without
                                      STORE_FP64 also each value's FP32 rounding
                                      remainder, which the FP64 residual adds back */
+  MSKM_PREFIX_NESTED = 1 << 3     /* prefix-nested sets X_1 c X_2 c ... (Section 2):
+                                     points holds only the largest level, and level
+                                     l is its first level_offsets[l+1] -
+                                     level_offsets[l] points */
 };
 
 /* flags of calls taking vectors */
@@ -107,7 +111,8 @@ typedef struct {
   int32_t dim;                  /* 2 or 3 */
   int32_t levels;               /* L >= 1 */
   const int64_t* level_offsets; /* host, [L+1], 0 = off[0] <= off[1] <= ... */
-  const double* points;         /* AoS [N][dim], N = off[L]; host unless POINTS_ON_DEVICE */
+  const double* points;         /* AoS [N][dim], N = off[L]; host unless POINTS_ON_DEVICE.
+                                   With PREFIX_NESTED: [P][dim], P = the largest level size */
   const double* delta;          /* host, [L], finite and > 0 */
   int32_t kernel;               /* MSKM_WENDLAND_3_1 */
   int32_t flags;                /* MSKM_POINTS_ON_DEVICE | MSKM_STORE_FP64 | MSKM_STORE_FP32;
@@ -242,13 +247,24 @@ mskm_status mskm_set_spmv_width(mskm_hier* h, int32_t op, int32_t prec, int32_t 
 /* ------------------------------------------------------------------ solve */
 
 enum { MSKM_ALG_MONOLITHIC = 0, MSKM_ALG_SEQUENTIAL = 1 };
-/* MSKM_PRECOND_LEARNED: the network's prediction as each level's CG start.
- * MSKM_PRECOND_BLOCK_JACOBI: CG on A_l preconditioned by the dense inverses
+/* MSKM_PRECOND_BLOCK_JACOBI: CG on A_l preconditioned by the dense inverses
  * of A_l's diagonal blocks over the cells of the level's grid (cells of more
  * than 32 points cut into chunks); built at the first such solve and kept
- * with the hierarchy. Both are build extensions (the paper's CG is plain);
- * the solution they converge to is the same. */
+ * with the hierarchy. MSKM_PRECOND_LEARNED: no preconditioner, the network's
+ * prediction as each level's CG start (the same as MSKM_PRECOND_NONE with
+ * warm_start = MSKM_START_LEARNED). Both are build extensions (the paper's
+ * CG is plain); the solution they converge to is the same. */
 enum { MSKM_PRECOND_NONE = 0, MSKM_PRECOND_LEARNED = 1, MSKM_PRECOND_BLOCK_JACOBI = 2 };
+
+/* Start of the per-level CG solves (mskm_solve_opts.warm_start):
+ *   MSKM_START_ZERO      x0 = 0 (the paper's Algorithm 1);
+ *   MSKM_START_PREVIOUS  Jacobi sweep m starts from sweep m-1's solution of the
+ *                        same level, the final D alpha = beta from the last
+ *                        sweep's (monolithic algorithm; zero elsewhere);
+ *   MSKM_START_LEARNED   the network opts.mlp predicts x0 from the level's
+ *                        right-hand side; combines with any precond. CG judges
+ *                        it: a level with ||b - A x0|| >= ||b|| restarts from 0. */
+enum { MSKM_START_ZERO = 0, MSKM_START_PREVIOUS = 1, MSKM_START_LEARNED = 2 };
 
 typedef struct mskm_mlp mskm_mlp;
 
@@ -260,16 +276,17 @@ typedef struct {
   double cg_rtol;         /* per-level CG stop: ||r|| <= cg_rtol * ||b|| */
   int32_t sweeps;         /* Jacobi sweeps; <= 0 means L */
   int32_t max_cg_iters;   /* cap per CG solve; <= 0 means 20000 */
-  int32_t warm_start;     /* 1: CG of sweep m starts from sweep m-1's solution */
+  int32_t warm_start;     /* MSKM_START_ZERO, _PREVIOUS or _LEARNED */
   double target_rel_residual; /* mixed path: stop refining when ||f-T alpha||/||f|| <= this */
   int32_t max_refine;     /* mixed path: cap on refinement steps; <= 0 means 10 */
-  int32_t precond;        /* MSKM_PRECOND_NONE, _LEARNED (warm start) or _BLOCK_JACOBI */
-  const mskm_mlp* mlp;    /* network for MSKM_PRECOND_LEARNED */
+  int32_t precond;        /* MSKM_PRECOND_NONE, _BLOCK_JACOBI or _LEARNED (learned start, no preconditioner) */
+  const mskm_mlp* mlp;    /* network for MSKM_START_LEARNED / MSKM_PRECOND_LEARNED */
   int32_t check_every;    /* CG convergence poll interval; <= 0 means 8 */
   int32_t flags;          /* MSKM_IO_DEVICE */
 } mskm_solve_opts;
 
-/* Defaults: FP64, monolithic, cg_rtol 1e-12, L sweeps, no warm start. */
+/* Defaults: FP64, monolithic, cg_rtol 1e-12, L sweeps, MSKM_START_ZERO, no
+ * preconditioner. */
 void mskm_solve_opts_default(mskm_solve_opts* o);
 
 typedef struct {
@@ -293,6 +310,26 @@ typedef struct {
  * was hit. */
 mskm_status mskm_solve(mskm_ctx* ctx, const mskm_hier* h, const double* f, int32_t nrhs,
                        const mskm_solve_opts* opts, double* alpha, mskm_report* rep);
+
+/* Solves nh separately created hierarchies h[0..nh) in the same launches
+ * (Section 3 for each; the levels of one depth of every hierarchy share each
+ * CG launch, as in a batch object). f[g], alpha[g]: [N_g][nrhs[g]] FP64 in
+ * hierarchy g's input order (host pointers, or device pointers with
+ * MSKM_IO_DEVICE in opts->flags); 1 <= nrhs[g] <= 512. reps: nullable, [nh]:
+ * reps[g] holds hierarchy g's levels, rel_residual (max over its right-hand
+ * sides) and cg_iters_last (by depth); cg_iters_total, refine_steps and
+ * solve_ms are those of the whole batch.
+ * The hierarchies need the same dim and stored precisions, must not be
+ * batch objects themselves, and must be distinct. The first call on a set of
+ * hierarchies assembles one internal batch object from their points (device
+ * memory about the sum of theirs, kept by the context and reused while the
+ * same hierarchies are solved again; destroying any of them releases it).
+ * Hierarchies solved with fewer right-hand sides than the largest nrhs are
+ * padded with zero right-hand sides, which converge at once.
+ * MSKM_ENOCONV if any hierarchy missed its tolerance. */
+mskm_status mskm_solve_batch(mskm_ctx* ctx, const mskm_hier* const* h, int32_t nh, const double* const* f,
+                             const int32_t* nrhs, const mskm_solve_opts* opts, double* const* alpha,
+                             mskm_report* reps);
 
 /* ||f - T_L alpha||_2 / ||f||_2 per right-hand side and per group (for a
  * batch, each hierarchy's own relative residual), FP64-accurate values

@@ -26,12 +26,13 @@ LIB_PATH = os.path.join(HERE, "libmskm.so")
 MSKM_OK, MSKM_ENOCONV = 0, 1
 MSKM_EINVAL, MSKM_ENOMEM, MSKM_EDEVICE, MSKM_ELIMIT, MSKM_ESTATE = -1, -2, -3, -4, -5
 MSKM_WENDLAND_3_1 = 31
-MSKM_POINTS_ON_DEVICE, MSKM_STORE_FP64, MSKM_STORE_FP32 = 1, 2, 4
+MSKM_POINTS_ON_DEVICE, MSKM_STORE_FP64, MSKM_STORE_FP32, MSKM_PREFIX_NESTED = 1, 2, 4, 8
 MSKM_IO_DEVICE = 1
 MSKM_OP_DIAG, MSKM_OP_LOWER, MSKM_OP_FULL = 0, 1, 2
 MSKM_PREC_FP64, MSKM_PREC_FP32 = 0, 1
 MSKM_ALG_MONOLITHIC, MSKM_ALG_SEQUENTIAL = 0, 1
 MSKM_PRECOND_NONE, MSKM_PRECOND_LEARNED, MSKM_PRECOND_BLOCK_JACOBI = 0, 1, 2
+MSKM_START_ZERO, MSKM_START_PREVIOUS, MSKM_START_LEARNED = 0, 1, 2
 
 EXPORTED = [
     "mskm_create", "mskm_destroy", "mskm_last_error", "mskm_abi_version",
@@ -39,7 +40,7 @@ EXPORTED = [
     "mskm_hier_level_info",
     "mskm_export_block", "mskm_export_rows", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
     "mskm_autotune", "mskm_spmv_width", "mskm_set_spmv_width",
-    "mskm_solve_opts_default", "mskm_solve", "mskm_residual", "mskm_evaluate",
+    "mskm_solve_opts_default", "mskm_solve", "mskm_solve_batch", "mskm_residual", "mskm_evaluate",
     "mskm_mlp_train", "mskm_mlp_fit", "mskm_mlp_destroy", "mskm_mlp_save", "mskm_mlp_load", "mskm_mlp_predict", "mskm_knn_export",
 ]
 
@@ -124,6 +125,8 @@ def lib():
     L.mskm_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
     L.mskm_solve_opts_default.restype = None
     L.mskm_solve.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(Report)]
+    L.mskm_solve_batch.argtypes = [vp, C.POINTER(vp), i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(SolveOpts),
+                                   C.POINTER(vp), C.POINTER(Report)]
     L.mskm_residual.argtypes = [vp, vp, vp, vp, i32, dp, i32]
     L.mskm_evaluate.argtypes = [vp, vp, vp, i32, vp, i64, vp, i32]
     L.mskm_mlp_train.argtypes = [vp, C.POINTER(TrainDesc), C.POINTER(vp), C.POINTER(C.c_float)]
@@ -193,15 +196,19 @@ def mskm_destroy(ctx) -> None:
 
 # --------------------------------------------------------------- hierarchy
 
-def mskm_hier_create(ctx, points, offsets, delta, dim: int | None = None, fp64: bool = True, fp32: bool = False):
+def mskm_hier_create(ctx, points, offsets, delta, dim: int | None = None, fp64: bool = True, fp32: bool = False,
+                     prefix_nested: bool = False):
     """Assemble all blocks of a hierarchy. points: [N][dim] float64 (numpy, or
-    a CUDA tensor), offsets: [L+1] int64, delta: [L] float64 (host)."""
+    a CUDA tensor), offsets: [L+1] int64, delta: [L] float64 (host). With
+    prefix_nested, points holds only the largest level and level l is its
+    first offsets[l+1] - offsets[l] points."""
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     delta = np.ascontiguousarray(delta, dtype=np.float64)
     if dim is None:
         dim = int(points.shape[1])
     pp, pdev = _ptr(points, np.float64)
-    flags = (MSKM_POINTS_ON_DEVICE if pdev else 0) | (MSKM_STORE_FP64 if fp64 else 0) | (MSKM_STORE_FP32 if fp32 else 0)
+    flags = (MSKM_POINTS_ON_DEVICE if pdev else 0) | (MSKM_STORE_FP64 if fp64 else 0) | \
+        (MSKM_STORE_FP32 if fp32 else 0) | (MSKM_PREFIX_NESTED if prefix_nested else 0)
     d = HierDesc(dim, len(delta), offsets.ctypes.data_as(C.POINTER(C.c_int64)), pp,
                  delta.ctypes.data_as(C.POINTER(C.c_double)), MSKM_WENDLAND_3_1, flags)
     out = C.c_void_p()
@@ -368,6 +375,37 @@ def mskm_solve(ctx, h, f, alpha, opts: SolveOpts | None = None, nrhs: int = 1) -
     r = {k: getattr(rep, k) for k, _ in Report._fields_}
     r["cg_iters_last"] = list(rep.cg_iters_last)[: rep.levels]
     return SolveResult(st, r)
+
+
+def mskm_solve_batch(ctx, hs, fs, alphas, opts: SolveOpts | None = None, nrhs=None):
+    """Separately created hierarchies hs solved in the same launches; fs /
+    alphas: one [N_g][nrhs_g] array per hierarchy (all host or all device).
+    Returns (status, one report dict per hierarchy)."""
+    nh = len(hs)
+    nrhs = [1] * nh if nrhs is None else list(nrhs)
+    opts = opts or mskm_solve_opts_default()
+    fps, aps, devs = [], [], set()
+    for f, a in zip(fs, alphas):
+        fp, fd = _ptr(f, np.float64)
+        ap, ad = _ptr(a, np.float64)
+        fps.append(fp.value)
+        aps.append(ap.value)
+        devs |= {fd, ad}
+    if len(devs) != 1:
+        raise ValueError("f and alpha arrays must all be host or all be device arrays")
+    o = SolveOpts()
+    C.pointer(o)[0] = opts
+    o.flags = (o.flags | MSKM_IO_DEVICE) if devs.pop() else (o.flags & ~MSKM_IO_DEVICE)
+    reps = (Report * nh)()
+    hv = (C.c_void_p * nh)(*[h.value if isinstance(h, C.c_void_p) else h for h in hs])
+    st = _check(lib().mskm_solve_batch(ctx, hv, nh, (C.c_void_p * nh)(*fps), (C.c_int32 * nh)(*nrhs), C.byref(o),
+                                       (C.c_void_p * nh)(*aps), reps), "mskm_solve_batch")
+    out = []
+    for g in range(nh):
+        r = {k: getattr(reps[g], k) for k, _ in Report._fields_}
+        r["cg_iters_last"] = list(reps[g].cg_iters_last)[: reps[g].levels]
+        out.append(r)
+    return st, out
 
 
 def mskm_residual(ctx, h, alpha, f, nrhs: int = 1) -> np.ndarray:

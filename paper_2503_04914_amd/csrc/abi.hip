@@ -2,6 +2,7 @@
 // thread-local error text. The numerical work lives in assemble.hip and
 // solve.hip.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -11,6 +12,7 @@
 
 namespace {
 thread_local std::string g_last_error;
+std::atomic<uint64_t> g_serial{0};
 
 bool valid_ctx(const mskm_ctx* c) { return c != nullptr; }
 
@@ -71,6 +73,11 @@ mskm_status mskm_destroy(mskm_ctx* c) {
   if (!c) return MSKM_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  for (auto& b : c->batch_cache) {
+    b.merged->ctx = nullptr;  // the cache is being torn down: no lookup in it
+    mskm_hier_destroy(b.merged);
+  }
+  c->batch_cache.clear();
   (void)hipEventDestroy(c->ev0);
   (void)hipEventDestroy(c->ev1);
   if (c->side) {
@@ -91,13 +98,17 @@ mskm_status check_desc(const mskm_hier_desc* d, int64_t* n) {
   if (d->kernel != MSKM_WENDLAND_3_1) return fail(MSKM_EINVAL, "unsupported kernel");
   if (!d->level_offsets || !d->points || !d->delta) return fail(MSKM_EINVAL, "NULL array in descriptor");
   if (d->level_offsets[0] != 0) return fail(MSKM_EINVAL, "level_offsets[0] must be 0");
+  int64_t largest = 0;
   for (int l = 0; l < d->levels; ++l) {
     if (d->level_offsets[l + 1] < d->level_offsets[l]) return fail(MSKM_EINVAL, "level_offsets must not decrease");
     if (!(d->delta[l] > 0.0) || !std::isfinite(d->delta[l])) return fail(MSKM_EINVAL, "delta must be finite and > 0");
+    largest = std::max(largest, d->level_offsets[l + 1] - d->level_offsets[l]);
   }
   *n = d->level_offsets[d->levels];
+  // points passed: all levels concatenated, or only the largest level of a prefix-nested hierarchy
+  const int64_t np = (d->flags & MSKM_PREFIX_NESTED) ? largest : *n;
   if (!(d->flags & MSKM_POINTS_ON_DEVICE)) {
-    for (int64_t i = 0; i < *n * d->dim; ++i)
+    for (int64_t i = 0; i < np * d->dim; ++i)
       if (!std::isfinite(d->points[i])) return fail(MSKM_EINVAL, "non-finite point coordinate");
   }
   return MSKM_OK;
@@ -131,6 +142,7 @@ mskm_status create_groups(mskm_ctx* ctx, const mskm_hier_desc* ds, int32_t count
   auto* h = new (std::nothrow) mskm_hier();
   if (!h) return fail(MSKM_ENOMEM, "hierarchy allocation");
   h->ctx = ctx;
+  h->serial = ++g_serial;
   h->dim = ds[0].dim;
   h->L = Ltot;
   h->N = N;
@@ -168,9 +180,19 @@ mskm_status create_groups(mskm_ctx* ctx, const mskm_hier_desc* ds, int32_t count
   mskm_status st = mskm::dalloc(&pts, (size_t)N * h->dim);
   for (int g = 0; g < count && st == MSKM_OK; ++g) {
     const bool dev = (ds[g].flags & MSKM_POINTS_ON_DEVICE) != 0;
-    if (gn[g] > 0 && hipMemcpyAsync(pts + h->h_group_in_off[g] * h->dim, ds[g].points, (size_t)gn[g] * h->dim * 8,
-                                    dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    double* dst = pts + h->h_group_in_off[g] * h->dim;
+    if (ds[g].flags & MSKM_PREFIX_NESTED) {  // level l = the first n_l points of the largest level
+      for (int l = 0; l < ds[g].levels && st == MSKM_OK; ++l) {
+        const int64_t nl = ds[g].level_offsets[l + 1] - ds[g].level_offsets[l];
+        if (nl > 0 && hipMemcpyAsync(dst + ds[g].level_offsets[l] * h->dim, ds[g].points, (size_t)nl * h->dim * 8, kind,
+                                     ctx->stream) != hipSuccess)
+          st = fail(MSKM_EDEVICE, "point upload failed");
+      }
+    } else if (gn[g] > 0 &&
+               hipMemcpyAsync(dst, ds[g].points, (size_t)gn[g] * h->dim * 8, kind, ctx->stream) != hipSuccess) {
       st = fail(MSKM_EDEVICE, "point upload failed");
+    }
   }
   if (st == MSKM_OK) st = mskm::assemble_hierarchy(h, pts, want64, want32);
   if (st == MSKM_OK) {  // widths tuned earlier on this context for the same shape
@@ -204,6 +226,18 @@ mskm_status mskm_hier_create_batch(mskm_ctx* ctx, const mskm_hier_desc* descs, i
 
 mskm_status mskm_hier_destroy(mskm_hier* h) {
   if (!h) return MSKM_OK;
+  if (h->ctx) {  // internal batch objects built from this hierarchy go with it
+    auto& bc = h->ctx->batch_cache;
+    for (size_t i = 0; i < bc.size();) {
+      if (std::find(bc[i].members.begin(), bc[i].members.end(), h) != bc[i].members.end()) {
+        mskm_hier* m = bc[i].merged;
+        bc.erase(bc.begin() + (long)i);
+        mskm_hier_destroy(m);
+      } else {
+        ++i;
+      }
+    }
+  }
   if (h->ctx) {
     (void)hipSetDevice(h->ctx->device);
     (void)hipStreamSynchronize(h->ctx->stream);
@@ -358,6 +392,27 @@ void mskm_solve_opts_default(mskm_solve_opts* o) {
   o->flags = 0;
 }
 
+namespace {
+// Option checks shared by mskm_solve and mskm_solve_batch.
+mskm_status check_opts(const mskm_solve_opts& o, const mskm_hier* h, int nrhs) {
+  if (o.precision != MSKM_PREC_FP64 && o.precision != MSKM_PREC_FP32) return fail(MSKM_EINVAL, "unknown precision");
+  if (o.algorithm != MSKM_ALG_MONOLITHIC && o.algorithm != MSKM_ALG_SEQUENTIAL)
+    return fail(MSKM_EINVAL, "unknown algorithm");
+  if (!(o.cg_rtol > 0.0) || !(o.cg_rtol < 1.0)) return fail(MSKM_EINVAL, "cg_rtol must be in (0, 1)");
+  if (o.precision == MSKM_PREC_FP32 && !(o.target_rel_residual > 0.0))
+    return fail(MSKM_EINVAL, "target_rel_residual must be > 0 on the mixed path");
+  if (o.precond != MSKM_PRECOND_NONE && o.precond != MSKM_PRECOND_LEARNED && o.precond != MSKM_PRECOND_BLOCK_JACOBI)
+    return fail(MSKM_EINVAL, "unknown precond");
+  if (o.warm_start != MSKM_START_ZERO && o.warm_start != MSKM_START_PREVIOUS && o.warm_start != MSKM_START_LEARNED)
+    return fail(MSKM_EINVAL, "unknown warm_start");
+  const bool learned = o.precond == MSKM_PRECOND_LEARNED || o.warm_start == MSKM_START_LEARNED;
+  if (learned && !o.mlp) return fail(MSKM_EINVAL, "learned warm start needs an mlp");
+  if (learned && o.mlp->dim != h->dim) return fail(MSKM_EINVAL, "network and hierarchy dimensions differ");
+  if (nrhs > 1 && learned) return fail(MSKM_EINVAL, "solves of several right-hand sides take no learned warm start");
+  return MSKM_OK;
+}
+}  // namespace
+
 mskm_status mskm_solve(mskm_ctx* ctx, const mskm_hier* h, const double* f, int32_t nrhs, const mskm_solve_opts* opts,
                        double* alpha, mskm_report* rep) {
   if (!valid_ctx(ctx) || !h || !f || !alpha) return fail(MSKM_EINVAL, "mskm_solve: NULL argument");
@@ -365,23 +420,145 @@ mskm_status mskm_solve(mskm_ctx* ctx, const mskm_hier* h, const double* f, int32
   mskm_solve_opts o;
   if (opts) o = *opts;
   else mskm_solve_opts_default(&o);
-  if (o.precision != MSKM_PREC_FP64 && o.precision != MSKM_PREC_FP32) return fail(MSKM_EINVAL, "unknown precision");
-  if (o.algorithm != MSKM_ALG_MONOLITHIC && o.algorithm != MSKM_ALG_SEQUENTIAL)
-    return fail(MSKM_EINVAL, "unknown algorithm");
-  if (!(o.cg_rtol > 0.0) || !(o.cg_rtol < 1.0)) return fail(MSKM_EINVAL, "cg_rtol must be in (0, 1)");
-  if (o.precision == MSKM_PREC_FP32 && !(o.target_rel_residual > 0.0))
-    return fail(MSKM_EINVAL, "target_rel_residual must be > 0 on the mixed path");
-  if (o.precond == MSKM_PRECOND_LEARNED && !o.mlp) return fail(MSKM_EINVAL, "learned warm start needs an mlp");
-  if (o.precond != MSKM_PRECOND_NONE && o.precond != MSKM_PRECOND_LEARNED && o.precond != MSKM_PRECOND_BLOCK_JACOBI)
-    return fail(MSKM_EINVAL, "unknown precond");
-  if (nrhs > 1 && o.precond == MSKM_PRECOND_LEARNED)
-    return fail(MSKM_EINVAL, "solves of several right-hand sides take no learned warm start");
+  MSKM_TRY(check_opts(o, h, nrhs));
   if (!(o.flags & MSKM_IO_DEVICE)) {
     for (int64_t i = 0; i < h->N * (int64_t)nrhs; ++i)
       if (!std::isfinite(f[i])) return fail(MSKM_EINVAL, "non-finite right-hand side");
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
   return mskm::solve(const_cast<mskm_hier*>(h), f, nrhs, &o, alpha, rep);
+}
+
+namespace {
+// The context's batch object for exactly these hierarchies (in this order),
+// assembled from their points at the first request.
+mskm_status merged_batch(mskm_ctx* ctx, const mskm_hier* const* hs, int nh, mskm_hier** out) {
+  for (const auto& b : ctx->batch_cache) {
+    if ((int)b.members.size() != nh) continue;
+    bool same = true;
+    for (int g = 0; g < nh && same; ++g) same = b.members[g] == hs[g] && b.serials[g] == hs[g]->serial;
+    if (same) {
+      *out = b.merged;
+      return MSKM_OK;
+    }
+  }
+  // points back in each hierarchy's input order, then one batch assembly
+  int64_t total = 0;
+  for (int g = 0; g < nh; ++g) total += hs[g]->N;
+  double* pts = nullptr;
+  MSKM_TRY(mskm::dalloc(&pts, (size_t)total * hs[0]->dim));
+  struct FreePts {
+    double* p;
+    ~FreePts() { (void)hipFree(p); }
+  } free_pts{pts};
+  std::vector<mskm_hier_desc> ds(nh);
+  int64_t o = 0;
+  for (int g = 0; g < nh; ++g) {
+    mskm_hier* hg = const_cast<mskm_hier*>(hs[g]);
+    MSKM_TRY(mskm::export_points_device(hg, pts + o * hg->dim));
+    ds[g].dim = hg->dim;
+    ds[g].levels = hg->L;
+    ds[g].level_offsets = hg->h_off.data();
+    ds[g].points = pts + o * hg->dim;
+    ds[g].delta = hg->h_delta.data();
+    ds[g].kernel = MSKM_WENDLAND_3_1;
+    ds[g].flags = MSKM_POINTS_ON_DEVICE | (hg->diag.val ? MSKM_STORE_FP64 : 0) | (hg->diag.val32 ? MSKM_STORE_FP32 : 0);
+    o += hg->N;
+  }
+  mskm_hier* m = nullptr;
+  MSKM_TRY(create_groups(ctx, ds.data(), nh, &m));
+  std::memcpy(m->spmv_g, hs[0]->spmv_g, sizeof(m->spmv_g));  // the members' SpMV choices
+  mskm::MergedBatch b;
+  b.members.assign(hs, hs + nh);
+  for (int g = 0; g < nh; ++g) b.serials.push_back(hs[g]->serial);
+  b.merged = m;
+  ctx->batch_cache.push_back(b);
+  *out = m;
+  return MSKM_OK;
+}
+}  // namespace
+
+mskm_status mskm_solve_batch(mskm_ctx* ctx, const mskm_hier* const* h, int32_t nh, const double* const* f,
+                             const int32_t* nrhs, const mskm_solve_opts* opts, double* const* alpha,
+                             mskm_report* reps) {
+  if (!valid_ctx(ctx) || !h || !f || !nrhs || !alpha || nh < 1)
+    return fail(MSKM_EINVAL, "mskm_solve_batch: NULL argument");
+  mskm_solve_opts o;
+  if (opts) o = *opts;
+  else mskm_solve_opts_default(&o);
+  int R = 0;
+  for (int g = 0; g < nh; ++g) {
+    if (!h[g] || !f[g] || !alpha[g]) return fail(MSKM_EINVAL, "mskm_solve_batch: NULL hierarchy or vector");
+    if (h[g]->ngroups != 1) return fail(MSKM_EINVAL, "mskm_solve_batch: a batch object cannot be a member");
+    if (h[g]->ctx != ctx) return fail(MSKM_EINVAL, "mskm_solve_batch: hierarchy of another context");
+    if (h[g]->dim != h[0]->dim || (h[g]->diag.val != nullptr) != (h[0]->diag.val != nullptr) ||
+        (h[g]->diag.val32 != nullptr) != (h[0]->diag.val32 != nullptr))
+      return fail(MSKM_EINVAL, "mskm_solve_batch: hierarchies need the same dim and stored precisions");
+    for (int k = 0; k < g; ++k)
+      if (h[k] == h[g]) return fail(MSKM_EINVAL, "mskm_solve_batch: a hierarchy appears twice");
+    if (nrhs[g] < 1 || nrhs[g] > 512) return fail(MSKM_EINVAL, "mskm_solve_batch: nrhs must be in [1, 512]");
+    R = std::max(R, (int)nrhs[g]);
+  }
+  MSKM_TRY(check_opts(o, h[0], R));
+  const bool io_dev = (o.flags & MSKM_IO_DEVICE) != 0;
+  if (!io_dev) {
+    for (int g = 0; g < nh; ++g)
+      for (int64_t i = 0; i < h[g]->N * (int64_t)nrhs[g]; ++i)
+        if (!std::isfinite(f[g][i])) return fail(MSKM_EINVAL, "non-finite right-hand side");
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  mskm_hier* m = nullptr;
+  MSKM_TRY(merged_batch(ctx, h, nh, &m));
+  // concatenated [N][R] right-hand sides (zero columns past a hierarchy's own nrhs)
+  hipStream_t s = ctx->stream;
+  const int64_t N = m->N;
+  double *F = nullptr, *A = nullptr;
+  MSKM_TRY(mskm::dalloc(&F, (size_t)N * R));
+  MSKM_TRY(mskm::dalloc(&A, (size_t)N * R));
+  struct FreeFA {
+    double *a, *b;
+    ~FreeFA() {
+      (void)hipFree(a);
+      (void)hipFree(b);
+    }
+  } free_fa{F, A};
+  const hipMemcpyKind in_kind = io_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const hipMemcpyKind out_kind = io_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  MSKM_HIP_TRY(hipMemsetAsync(F, 0, (size_t)N * R * 8, s));
+  for (int g = 0; g < nh; ++g)
+    if (h[g]->N > 0)
+      MSKM_HIP_TRY(hipMemcpy2DAsync(F + m->h_group_in_off[g] * R, (size_t)R * 8, f[g], (size_t)nrhs[g] * 8,
+                                    (size_t)nrhs[g] * 8, (size_t)h[g]->N, in_kind, s));
+  o.flags |= MSKM_IO_DEVICE;
+  mskm_report all;
+  const mskm_status st = mskm::solve(m, F, R, &o, A, &all);
+  MSKM_TRY(st);
+  for (int g = 0; g < nh; ++g)
+    if (h[g]->N > 0)
+      MSKM_HIP_TRY(hipMemcpy2DAsync(alpha[g], (size_t)nrhs[g] * 8, A + m->h_group_in_off[g] * R, (size_t)R * 8,
+                                    (size_t)nrhs[g] * 8, (size_t)h[g]->N, out_kind, s));
+  std::vector<double> rel((size_t)R * nh, 0.0);
+  MSKM_TRY(mskm::residual(m, A, F, R, rel.data(), true));
+  bool missed = false;
+  for (int g = 0; g < nh; ++g) {
+    double worst = 0.0;
+    for (int r = 0; r < nrhs[g]; ++r) worst = std::max(worst, rel[(size_t)r * nh + g]);
+    if (o.precision == MSKM_PREC_FP32 && worst > o.target_rel_residual) missed = true;
+    if (!reps) continue;
+    mskm_report& rp = reps[g];
+    std::memset(&rp, 0, sizeof(rp));
+    rp.levels = h[g]->L;
+    rp.sweeps_done = all.sweeps_done;
+    rp.refine_steps = all.refine_steps;
+    rp.cg_iters_total = all.cg_iters_total;
+    for (int l = 0; l < m->L && l < 64; ++l)
+      if (m->h_group[l] == g && m->h_depth[l] < 64) rp.cg_iters_last[m->h_depth[l]] = all.cg_iters_last[l];
+    rp.rel_residual = worst;
+    rp.solve_ms = all.solve_ms;
+    rp.warm_fallbacks = all.warm_fallbacks;
+  }
+  MSKM_HIP_TRY(hipStreamSynchronize(s));
+  return (st == MSKM_ENOCONV || missed) ? MSKM_ENOCONV : MSKM_OK;
 }
 
 mskm_status mskm_residual(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, const double* f, int32_t nrhs,

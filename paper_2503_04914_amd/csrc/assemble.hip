@@ -86,21 +86,44 @@ __global__ void __launch_bounds__(kBlock) k_scan_final(const int64_t* __restrict
   }
 }
 
-// out[0..n) = exclusive scan of in[0..n). in and out may not alias.
-mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n) {
+int64_t scan_parts(int64_t n) { return std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile); }
+
+// out[0..n) = exclusive scan of in[0..n), stream-ordered (no host
+// synchronisation). in and out may not alias; part is scratch of
+// scan_parts(n) entries, free again once the scan's kernels have run.
+mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n, int64_t* part) {
   if (n <= 0) return MSKM_OK;
-  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  const int64_t nb = scan_parts(n);
   if (nb > (int64_t)INT32_MAX) return fail(MSKM_ELIMIT, "scan too large");
-  int64_t* part = nullptr;
-  MSKM_TRY(dalloc(&part, (size_t)nb));
   hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, part);
   hipLaunchKernelGGL(k_scan_partials_scan, dim3(1), dim3(kBlock), 0, s, part, nb);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, part, out);
-  hipError_t e = hipStreamSynchronize(s);
-  (void)hipFree(part);
-  if (e != hipSuccess) return fail(MSKM_EDEVICE, std::string("scan: ") + hipGetErrorString(e));
+  MSKM_HIP_TRY(hipGetLastError());
   return MSKM_OK;
 }
+
+// Pieces of one device allocation, each aligned to 256 bytes.
+struct Carve {
+  size_t bytes = 0;
+  std::vector<std::pair<void**, size_t>> want;
+  template <typename T>
+  void add(T** p, size_t count) {
+    want.push_back({reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T)});
+    bytes += (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+  }
+  // one hipMalloc for all pieces; *base receives it (freed by the caller)
+  mskm_status alloc(void** base) {
+    char* b = nullptr;
+    MSKM_TRY(dalloc(&b, bytes));
+    *base = b;
+    size_t o = 0;
+    for (auto& w : want) {
+      *w.first = b + o;
+      o += (w.second + 255) / 256 * 256;
+    }
+    return MSKM_OK;
+  }
+};
 
 // ------------------------------------------------------------- cell lists
 
@@ -653,18 +676,25 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
     rng[2 * l] = h->h_in_off[l];
     rng[2 * l + 1] = h->h_in_off[l] + (h->h_off[l + 1] - h->h_off[l]);
   }
-  int64_t* d_off = nullptr;
-  MSKM_TRY(dalloc(&d_off, 2 * (size_t)L));
-  MSKM_HIP_TRY(hipMemcpyAsync(d_off, rng.data(), rng.size() * 8, hipMemcpyHostToDevice, s));
-
   // 1. bounding boxes
-  double* d_part = nullptr;
-  MSKM_TRY(dalloc(&d_part, (size_t)L * kBboxBlocks * 6));
-  hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks, L), dim3(kBlock), 0, s, pts, d_off, dim, d_part);
-  std::vector<double> part((size_t)L * kBboxBlocks * 6);
-  MSKM_HIP_TRY(hipMemcpyAsync(part.data(), d_part, part.size() * 8, hipMemcpyDeviceToHost, s));
-  MSKM_HIP_TRY(hipStreamSynchronize(s));
-  (void)hipFree(d_part);
+  std::vector<double> bbox((size_t)L * kBboxBlocks * 6);
+  {
+    int64_t* d_off = nullptr;
+    double* d_part = nullptr;
+    void* bb = nullptr;
+    Carve cv;
+    cv.add(&d_off, 2 * (size_t)L);
+    cv.add(&d_part, bbox.size());
+    MSKM_TRY(cv.alloc(&bb));
+    struct FreeBb {
+      void* p;
+      ~FreeBb() { (void)hipFree(p); }
+    } free_bb{bb};
+    MSKM_HIP_TRY(hipMemcpyAsync(d_off, rng.data(), rng.size() * 8, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks, L), dim3(kBlock), 0, s, pts, d_off, dim, d_part);
+    MSKM_HIP_TRY(hipMemcpyAsync(bbox.data(), d_part, bbox.size() * 8, hipMemcpyDeviceToHost, s));
+    MSKM_HIP_TRY(hipStreamSynchronize(s));
+  }
 
   // 2. level grids (host): cell side delta*(1+1e-6), enlarged if the grid
   //    would exceed max(4n, 64) cells
@@ -685,7 +715,7 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
       hi[d] = -INFINITY;
     }
     for (int b = 0; b < kBboxBlocks; ++b) {
-      const double* o = &part[((size_t)l * kBboxBlocks + b) * 6];
+      const double* o = &bbox[((size_t)l * kBboxBlocks + b) * 6];
       for (int d = 0; d < dim; ++d) {
         if (std::isnan(o[d]) || std::isnan(o[3 + d])) return fail(MSKM_EINVAL, "non-finite point coordinate");
         lo[d] = std::min(lo[d], o[d]);
@@ -721,14 +751,28 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   MSKM_TRY(halloc(h, &h->d_lev, L));
   MSKM_HIP_TRY(hipMemcpyAsync(h->d_lev, h->h_lev.data(), L * sizeof(DevLevel), hipMemcpyHostToDevice, s));
 
-  // 3. counting sort into cells
+  // 3. counting sort into cells. Scratch of the sort, the counts and the
+  //    scans: one allocation, freed once the fill pass is queued (a free
+  //    between kernels would synchronise the device)
   int32_t *key = nullptr, *count = nullptr, *tmp = nullptr;
-  int64_t *count64 = nullptr, *cs64 = nullptr;
-  MSKM_TRY(dalloc(&key, N));
-  MSKM_TRY(dalloc(&count, cs_total));
-  MSKM_TRY(dalloc(&count64, cs_total));
-  MSKM_TRY(dalloc(&cs64, cs_total));
-  MSKM_TRY(dalloc(&tmp, N));
+  int64_t *count64 = nullptr, *cs64 = nullptr, *cnt_d = nullptr, *cnt_l = nullptr, *part = nullptr;
+  void* scratch = nullptr;
+  {
+    Carve cv;
+    cv.add(&key, N);
+    cv.add(&count, cs_total);
+    cv.add(&count64, cs_total);
+    cv.add(&cs64, cs_total);
+    cv.add(&tmp, N);
+    cv.add(&cnt_d, N + 1);
+    cv.add(&cnt_l, N + 1);
+    cv.add(&part, std::max(scan_parts(cs_total), scan_parts(N + 1)));
+    MSKM_TRY(cv.alloc(&scratch));
+  }
+  struct FreeScratch {
+    void* p;
+    ~FreeScratch() { (void)hipFree(p); }
+  } free_scratch{scratch};
   MSKM_HIP_TRY(hipMemsetAsync(count, 0, cs_total * 4, s));
   for (int l = 0; l < L; ++l) {
     const int64_t n = h->h_lev[l].n;
@@ -742,7 +786,7 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   // global indices directly.
   MSKM_TRY(halloc(h, &h->cell_start, cs_total));
   hipLaunchKernelGGL(k_widen, dim3(grid_for(cs_total, kBlock)), dim3(kBlock), 0, s, count, count64, cs_total);
-  MSKM_TRY(exclusive_scan_i64(s, count64, cs64, cs_total));
+  MSKM_TRY(exclusive_scan_i64(s, count64, cs64, cs_total, part));
   hipLaunchKernelGGL(k_narrow, dim3(grid_for(cs_total, kBlock)), dim3(kBlock), 0, s, cs64, h->cell_start, cs_total);
   MSKM_HIP_TRY(hipMemsetAsync(count, 0, cs_total * 4, s));  // reuse as cursors
   MSKM_TRY(halloc(h, &h->perm, N));
@@ -767,9 +811,6 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
                      h->prec);
 
   // 4. count pass
-  int64_t *cnt_d = nullptr, *cnt_l = nullptr;
-  MSKM_TRY(dalloc(&cnt_d, N + 1));
-  MSKM_TRY(dalloc(&cnt_l, N + 1));
   MSKM_HIP_TRY(hipMemsetAsync(cnt_d + N, 0, 8, s));
   MSKM_HIP_TRY(hipMemsetAsync(cnt_l + N, 0, 8, s));
   for (int k = 0; k < L; ++k) {
@@ -784,19 +825,11 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   }
   MSKM_TRY(halloc(h, &h->diag.rowptr, N + 1));
   MSKM_TRY(halloc(h, &h->lower.rowptr, N + 1));
-  MSKM_TRY(exclusive_scan_i64(s, cnt_d, h->diag.rowptr, N + 1));
-  MSKM_TRY(exclusive_scan_i64(s, cnt_l, h->lower.rowptr, N + 1));
+  MSKM_TRY(exclusive_scan_i64(s, cnt_d, h->diag.rowptr, N + 1, part));
+  MSKM_TRY(exclusive_scan_i64(s, cnt_l, h->lower.rowptr, N + 1, part));
   MSKM_HIP_TRY(hipMemcpyAsync(&h->diag.nnz, h->diag.rowptr + N, 8, hipMemcpyDeviceToHost, s));
   MSKM_HIP_TRY(hipMemcpyAsync(&h->lower.nnz, h->lower.rowptr + N, 8, hipMemcpyDeviceToHost, s));
   MSKM_HIP_TRY(hipStreamSynchronize(s));
-  (void)hipFree(cnt_d);
-  (void)hipFree(cnt_l);
-  (void)hipFree(key);
-  (void)hipFree(count);
-  (void)hipFree(count64);
-  (void)hipFree(cs64);
-  (void)hipFree(tmp);
-  (void)hipFree(d_off);
 
   // 5. fill pass (FP32-only hierarchies also keep the FP32 rounding remainders)
   const bool want_lo = want32 && !want64;
@@ -879,6 +912,9 @@ __global__ void __launch_bounds__(kSellC)
   const int64_t s = blockIdx.x;
   const int t = threadIdx.x;
   const int32_t row = rows[s * kSellC + t];
+  // pad column of an empty slot (past the level's last row): the slice's
+  // first row, so that it stays inside the slice's column span
+  const int32_t row_first = __shfl(row, 0, kSellC);
   const int64_t b = row >= 0 ? rp[row] : 0;
   const int64_t len = row >= 0 ? rp[row + 1] - b : 0;
   const int64_t e0 = sptr[s], w = (sptr[s + 1] - e0) / kSellC;
@@ -890,7 +926,7 @@ __global__ void __launch_bounds__(kSellC)
       const int32_t rowrr = __shfl(row, rr, kSellC);
       const int64_t k = k0 + kk;
       const bool in = k < lrr;
-      tc[kk][rr] = in ? col[brr + k] : (rowrr >= 0 ? rowrr : 0);
+      tc[kk][rr] = in ? col[brr + k] : (rowrr >= 0 ? rowrr : row_first);
       if (val) tv[kk][rr] = in ? val[brr + k] : 0.0;
       if (val32) tf[kk][rr] = in ? val32[brr + k] : 0.0f;
     }
@@ -957,14 +993,26 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32) {
       hipLaunchKernelGGL(k_sell_rows, dim3(grid_for(nslots, kBlock)), dim3(kBlock), 0, s, h->h_off[l],
                          h->h_off[l + 1] - h->h_off[l], S.h_slice_begin[l] * kSellC, nslots, S.rows);
   }
-  int64_t* d_w = nullptr;
-  MSKM_TRY(dalloc(&d_w, (size_t)S.nslices + 1));
+  // scratch: slice widths, scan partials, the wide-slice counter
+  int64_t *d_w = nullptr, *part = nullptr;
+  int32_t* d_wide = nullptr;
+  void* scratch = nullptr;
+  {
+    Carve cv;
+    cv.add(&d_w, (size_t)S.nslices + 1);
+    cv.add(&part, scan_parts(S.nslices + 1));
+    cv.add(&d_wide, 1);
+    MSKM_TRY(cv.alloc(&scratch));
+  }
+  struct FreeScratch {
+    void* p;
+    ~FreeScratch() { (void)hipFree(p); }
+  } free_scratch{scratch};
   hipLaunchKernelGGL(k_sell_width, dim3(grid_for(S.nslices + 1, kBlock)), dim3(kBlock), 0, s, S.nslices, S.rows,
                      h->diag.rowptr, d_w);
-  MSKM_TRY(exclusive_scan_i64(s, d_w, S.sptr, S.nslices + 1));
+  MSKM_TRY(exclusive_scan_i64(s, d_w, S.sptr, S.nslices + 1, part));
   MSKM_HIP_TRY(hipMemcpyAsync(&S.entries, S.sptr + S.nslices, 8, hipMemcpyDeviceToHost, s));
   MSKM_HIP_TRY(hipStreamSynchronize(s));
-  (void)hipFree(d_w);
   MSKM_TRY(halloc(h, &S.col, (size_t)S.entries));
   if (want64) MSKM_TRY(halloc(h, &S.val, (size_t)S.entries));
   if (want32) MSKM_TRY(halloc(h, &S.val32, (size_t)S.entries));
@@ -974,10 +1022,8 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32) {
   // 16-bit column offsets when every slice's columns span at most 65536 rows
   if (S.nslices > 0) {
     int32_t* cbase = nullptr;
-    int32_t* d_wide = nullptr;
     int32_t wide = 0;
     MSKM_TRY(dalloc(&cbase, (size_t)S.nslices));
-    MSKM_TRY(dalloc(&d_wide, 1));
     mskm_status st = MSKM_OK;
     if (hipMemsetAsync(d_wide, 0, 4, s) != hipSuccess) st = fail(MSKM_EDEVICE, "memset");
     if (st == MSKM_OK) {
@@ -986,7 +1032,6 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32) {
           hipStreamSynchronize(s) != hipSuccess)
         st = fail(MSKM_EDEVICE, "SELL column span");
     }
-    (void)hipFree(d_wide);
     if (st == MSKM_OK && wide == 0) {
       h->allocs.push_back(cbase);
       h->device_bytes += S.nslices * 4;
@@ -1034,6 +1079,23 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32) {
 }
 
 // ------------------------------------------------------------------ export
+
+// pts[perm[i]][a] = xs[a][i]: the points back in the input order (AoS).
+__global__ void __launch_bounds__(kBlock) k_points_to_input(int dim, const double* __restrict__ xs, int64_t N,
+                                                            const int32_t* __restrict__ perm,
+                                                            double* __restrict__ pts) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= N) return;
+  const int64_t o = (int64_t)perm[i] * dim;
+  for (int a = 0; a < dim; ++a) pts[o + a] = xs[a * N + i];
+}
+
+mskm_status export_points_device(mskm_hier* h, double* pts_dev) {
+  hipLaunchKernelGGL(k_points_to_input, dim3(grid_for(h->N, kBlock)), dim3(kBlock), 0, h->ctx->stream, h->dim, h->xs,
+                     h->N, h->perm, pts_dev);
+  MSKM_HIP_TRY(hipGetLastError());
+  return MSKM_OK;
+}
 
 // Entries of block (k, j) in canonical row r (or in row rows[r] of level k
 // when a row list is given): count pass.
@@ -1098,14 +1160,17 @@ mskm_status export_block(mskm_hier* h, int k, int j, int64_t* rowptr, int32_t* c
     int64_t* p;
     ~FreeRows() { (void)hipFree(p); }
   } free_rows{rows};
-  int64_t *cnt = nullptr, *optr = nullptr;
+  int64_t *cnt = nullptr, *optr = nullptr, *part = nullptr;
   MSKM_TRY(dalloc(&cnt, nrows + 1));
   MSKM_TRY(dalloc(&optr, nrows + 1));
+  MSKM_TRY(dalloc(&part, scan_parts(nrows + 1)));
   MSKM_HIP_TRY(hipMemsetAsync(cnt + nrows, 0, 8, s));
   if (nrows > 0)
     hipLaunchKernelGGL(k_export_count, dim3(grid_for(nrows, kBlock)), dim3(kBlock), 0, s, C.rowptr, C.col, h->iperm,
                        row_off, nrows, c0, c1, rows, cnt);
-  mskm_status st = exclusive_scan_i64(s, cnt, optr, nrows + 1);
+  mskm_status st = exclusive_scan_i64(s, cnt, optr, nrows + 1, part);
+  if (st == MSKM_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(MSKM_EDEVICE, "export scan");
+  (void)hipFree(part);
   int64_t nnz = 0;
   if (st == MSKM_OK) {
     (void)hipMemcpy(&nnz, optr + nrows, 8, hipMemcpyDeviceToHost);

@@ -140,8 +140,19 @@ struct TuneEntry {
 };
 }  // namespace mskm
 
+namespace mskm {
+// Internal batch object assembled for mskm_solve_batch from separately
+// created hierarchies (identified by handle and creation serial).
+struct MergedBatch {
+  std::vector<const mskm_hier*> members;
+  std::vector<uint64_t> serials;
+  mskm_hier* merged = nullptr;
+};
+}  // namespace mskm
+
 struct mskm_ctx {
   std::vector<mskm::TuneEntry> tune_cache;  // shape -> SpMV widths
+  std::vector<mskm::MergedBatch> batch_cache;  // mskm_solve_batch objects
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -167,6 +178,7 @@ struct mskm_mlp {
 
 struct mskm_hier {
   mskm_ctx* ctx = nullptr;
+  uint64_t serial = 0;                  // creation number (unique per process)
   int32_t dim = 0, L = 0;
   int64_t N = 0;
   std::vector<int64_t> h_off;           // [L+1] internal offsets (level order)
@@ -243,11 +255,15 @@ mskm_status dalloc(T** p, size_t count) {
 
 // assemble.hip
 mskm_status assemble_hierarchy(mskm_hier* h, const double* points_dev, bool want64, bool want32);
+// The hierarchy's points in its input order, AoS [N][dim], into device memory.
+mskm_status export_points_device(mskm_hier* h, double* pts_dev);
 // rows_host == nullptr: every row of the level; else the listed rows (indices
 // within the row level, host array of nrows_sel entries).
 mskm_status export_block(mskm_hier* h, int row_level, int col_level, int64_t* rowptr, int32_t* col, double* val,
                          int64_t* nnz_out, const int64_t* rows_host = nullptr, int64_t nrows_sel = 0);
-mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n);
+// Stream-ordered exclusive scan; part: scratch of scan_parts(n) entries.
+int64_t scan_parts(int64_t n);
+mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n, int64_t* part);
 // Rows of each level split into blocks of max(min_rows, n_l / max_blocks) rows,
 // so that no level has more than max_blocks blocks.
 mskm_status build_work_table(mskm_hier* h, WorkTable* wt, int min_rows, int max_blocks_per_level);

@@ -214,10 +214,17 @@ mskm_status build_block_jacobi(mskm_hier* h) {
   // cell slot plus one per kBjMax rows), the exact counts read back once
   const int64_t nslots = (int64_t)last.cs_off + last.ncell_tot;
   const int64_t nb_max = nslots + h->N / kBjMax + 1;
-  int64_t *nch = nullptr, *bbase = nullptr, *msq = nullptr;
-  mskm_status st = dalloc(&nch, (size_t)nslots + 1);
-  if (st == MSKM_OK) st = dalloc(&bbase, (size_t)nslots + 1);
-  if (st == MSKM_OK) st = dalloc(&msq, (size_t)nb_max + 1);
+  // scratch (one allocation): chunk counts, block bases, block sizes, scan partials
+  int64_t *nch = nullptr, *bbase = nullptr, *msq = nullptr, *part = nullptr;
+  const size_t a1 = ((size_t)nslots + 1 + 31) / 32 * 32, a2 = ((size_t)nb_max + 1 + 31) / 32 * 32;
+  int64_t* scratch = nullptr;
+  mskm_status st = dalloc(&scratch, 2 * a1 + a2 + (size_t)std::max(scan_parts(nslots + 1), scan_parts(nb_max + 1)));
+  if (st == MSKM_OK) {
+    nch = scratch;
+    bbase = scratch + a1;
+    msq = scratch + 2 * a1;
+    part = scratch + 2 * a1 + a2;
+  }
   if (st == MSKM_OK) st = halloc(h, &B.start, (size_t)nb_max + 1);
   if (st == MSKM_OK) st = halloc(h, &B.off, (size_t)nb_max + 1);
   if (st == MSKM_OK) st = halloc(h, &B.of_row, (size_t)h->N);
@@ -229,13 +236,13 @@ mskm_status build_block_jacobi(mskm_hier* h) {
   if (st == MSKM_OK) {
     const unsigned gs = (unsigned)((nslots + kBlock) / kBlock);
     hipLaunchKernelGGL(k_bj_cell_chunks, dim3(gs), dim3(kBlock), 0, s, h->cell_start, nslots, nch);
-    st = exclusive_scan_i64(s, nch, bbase, nslots + 1);
+    st = exclusive_scan_i64(s, nch, bbase, nslots + 1, part);
     if (st == MSKM_OK) {
       if (hipMemsetAsync(msq, 0, ((size_t)nb_max + 1) * 8, s) != hipSuccess) st = fail(MSKM_EDEVICE, "memset");
       hipLaunchKernelGGL(k_bj_blocks, dim3(gs), dim3(kBlock), 0, s, h->cell_start, nslots, bbase, B.start, msq,
                          B.of_row);
     }
-    if (st == MSKM_OK) st = exclusive_scan_i64(s, msq, B.off, nb_max + 1);
+    if (st == MSKM_OK) st = exclusive_scan_i64(s, msq, B.off, nb_max + 1, part);
     if (st == MSKM_OK && (hipMemcpyAsync(&counts[0], bbase + nslots, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
                           hipMemcpyAsync(&counts[1], B.off + nb_max, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
                           (side0 < L && hipMemcpyAsync(&counts[2], bbase + h->h_lev[side0].cs_off, 8,
@@ -243,9 +250,7 @@ mskm_status build_block_jacobi(mskm_hier* h) {
                           hipStreamSynchronize(s) != hipSuccess))
       st = fail(MSKM_EDEVICE, "block-Jacobi counts");
   }
-  (void)hipFree(nch);
-  (void)hipFree(bbase);
-  (void)hipFree(msq);
+  (void)hipFree(scratch);
   MSKM_TRY(st);
   B.nblocks = counts[0];
   B.nvals = counts[1];

@@ -1394,7 +1394,11 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
   const int L = h->L;
   TX* beta = (TX*)W.beta;
   TX* t = (TX*)W.t;
-  const mskm_mlp* mlp = o->precond == MSKM_PRECOND_LEARNED ? o->mlp : nullptr;
+  // learned start (with or without the block-Jacobi preconditioner), or the
+  // previous sweep's solution as the start of the monolithic sweeps
+  const bool learned = o->precond == MSKM_PRECOND_LEARNED || o->warm_start == MSKM_START_LEARNED;
+  const mskm_mlp* mlp = learned ? o->mlp : nullptr;
+  const bool prev = o->warm_start == MSKM_START_PREVIOUS;
   const bool bj = o->precond == MSKM_PRECOND_BLOCK_JACOBI;
   const int maxit = o->max_cg_iters > 0 ? o->max_cg_iters : 20000;
   int K = o->check_every > 0 ? o->check_every : 8;
@@ -1428,14 +1432,13 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
   MSKM_HIP_TRY(hipMemsetAsync(t, 0, N * sizeof(TX), s));
   for (int l = 0; l < L; ++l) on[l] = h->h_next[l] >= 0;  // every level below its hierarchy's top
   for (int sw = 0; sw < S && Lmax > 1; ++sw) {
-    MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, t, o->cg_rtol, maxit, o->warm_start != 0 && sw > 0, K, cs,
-                             nullptr, bj)));
+    MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, t, o->cg_rtol, maxit, prev && sw > 0, K, cs, nullptr, bj)));
     lower_update<TV, TX>(h, lval, t, f, beta, 0, N);
     *sweeps_done = sw + 1;
   }
-  if (o->warm_start) MSKM_HIP_TRY(hipMemcpyAsync(alpha, t, N * sizeof(TX), hipMemcpyDeviceToDevice, s));
+  if (prev) MSKM_HIP_TRY(hipMemcpyAsync(alpha, t, N * sizeof(TX), hipMemcpyDeviceToDevice, s));
   std::fill(on.begin(), on.end(), 1);
-  MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, o->warm_start != 0, K, cs, mlp, bj)));
+  MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, prev, K, cs, prev ? nullptr : mlp, bj)));
   return flush_deferred(h, W, cs);
 }
 
