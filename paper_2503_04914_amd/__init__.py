@@ -40,7 +40,8 @@ EXPORTED = [
     "mskm_hier_level_info",
     "mskm_export_block", "mskm_export_rows", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
     "mskm_autotune", "mskm_spmv_width", "mskm_set_spmv_width",
-    "mskm_solve_opts_default", "mskm_solve", "mskm_solve_batch", "mskm_residual", "mskm_evaluate",
+    "mskm_solve_opts_default", "mskm_solve", "mskm_solve_batch", "mskm_residual", "mskm_residual_noalloc",
+    "mskm_evaluate",
     "mskm_mlp_train", "mskm_mlp_fit", "mskm_mlp_destroy", "mskm_mlp_save", "mskm_mlp_load", "mskm_mlp_predict", "mskm_knn_export",
 ]
 
@@ -102,6 +103,14 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise MskmLibraryMissing(f"{LIB_PATH} not found: build it with python -m paper_2503_04914_amd.build")
+    # torch ships its own HIP runtime under the same soname. Loading torch
+    # first makes the library bind to that runtime, so device pointers and
+    # streams are shared and only one runtime opens the GPU; loaded the other
+    # way round, the process holds two runtimes and torch's finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
     L.mskm_create.argtypes = [i32, vp, C.POINTER(vp)]
@@ -128,6 +137,7 @@ def lib():
     L.mskm_solve_batch.argtypes = [vp, C.POINTER(vp), i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(SolveOpts),
                                    C.POINTER(vp), C.POINTER(Report)]
     L.mskm_residual.argtypes = [vp, vp, vp, vp, i32, dp, i32]
+    L.mskm_residual_noalloc.argtypes = [vp, vp, vp, vp, i32, vp]
     L.mskm_evaluate.argtypes = [vp, vp, vp, i32, vp, i64, vp, i32]
     L.mskm_mlp_train.argtypes = [vp, C.POINTER(TrainDesc), C.POINTER(vp), C.POINTER(C.c_float)]
     L.mskm_mlp_fit.argtypes = [vp, vp, vp, vp, i64, i32, C.c_float, i32, C.POINTER(C.c_float)]
@@ -418,6 +428,17 @@ def mskm_residual(ctx, h, alpha, f, nrhs: int = 1) -> np.ndarray:
     _check(lib().mskm_residual(ctx, h, ap, fp, nrhs, out.ctypes.data_as(C.POINTER(C.c_double)),
                                MSKM_IO_DEVICE if ad else 0), "mskm_residual")
     return out
+
+
+def mskm_residual_noalloc(ctx, h, alpha, f, rel_out, nrhs: int = 1) -> None:
+    """Allocation-free residual: alpha, f [N][nrhs] and rel_out [nrhs * ngroups]
+    are device tensors; stream-ordered on the context's stream (no host sync)."""
+    ap, ad = _ptr(alpha, np.float64)
+    fp, fd = _ptr(f, np.float64)
+    op, od = _ptr(rel_out, np.float64)
+    if not (ad and fd and od):
+        raise ValueError("alpha, f and rel_out must be device tensors")
+    _check(lib().mskm_residual_noalloc(ctx, h, ap, fp, nrhs, op), "mskm_residual_noalloc")
 
 
 def mskm_evaluate(ctx, h, alpha, query, out, nrhs: int = 1) -> None:
