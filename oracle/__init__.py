@@ -23,6 +23,11 @@ kernel-based multi-scale algorithm", arXiv 2503.04914):
                     the monolithic residual f - T alpha (eq. (bigt)), the
                     multiscale approximant (eq. (fapproximation)), and the
                     spectral norm of M = I - T' (Section 5.1, Figure 1).
+* ``truncation`` -- the thresholded Jacobi of Section 4: the Lagrange blocks
+                    X_{kj} = B_{kj} A_j^-1 of M, their truncation X~_{kj}(T)
+                    (entries with distance >= T q_j dropped, eq.
+                    (perturbedmatrix)), the quantities of Figures 2-3 and the
+                    solution of the perturbed split (eq. (perturbed_split)).
 
 Conventions (readings of the paper, listed with reasons in the design notes):
 
@@ -40,7 +45,7 @@ Parity status: every function is pinned by a test in tests/test_oracle_*.py
 against closed forms, brute force, dense Cholesky, the paper's invariants or
 values printed in the paper; none is "parity unpinned".
 """
-from . import wendland, neighbours, multiscale  # noqa: F401
+from . import wendland, neighbours, multiscale, truncation  # noqa: F401
 from .wendland import phi31  # noqa: F401
 from .neighbours import block_bruteforce, block_cells, sqdist_pairs  # noqa: F401
 from .multiscale import (  # noqa: F401
