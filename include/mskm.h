@@ -337,6 +337,23 @@ mskm_status mskm_solve_batch(mskm_ctx* ctx, const mskm_hier* const* h, int32_t n
 mskm_status mskm_residual(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, const double* f, int32_t nrhs,
                           double* rel_out, int32_t flags);
 
+/* Allocation-free variant of mskm_residual, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). alpha, f: device [N][nrhs] FP64 in input order; rel_out:
+ * device [nrhs][ngroups], receives ||f - T_L alpha||_2 / ||f||_2 per
+ * right-hand side and group (||r||_2 where ||f||_2 = 0). All three must be
+ * device memory of the context's device (MSKM_EINVAL otherwise); the caller
+ * keeps ownership. The work is enqueued on the context stream and the call
+ * returns without waiting: synchronise that stream before reading rel_out.
+ * Nothing is allocated: the per-block partials live in a static 2 MiB device
+ * array of the library (one per device, held until the process ends), so
+ * hierarchies of more than 131072 row blocks of 64 rows (about 8.4M points)
+ * get MSKM_ELIMIT. Calls on one device share that array: calls that overlap
+ * on one device (other streams, other threads) race and must be ordered by
+ * the caller. Sums differ from mskm_residual's only in summation order. */
+mskm_status mskm_residual_noalloc(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, const double* f,
+                                  int32_t nrhs, double* rel_out);
+
 /* f_L at query points (eq. (fapproximation)): out[q][r] = sum over levels.
  * query: [nq][dim]; out: [nq][nrhs]. */
 mskm_status mskm_evaluate(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, int32_t nrhs, const double* query,

@@ -40,7 +40,7 @@ EXPORTED = [
     "mskm_hier_level_info",
     "mskm_export_block", "mskm_export_rows", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
     "mskm_autotune", "mskm_spmv_width", "mskm_set_spmv_width",
-    "mskm_solve_opts_default", "mskm_solve", "mskm_solve_batch", "mskm_residual",
+    "mskm_solve_opts_default", "mskm_solve", "mskm_solve_batch", "mskm_residual", "mskm_residual_noalloc",
     "mskm_evaluate",
     "mskm_mlp_train", "mskm_mlp_fit", "mskm_mlp_destroy", "mskm_mlp_save", "mskm_mlp_load", "mskm_mlp_predict", "mskm_knn_export",
 ]
@@ -137,6 +137,7 @@ def lib():
     L.mskm_solve_batch.argtypes = [vp, C.POINTER(vp), i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(SolveOpts),
                                    C.POINTER(vp), C.POINTER(Report)]
     L.mskm_residual.argtypes = [vp, vp, vp, vp, i32, dp, i32]
+    L.mskm_residual_noalloc.argtypes = [vp, vp, vp, vp, i32, vp]
     L.mskm_evaluate.argtypes = [vp, vp, vp, i32, vp, i64, vp, i32]
     L.mskm_mlp_train.argtypes = [vp, C.POINTER(TrainDesc), C.POINTER(vp), C.POINTER(C.c_float)]
     L.mskm_mlp_fit.argtypes = [vp, vp, vp, vp, i64, i32, C.c_float, i32, C.POINTER(C.c_float)]
@@ -427,6 +428,17 @@ def mskm_residual(ctx, h, alpha, f, nrhs: int = 1) -> np.ndarray:
     _check(lib().mskm_residual(ctx, h, ap, fp, nrhs, out.ctypes.data_as(C.POINTER(C.c_double)),
                                MSKM_IO_DEVICE if ad else 0), "mskm_residual")
     return out
+
+
+def mskm_residual_noalloc(ctx, h, alpha, f, rel_out, nrhs: int = 1) -> None:
+    """Allocation-free residual: alpha, f [N][nrhs] and rel_out [nrhs * ngroups]
+    are device tensors; enqueued on the context's stream (no host wait)."""
+    ap, ad = _ptr(alpha, np.float64)
+    fp, fd = _ptr(f, np.float64)
+    op, od = _ptr(rel_out, np.float64)
+    if not (ad and fd and od):
+        raise ValueError("alpha, f and rel_out must be device tensors")
+    _check(lib().mskm_residual_noalloc(ctx, h, ap, fp, nrhs, op), "mskm_residual_noalloc")
 
 
 def mskm_evaluate(ctx, h, alpha, query, out, nrhs: int = 1) -> None:

@@ -45,6 +45,8 @@ mskm_status mskm_create(int32_t device, void* hip_stream, mskm_ctx** out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(MSKM_EDEVICE, "no HIP device");
   if (device < 0 || device >= ndev) return fail(MSKM_EINVAL, "device index out of range");
   if (hipSetDevice(device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  // device address of the allocation-free residual's static scratch array
+  MSKM_TRY(mskm::noalloc_init(device));
   auto* c = new (std::nothrow) mskm_ctx();
   if (!c) return fail(MSKM_ENOMEM, "context allocation");
   c->device = device;
@@ -567,6 +569,31 @@ mskm_status mskm_residual(mskm_ctx* ctx, const mskm_hier* h, const double* alpha
   if (nrhs < 1) return fail(MSKM_EINVAL, "nrhs must be >= 1");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
   return mskm::residual(const_cast<mskm_hier*>(h), alpha, f, nrhs, rel_out, (flags & MSKM_IO_DEVICE) != 0);
+}
+
+namespace {
+// True when p is device memory of `device` (hipMalloc'd or managed).
+bool on_device(const void* p, int device) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();  // host memory the runtime does not know: clear the error
+    return false;
+  }
+  return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == device;
+}
+}  // namespace
+
+mskm_status mskm_residual_noalloc(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, const double* f,
+                                  int32_t nrhs, double* rel_out) {
+  if (!valid_ctx(ctx) || !h || !alpha || !f || !rel_out)
+    return fail(MSKM_EINVAL, "mskm_residual_noalloc: NULL argument");
+  if (nrhs < 1) return fail(MSKM_EINVAL, "nrhs must be >= 1");
+  if (!h->ctx || h->ctx->device != ctx->device)
+    return fail(MSKM_EINVAL, "mskm_residual_noalloc: hierarchy lives on another device");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  if (!on_device(alpha, ctx->device) || !on_device(f, ctx->device) || !on_device(rel_out, ctx->device))
+    return fail(MSKM_EINVAL, "mskm_residual_noalloc: alpha, f and rel_out must be device memory of the context's device");
+  return mskm::residual_noalloc(const_cast<mskm_hier*>(h), alpha, f, nrhs, rel_out);
 }
 
 mskm_status mskm_evaluate(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, int32_t nrhs, const double* query,

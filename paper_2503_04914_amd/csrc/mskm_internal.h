@@ -304,6 +304,10 @@ bool mr_supported(int nrhs);
 mskm_status solve_multi(mskm_hier* h, const double* f, int nrhs, const mskm_solve_opts* o, double* alpha,
                         mskm_report* rep);
 mskm_status residual(mskm_hier* h, const double* alpha, const double* f, int nrhs, double* rel_out, bool io_dev);
+// Allocation-free residual: device vectors in input order, partials in the
+// static scratch array (noalloc_init at context creation), stream-ordered.
+mskm_status noalloc_init(int device);
+mskm_status residual_noalloc(mskm_hier* h, const double* alpha, const double* f, int nrhs, double* rel_out);
 mskm_status evaluate(mskm_hier* h, const double* alpha, int nrhs, const double* query, int64_t nq, double* out,
                      bool io_dev);
 

@@ -8,6 +8,7 @@
 // permute inputs in and outputs out. Reductions are deterministic: each block
 // reduces in a fixed tree, the last block of a level to arrive sums the
 // per-block partials in block order (agent-scope fences + an arrival ticket).
+#include <mutex>
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -1448,11 +1449,36 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
 // with per-block partials of r.r and f.f (summed per level, then per group,
 // on the host in block order).
 
+// Vector access of the residual kernels: an internal-order device vector, or
+// an input-order [N][nrhs] vector read through the permutation (used by the
+// allocation-free residual, which keeps no internal-order copies).
+struct VecDirect {
+  const double* v;
+  __device__ __forceinline__ double operator()(int64_t i) const { return v[i]; }
+};
+struct VecPerm {
+  const double* v;
+  const int32_t* perm;
+  int32_t nrhs, r;
+  __device__ __forceinline__ double operator()(int64_t i) const { return v[(int64_t)perm[i] * nrhs + r]; }
+};
+
+// Lane gl's share of CSR row `row` dotted with x (FP64 values).
+template <int G, typename VA>
+__device__ __forceinline__ double res_row_part(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                               const double* __restrict__ val, const VA& x, int64_t row, int gl) {
+  const int64_t e = rp[row + 1];
+  double acc = 0.0;
+  for (int64_t k = rp[row] + gl; k < e; k += G) acc += val[k] * x(col[k]);
+  return acc;
+}
+
+template <typename VA>
 __global__ void __launch_bounds__(kBlock)
     k_residual64(const WorkTable wt, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
                  const double* __restrict__ dv, const int64_t* __restrict__ lrp, const int32_t* __restrict__ lc,
-                 const double* __restrict__ lv, const double* __restrict__ a, const double* __restrict__ f,
-                 double* __restrict__ part, double* __restrict__ rout) {
+                 const double* __restrict__ lv, const VA a, const VA f, double* __restrict__ part,
+                 double* __restrict__ rout) {
   constexpr int G = 16;
   __shared__ double sm[kBlock / kWave];
   const int blk = xcd_block_id(gridDim.x);
@@ -1460,13 +1486,14 @@ __global__ void __launch_bounds__(kBlock)
   const int gl = threadIdx.x % G;
   double srr = 0.0, sff = 0.0;
   for (int64_t i = row0 + threadIdx.x / G; i < row1; i += kBlock / G) {
-    double acc = csr_row_dot<G, double, double, double>(drp, dc, dv, a, i, gl);
-    acc += csr_row_dot<G, double, double, double>(lrp, lc, lv, a, i, gl);
+    double acc = group_sum<G>(res_row_part<G>(drp, dc, dv, a, i, gl));
+    acc += group_sum<G>(res_row_part<G>(lrp, lc, lv, a, i, gl));
     if (gl == 0) {
-      const double ri = f[i] - acc;
+      const double fi = f(i);
+      const double ri = fi - acc;
       if (rout) rout[i] = ri;
       srr += ri * ri;
-      sff += f[i] * f[i];
+      sff += fi * fi;
     }
   }
   srr = block_sum(srr, sm);
@@ -1483,10 +1510,10 @@ __global__ void __launch_bounds__(kBlock)
 // rounded down to a multiple of 4, entries outside the row masked; the arrays
 // carry a tail pad of kCsrPad entries. Lane gl's share of the row's dot (the
 // caller sums over the G lanes).
-template <int G>
+template <int G, typename VA>
 __device__ __forceinline__ double split_row_part(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                  const float* __restrict__ hi, const float* __restrict__ lo,
-                                                 const double* __restrict__ x, int64_t row, int gl) {
+                                                 const VA& x, int64_t row, int gl) {
   const int64_t s = rp[row], e = rp[row + 1];
   double acc = 0.0;
   for (int64_t k = (s & ~(int64_t)3) + (int64_t)gl * 4; k < e; k += (int64_t)G * 4) {
@@ -1497,19 +1524,19 @@ __device__ __forceinline__ double split_row_part(const int64_t* __restrict__ rp,
     const int32_t cv[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (k + u >= s && k + u < e) acc += ((double)hv[u] + (double)lv[u]) * x[cv[u]];
+      if (k + u >= s && k + u < e) acc += ((double)hv[u] + (double)lv[u]) * x(cv[u]);
   }
   return acc;
 }
 
 constexpr int kSplitG = 16;  // lanes per row of the split-value residual
 
+template <typename VA>
 __global__ void __launch_bounds__(kBlock)
     k_residual_split(const WorkTable wt, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
                      const float* __restrict__ dh, const float* __restrict__ dl, const int64_t* __restrict__ lrp,
                      const int32_t* __restrict__ lc, const float* __restrict__ lh, const float* __restrict__ ll,
-                     const double* __restrict__ a, const double* __restrict__ f, double* __restrict__ part,
-                     double* __restrict__ rout) {
+                     const VA a, const VA f, double* __restrict__ part, double* __restrict__ rout) {
   constexpr int G = kSplitG;
   __shared__ double sm[kBlock / kWave];
   const int blk = xcd_block_id(gridDim.x);
@@ -1520,10 +1547,11 @@ __global__ void __launch_bounds__(kBlock)
     double acc = split_row_part<G>(lrp, lc, lh, ll, a, i, gl) + split_row_part<G>(drp, dc, dh, dl, a, i, gl);
     acc = group_sum<G>(acc);
     if (gl == 0) {
-      const double ri = f[i] - acc;
+      const double fi = f(i);
+      const double ri = fi - acc;
       if (rout) rout[i] = ri;
       srr += ri * ri;
-      sff += f[i] * f[i];
+      sff += fi * fi;
     }
   }
   srr = block_sum(srr, sm);
@@ -1531,6 +1559,23 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) {
     part[2 * blk] = srr;
     part[2 * blk + 1] = sff;
+  }
+}
+
+// The residual product over the SpMV table's blocks: FP64 values when
+// stored, else the split FP32 values (an FP32-only hierarchy stores the
+// remainders). Partials r.r, f.f per block into part[2 b], part[2 b + 1].
+template <typename VA>
+static void launch_residual(mskm_hier* h, const VA& a, const VA& f, double* part, double* rout) {
+  hipStream_t s = h->ctx->stream;
+  const WorkTable& wt = h->wt_spmv;
+  if (h->diag.val && h->lower.val) {
+    hipLaunchKernelGGL(k_residual64<VA>, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->diag.rowptr, h->diag.col,
+                       h->diag.val, h->lower.rowptr, h->lower.col, h->lower.val, a, f, part, rout);
+  } else {
+    hipLaunchKernelGGL(k_residual_split<VA>, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->diag.rowptr, h->diag.col,
+                       h->diag.val32, h->diag.val32lo, h->lower.rowptr, h->lower.col, h->lower.val32,
+                       h->lower.val32lo, a, f, part, rout);
   }
 }
 
@@ -1563,16 +1608,10 @@ static mskm_status residual_internal(mskm_hier* h, SolveWS& W, const double* a, 
   hipStream_t s = h->ctx->stream;
   const WorkTable& wt = h->wt_spmv;
   double* part = W.part_res;
-  if (a_zero) {
+  if (a_zero)
     hipLaunchKernelGGL(k_residual_zero, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, f, part, rout);
-  } else if (h->diag.val && h->lower.val) {
-    hipLaunchKernelGGL(k_residual64, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->diag.rowptr, h->diag.col,
-                       h->diag.val, h->lower.rowptr, h->lower.col, h->lower.val, a, f, part, rout);
-  } else {  // FP32 values and their remainders
-    hipLaunchKernelGGL(k_residual_split, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->diag.rowptr, h->diag.col,
-                       h->diag.val32, h->diag.val32lo, h->lower.rowptr, h->lower.col, h->lower.val32,
-                       h->lower.val32lo, a, f, part, rout);
-  }
+  else
+    launch_residual(h, VecDirect{a}, VecDirect{f}, part, rout);
   const double* hp = W.h_part_res;
   hipError_t e = hipMemcpyAsync(W.h_part_res, part, 2 * (size_t)wt.nblocks * 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -2009,6 +2048,77 @@ mskm_status evaluate(mskm_hier* h, const double* alpha, int nrhs, const double* 
   if (own) (void)hipFree(ai);
   MSKM_HIP_TRY(hipGetLastError());
   return st;
+}
+
+
+// ------------------------------------------------ allocation-free residual
+//
+// mskm_residual_noalloc takes the per-block partials of the residual product
+// from `scratch`, a static device array (one copy per device, held until the
+// process ends), instead of the solver workspace, and reduces them per
+// group on the device: nothing is allocated and the host never waits. The
+// partials are fully rewritten by every product, so nothing needs clearing.
+// Calls that overlap on one device share the array and race.
+constexpr size_t kNoallocDoubles = (size_t)1 << 18;  // 2 MiB: r.r and f.f of up to 131072 blocks
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+constexpr int kNoallocDevices = 64;
+static double* g_scratch[kNoallocDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Device address of this device's `scratch` (the symbol's name is a host
+// stand-in and must not reach a kernel). Called with `device` current.
+mskm_status noalloc_init(int device) {
+  if (device < 0 || device >= kNoallocDevices) return fail(MSKM_ELIMIT, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return MSKM_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return fail(MSKM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch[device] = static_cast<double*>(p);
+  return MSKM_OK;
+}
+
+// rel[g] = sqrt(rr_g / ff_g) (sqrt(rr_g) when ff_g = 0), rr_g and ff_g the
+// sums of the partials of group g's levels; one workgroup per group, a
+// fixed-order sum (deterministic). A group's first level is its group index
+// (depth 0 of every group comes first, in group order).
+__global__ void __launch_bounds__(kBlock)
+    k_residual_rel(int L, const DevLevel* __restrict__ lev, const int32_t* __restrict__ lev_begin,
+                   const double* __restrict__ part, double* __restrict__ rel) {
+  __shared__ double sm[kBlock / kWave];
+  const int g = blockIdx.x;
+  double rr = 0.0, ff = 0.0;
+  for (int l = 0; l < L; ++l) {
+    if (lev[l].first != g) continue;
+    for (int b = lev_begin[l] + (int)threadIdx.x; b < lev_begin[l + 1]; b += kBlock) {
+      rr += part[2 * b];
+      ff += part[2 * b + 1];
+    }
+  }
+  rr = block_sum(rr, sm);
+  ff = block_sum(ff, sm);
+  if (threadIdx.x == 0) rel[g] = ff > 0.0 ? sqrt(rr / ff) : sqrt(rr);
+}
+
+mskm_status residual_noalloc(mskm_hier* h, const double* alpha, const double* f, int nrhs, double* rel_out) {
+  const WorkTable& wt = h->wt_spmv;
+  if (2 * (size_t)wt.nblocks > kNoallocDoubles)
+    return fail(MSKM_ELIMIT, "mskm_residual_noalloc: " + std::to_string(wt.nblocks) +
+                                 " row blocks exceed the scratch limit of 131072 (about 8.4M points)");
+  double* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    part = h->ctx->device < kNoallocDevices ? g_scratch[h->ctx->device] : nullptr;
+  }
+  if (!part) return fail(MSKM_ESTATE, "mskm_residual_noalloc: scratch not initialised for this device");
+  hipStream_t s = h->ctx->stream;
+  for (int r = 0; r < nrhs; ++r) {
+    launch_residual(h, VecPerm{alpha, h->perm, nrhs, r}, VecPerm{f, h->perm, nrhs, r}, part, nullptr);
+    hipLaunchKernelGGL(k_residual_rel, dim3(h->ngroups), dim3(kBlock), 0, s, h->L, h->d_lev, wt.lev_begin, part,
+                       rel_out + (size_t)r * h->ngroups);
+  }
+  MSKM_HIP_TRY(hipGetLastError());
+  return MSKM_OK;
 }
 
 }  // namespace mskm
