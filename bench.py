@@ -86,6 +86,15 @@ def spmv_kernel_name(code: int, t: str, col16: bool = False) -> str:
     return f"k_spmv_v<{g},{t}{',nontemporal' if kind == 2 else ''}>"
 
 
+def cg_product_kernel_name(code: int, col16: bool) -> str:
+    """Product kernel of the preconditioned CG iteration for diagonal variant
+    `code` (FP32 values and vectors): the sliced copy's for 4064 / 4032, else
+    the CSR one with `code % 1000` lanes per row."""
+    if code in (4064, 4032):
+        return f"k_cg_spmv1_sell<float,float,{'true' if code == 4064 and col16 else 'false'}>"
+    return f"k_cg_spmv1<{code % 1000},{'true' if code // 1000 else 'false'},float,float>"
+
+
 def calibrate(m, ctx, hd, f_dev, alpha_dev, base_opts: dict, label: str):
     """Fastest inner CG tolerance of the ladder whose solution verifies the
     target by the independent FP64 residual, with a 5% margin (the timed
@@ -109,10 +118,35 @@ def calibrate(m, ctx, hd, f_dev, alpha_dev, base_opts: dict, label: str):
     return min(passing)[1]
 
 
-def cpu_baseline(levels_sample: int, rtol: float):
-    """The oracle as it stands, single-threaded, on the first levels of the
-    same hierarchy: assembly + the paper's Jacobi/CG solve (L sweeps) to the
-    same 1e-8 relative residual."""
+def host_cpu() -> dict:
+    """Host facts for the CPU baseline record: logical CPUs and model name."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(levels_sample: int, levels_full: int, nnz_full_diag: list, nnz_full_lower: list):
+    """The oracle as it stands, single-threaded, on the first `levels_sample`
+    levels of the bench hierarchy: its assembly, then the block forward
+    substitution (eq. (mas)) level by level, each level's right-hand side by
+    the oracle's sparse products and its solve by the oracle's textbook CG from
+    zero, at the loosest tolerance of a short ladder whose result verifies the
+    1e-8 relative residual by the oracle's own FP64 residual.
+
+    The full workload's time is estimated from this sample level by level:
+    each measured level contributes its measured time; a missing finer level
+    takes the last measured level's time per CG iteration per diagonal
+    nonzero times its own diagonal nonzeros, times an iteration count grown
+    from the last measured level by the measured growth ratio of the last two
+    levels; its right-hand side product and assembly scale with its lower /
+    all nonzeros at the sample's measured rates."""
     import oracle
     import synth
     from oracle import multiscale as ms
@@ -123,20 +157,51 @@ def cpu_baseline(levels_sample: int, rtol: float):
         threadpool_limits = None
     h = synth.halton_hierarchy(levels_sample)
     f = synth.fourier_target(1000)(h.points)
-    ctxm = threadpool_limits(1) if threadpool_limits else None
+    lim = threadpool_limits(1) if threadpool_limits else None
     try:
         t0 = time.perf_counter()
         blk = ms.assemble(h.points, h.offsets, h.delta)
-        t1 = time.perf_counter()
-        a = oracle.monolithic_solve(blk, f, sweeps=h.levels, solver="cg", rtol=rtol)
-        t2 = time.perf_counter()
+        t_asm = time.perf_counter() - t0
+        fl = ms.split_levels(f, blk.sizes)
+        chosen = None
+        for rtol in (1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11):
+            alphas, rows = [], []
+            for l in range(h.levels):
+                t1 = time.perf_counter()
+                b = fl[l].copy()
+                for k in range(l):
+                    b -= blk.mat(l, k) @ alphas[k]
+                t2 = time.perf_counter()
+                a, it = ms.cg(blk.mat(l, l), b, rtol)
+                t3 = time.perf_counter()
+                alphas.append(a)
+                rows.append({"level": l, "rhs_s": t2 - t1, "cg_s": t3 - t2, "cg_iters": it,
+                             "nnz_diag": blk.nnz(l, l), "nnz_lower": sum(blk.nnz(l, k) for k in range(l))})
+            rel = float(oracle.residual(blk, np.concatenate(alphas), f)[0])
+            log(f"cpu baseline: oracle rtol {rtol:g} -> rel. residual {rel:.3e}")
+            if rel <= TARGET:
+                chosen = rtol
+                break
     finally:
-        if ctxm is not None:
-            ctxm.__exit__(None, None, None)
-    rel = oracle.residual(blk, a, f)[0]
-    nnz = sum(blk.nnz(k, j) for k in range(h.levels) for j in range(k + 1))
-    return {"assemble_ms": (t1 - t0) * 1e3, "solve_ms": (t2 - t1) * 1e3, "rel_residual": rel,
-            "n_points": h.n_total, "levels": h.levels, "nnz": nnz}
+        if lim is not None:
+            lim.__exit__(None, None, None)
+    if chosen is None:
+        raise RuntimeError("cpu baseline: no oracle tolerance reached 1e-8")
+    nnz_sample = sum(blk.nnz(k, j) for k in range(h.levels) for j in range(k + 1))
+    last, prev = rows[-1], rows[-2]
+    growth = last["cg_iters"] / max(prev["cg_iters"], 1)
+    s_per_iter_nnz = last["cg_s"] / max(last["cg_iters"] * last["nnz_diag"], 1)
+    s_per_lower_nnz = last["rhs_s"] / max(last["nnz_lower"], 1)
+    est = [r["rhs_s"] + r["cg_s"] for r in rows]
+    iters = last["cg_iters"]
+    for l in range(levels_sample, levels_full):
+        iters *= growth
+        est.append(iters * nnz_full_diag[l] * s_per_iter_nnz + nnz_full_lower[l] * s_per_lower_nnz)
+    nnz_full = sum(nnz_full_diag) + sum(nnz_full_lower)
+    return {"solve_ms_est": sum(est) * 1e3, "assemble_ms_est": t_asm * nnz_full / nnz_sample * 1e3,
+            "sample_solve_ms": sum(r["rhs_s"] + r["cg_s"] for r in rows) * 1e3, "sample_assemble_ms": t_asm * 1e3,
+            "rel_residual": rel, "cg_rtol": chosen, "levels": rows, "iter_growth": growth,
+            "n_points": h.n_total, "nnz": nnz_sample}
 
 
 def batched(m, ctx, hd, h, pts_dev, dev, fast_opts, rt_fast, nrhs, count):
@@ -309,6 +374,47 @@ def paper_workload(m, ctx, dev, levels_list):
     return out
 
 
+def thresholded(m, ctx, dev, L: int, Ts):
+    """Section 4's thresholded Jacobi on the Table 1 grids (Franke target):
+    the truncated Lagrange blocks X~(T) built on the device (Lagrange
+    coefficients by many-right-hand-side CG), then the perturbed split as the
+    inner solve of an FP64 residual refinement to 1e-8 (Jacobi sweeps = one
+    product with X~ each, then block-Jacobi preconditioned CG on every
+    level)."""
+    import torch
+
+    import synth
+
+    h = synth.table1_hierarchy(L)
+    f = torch.from_numpy(synth.franke(h.points)).to(dev)
+    pts = torch.from_numpy(h.points).to(dev)
+    a = torch.zeros_like(f)
+    hd = m.mskm_hier_create(ctx, pts, h.offsets, h.delta, fp64=True, fp32=False)
+    st = m.mskm_hier_stats_get(hd)
+    out = {"workload": f"table1_L{L}_franke", "n_points": st["n_total"], "nnz_lower_T": st["nnz_lower"], "rows": []}
+    for T in Ts:
+        status, t = m.mskm_trunc_create(ctx, hd, float(T))
+        info = m.mskm_trunc_info(t, L)
+        o = m.solve_opts(cg_rtol=1e-6, target_rel_residual=TARGET, max_refine=40,
+                         precond=m.MSKM_PRECOND_BLOCK_JACOBI)
+        m.mskm_trunc_solve(ctx, t, f, a, o)
+        ts = []
+        for _ in range(3):
+            r = m.mskm_trunc_solve(ctx, t, f, a, o)
+            ts.append(r.report["solve_ms"])
+        rel = float(m.mskm_residual(ctx, hd, a, f)[0])
+        out["rows"].append({"T": T, "status": status, "build_ms": round(info["build_ms"], 2), "nnz": info["nnz"],
+                            "lagrange_cg_iters": info["cg_iters"], "time_to_1e-8_ms": round(float(np.median(ts)), 3),
+                            "rounds": r.report["refine_steps"], "cg_iters_total": r.report["cg_iters_total"],
+                            "rel_residual": rel, "solve_status": r.status})
+        m.mskm_trunc_destroy(t)
+    log("thresholded", out)
+    m.mskm_hier_destroy(hd)
+    del f, pts, a
+    torch.cuda.empty_cache()
+    return out
+
+
 def train_warm_start(m, ctx, args):
     """Train the warm-start network on (rhs -> correction) pairs from plain
     solves of a 6-level Halton hierarchy with random Fourier targets."""
@@ -338,7 +444,7 @@ def main():
     ap.add_argument("--levels", type=int, default=8)
     ap.add_argument("--spmv-repeats", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-levels", type=int, default=6)
+    ap.add_argument("--cpu-levels", type=int, default=7)
     ap.add_argument("--nq", type=int, default=65536)
     ap.add_argument("--rhs", type=int, default=256, help="right-hand sides of the batched solve (0: skip)")
     ap.add_argument("--train-rhs", type=int, default=16)
@@ -348,14 +454,17 @@ def main():
     ap.add_argument("--fast-rtol", type=float, default=0.0,
                     help="inner CG tolerance of the fast form (default: calibrated, the fastest that verifies 1e-8)")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D mixed-precision workload")
-    ap.add_argument("--paper-levels", default="7,9,11",
+    ap.add_argument("--paper-levels", default="7,8,9,10,11",
                     help="Table 1 grid hierarchies (comma-separated L) of the paper's own workload ('' to skip)")
+    ap.add_argument("--trunc-levels", type=int, default=7,
+                    help="Table 1 levels of the thresholded-Jacobi workload (0: skip)")
     ap.add_argument("--spmv-only", action="store_true",
                     help="assemble, autotune, then only time one SpMV operator and a 1 GiB streaming copy kernel "
                          "(the counter-collection runs)")
     ap.add_argument("--spmv-variant", type=int, default=0,
                     help="with --spmv-only: pin this SpMV variant code instead of autotuning")
-    ap.add_argument("--spmv-op", choices=("diag", "lower", "full"), default="diag", help="with --spmv-only")
+    ap.add_argument("--spmv-op", choices=("diag", "lower", "full", "cg"), default="diag",
+                    help="with --spmv-only (cg: the CG product kernel on the finest level)")
     ap.add_argument("--spmv-prec", choices=("fp32", "fp64"), default="fp32", help="with --spmv-only")
     ap.add_argument("--batch-count", type=int, default=64, help="hierarchies of the batched solve (0: skip)")
     args = ap.parse_args()
@@ -385,7 +494,7 @@ def main():
     hd = m.mskm_hier_create(ctx, pts_dev, h.offsets, h.delta, fp64=True, fp32=True)
     if args.spmv_only:
         st = m.mskm_hier_stats_get(hd)
-        op = {"diag": m.MSKM_OP_DIAG, "lower": m.MSKM_OP_LOWER, "full": m.MSKM_OP_FULL}[args.spmv_op]
+        op = {"diag": m.MSKM_OP_DIAG, "lower": m.MSKM_OP_LOWER, "full": m.MSKM_OP_FULL, "cg": m.MSKM_OP_DIAG}[args.spmv_op]
         prec = m.MSKM_PREC_FP32 if args.spmv_prec == "fp32" else m.MSKM_PREC_FP64
         if args.spmv_variant:
             m.mskm_set_spmv_width(hd, op, prec, args.spmv_variant)
@@ -394,8 +503,13 @@ def main():
         dt = torch.float32 if prec == m.MSKM_PREC_FP32 else torch.float64
         x = torch.randn(N, dtype=dt, device=dev)
         y = torch.empty_like(x)
-        m.mskm_apply_internal(ctx, hd, op, x, y, prec=prec, repeats=2)
-        ms = m.mskm_apply_internal(ctx, hd, op, x, y, prec=prec, repeats=args.spmv_repeats)
+        if args.spmv_op == "cg":  # the CG product kernel on the finest level
+            top = args.levels - 1
+            m.mskm_cg_product_time(ctx, hd, top, prec, repeats=2)
+            ms = m.mskm_cg_product_time(ctx, hd, top, prec, repeats=args.spmv_repeats)
+        else:
+            m.mskm_apply_internal(ctx, hd, op, x, y, prec=prec, repeats=2)
+            ms = m.mskm_apply_internal(ctx, hd, op, x, y, prec=prec, repeats=args.spmv_repeats)
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
         dst = torch.empty_like(src)
         torch.mul(src, 1.0, out=dst)
@@ -406,20 +520,28 @@ def main():
             torch.mul(src, 1.0, out=dst)  # a plain streaming kernel: reads 1 GiB, writes 1 GiB
         e1.record()
         torch.cuda.synchronize()
-        nnz = {"diag": st["nnz_diag"], "lower": st["nnz_lower"], "full": st["nnz_diag"] + st["nnz_lower"]}[args.spmv_op]
         sv = 4 if prec == m.MSKM_PREC_FP32 else 8
         code = m.mskm_spmv_width(hd, op, prec)
-        sc = diag_col_bytes(code, st) if args.spmv_op == "diag" else 4
-        b = spmv_bytes(nnz, N, 2 if args.spmv_op == "full" else 1, sv, sv, sc)
+        if args.spmv_op == "cg":
+            top = args.levels - 1
+            n_top = int(h.offsets[top + 1] - h.offsets[top])
+            b = spmv_bytes(m.block_nnz(ctx, hd, top, top), n_top, 1, sv, sv) + n_top * sv
+            kname = cg_product_kernel_name(code, bool(st["sell_col16"]))
+        else:
+            nnz = {"diag": st["nnz_diag"], "lower": st["nnz_lower"], "full": st["nnz_diag"] + st["nnz_lower"]}[args.spmv_op]
+            sc = diag_col_bytes(code, st) if args.spmv_op == "diag" else 4
+            b = spmv_bytes(nnz, N, 2 if args.spmv_op == "full" else 1, sv, sv, sc)
+            kname = spmv_kernel_name(code, "float" if sv == 4 else "double", st["sell_col16"])
         print(json.dumps({"op": args.spmv_op, "prec": args.spmv_prec, "ms": ms, "bytes": b, "GBps": b / ms / 1e6,
-                          "variant": code, "sell_col16": st["sell_col16"],
-                          "kernel": spmv_kernel_name(code, "float" if sv == 4 else "double", st["sell_col16"]),
+                          "variant": code, "sell_col16": st["sell_col16"], "kernel": kname,
                           "copy_bytes_each_way": 1 << 30, "copy_ms": e0.elapsed_time(e1) / args.spmv_repeats}))
         m.mskm_hier_destroy(hd)
         m.mskm_destroy(ctx)
         return
     stats = m.mskm_hier_stats_get(hd)
     log("hierarchy", stats)
+    nnz_levels = {"diag": [m.block_nnz(ctx, hd, l, l) for l in range(args.levels)],
+                  "lower": [sum(m.block_nnz(ctx, hd, l, j) for j in range(l)) for l in range(args.levels)]}
     tune = m.mskm_autotune(ctx, hd, repeats=5)
     widths = {f"{op}_{pr}": m.mskm_spmv_width(hd, i, j) for i, op in enumerate(("diag", "lower", "full"))
               for j, pr in enumerate(("fp64", "fp32"))}
@@ -438,7 +560,10 @@ def main():
         cmp = {}
         # the warm start replaces the preconditioner: compare it with plain CG from zero
         for label, extra in (("zero_start", {"precond": m.MSKM_PRECOND_NONE}),
-                             ("learned_start", {"precond": m.MSKM_PRECOND_LEARNED, "mlp": net.value})):
+                             ("learned_start", {"precond": m.MSKM_PRECOND_LEARNED, "mlp": net.value}),
+                             ("learned_start_block_jacobi", {"warm_start": m.MSKM_START_LEARNED, "mlp": net.value}),
+                             ("flexible_cg_learned_preconditioner",
+                              {"precond": m.MSKM_PRECOND_FLEX_LEARNED, "mlp": net.value})):
             o = m.solve_opts(cg_rtol=rt_fast, **dict(fast_opts, **extra))
             m.mskm_solve(ctx, hd, f_ho, alpha_dev, o)
             ts = []
@@ -455,11 +580,17 @@ def main():
         o = m.solve_opts(cg_rtol=rt_fast, **fast_opts)
         m.mskm_solve(ctx, hd, f_ho, alpha_dev, o)
         learned["block_jacobi_fast_form_ms"] = round(m.mskm_solve(ctx, hd, f_ho, alpha_dev, o).report["solve_ms"], 3)
-        use = (cmp["learned_start"]["time_to_1e-8_ms"] < learned["block_jacobi_fast_form_ms"]
-               and cmp["learned_start"]["rel_residual"] <= TARGET)
-        learned["used_in_fast_form"] = bool(use)
+        # the fastest learned form that verifies the target replaces the fast form if it beats it
+        best = min(("learned_start", "learned_start_block_jacobi", "flexible_cg_learned_preconditioner"),
+                   key=lambda k: cmp[k]["time_to_1e-8_ms"] if cmp[k]["rel_residual"] <= TARGET else float("inf"))
+        use = (cmp[best]["time_to_1e-8_ms"] < learned["block_jacobi_fast_form_ms"]
+               and cmp[best]["rel_residual"] <= TARGET)
+        learned["used_in_fast_form"] = best if use else None
         if use:
-            fast_opts = dict(fast_opts, precond=m.MSKM_PRECOND_LEARNED, mlp=net.value)
+            extra = {"learned_start": {"precond": m.MSKM_PRECOND_LEARNED},
+                     "learned_start_block_jacobi": {"warm_start": m.MSKM_START_LEARNED},
+                     "flexible_cg_learned_preconditioner": {"precond": m.MSKM_PRECOND_FLEX_LEARNED}}[best]
+            fast_opts = dict(fast_opts, mlp=net.value, **extra)
     fast = m.solve_opts(cg_rtol=rt_fast, **fast_opts)
 
     def step():
@@ -531,18 +662,29 @@ def main():
         b = spmv_bytes(nnz, N, nrp, sval, sx, sc)
         spmv[name] = {"ms": ms, "bytes": b, "GBps": b / ms / 1e6}
     log("spmv", spmv)
+    # the dominant kernel of the timed step: the CG product on the diagonal
+    # blocks, FP32, at the launch shape of the finest level (its largest launch)
+    top = args.levels - 1
+    n_top = int(h.offsets[top + 1] - h.offsets[top])
+    m.mskm_cg_product_time(ctx, hd, top, m.MSKM_PREC_FP32, repeats=3)
+    cg_ms = m.mskm_cg_product_time(ctx, hd, top, m.MSKM_PREC_FP32, repeats=args.spmv_repeats)
+    # SpMV bytes of the level (values + int32 columns, row metadata, x read, q
+    # written) + the second vector its dot partials read (r)
+    cg_bytes = spmv_bytes(nnz_levels["diag"][top], n_top, 1, 4, 4) + n_top * 4
+    cg_stored = spmv_bytes(nnz_levels["diag"][top], n_top, 1, 4, 4, diag_col_bytes(widths["diag_fp32"], stats)) + n_top * 4
+    cg_kernel = cg_product_kernel_name(widths["diag_fp32"], bool(stats["sell_col16"]))
+    log("cg product", cg_kernel, cg_ms, cg_bytes / cg_ms / 1e6)
     bt = batched(m, ctx, hd, h, pts_dev, dev, fast_opts, rt_fast, args.rhs, args.batch_count)
     m.mskm_hier_destroy(hd)
     u3 = None if args.no_3d else uniform3d(m, ctx, dev, args)
     pw = paper_workload(m, ctx, dev, [int(x) for x in args.paper_levels.split(",") if x]) if args.paper_levels else None
+    thr = thresholded(m, ctx, dev, args.trunc_levels, (2, 4, 6)) if args.trunc_levels > 0 else None
     m.mskm_destroy(ctx)
 
-    # dominant kernel of the timed step: the CG products on the diagonal blocks (FP32)
-    dom = spmv["diag_fp32"]
-    dom_kernel = spmv_kernel_name(widths["diag_fp32"], "float", stats["sell_col16"])
-    pmc = PMC_TRAFFIC.get((f"halton2d_L{args.levels}", dom_kernel))
+    pmc = PMC_TRAFFIC.get((f"halton2d_L{args.levels}", cg_kernel, f"level {top}"))
     traffic = None if pmc is None else int(pmc["fetch_kib"] * pmc["fetch_scale"] * 1024
                                            + pmc["write_kib"] * pmc["write_scale"] * 1024)
+    cg_gbps = cg_bytes / cg_ms / 1e6
     out = {
         "metric": "time-to-1e-8 rel. residual + kernel SpMV GB/s, plain FP64 vs mixed/learned",
         "value": round(fast_ms, 3),
@@ -560,7 +702,7 @@ def main():
                    "nnz": nnz_d + nnz_l, "kernel": "wendland_3_1", "neighbours_per_row": 40,
                    "target": "fourier32_seed1000", "parallelism": "single_gpu"},
         "fast_form": {"name": "mixed FP32/FP64-refined, block forward substitution, "
-                      + ("learned warm start" if learned and learned.get("used_in_fast_form")
+                      + (learned["used_in_fast_form"].replace("_", " ") if learned and learned.get("used_in_fast_form")
                          else "cell block-Jacobi preconditioned CG"),
                       "cg_rtol": rt_fast,
                       "time_to_1e-8_ms": round(fast_ms, 3), "steps": steps},
@@ -575,24 +717,31 @@ def main():
         "learned": learned,
         "uniform3d_mixed": u3,
         "paper_table1_franke": pw,
-        "spmv_GBps": round(dom["GBps"], 1),
+        "thresholded_jacobi": thr,
+        "spmv_GBps": round(spmv["diag_fp32"]["GBps"], 1),
         "spmv_widths": widths,
-        "roofline": {"bound": "hbm", "achieved": round(dom["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(dom["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": dom_kernel + " (D, the diagonal blocks of all levels, FP32 values: the CG products)",
-                     "algorithmic_bytes": dom["bytes"], "ms": round(dom["ms"], 5)},
+        "roofline": {"bound": "hbm", "achieved": round(cg_gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(cg_gbps / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": cg_kernel + f" (CG product q = A_l z with its dot partials, level {top}: "
+                               f"{n_top} rows, {nnz_levels['diag'][top]} nonzeros, FP32)",
+                     "algorithmic_bytes": cg_bytes, "ms": round(cg_ms, 5),
+                     "stored_bytes": cg_stored, "frac_stored_bytes": round(cg_stored / cg_ms / 1e6 / HBM_PEAK_GBS, 4)},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 1 thread)")
-        cb = cpu_baseline(args.cpu_levels, 1e-7)
-        scale = (nnz_d + nnz_l) / cb["nnz"]
+        cb = cpu_baseline(args.cpu_levels, args.levels, nnz_levels["diag"], nnz_levels["lower"])
         out["cpu_baseline"] = {
-            "value": round(cb["solve_ms"] * scale, 1), "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": f"first {cb['levels']} of the {args.levels} Halton levels ({cb['n_points']} points, "
-                      f"{cb['nnz']} nonzeros): the oracle's Jacobi sweeps ({cb['levels']}) with CG rtol 1e-7 to "
-                      f"rel. residual {cb['rel_residual']:.2e}, single thread; value = the sample's solve time "
-                      f"x {scale:.1f} (nonzero ratio of the full workload, linear extrapolation)",
-            "sample_solve_ms": round(cb["solve_ms"], 1), "sample_assemble_ms": round(cb["assemble_ms"], 1)}
+            "value": round(cb["solve_ms_est"], 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"first {len(cb['levels'])} of the {args.levels} Halton levels ({cb['n_points']} points, "
+                      f"{cb['nnz']} nonzeros), the oracle's block forward substitution with textbook CG from zero "
+                      f"(rtol {cb['cg_rtol']:g}) to rel. residual {cb['rel_residual']:.2e}, single thread, measured "
+                      f"per level; value = measured levels + each missing finer level estimated from the last "
+                      f"measured one (time per CG iteration per diagonal nonzero, iterations x "
+                      f"{cb['iter_growth']:.2f} per level, the measured growth of the last two levels)",
+            "sample_solve_ms": round(cb["sample_solve_ms"], 1), "sample_assemble_ms": round(cb["sample_assemble_ms"], 1),
+            "assemble_ms_est": round(cb["assemble_ms_est"], 1),
+            "per_level": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for r in cb["levels"]],
+            **host_cpu()}
     print(json.dumps(out), flush=True)
 
 

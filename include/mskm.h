@@ -235,6 +235,17 @@ mskm_status mskm_apply_internal(mskm_ctx* ctx, const mskm_hier* h, int32_t op, i
  * counts start with the tuned widths. */
 mskm_status mskm_autotune(mskm_ctx* ctx, mskm_hier* h, int32_t repeats, float* times_ms);
 
+/* Mean device time (avg_ms, host) of the product kernel of the
+ * preconditioned CG iteration (Theorem cg; q = A_l z with the dot partials
+ * z.q, z.r and r.r the iteration needs) on level `level` alone, in the
+ * diagonal variant chosen for prec and the vector precision of prec, launched
+ * `repeats` (>= 1) times back to back between two HIP events on the context
+ * stream: the launch shape of the solver's CG products, for bandwidth
+ * measurement. Overwrites the hierarchy's solver workspace (no solve may be
+ * in flight on it). */
+mskm_status mskm_cg_product_time(mskm_ctx* ctx, mskm_hier* h, int32_t level, int32_t prec, int32_t repeats,
+                                 float* avg_ms);
+
 /* Current SpMV variant code for op (MSKM_OP_*) and prec (MSKM_PREC_*). */
 mskm_status mskm_spmv_width(const mskm_hier* h, int32_t op, int32_t prec, int32_t* width);
 
@@ -252,9 +263,23 @@ enum { MSKM_ALG_MONOLITHIC = 0, MSKM_ALG_SEQUENTIAL = 1 };
  * than 32 points cut into chunks); built at the first such solve and kept
  * with the hierarchy. MSKM_PRECOND_LEARNED: no preconditioner, the network's
  * prediction as each level's CG start (the same as MSKM_PRECOND_NONE with
- * warm_start = MSKM_START_LEARNED). Both are build extensions (the paper's
- * CG is plain); the solution they converge to is the same. */
-enum { MSKM_PRECOND_NONE = 0, MSKM_PRECOND_LEARNED = 1, MSKM_PRECOND_BLOCK_JACOBI = 2 };
+ * warm_start = MSKM_START_LEARNED). MSKM_PRECOND_FLEX_LEARNED: the network
+ * as a preconditioner applied at every iteration, z = M^-1 r + net(r) (M the
+ * block-Jacobi matrix above, net(r) the network's prediction of A_l^-1 r from
+ * r's stencils, see the learned warm start below), inside flexible CG
+ * (Notay's FCG with one previous direction, which tolerates a preconditioner
+ * that changes between iterations); sequential algorithm, one right-hand
+ * side, zero start. Block-Jacobi PCG is its fallback: a level whose r.r has
+ * not fallen by 4x over a window of 8 iterations drops the network for the
+ * rest of its solve (counted in mskm_report.warm_fallbacks). All are build
+ * extensions (the paper's CG is plain); the solution they converge to is the
+ * same: the stopping test is on the true residual. */
+enum {
+  MSKM_PRECOND_NONE = 0,
+  MSKM_PRECOND_LEARNED = 1,
+  MSKM_PRECOND_BLOCK_JACOBI = 2,
+  MSKM_PRECOND_FLEX_LEARNED = 3
+};
 
 /* Start of the per-level CG solves (mskm_solve_opts.warm_start):
  *   MSKM_START_ZERO      x0 = 0 (the paper's Algorithm 1);
@@ -279,8 +304,9 @@ typedef struct {
   int32_t warm_start;     /* MSKM_START_ZERO, _PREVIOUS or _LEARNED */
   double target_rel_residual; /* mixed path: stop refining when ||f-T alpha||/||f|| <= this */
   int32_t max_refine;     /* mixed path: cap on refinement steps; <= 0 means 10 */
-  int32_t precond;        /* MSKM_PRECOND_NONE, _BLOCK_JACOBI or _LEARNED (learned start, no preconditioner) */
-  const mskm_mlp* mlp;    /* network for MSKM_START_LEARNED / MSKM_PRECOND_LEARNED */
+  int32_t precond;        /* MSKM_PRECOND_NONE, _BLOCK_JACOBI, _LEARNED (learned start, no preconditioner)
+                             or _FLEX_LEARNED (learned preconditioner in flexible CG) */
+  const mskm_mlp* mlp;    /* network for MSKM_START_LEARNED / MSKM_PRECOND_LEARNED / _FLEX_LEARNED */
   int32_t check_every;    /* CG convergence poll interval; <= 0 means 8 */
   int32_t flags;          /* MSKM_IO_DEVICE */
 } mskm_solve_opts;
@@ -297,7 +323,8 @@ typedef struct {
   int32_t cg_iters_last[64];     /* iterations of each level's last CG solve (levels <= 64) */
   double rel_residual;           /* ||f - T alpha|| / ||f|| (FP64), max over rhs */
   double solve_ms;               /* device time of the solve */
-  int32_t warm_fallbacks;        /* learned warm starts rejected (||b - A x0|| >= ||b||) */
+  int32_t warm_fallbacks;        /* learned warm starts rejected (||b - A x0|| >= ||b||), or levels
+                                    whose flexible solve dropped the network */
 } mskm_report;
 
 /* alpha = T_L^-1 f per right-hand side (Section 3). f, alpha: [N][nrhs] FP64
@@ -358,6 +385,64 @@ mskm_status mskm_residual_noalloc(mskm_ctx* ctx, const mskm_hier* h, const doubl
  * query: [nq][dim]; out: [nq][nrhs]. */
 mskm_status mskm_evaluate(mskm_ctx* ctx, const mskm_hier* h, const double* alpha, int32_t nrhs, const double* query,
                           int64_t nq, double* out, int32_t flags);
+
+/* ------------------------------------------------------- thresholded Jacobi
+ *
+ * Section 4 ("Thresholding"): the blocks of M = I - T' are frak X_{kj} =
+ * B_{kj} A_j^-1 (k > j); entry (i, n) is the Lagrange function chi_n^(j) of
+ * centre x_n^(j) (coefficients A_j^-1 e_n, so chi_n^(j)(x_m^(j)) = delta_nm)
+ * evaluated at x_i^(k). The truncated block frak X~_{kj}(T) keeps entry
+ * (i, n) iff ||x_i^(k) - x_n^(j)|| < T q_j, q_j the separation distance of
+ * level j (half the smallest distance between two of its points; squared
+ * distances as in the support test, compared with (T q_j)^2 in FP64), and is
+ * zero elsewhere (eq. (perturbedmatrix)). The perturbed split
+ * (eq. (perturbed_split)) solves (I - M~(T)) beta~ = f by Jacobi sweeps, one
+ * product with the truncated blocks each and no inner solve, then
+ * alpha~ = D^-1 beta~. */
+typedef struct mskm_trunc mskm_trunc;
+
+/* Builds every frak X~_{kj}(T), k > j, of hierarchy h (or of each hierarchy
+ * of a batch object) on the device: q_j per level, the pattern by a cell
+ * search of radius T q_j, and the values from A_j^-1 e_n computed by CG
+ * (many right-hand sides, up to 512 centres per launch sequence, from zero,
+ * to ||r|| <= cg_rtol) then chi_n(x_i) = sum_m B_kj[i][m] (A_j^-1 e_n)[m].
+ * T = INFINITY keeps every entry (the dense M). Needs FP64 block values
+ * (MSKM_ESTATE otherwise). The object keeps its own device memory (12 bytes
+ * per kept entry); destroy it before or after h (after h is destroyed, the
+ * calls below return MSKM_ESTATE). MSKM_ENOCONV (object returned) when a
+ * coefficient solve hit its cap of 20000 iterations. MSKM_ELIMIT when a
+ * level of more than 65536 points has no two points closer than its support
+ * radius. */
+mskm_status mskm_trunc_create(mskm_ctx* ctx, mskm_hier* h, double T, double cg_rtol, mskm_trunc** out);
+mskm_status mskm_trunc_destroy(mskm_trunc* t);
+
+/* q: host [L] separation distances (INFINITY for levels of fewer than two
+ * points), nnz: kept entries over all blocks, cg_iters: CG iterations of the
+ * coefficient solves (sum over centres), build_ms: device time of the build.
+ * Each output is nullable. */
+mskm_status mskm_trunc_info(const mskm_trunc* t, double* q, int64_t* nnz, int64_t* cg_iters, double* build_ms);
+
+/* frak X~_{row_level, col_level}(T) in the canonical CSR of
+ * mskm_export_block (rows in input order of row_level, columns = input index
+ * within col_level, ascending; host arrays; col == NULL queries the count).
+ * The column level must be coarser than the row level. */
+mskm_status mskm_trunc_export_block(mskm_ctx* ctx, const mskm_trunc* t, int32_t row_level, int32_t col_level,
+                                    int64_t* rowptr, int32_t* col, double* val, int64_t* nnz_out);
+
+/* alpha~ of the perturbed split for one right-hand side f ([N] FP64, input
+ * order; device pointers with MSKM_IO_DEVICE in opts->flags). FP64 only
+ * (opts->precision = MSKM_PREC_FP64). Jacobi sweeps: opts->sweeps, <= 0
+ * meaning L-1 (exact for the perturbed system, whose M~ is strictly block
+ * lower); then CG on every level (opts->cg_rtol, max_cg_iters,
+ * MSKM_PRECOND_NONE or _BLOCK_JACOBI). With opts->target_rel_residual > 0 (the
+ * default options carry 1e-8) the perturbed solve is the inner solve of an
+ * FP64 residual refinement of the exact system: alpha += alpha~(f - T_L alpha)
+ * until ||f - T_L alpha|| / ||f|| <= target or max_refine rounds (MSKM_ENOCONV
+ * then); with target <= 0, one perturbed solve, alpha = alpha~. rep (nullable)
+ * reports sweeps per round, rounds (refine_steps), CG iterations, the final
+ * FP64 relative residual of the exact system and the device time. */
+mskm_status mskm_trunc_solve(mskm_ctx* ctx, const mskm_trunc* t, const double* f, const mskm_solve_opts* opts,
+                             double* alpha, mskm_report* rep);
 
 /* --------------------------------------------------------- learned warm start
  *

@@ -31,7 +31,7 @@ MSKM_IO_DEVICE = 1
 MSKM_OP_DIAG, MSKM_OP_LOWER, MSKM_OP_FULL = 0, 1, 2
 MSKM_PREC_FP64, MSKM_PREC_FP32 = 0, 1
 MSKM_ALG_MONOLITHIC, MSKM_ALG_SEQUENTIAL = 0, 1
-MSKM_PRECOND_NONE, MSKM_PRECOND_LEARNED, MSKM_PRECOND_BLOCK_JACOBI = 0, 1, 2
+MSKM_PRECOND_NONE, MSKM_PRECOND_LEARNED, MSKM_PRECOND_BLOCK_JACOBI, MSKM_PRECOND_FLEX_LEARNED = 0, 1, 2, 3
 MSKM_START_ZERO, MSKM_START_PREVIOUS, MSKM_START_LEARNED = 0, 1, 2
 
 EXPORTED = [
@@ -39,9 +39,10 @@ EXPORTED = [
     "mskm_hier_create", "mskm_hier_create_batch", "mskm_hier_destroy", "mskm_hier_stats_get", "mskm_hier_offsets",
     "mskm_hier_level_info",
     "mskm_export_block", "mskm_export_rows", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
-    "mskm_autotune", "mskm_spmv_width", "mskm_set_spmv_width",
+    "mskm_autotune", "mskm_spmv_width", "mskm_set_spmv_width", "mskm_cg_product_time",
     "mskm_solve_opts_default", "mskm_solve", "mskm_solve_batch", "mskm_residual", "mskm_residual_noalloc",
     "mskm_evaluate",
+    "mskm_trunc_create", "mskm_trunc_destroy", "mskm_trunc_info", "mskm_trunc_export_block", "mskm_trunc_solve",
     "mskm_mlp_train", "mskm_mlp_fit", "mskm_mlp_destroy", "mskm_mlp_save", "mskm_mlp_load", "mskm_mlp_predict", "mskm_knn_export",
 ]
 
@@ -131,6 +132,7 @@ def lib():
     L.mskm_autotune.argtypes = [vp, vp, i32, C.POINTER(C.c_float)]
     L.mskm_spmv_width.argtypes = [vp, i32, i32, C.POINTER(i32)]
     L.mskm_set_spmv_width.argtypes = [vp, i32, i32, i32]
+    L.mskm_cg_product_time.argtypes = [vp, vp, i32, i32, i32, C.POINTER(C.c_float)]
     L.mskm_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
     L.mskm_solve_opts_default.restype = None
     L.mskm_solve.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(Report)]
@@ -139,6 +141,11 @@ def lib():
     L.mskm_residual.argtypes = [vp, vp, vp, vp, i32, dp, i32]
     L.mskm_residual_noalloc.argtypes = [vp, vp, vp, vp, i32, vp]
     L.mskm_evaluate.argtypes = [vp, vp, vp, i32, vp, i64, vp, i32]
+    L.mskm_trunc_create.argtypes = [vp, vp, C.c_double, C.c_double, C.POINTER(vp)]
+    L.mskm_trunc_destroy.argtypes = [vp]
+    L.mskm_trunc_info.argtypes = [vp, vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(C.c_double)]
+    L.mskm_trunc_export_block.argtypes = [vp, vp, i32, i32, vp, vp, vp, C.POINTER(i64)]
+    L.mskm_trunc_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), vp, C.POINTER(Report)]
     L.mskm_mlp_train.argtypes = [vp, C.POINTER(TrainDesc), C.POINTER(vp), C.POINTER(C.c_float)]
     L.mskm_mlp_fit.argtypes = [vp, vp, vp, vp, i64, i32, C.c_float, i32, C.POINTER(C.c_float)]
     L.mskm_mlp_destroy.argtypes = [vp]
@@ -276,6 +283,13 @@ def mskm_export_block(ctx, h, row_level: int, col_level: int, values: bool = Tru
     return rowptr, col[:n], (val[:n] if values else None)
 
 
+def block_nnz(ctx, h, row_level: int, col_level: int) -> int:
+    """Stored entries of B_{row,col} (mskm_export_block's size query)."""
+    nnz = C.c_int64()
+    _check(lib().mskm_export_block(ctx, h, row_level, col_level, None, None, None, C.byref(nnz)), "export (size)")
+    return int(nnz.value)
+
+
 def mskm_export_rows(ctx, h, row_level: int, col_level: int, rows, values: bool = True):
     """Canonical CSR of the listed rows (indices within row_level) of B_{row,col}."""
     rows = np.ascontiguousarray(rows, dtype=np.int64)
@@ -343,6 +357,13 @@ def mskm_spmv_width(h, op: int, prec: int = MSKM_PREC_FP64) -> int:
     w = C.c_int32()
     _check(lib().mskm_spmv_width(h, op, prec, C.byref(w)), "mskm_spmv_width")
     return int(w.value)
+
+
+def mskm_cg_product_time(ctx, h, level: int, prec: int = MSKM_PREC_FP32, repeats: int = 20) -> float:
+    """Mean ms per launch of the CG product kernel on one level."""
+    ms = C.c_float()
+    _check(lib().mskm_cg_product_time(ctx, h, level, prec, repeats, C.byref(ms)), "mskm_cg_product_time")
+    return float(ms.value)
 
 
 def mskm_set_spmv_width(h, op: int, prec: int, width: int) -> None:
@@ -439,6 +460,59 @@ def mskm_residual_noalloc(ctx, h, alpha, f, rel_out, nrhs: int = 1) -> None:
     if not (ad and fd and od):
         raise ValueError("alpha, f and rel_out must be device tensors")
     _check(lib().mskm_residual_noalloc(ctx, h, ap, fp, nrhs, op), "mskm_residual_noalloc")
+
+
+# ------------------------------------------------------- thresholded Jacobi
+
+def mskm_trunc_create(ctx, h, T: float, cg_rtol: float = 1e-13):
+    """Truncated Lagrange blocks X~_kj(T) of hierarchy h (status, handle)."""
+    out = C.c_void_p()
+    st = _check(lib().mskm_trunc_create(ctx, h, float(T), float(cg_rtol), C.byref(out)), "mskm_trunc_create")
+    return st, out
+
+
+def mskm_trunc_destroy(t) -> None:
+    _check(lib().mskm_trunc_destroy(t), "mskm_trunc_destroy")
+
+
+def mskm_trunc_info(t, levels: int) -> dict:
+    q = np.zeros(levels, dtype=np.float64)
+    nnz, it, ms = C.c_int64(), C.c_int64(), C.c_double()
+    _check(lib().mskm_trunc_info(t, C.c_void_p(q.ctypes.data), C.byref(nnz), C.byref(it), C.byref(ms)),
+           "mskm_trunc_info")
+    return {"q": q, "nnz": int(nnz.value), "cg_iters": int(it.value), "build_ms": float(ms.value)}
+
+
+def mskm_trunc_export_block(ctx, t, row_level: int, col_level: int, n_rows: int):
+    """Canonical CSR (rowptr, col, val) of X~_{row,col}; n_rows = points of row_level."""
+    nnz = C.c_int64()
+    _check(lib().mskm_trunc_export_block(ctx, t, row_level, col_level, None, None, None, C.byref(nnz)),
+           "trunc export (size)")
+    n = nnz.value
+    rowptr = np.zeros(n_rows + 1, dtype=np.int64)
+    col = np.zeros(max(n, 1), dtype=np.int32)
+    val = np.zeros(max(n, 1), dtype=np.float64)
+    _check(lib().mskm_trunc_export_block(ctx, t, row_level, col_level, C.c_void_p(rowptr.ctypes.data),
+                                         C.c_void_p(col.ctypes.data), C.c_void_p(val.ctypes.data), C.byref(nnz)),
+           "mskm_trunc_export_block")
+    return rowptr, col[:n], val[:n]
+
+
+def mskm_trunc_solve(ctx, t, f, alpha, opts: SolveOpts | None = None) -> SolveResult:
+    """alpha~ of the perturbed split (with refinement when opts.target_rel_residual > 0)."""
+    opts = opts or mskm_solve_opts_default()
+    fp, fd = _ptr(f, np.float64)
+    ap, ad = _ptr(alpha, np.float64)
+    if fd != ad:
+        raise ValueError("f and alpha must both be host or both be device arrays")
+    o = SolveOpts()
+    C.pointer(o)[0] = opts
+    o.flags = (o.flags | MSKM_IO_DEVICE) if fd else (o.flags & ~MSKM_IO_DEVICE)
+    rep = Report()
+    st = _check(lib().mskm_trunc_solve(ctx, t, fp, C.byref(o), ap, C.byref(rep)), "mskm_trunc_solve")
+    r = {k: getattr(rep, k) for k, _ in Report._fields_}
+    r["cg_iters_last"] = list(rep.cg_iters_last)[: rep.levels]
+    return SolveResult(st, r)
 
 
 def mskm_evaluate(ctx, h, alpha, query, out, nrhs: int = 1) -> None:

@@ -250,6 +250,7 @@ mskm_status mskm_hier_destroy(mskm_hier* h) {
       (void)hipEventDestroy(e);
     }
   if (h->solve_ws_free) h->solve_ws_free(h->solve_ws);
+  for (mskm_trunc* t : h->truncs) t->h = nullptr;  // they keep their own memory until destroyed
   for (void* p : h->allocs) (void)hipFree(p);
   delete h;
   return MSKM_OK;
@@ -403,8 +404,17 @@ mskm_status check_opts(const mskm_solve_opts& o, const mskm_hier* h, int nrhs) {
   if (!(o.cg_rtol > 0.0) || !(o.cg_rtol < 1.0)) return fail(MSKM_EINVAL, "cg_rtol must be in (0, 1)");
   if (o.precision == MSKM_PREC_FP32 && !(o.target_rel_residual > 0.0))
     return fail(MSKM_EINVAL, "target_rel_residual must be > 0 on the mixed path");
-  if (o.precond != MSKM_PRECOND_NONE && o.precond != MSKM_PRECOND_LEARNED && o.precond != MSKM_PRECOND_BLOCK_JACOBI)
+  if (o.precond != MSKM_PRECOND_NONE && o.precond != MSKM_PRECOND_LEARNED && o.precond != MSKM_PRECOND_BLOCK_JACOBI &&
+      o.precond != MSKM_PRECOND_FLEX_LEARNED)
     return fail(MSKM_EINVAL, "unknown precond");
+  if (o.precond == MSKM_PRECOND_FLEX_LEARNED) {
+    if (!o.mlp) return fail(MSKM_EINVAL, "the flexible learned preconditioner needs an mlp");
+    if (o.mlp->dim != h->dim) return fail(MSKM_EINVAL, "network and hierarchy dimensions differ");
+    if (o.algorithm != MSKM_ALG_SEQUENTIAL)
+      return fail(MSKM_EINVAL, "the flexible learned preconditioner runs with the sequential algorithm");
+    if (nrhs > 1) return fail(MSKM_EINVAL, "the flexible learned preconditioner takes one right-hand side");
+    if (o.warm_start != MSKM_START_ZERO) return fail(MSKM_EINVAL, "the flexible learned preconditioner starts from zero");
+  }
   if (o.warm_start != MSKM_START_ZERO && o.warm_start != MSKM_START_PREVIOUS && o.warm_start != MSKM_START_LEARNED)
     return fail(MSKM_EINVAL, "unknown warm_start");
   const bool learned = o.precond == MSKM_PRECOND_LEARNED || o.warm_start == MSKM_START_LEARNED;
@@ -569,6 +579,83 @@ mskm_status mskm_residual(mskm_ctx* ctx, const mskm_hier* h, const double* alpha
   if (nrhs < 1) return fail(MSKM_EINVAL, "nrhs must be >= 1");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
   return mskm::residual(const_cast<mskm_hier*>(h), alpha, f, nrhs, rel_out, (flags & MSKM_IO_DEVICE) != 0);
+}
+
+mskm_status mskm_cg_product_time(mskm_ctx* ctx, mskm_hier* h, int32_t level, int32_t prec, int32_t repeats,
+                                 float* avg_ms) {
+  if (!valid_ctx(ctx) || !h || !avg_ms) return fail(MSKM_EINVAL, "mskm_cg_product_time: NULL argument");
+  if (level < 0 || level >= h->L) return fail(MSKM_EINVAL, "level out of range");
+  if (prec != MSKM_PREC_FP64 && prec != MSKM_PREC_FP32) return fail(MSKM_EINVAL, "unknown precision");
+  if (repeats < 1) return fail(MSKM_EINVAL, "repeats must be >= 1");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::time_cg_product(h, level, prec, repeats, avg_ms);
+}
+
+// ------------------------------------------------------- thresholded Jacobi
+
+mskm_status mskm_trunc_create(mskm_ctx* ctx, mskm_hier* h, double T, double cg_rtol, mskm_trunc** out) {
+  if (!valid_ctx(ctx) || !h || !out) return fail(MSKM_EINVAL, "mskm_trunc_create: NULL argument");
+  *out = nullptr;
+  if (!(T > 0.0) || std::isnan(T)) return fail(MSKM_EINVAL, "T must be > 0 (INFINITY keeps every entry)");
+  if (!(cg_rtol > 0.0 && cg_rtol < 1.0)) return fail(MSKM_EINVAL, "cg_rtol must lie in (0, 1)");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  auto* t = new (std::nothrow) mskm_trunc();
+  if (!t) return fail(MSKM_ENOMEM, "truncated-block object allocation");
+  t->h = h;
+  t->T = T;
+  const mskm_status st = mskm::trunc_build(h, T, cg_rtol, t);
+  if (st < 0) {
+    delete t;
+    return st;
+  }
+  h->truncs.push_back(t);
+  *out = t;
+  return t->capped ? MSKM_ENOCONV : MSKM_OK;
+}
+
+mskm_status mskm_trunc_destroy(mskm_trunc* t) {
+  if (!t) return MSKM_OK;
+  if (t->h) {
+    auto& v = t->h->truncs;
+    v.erase(std::remove(v.begin(), v.end(), t), v.end());
+    if (t->h->ctx) {
+      (void)hipSetDevice(t->h->ctx->device);
+      (void)hipStreamSynchronize(t->h->ctx->stream);
+    }
+  }
+  delete t;
+  return MSKM_OK;
+}
+
+mskm_status mskm_trunc_info(const mskm_trunc* t, double* q, int64_t* nnz, int64_t* cg_iters, double* build_ms) {
+  if (!t) return fail(MSKM_EINVAL, "mskm_trunc_info: NULL handle");
+  if (q) std::copy(t->q.begin(), t->q.end(), q);
+  if (nnz) *nnz = t->X.nnz;
+  if (cg_iters) *cg_iters = t->cg_iters;
+  if (build_ms) *build_ms = t->build_ms;
+  return MSKM_OK;
+}
+
+mskm_status mskm_trunc_export_block(mskm_ctx* ctx, const mskm_trunc* t, int32_t row_level, int32_t col_level,
+                                    int64_t* rowptr, int32_t* col, double* val, int64_t* nnz_out) {
+  if (!valid_ctx(ctx) || !t) return fail(MSKM_EINVAL, "mskm_trunc_export_block: NULL handle");
+  if (!t->h) return fail(MSKM_ESTATE, "the hierarchy of these blocks was destroyed");
+  if (!valid_block(t->h, row_level, col_level) || row_level == col_level)
+    return fail(MSKM_EINVAL, "no such block: need levels of one hierarchy with depth(col) < depth(row)");
+  if (col && !rowptr) return fail(MSKM_EINVAL, "rowptr required with col");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::export_block(t->h, row_level, col_level, rowptr, col, val, nnz_out, nullptr, 0, &t->X);
+}
+
+mskm_status mskm_trunc_solve(mskm_ctx* ctx, const mskm_trunc* t, const double* f, const mskm_solve_opts* opts,
+                             double* alpha, mskm_report* rep) {
+  if (!valid_ctx(ctx) || !t || !f || !opts || !alpha) return fail(MSKM_EINVAL, "mskm_trunc_solve: NULL argument");
+  if (!t->h) return fail(MSKM_ESTATE, "the hierarchy of these blocks was destroyed");
+  if (!(opts->cg_rtol > 0.0)) return fail(MSKM_EINVAL, "cg_rtol must be > 0");
+  if (opts->precond != MSKM_PRECOND_NONE && opts->precond != MSKM_PRECOND_BLOCK_JACOBI)
+    return fail(MSKM_EINVAL, "the thresholded solve takes no learned start");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::trunc_solve(t->h, t->X, f, opts, alpha, rep);
 }
 
 namespace {

@@ -1144,9 +1144,9 @@ __global__ void __launch_bounds__(kBlock) k_export_fill(const int64_t* __restric
 }
 
 mskm_status export_block(mskm_hier* h, int k, int j, int64_t* rowptr, int32_t* col, double* val, int64_t* nnz_out,
-                         const int64_t* rows_host, int64_t nrows_sel) {
+                         const int64_t* rows_host, int64_t nrows_sel, const Csr* csr) {
   hipStream_t s = h->ctx->stream;
-  const Csr& C = (k == j) ? h->diag : h->lower;
+  const Csr& C = csr ? *csr : (k == j) ? h->diag : h->lower;
   const int64_t row_off = h->h_in_off[k];
   const int64_t nrows = rows_host ? nrows_sel : h->h_off[k + 1] - h->h_off[k];
   const int64_t c0 = h->h_off[j], c1 = h->h_off[j + 1];

@@ -163,6 +163,25 @@ struct mskm_ctx {
   hipStream_t side = nullptr;
 };
 
+// Truncated Lagrange blocks frak X~_{kj}(T) of one hierarchy (trunc.hip):
+// one CSR over its internal rows whose row i (level k) holds the kept
+// entries of every block (k, j), j < k, level 0's columns first (columns =
+// internal global indices, ascending), FP64 values, arrays padded by
+// kCsrPad entries for the 16-byte-load product.
+struct mskm_trunc {
+  mskm_hier* h = nullptr;         // null once the hierarchy was destroyed
+  double T = 0.0;
+  std::vector<double> q, r2;      // [L] separation distance, (T q)^2 (inf: keep all)
+  mskm::Csr X;
+  std::vector<void*> allocs;
+  int64_t cg_iters = 0;           // CG iterations of the Lagrange coefficient solves
+  bool capped = false;            // a coefficient solve hit its iteration cap
+  double build_ms = 0.0;
+  ~mskm_trunc() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
 // Learned warm start network (learned.hip).
 struct mskm_mlp {
   int32_t dim = 2, F = 56;         // point dimension, padded feature count
@@ -207,6 +226,7 @@ struct mskm_hier {
   double assemble_ms = 0.0;
   std::vector<void*> allocs;            // everything to free
   int32_t* knn = nullptr;               // [N][16] same-level nearest neighbours (learned warm start)
+  std::vector<mskm_trunc*> truncs;      // thresholded blocks built on this hierarchy (detached at destroy)
   void* solve_ws = nullptr;             // solver workspace (solve.hip), created on first solve
   void (*solve_ws_free)(void*) = nullptr;
 };
@@ -259,8 +279,11 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* points_dev, bool want
 mskm_status export_points_device(mskm_hier* h, double* pts_dev);
 // rows_host == nullptr: every row of the level; else the listed rows (indices
 // within the row level, host array of nrows_sel entries).
+// csr: another CSR over the hierarchy's rows with the same column
+// convention (the truncated blocks) instead of its own blocks.
 mskm_status export_block(mskm_hier* h, int row_level, int col_level, int64_t* rowptr, int32_t* col, double* val,
-                         int64_t* nnz_out, const int64_t* rows_host = nullptr, int64_t nrows_sel = 0);
+                         int64_t* nnz_out, const int64_t* rows_host = nullptr, int64_t nrows_sel = 0,
+                         const Csr* csr = nullptr);
 // Stream-ordered exclusive scan; part: scratch of scan_parts(n) entries.
 int64_t scan_parts(int64_t n);
 mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n, int64_t* part);
@@ -281,8 +304,21 @@ void launch_bj_apply(mskm_hier* h, int lo, int hi, const TX* r, TX* u);
 mskm_status apply_op(mskm_hier* h, int op, int prec, const double* x_in, int nrhs, double* y_in, bool io_dev);
 mskm_status apply_internal(mskm_hier* h, int op, int prec, const void* x, void* y, int repeats, float* avg_ms);
 mskm_status autotune(mskm_hier* h, int repeats, float* times_out);
+mskm_status time_cg_product(mskm_hier* h, int level, int prec, int repeats, float* avg_ms);
 mskm_status solve(mskm_hier* h, const double* f, int nrhs, const mskm_solve_opts* o, double* alpha,
                   mskm_report* rep);
+// trunc.hip: q per level, pattern and values of the truncated blocks
+mskm_status trunc_build(mskm_hier* h, double T, double cg_rtol, mskm_trunc* tr);
+// allocation owned by a truncated-block object
+template <typename T>
+mskm_status tr_alloc(mskm_trunc* tr, T** p, size_t count) {
+  MSKM_TRY(dalloc(p, count));
+  tr->allocs.push_back(*p);
+  return MSKM_OK;
+}
+// solve.hip: the perturbed split with the truncated blocks (one right-hand side)
+mskm_status trunc_solve(mskm_hier* h, const Csr& X, const double* f, const mskm_solve_opts* o, double* alpha,
+                        mskm_report* rep);
 // learned.hip
 mskm_status ensure_knn(mskm_hier* h);
 mskm_status mlp_new(int dim, uint64_t seed, mskm_mlp** out);
@@ -301,6 +337,13 @@ mskm_status train_pairs(mskm_hier* h, const double* f, int nrhs, bool io_dev, do
 
 // solve_mr.hip: many right-hand sides in the same launches (2 <= nrhs <= 512)
 bool mr_supported(int nrhs);
+// Columns n0 .. n0+R-1 of A_l^-1 (the coefficient vectors of level l's
+// Lagrange functions, Section 4) by CG from zero on A_l with unit right-hand
+// sides: Z [N][R] FP64 device, internal order, rows of level l written
+// (columns past the level's end are zero). The CG iterations (sum over the
+// R systems) and whether a cap stopped one are returned.
+mskm_status lagrange_columns(mskm_hier* h, int l, int64_t n0, int R, double rtol, int maxit, double* Z,
+                             int64_t* iters, bool* capped);
 mskm_status solve_multi(mskm_hier* h, const double* f, int nrhs, const mskm_solve_opts* o, double* alpha,
                         mskm_report* rep);
 mskm_status residual(mskm_hier* h, const double* alpha, const double* f, int nrhs, double* rel_out, bool io_dev);

@@ -65,54 +65,74 @@ __device__ __forceinline__ TA csr_row_dot(const int64_t* __restrict__ rp, const 
   return group_sum<G>(acc);
 }
 
+// V = 16 / sizeof(TV) consecutive values and columns of a CSR row from
+// entry k, one 16-byte value load and one 8- or 16-byte column load (NT: the
+// matrix streams are read once per SpMV; non-temporal loads keep them from
+// displacing the gathered x entries in the caches).
+template <typename TV, bool NT>
+__device__ __forceinline__ void csr_load_v(const int32_t* __restrict__ col, const TV* __restrict__ val, int64_t k,
+                                           TV* v, int32_t* c) {
+  if constexpr (sizeof(TV) == 8) {
+    typedef double nd2 __attribute__((ext_vector_type(2)));
+    typedef int ni2 __attribute__((ext_vector_type(2)));
+    nd2 a;
+    ni2 b;
+    if constexpr (NT) {
+      a = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(val + k));
+      b = __builtin_nontemporal_load(reinterpret_cast<const ni2*>(col + k));
+    } else {
+      a = *reinterpret_cast<const nd2*>(val + k);
+      b = *reinterpret_cast<const ni2*>(col + k);
+    }
+    v[0] = a.x; v[1] = a.y; c[0] = b.x; c[1] = b.y;
+  } else {
+    typedef float nf4 __attribute__((ext_vector_type(4)));
+    typedef int ni4 __attribute__((ext_vector_type(4)));
+    nf4 a;
+    ni4 b;
+    if constexpr (NT) {
+      a = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(val + k));
+      b = __builtin_nontemporal_load(reinterpret_cast<const ni4*>(col + k));
+    } else {
+      a = *reinterpret_cast<const nf4*>(val + k);
+      b = *reinterpret_cast<const ni4*>(col + k);
+    }
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    c[0] = b.x; c[1] = b.y; c[2] = b.z; c[3] = b.w;
+  }
+}
+
 // Same dot with 16-byte loads: each lane takes V = 16/sizeof(TV) consecutive
-// entries (values as one 16-byte load, columns as one 8- or 16-byte load)
-// starting from the row start rounded down to a multiple of V; entries
-// outside the row are masked. Value and column arrays carry a tail pad of
-// kCsrPad entries, so the rounded loads never leave their allocation.
+// entries starting from the row start rounded down to a multiple of V;
+// entries outside the row are masked. Two such chunks (G V entries apart)
+// are loaded before either is used, so each lane keeps two loads of each
+// stream in flight. Value and column arrays carry a tail pad of kCsrPad
+// entries, so the rounded loads never leave their allocation.
 template <int G, typename TV, typename TX, typename TA, bool NT = false>
 __device__ __forceinline__ TA csr_row_dot_v(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                             const TV* __restrict__ val, const TX* __restrict__ x, int64_t row,
                                             int gl) {
   constexpr int V = 16 / sizeof(TV);
+  constexpr int64_t step = (int64_t)G * V;
   const int64_t s = rp[row], e = rp[row + 1];
   TA acc = 0;
-  for (int64_t k = (s & ~(int64_t)(V - 1)) + (int64_t)gl * V; k < e; k += (int64_t)G * V) {
+  int64_t k = (s & ~(int64_t)(V - 1)) + (int64_t)gl * V;
+  for (; k + step < e; k += 2 * step) {
+    TV v[2 * V];
+    int32_t c[2 * V];
+    csr_load_v<TV, NT>(col, val, k, v, c);
+    csr_load_v<TV, NT>(col, val, k + step, v + V, c + V);
+#pragma unroll
+    for (int u = 0; u < V; ++u)
+      if (k + u >= s) acc += (TA)v[u] * (TA)x[c[u]];
+#pragma unroll
+    for (int u = 0; u < V; ++u)
+      if (k + step + u < e) acc += (TA)v[V + u] * (TA)x[c[V + u]];
+  }
+  if (k < e) {
     TV v[V];
     int32_t c[V];
-    // NT: the matrix streams are read once per SpMV; non-temporal loads keep
-    // them from displacing the gathered x entries in the caches
-    if constexpr (V == 2) {
-      double2 vv;
-      int2 cc;
-      if constexpr (NT) {
-        typedef double nd2 __attribute__((ext_vector_type(2)));
-        typedef int ni2 __attribute__((ext_vector_type(2)));
-        const nd2 a = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(val + k));
-        const ni2 b = __builtin_nontemporal_load(reinterpret_cast<const ni2*>(col + k));
-        vv.x = a.x; vv.y = a.y; cc.x = b.x; cc.y = b.y;
-      } else {
-        vv = *reinterpret_cast<const double2*>(val + k);
-        cc = *reinterpret_cast<const int2*>(col + k);
-      }
-      v[0] = vv.x; v[1] = vv.y; c[0] = cc.x; c[1] = cc.y;
-    } else {
-      float4 vv;
-      int4 cc;
-      if constexpr (NT) {
-        typedef float nf4 __attribute__((ext_vector_type(4)));
-        typedef int ni4 __attribute__((ext_vector_type(4)));
-        const nf4 a = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(val + k));
-        const ni4 b = __builtin_nontemporal_load(reinterpret_cast<const ni4*>(col + k));
-        vv.x = a.x; vv.y = a.y; vv.z = a.z; vv.w = a.w;
-        cc.x = b.x; cc.y = b.y; cc.z = b.z; cc.w = b.w;
-      } else {
-        vv = *reinterpret_cast<const float4*>(val + k);
-        cc = *reinterpret_cast<const int4*>(col + k);
-      }
-      v[0] = vv.x; v[1] = vv.y; v[2] = vv.z; v[3] = vv.w;
-      c[0] = cc.x; c[1] = cc.y; c[2] = cc.z; c[3] = cc.w;
-    }
+    csr_load_v<TV, NT>(col, val, k, v, c);
 #pragma unroll
     for (int u = 0; u < V; ++u)
       if (k + u >= s && k + u < e) acc += (TA)v[u] * (TA)x[c[u]];
@@ -332,7 +352,7 @@ struct CgLevel {
   int32_t iters;  // iterations done
   int32_t done;   // stopped (converged, capped or broken down)
   int32_t capped; // stopped by the cap or by non-finite data
-  int32_t pad;
+  int32_t fallback; // flexible CG: 0 network in use, 2 just dropped (restart), 1 dropped
   double rr_prev;   // single-reduction form: r.r and step of the previous iteration
   double alpha_prev;
 };
@@ -1077,6 +1097,29 @@ static PcArgs<TX> pc_args(mskm_hier* h, SolveWS& W) {
   return a;
 }
 
+// The CG product q = A v over blocks [qb0, qb0 + qbn) of the product's launch
+// table (the sliced copy's for variants kSellCode / kSell32Code, else the
+// CSR table), with the per-block partials v.q into W.part_s and, when given,
+// v.rv (v.v without rv) into pp and rv.rv into p3.
+template <typename TV, typename TX>
+static void launch_cg_product(mskm_hier* h, SolveWS& W, const TV* dval, int G, int qb0, int qbn, const TX* v, TX* q,
+                              double* pp, const TX* rv, double* p3, const CgLevel* st) {
+  if (qbn <= 0) return;
+  hipStream_t s = h->ctx->stream;
+  const bool sell = G == kSellCode || G == kSell32Code;
+  if (sell && G == kSellCode && h->sell.col16)
+    hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX, true>), dim3(qbn), dim3(kBlock), 0, s, h->wt_sell, qb0, h->sell.sptr,
+                       h->sell.rows, SellCols<true>{h->sell.col16, h->sell.cbase}, sell_values<TV>(h->sell), v, q, st,
+                       W.part_s, pp, rv, p3);
+  else if (sell)
+    hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX, false>), dim3(qbn), dim3(kBlock), 0, s, h->wt_sell, qb0, h->sell.sptr,
+                       h->sell.rows, SellCols<false>{h->sell.col}, sell_values<TV>(h->sell), v, q, st, W.part_s, pp, rv,
+                       p3);
+  else
+    launch_cg_spmv1<TV, TX>(s, G, h->wt_spmv, qb0, qbn, h->diag, dval, v, q, st, W.part_s, h->prec, h->dim, pp, rv,
+                            p3);
+}
+
 // K CG iterations of the given form on levels lo..hi.
 template <typename TV, typename TX>
 static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int hi, TX* x, int K, int G, int form) {
@@ -1098,17 +1141,7 @@ static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int 
   const PcArgs<TX> pc = pc_args<TX>(h, W);
   // q = A v with partials v.q, v.rv (v.v without rv) when pp, rv.rv when p3
   auto product = [&](const TX* v, double* pp, const TX* rv, double* p3, const CgLevel* st) {
-    if (qbn <= 0) return;
-    if (sell && c16)
-      hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX, true>), dim3(qbn), dim3(kBlock), 0, s, wc, qb0, h->sell.sptr,
-                         h->sell.rows, SellCols<true>{h->sell.col16, h->sell.cbase}, sell_values<TV>(h->sell), v, q,
-                         st, W.part_s, pp, rv, p3);
-    else if (sell)
-      hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX, false>), dim3(qbn), dim3(kBlock), 0, s, wc, qb0, h->sell.sptr,
-                         h->sell.rows, SellCols<false>{h->sell.col}, sell_values<TV>(h->sell), v, q, st, W.part_s, pp,
-                         rv, p3);
-    else
-      launch_cg_spmv1<TV, TX>(s, G, ws, qb0, qbn, h->diag, dval, v, q, st, W.part_s, h->prec, h->dim, pp, rv, p3);
+    launch_cg_product<TV, TX>(h, W, dval, G, qb0, qbn, v, q, pp, rv, p3, st);
   };
   // fold the reduction into the update when every level's partials are few
   int maxpart = 0;
@@ -1372,6 +1405,249 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
   return MSKM_OK;
 }
 
+// ------------------------------------------------- flexible CG (learned)
+//
+// Flexible conjugate gradients with one previous direction kept (Notay's
+// FCG(1); with a fixed SPD preconditioner the iterates are those of PCG):
+// the preconditioner may change from one iteration to the next, as a
+// nonlinear learned one does. With z = P(r):
+//   q = A p; alpha = p.r / p.q; x += alpha p; r -= alpha q;
+//   z = P(r); beta = -z.q / p.q; p = z + beta p,
+// from p = z = P(b), x = 0. Here P(r) = M^-1 r + net(r): the cell
+// block-Jacobi inverse plus the learned network's prediction of A^-1 r from
+// r's 17-point stencils. CG stays the judge: the stopping test is the true
+// residual ||r|| <= rtol ||b||; and plain preconditioned CG is the fallback:
+// a level whose r.r has not fallen by the factor kFcgWindowDrop over a window
+// of kFcgWindow iterations drops the network for the rest of its solve
+// (z = M^-1 r, direction restarted: FCG with a fixed SPD preconditioner is
+// PCG). State per level in CgLevel: bb, rr, alpha, beta, fallback; rr_prev
+// holds p.q of the current iteration, alpha_prev r.r at the start of the
+// window.
+constexpr int kFcgWindow = 8;
+constexpr double kFcgWindowDrop = 0.25;
+
+// x = 0, r = b, partial b.b per block of the vector table.
+template <typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_fcg_init(const WorkTable wt, int base, const TX* __restrict__ b, TX* __restrict__ x, TX* __restrict__ r,
+               double* __restrict__ part) {
+  __shared__ double sm[kBlock / kWave];
+  const int blk = base + xcd_block_id(gridDim.x);
+  double acc = 0.0;
+  for (int64_t i = wt.row0[blk] + threadIdx.x; i < wt.row1[blk]; i += kBlock) {
+    const TX bi = b[i];
+    x[i] = (TX)0;
+    r[i] = bi;
+    acc += (double)bi * (double)bi;
+  }
+  block_partial(acc, sm, part, blk);
+}
+
+// z = u (+ w) on running levels (u: block-Jacobi part or null, w: network
+// part or null; levels that fell back take u only)
+template <typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_fcg_precond(const WorkTable wt, int base, const TX* __restrict__ u, const TX* __restrict__ w, TX* __restrict__ z,
+                  const CgLevel* __restrict__ st) {
+  const int blk = base + xcd_block_id(gridDim.x);
+  const CgLevel& S = st[wt.lev[blk]];
+  if (S.done) return;
+  const TX* wn = S.fallback ? nullptr : w;
+  for (int64_t i = wt.row0[blk] + threadIdx.x; i < wt.row1[blk]; i += kBlock)
+    z[i] = (u ? u[i] : (TX)0) + (wn ? wn[i] : (TX)0);
+}
+
+// x += alpha p; r -= alpha q; partial r.r (running levels).
+template <typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_fcg_update(const WorkTable wt, int base, TX* __restrict__ x, TX* __restrict__ r, const TX* __restrict__ p,
+                 const TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ part) {
+  __shared__ double sm[kBlock / kWave];
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  double acc = 0.0;
+  if (!st[l].done) {
+    const TX a = (TX)st[l].alpha;
+    for (int64_t i = wt.row0[blk] + threadIdx.x; i < wt.row1[blk]; i += kBlock) {
+      x[i] += a * p[i];
+      const TX ri = r[i] - a * q[i];
+      r[i] = ri;
+      acc += (double)ri * (double)ri;
+    }
+  }
+  block_partial(acc, sm, part, blk);
+}
+
+// partial z.q (running levels)
+template <typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_fcg_dot(const WorkTable wt, int base, const TX* __restrict__ z, const TX* __restrict__ q,
+              const CgLevel* __restrict__ st, double* __restrict__ part) {
+  __shared__ double sm[kBlock / kWave];
+  const int blk = base + xcd_block_id(gridDim.x);
+  double acc = 0.0;
+  if (!st[wt.lev[blk]].done)
+    for (int64_t i = wt.row0[blk] + threadIdx.x; i < wt.row1[blk]; i += kBlock) acc += (double)z[i] * (double)q[i];
+  block_partial(acc, sm, part, blk);
+}
+
+// p = z + beta p (first: p = z)
+template <typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_fcg_dir(const WorkTable wt, int base, const TX* __restrict__ z, TX* __restrict__ p,
+              const CgLevel* __restrict__ st, int first) {
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (st[l].done) return;
+  const TX beta = (TX)st[l].beta;
+  for (int64_t i = wt.row0[blk] + threadIdx.x; i < wt.row1[blk]; i += kBlock) p[i] = first ? z[i] : z[i] + beta * p[i];
+}
+
+// Per-level scalar steps of FCG (one block per level, fixed-order sums):
+//   phase 0 (init):  bb = rr = sum(part_v); stop if bb = 0
+//   phase 1 (alpha): pq = sum(part_q), alpha = sum(part_q2) / pq (p.r / p.q)
+//   phase 2 (stop):  rr = sum(part_v); iters++; stop on rr <= rtol^2 bb or the cap
+//   phase 3 (beta):  beta = -sum(part_v) / pq (z.q / p.q)
+__global__ void __launch_bounds__(kRedBlock)
+    k_fcg_red(int phase, int lev0, const int32_t* __restrict__ qbeg, const double* __restrict__ part_q,
+              const double* __restrict__ part_q2, const int32_t* __restrict__ vbeg, const double* __restrict__ part_v,
+              CgLevel* __restrict__ st) {
+  __shared__ double sm[kRedBlock / kWave];
+  const int l = lev0 + blockIdx.x;
+  CgLevel& S = st[l];
+  if (phase > 0 && S.done) return;
+  if (phase == 1) {
+    const double pq = block_range_sum(part_q, qbeg[l], qbeg[l + 1], sm);
+    const double pr = block_range_sum(part_q2, qbeg[l], qbeg[l + 1], sm);
+    if (threadIdx.x == 0) {
+      if (pq > 0.0 && isfinite(pq) && isfinite(pr)) {
+        S.rr_prev = pq;
+        S.alpha = pr / pq;
+      } else {  // breakdown: stop the level (reported as capped unless converged)
+        S.alpha = 0.0;
+        S.done = 1;
+        S.capped = 1;
+      }
+    }
+    return;
+  }
+  const double v = block_range_sum(part_v, vbeg[l], vbeg[l + 1], sm);
+  if (threadIdx.x != 0) return;
+  if (phase == 0) {
+    S.bb = v;
+    S.rr = v;
+    S.iters = 0;
+    S.alpha = S.beta = 0.0;
+    S.alpha_prev = v;  // r.r at the start of the first window
+    S.fallback = 0;
+    const bool finite = isfinite(v);
+    const bool conv = finite && !(v > S.rtol2 * v);
+    S.capped = S.on && !conv && (!finite || S.maxit <= 0);
+    S.done = !S.on || conv || S.capped;
+  } else if (phase == 2) {
+    S.rr = v;
+    S.iters += 1;
+    const bool conv = isfinite(v) && v <= S.rtol2 * S.bb;
+    if (conv) S.done = 1;
+    else if (!isfinite(v) || S.iters >= S.maxit) S.done = S.capped = 1;
+    else if (S.iters % kFcgWindow == 0) {
+      if (!S.fallback && v > kFcgWindowDrop * S.alpha_prev) S.fallback = 2;  // restart at the next direction
+      S.alpha_prev = v;
+    }
+  } else {
+    if (S.fallback == 2) {  // first direction of the fallback: p = z = M^-1 r
+      S.beta = 0.0;
+      S.fallback = 1;
+    } else {
+      S.beta = -v / S.rr_prev;
+    }
+  }
+}
+
+template <typename TV, typename TX>
+static mskm_status fcg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::vector<char>& on, const TX* b, TX* x,
+                           double rtol, int maxit, int K, CgStats* cs, const mskm_mlp* mlp, bool bj) {
+  hipStream_t s = h->ctx->stream;
+  int lo = 0, hi = h->L - 1;
+  while (lo < h->L && !on[lo]) ++lo;
+  while (hi >= 0 && !on[hi]) --hi;
+  if (lo > hi) return MSKM_OK;
+  MSKM_TRY(flush_deferred(h, W, cs));
+  if (bj) MSKM_TRY(bj_wait(h, hi));
+  int G = h->spmv_g[MSKM_OP_DIAG][sizeof(TX) == 4 ? 1 : 0];
+  if (G >= 2 * kVecFlag && G < 3 * kVecFlag) G -= kVecFlag;
+  const bool sell = G == kSellCode || G == kSell32Code;
+  const WorkTable& wq = sell ? h->wt_sell : h->wt_spmv;
+  const WorkTable& wv = h->wt_vec;
+  const int nlev = hi - lo + 1;
+  const int qb0 = wq.h_lev_begin[lo], qbn = wq.h_lev_begin[hi + 1] - qb0;
+  const int vb0 = wv.h_lev_begin[lo], vbn = wv.h_lev_begin[hi + 1] - vb0;
+  TX* r = (TX*)W.r;
+  TX* p = (TX*)W.p0;
+  TX* q = (TX*)W.q;
+  TX* z = (TX*)W.z;
+  TX* tz = (TX*)W.p1;  // network part of z
+  TX* bz = (TX*)W.t;   // block-Jacobi part of z (W.t is free in the sequential algorithm)
+  for (int l = 0; l < h->L; ++l) {
+    CgLevel& S = W.h_st[l];
+    std::memset(&S, 0, sizeof(S));
+    S.rtol2 = rtol * rtol;
+    S.maxit = maxit;
+    S.on = on[l] ? 1 : 0;
+    S.done = 1;
+  }
+  MSKM_HIP_TRY(hipMemcpyAsync(W.st, W.h_st, h->L * sizeof(CgLevel), hipMemcpyHostToDevice, s));
+  auto precond = [&]() -> mskm_status {
+    if (bj) launch_bj_apply<TX>(h, lo, hi, (const TX*)r, bz);
+    if (mlp)
+      for (int l = lo; l <= hi; ++l)
+        if (on[l]) MSKM_TRY(mlp_predict_rows<TX>(h, mlp, l, (const TX*)r, tz));
+    if (vbn > 0)
+      hipLaunchKernelGGL(k_fcg_precond<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, bj ? (const TX*)bz : nullptr,
+                         mlp ? (const TX*)tz : nullptr, z, W.st);
+    return MSKM_OK;
+  };
+  if (vbn > 0) hipLaunchKernelGGL(k_fcg_init<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, b, x, r, W.part_v);
+  hipLaunchKernelGGL(k_fcg_red, dim3(nlev), dim3(kRedBlock), 0, s, 0, lo, wq.lev_begin, W.part_s, W.part_s2,
+                     wv.lev_begin, W.part_v, W.st);
+  MSKM_TRY(precond());
+  if (vbn > 0) hipLaunchKernelGGL(k_fcg_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, (const TX*)z, p, W.st, 1);
+  std::vector<CgLevel> fin(h->L);
+  for (int it = 0; it < maxit; it += K) {
+    for (int kk = 0; kk < K; ++kk) {
+      launch_cg_product<TV, TX>(h, W, dval, G, qb0, qbn, (const TX*)p, q, W.part_s2, (const TX*)r, nullptr, W.st);
+      hipLaunchKernelGGL(k_fcg_red, dim3(nlev), dim3(kRedBlock), 0, s, 1, lo, wq.lev_begin, W.part_s, W.part_s2,
+                         wv.lev_begin, W.part_v, W.st);
+      if (vbn > 0)
+        hipLaunchKernelGGL(k_fcg_update<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, x, r, (const TX*)p, (const TX*)q,
+                           W.st, W.part_v);
+      hipLaunchKernelGGL(k_fcg_red, dim3(nlev), dim3(kRedBlock), 0, s, 2, lo, wq.lev_begin, W.part_s, W.part_s2,
+                         wv.lev_begin, W.part_v, W.st);
+      MSKM_TRY(precond());
+      if (vbn > 0)
+        hipLaunchKernelGGL(k_fcg_dot<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, (const TX*)z, (const TX*)q, W.st,
+                           W.part_v);
+      hipLaunchKernelGGL(k_fcg_red, dim3(nlev), dim3(kRedBlock), 0, s, 3, lo, wq.lev_begin, W.part_s, W.part_s2,
+                         wv.lev_begin, W.part_v, W.st);
+      if (vbn > 0) hipLaunchKernelGGL(k_fcg_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, (const TX*)z, p, W.st, 0);
+    }
+    MSKM_HIP_TRY(hipMemcpyAsync(fin.data(), W.st, h->L * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
+    MSKM_HIP_TRY(hipStreamSynchronize(s));
+    bool any = false;
+    for (int l = lo; l <= hi; ++l) any |= on[l] && !fin[l].done;
+    if (!any) break;
+  }
+  MSKM_HIP_TRY(hipGetLastError());
+  for (int l = lo; l <= hi; ++l) {
+    if (!on[l]) continue;
+    cs->iters_total += fin[l].iters;
+    if (l < kMaxLevels) cs->last_iters[l] = fin[l].iters;
+    if (fin[l].capped || !fin[l].done) cs->capped = true;
+    if (fin[l].fallback) cs->warm_fallbacks += 1;  // the network was dropped on this level
+  }
+  return MSKM_OK;
+}
+
 template <typename T>
 static void spmv_launch(hipStream_t s, int G, const Csr* A1, const T* v1, const Csr* A2, const T* v2, const T* x,
                         const T* b, T* y, T sign, int64_t r0, int64_t r1);
@@ -1401,6 +1677,7 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
   const mskm_mlp* mlp = learned ? o->mlp : nullptr;
   const bool prev = o->warm_start == MSKM_START_PREVIOUS;
   const bool bj = o->precond == MSKM_PRECOND_BLOCK_JACOBI;
+  const bool flex = o->precond == MSKM_PRECOND_FLEX_LEARNED;  // sequential algorithm only (checked by the caller)
   const int maxit = o->max_cg_iters > 0 ? o->max_cg_iters : 20000;
   int K = o->check_every > 0 ? o->check_every : 8;
   K += K & 1;  // even chunk length
@@ -1419,8 +1696,11 @@ static mskm_status solve_internal(mskm_hier* h, SolveWS& W, const TV* dval, cons
       std::fill(next.begin(), next.end(), 0);
       if (d + 1 < D)
         for (int l = l1; l < h->h_depth_begin[d + 2]; ++l) next[l] = 1;
-      MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, false, K, cs, mlp, bj,
-                               d + 1 < D ? &next : nullptr)));
+      if (flex)
+        MSKM_TRY((fcg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, K, cs, o->mlp, true)));
+      else
+        MSKM_TRY((cg_run<TV, TX>(h, W, dval, on, beta, alpha, o->cg_rtol, maxit, false, K, cs, mlp, bj,
+                                 d + 1 < D ? &next : nullptr)));
     }
     *sweeps_done = 0;
     return flush_deferred(h, W, cs);
@@ -1514,6 +1794,9 @@ template <int G, typename VA>
 __device__ __forceinline__ double split_row_part(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                  const float* __restrict__ hi, const float* __restrict__ lo,
                                                  const VA& x, int64_t row, int gl) {
+  // one chunk of four entries per lane and step: two chunks in flight (as in
+  // the CSR product) measured slower here (1.29 -> 1.59 ms on 389M nonzeros),
+  // the three streams per chunk already keep enough loads outstanding
   const int64_t s = rp[row], e = rp[row + 1];
   double acc = 0.0;
   for (int64_t k = (s & ~(int64_t)3) + (int64_t)gl * 4; k < e; k += (int64_t)G * 4) {
@@ -1907,7 +2190,8 @@ mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_o
   const bool io_dev = (o->flags & MSKM_IO_DEVICE) != 0;
   const bool mixed = o->precision == MSKM_PREC_FP32;
   if (mixed ? !h->diag.val32 : !h->diag.val) return fail(MSKM_ESTATE, "requested precision's values are not stored");
-  if (o->precond == MSKM_PRECOND_BLOCK_JACOBI) MSKM_TRY(build_block_jacobi(h));
+  if (o->precond == MSKM_PRECOND_BLOCK_JACOBI || o->precond == MSKM_PRECOND_FLEX_LEARNED)
+    MSKM_TRY(build_block_jacobi(h));
   DevBuf F, A;
   MSKM_TRY(stage_in(s, f_in, (size_t)N * nrhs, io_dev, F));
   MSKM_TRY(stage_out_alloc(alpha_out, (size_t)N * nrhs, io_dev, A));
@@ -1970,6 +2254,85 @@ mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_o
     rep->warm_fallbacks = cs.warm_fallbacks;
   }
   MSKM_HIP_TRY(hipGetLastError());
+  return enoconv ? MSKM_ENOCONV : MSKM_OK;
+}
+
+__global__ void __launch_bounds__(kBlock) k_axpy64(const double* __restrict__ d, double* __restrict__ a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) a[i] += d[i];
+}
+
+// Thresholded solve (Section 4, eq. (perturbed_split)): Jacobi sweeps on
+// (I - M~) beta~ = r, each one product with the truncated blocks X~
+// (beta~ <- r - X~ beta~, from beta~ = r), then alpha~ = D^-1 beta~ by CG on
+// every level. With a target residual the perturbed solve is the inner
+// solve of an FP64 residual refinement: alpha += alpha~(f - T alpha) until
+// ||f - T alpha|| / ||f|| <= target (the refinement converges when the
+// truncation is small, ||M - M~|| < 1 in effect).
+mskm_status trunc_solve(mskm_hier* h, const Csr& X, const double* f_in, const mskm_solve_opts* o, double* alpha_out,
+                        mskm_report* rep) {
+  hipStream_t s = h->ctx->stream;
+  const int64_t N = h->N;
+  const bool io_dev = (o->flags & MSKM_IO_DEVICE) != 0;
+  if (o->precision != MSKM_PREC_FP64) return fail(MSKM_EINVAL, "the thresholded solve runs in FP64");
+  if (!h->diag.val) return fail(MSKM_ESTATE, "FP64 values are not stored");
+  const bool bj = o->precond == MSKM_PRECOND_BLOCK_JACOBI;
+  if (bj) MSKM_TRY(build_block_jacobi(h));
+  DevBuf F, A;
+  MSKM_TRY(stage_in(s, f_in, (size_t)N, io_dev, F));
+  MSKM_TRY(stage_out_alloc(alpha_out, (size_t)N, io_dev, A));
+  SolveWS* Wp = nullptr;
+  MSKM_TRY(get_ws(h, &Wp));
+  SolveWS& W = *Wp;
+  int Lmax = 0;
+  for (int g = 0; g < h->ngroups; ++g) Lmax = std::max(Lmax, (int)h->h_group_levels[g]);
+  const int S = o->sweeps > 0 ? o->sweeps : Lmax - 1;
+  const int maxit = o->max_cg_iters > 0 ? o->max_cg_iters : 20000;
+  int K = o->check_every > 0 ? o->check_every : 8;
+  K += K & 1;
+  const bool refine_on = o->target_rel_residual > 0.0;
+  const int maxref = refine_on ? (o->max_refine > 0 ? o->max_refine : 10) : 1;
+  CgStats cs;
+  std::vector<char> on(h->L, 1);
+  double rel = 0.0;
+  int rounds = 0;
+  MSKM_HIP_TRY(hipEventRecord(h->ctx->ev0, s));
+  hipLaunchKernelGGL(k_to_internal<double>, dim3(nblk(N)), dim3(kBlock), 0, s, F.p, h->perm, W.fi, N, 1, 0);
+  MSKM_HIP_TRY(hipMemsetAsync(W.ai, 0, N * 8, s));
+  MSKM_TRY(residual_internal(h, W, W.ai, W.fi, &rel, W.res, nullptr, true));  // r = f
+  while (rounds < maxref && !(refine_on && rel <= o->target_rel_residual)) {
+    double* b = W.beta;
+    double* nb = W.t;
+    MSKM_HIP_TRY(hipMemcpyAsync(b, W.res, N * 8, hipMemcpyDeviceToDevice, s));
+    for (int sw = 0; sw < S; ++sw) {
+      spmv_launch<double>(s, 16 + kVecFlag, &X, X.val, nullptr, nullptr, b, W.res, nb, -1.0, 0, N, h->prec, h->dim);
+      std::swap(b, nb);
+    }
+    double rtol = o->cg_rtol;
+    if (refine_on && rounds > 0) rtol = std::min(0.1, std::max(o->cg_rtol, 0.5 * o->target_rel_residual / rel));
+    MSKM_TRY((cg_run<double, double>(h, W, h->diag.val, on, b, nb, rtol, maxit, false, K, &cs, nullptr, bj)));
+    MSKM_TRY(flush_deferred(h, W, &cs));
+    hipLaunchKernelGGL(k_axpy64, dim3(nblk(N)), dim3(kBlock), 0, s, (const double*)nb, W.ai, N);
+    ++rounds;
+    MSKM_TRY(residual_internal(h, W, W.ai, W.fi, &rel, W.res));
+  }
+  hipLaunchKernelGGL(k_to_input<double>, dim3(nblk(N)), dim3(kBlock), 0, s, (const double*)W.ai, h->perm, A.p, N, 1, 0);
+  MSKM_HIP_TRY(hipEventRecord(h->ctx->ev1, s));
+  MSKM_TRY(stage_out_copy(s, alpha_out, (size_t)N, io_dev, A));
+  float ms = 0.f;
+  MSKM_HIP_TRY(hipEventElapsedTime(&ms, h->ctx->ev0, h->ctx->ev1));
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->levels = h->L;
+    rep->sweeps_done = S;
+    rep->refine_steps = rounds;
+    rep->cg_iters_total = cs.iters_total;
+    for (int l = 0; l < std::min(h->L, 64); ++l) rep->cg_iters_last[l] = cs.last_iters[l];
+    rep->rel_residual = rel;
+    rep->solve_ms = ms;
+  }
+  MSKM_HIP_TRY(hipGetLastError());
+  const bool enoconv = refine_on ? rel > o->target_rel_residual : cs.capped;
   return enoconv ? MSKM_ENOCONV : MSKM_OK;
 }
 
@@ -2050,6 +2413,55 @@ mskm_status evaluate(mskm_hier* h, const double* alpha, int nrhs, const double* 
   return st;
 }
 
+
+// ------------------------------------------------------------- timing
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ v, int64_t n, T x) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) v[i] = x;
+}
+
+// Mean device time of the CG product kernel that the preconditioned
+// single-reduction CG launches for one level (q = A_l z with the partials
+// z.q, z.r and r.r), in the hierarchy's current diagonal variant and the
+// given precision, launched `repeats` times between two events.
+template <typename TV, typename TX>
+static mskm_status time_cg_product_t(mskm_hier* h, const TV* dval, int level, int repeats, float* avg_ms) {
+  hipStream_t s = h->ctx->stream;
+  SolveWS* Wp = nullptr;
+  MSKM_TRY(get_ws(h, &Wp));
+  SolveWS& W = *Wp;
+  const int G = h->spmv_g[MSKM_OP_DIAG][sizeof(TV) == 4 ? 1 : 0];
+  const bool sell = G == kSellCode || G == kSell32Code;
+  const WorkTable& wq = sell ? h->wt_sell : h->wt_spmv;
+  const int qb0 = wq.h_lev_begin[level], qbn = wq.h_lev_begin[level + 1] - qb0;
+  const int64_t N = h->N;
+  TX* z = (TX*)W.z;
+  TX* r = (TX*)W.r;
+  hipLaunchKernelGGL(k_fill<TX>, dim3(nblk(N)), dim3(kBlock), 0, s, z, N, (TX)1);
+  hipLaunchKernelGGL(k_fill<TX>, dim3(nblk(N)), dim3(kBlock), 0, s, r, N, (TX)1);
+  MSKM_HIP_TRY(hipMemsetAsync(W.st, 0, 2 * (size_t)h->L * sizeof(CgLevel), s));  // every level running
+  MSKM_HIP_TRY(hipEventRecord(h->ctx->ev0, s));
+  for (int k = 0; k < repeats; ++k)
+    launch_cg_product<TV, TX>(h, W, dval, G, qb0, qbn, z, (TX*)W.q, W.part_s2, r, W.part_s3, W.st);
+  MSKM_HIP_TRY(hipEventRecord(h->ctx->ev1, s));
+  MSKM_HIP_TRY(hipEventSynchronize(h->ctx->ev1));
+  float ms = 0.f;
+  MSKM_HIP_TRY(hipEventElapsedTime(&ms, h->ctx->ev0, h->ctx->ev1));
+  if (avg_ms) *avg_ms = ms / (float)repeats;
+  MSKM_HIP_TRY(hipGetLastError());
+  return MSKM_OK;
+}
+
+mskm_status time_cg_product(mskm_hier* h, int level, int prec, int repeats, float* avg_ms) {
+  if (prec == MSKM_PREC_FP32) {
+    if (!h->diag.val32) return fail(MSKM_ESTATE, "FP32 values are not stored");
+    return time_cg_product_t<float, float>(h, h->diag.val32, level, repeats, avg_ms);
+  }
+  if (!h->diag.val) return fail(MSKM_ESTATE, "FP64 values are not stored");
+  return time_cg_product_t<double, double>(h, h->diag.val, level, repeats, avg_ms);
+}
 
 // ------------------------------------------------ allocation-free residual
 //

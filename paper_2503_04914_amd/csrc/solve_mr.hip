@@ -671,6 +671,46 @@ mskm_status mr_residual(mskm_hier* h, MrWS& W, const double* a, const double* f,
 
 bool mr_supported(int nrhs) { return nrhs >= 2 && nrhs <= 64 * kMaxRPerLane; }
 
+// Unit right-hand sides of level l: E[i][r] = 1 for i = off + n0 + r (r < nr).
+__global__ void __launch_bounds__(kBlock) k_mr_unit(double* __restrict__ E, int64_t off, int64_t n0, int nr, int R) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r < nr) E[(off + n0 + r) * R + r] = 1.0;
+}
+
+mskm_status lagrange_columns(mskm_hier* h, int l, int64_t n0, int R, double rtol, int maxit, double* Z,
+                             int64_t* iters, bool* capped) {
+  if (R < 1 || R > 64 * kMaxRPerLane) return fail(MSKM_EINVAL, "lagrange_columns: R out of range");
+  if (!h->diag.val) return fail(MSKM_ESTATE, "lagrange_columns: FP64 values are not stored");
+  hipStream_t s = h->ctx->stream;
+  const int64_t nl = h->h_off[l + 1] - h->h_off[l];
+  const int nr = (int)std::max<int64_t>(0, std::min<int64_t>(R, nl - n0));
+  MrWS W;
+  W.c = mr_cfg(R);
+  W.NR = (size_t)h->N * R;
+  const size_t NR = W.NR;
+  MSKM_TRY(dalloc(&W.fi, NR));
+  for (void** v : {&W.r, &W.p, &W.q}) MSKM_TRY(dalloc(reinterpret_cast<char**>(v), NR * 8));
+  const size_t nbp = (size_t)std::max(h->wt_spmv.nblocks, h->wt_vec.nblocks) * R;
+  MSKM_TRY(dalloc(&W.part_s, nbp));
+  MSKM_TRY(dalloc(&W.part_v, nbp));
+  MSKM_TRY(dalloc(&W.part_v2, nbp));
+  MSKM_TRY(dalloc(&W.st, (size_t)h->L * R));
+  MSKM_TRY(dalloc(&W.lev_done, h->L));
+  MSKM_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&W.h_lev_done), h->L * 4, hipHostMallocDefault));
+  MSKM_HIP_TRY(hipMemsetAsync(W.fi, 0, NR * 8, s));
+  if (nr > 0)
+    hipLaunchKernelGGL(k_mr_unit, dim3((nr + kBlock - 1) / kBlock), dim3(kBlock), 0, s, W.fi, h->h_off[l], n0, nr, R);
+  std::vector<char> on(h->L, 0);
+  on[l] = 1;
+  MrStats ms;
+  ms.last_iters.assign(h->L, 0);
+  MSKM_TRY((mr_cg<double, double>(h, W, h->diag.val, on, W.fi, Z, rtol, maxit, 8, &ms)));
+  MSKM_HIP_TRY(hipStreamSynchronize(s));
+  if (iters) *iters = ms.iters_total;
+  if (capped) *capped = ms.capped;
+  return MSKM_OK;
+}
+
 // Multi-rhs solve: f, alpha [N][nrhs] (input order; device if io_dev).
 mskm_status solve_multi(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_opts* o, double* alpha_out,
                         mskm_report* rep) {

@@ -8,8 +8,9 @@
   bound of the gradient; a 100-step loss trajectory against the oracle's
   FP64 training run; determinism; the loss falls on pairs from the solver;
   save/load round trip;
-* solves with the warm start: coefficients still match the oracle (CG is the
-  judge), FP64 <= 1e-10.
+* solves with the warm start, and with the network as a preconditioner inside
+  flexible CG: coefficients still match the oracle (the true residual is the
+  judge), FP64 <= 1e-10, mixed <= 1e-8.
 """
 import numpy as np
 import pytest
@@ -109,6 +110,18 @@ def test_train_and_solve(env):
                                                           precond=m.MSKM_PRECOND_LEARNED, mlp=net.value))
         assert res2.status == m.MSKM_OK
         assert np.linalg.norm(a2 - ref) / np.linalg.norm(ref) <= 1e-8
+        # the network as a preconditioner at every iteration (flexible CG), FP64 and mixed
+        for prec, kw, bar in ((m.MSKM_PREC_FP64, dict(cg_rtol=1e-14), 1e-10),
+                              (m.MSKM_PREC_FP32, dict(cg_rtol=1e-5, target_rel_residual=1e-13, max_refine=20), 1e-8)):
+            a3 = np.zeros_like(f)
+            res3 = m.mskm_solve(ctx, hd, f, a3, m.solve_opts(precision=prec, algorithm=m.MSKM_ALG_SEQUENTIAL,
+                                                              precond=m.MSKM_PRECOND_FLEX_LEARNED, mlp=net.value,
+                                                              **kw))
+            assert res3.status == m.MSKM_OK, res3.report
+            assert np.linalg.norm(a3 - ref) / np.linalg.norm(ref) <= bar, prec
+        # the flexible form takes the sequential algorithm and one right-hand side only
+        with pytest.raises(m.MskmError):
+            m.mskm_solve(ctx, hd, f, a3, m.solve_opts(precond=m.MSKM_PRECOND_FLEX_LEARNED, mlp=net.value))
     finally:
         m.mskm_mlp_destroy(net)
 
