@@ -34,14 +34,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the roofline kernel: rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch) of `bench.py --spmv-only --spmv-op diag
-# --spmv-prec fp32 --spmv-variant 4064`, each scaled by the factor that makes
-# the same counter read 1 GiB for the 1 GiB streaming copy kernel of those
-# runs. Only valid for that kernel on that workload (None: not measured).
+# HBM bytes per launch of the roofline kernel (the CG product on the finest
+# level): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of
+# `bench.py --spmv-only --spmv-op cg --spmv-prec fp32 --spmv-variant 4064`,
+# each scaled by the factor that makes the same counter read 1 GiB for the
+# 1 GiB streaming copy kernel of those runs. Only valid for that kernel, at
+# that launch, on that workload, as built when the counters were taken.
 PMC_TRAFFIC = {
-    ("halton2d_L8", "k_spmv_sell<float,true>"): {"fetch_kib": 191687.4375, "fetch_scale": 1048576 / 524299.0,
-                                                "write_kib": 5461.25, "write_scale": 1048576 / 1048604.1875},
+    ("halton2d_L8", "k_cg_spmv1_sell<float,float,true>", "level 7"): {
+        "fetch_kib": 146135.97, "fetch_scale": 1048576 / 524300.42,
+        "write_kib": 4192.75, "write_scale": 1048576 / 1048628.35},
 }
 TARGET = 1e-8
 RTOL_LADDER = [3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12]
@@ -277,7 +279,7 @@ def uniform3d(m, ctx, dev, args):
     a3 = torch.zeros_like(f3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hd3 = m.mskm_hier_create(ctx, p3, h3.offsets, h3.delta, fp64=True, fp32=True)
+    hd3 = m.mskm_hier_create(ctx, p3, h3.offsets, h3.delta, fp64=True, fp32=True, sliced_lower=True)
     torch.cuda.synchronize()
     t_asm = (time.perf_counter() - t0) * 1e3
     st = m.mskm_hier_stats_get(hd3)
@@ -491,7 +493,7 @@ def main():
     ctx = m.mskm_create(0, stream="torch")
 
     # ---- calibration of the tolerances (untimed)
-    hd = m.mskm_hier_create(ctx, pts_dev, h.offsets, h.delta, fp64=True, fp32=True)
+    hd = m.mskm_hier_create(ctx, pts_dev, h.offsets, h.delta, fp64=True, fp32=True, sliced_lower=True)
     if args.spmv_only:
         st = m.mskm_hier_stats_get(hd)
         op = {"diag": m.MSKM_OP_DIAG, "lower": m.MSKM_OP_LOWER, "full": m.MSKM_OP_FULL, "cg": m.MSKM_OP_DIAG}[args.spmv_op]
@@ -596,7 +598,7 @@ def main():
     def step():
         e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         e[0].record()
-        hs = m.mskm_hier_create(ctx, pts_dev, h.offsets, h.delta, fp64=False, fp32=True)
+        hs = m.mskm_hier_create(ctx, pts_dev, h.offsets, h.delta, fp64=False, fp32=True, sliced_lower=True)
         e[1].record()
         res = m.mskm_solve(ctx, hs, f_dev, alpha_dev, fast)
         e[2].record()
@@ -660,7 +662,7 @@ def main():
         ms = m.mskm_apply_internal(ctx, hd, op, x, y, prec=prec, repeats=args.spmv_repeats)
         sc = diag_col_bytes(m.mskm_spmv_width(hd, op, prec), stats) if op == m.MSKM_OP_DIAG else 4
         b = spmv_bytes(nnz, N, nrp, sval, sx, sc)
-        spmv[name] = {"ms": ms, "bytes": b, "GBps": b / ms / 1e6}
+        spmv[name] = {"ms": ms, "bytes": b, "GBps": b / ms / 1e6, "variant": m.mskm_spmv_width(hd, op, prec)}
     log("spmv", spmv)
     # the dominant kernel of the timed step: the CG product on the diagonal
     # blocks, FP32, at the launch shape of the finest level (its largest launch)

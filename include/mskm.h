@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define MSKM_ABI_VERSION 2
+#define MSKM_ABI_VERSION 3
 
 typedef int32_t mskm_status;
 enum {
@@ -79,10 +79,16 @@ enum {
   MSKM_STORE_FP32 = 1 << 2,       /* keep FP32 block values (mixed path); without
                                      STORE_FP64 also each value's FP32 rounding
                                      remainder, which the FP64 residual adds back */
-  MSKM_PREFIX_NESTED = 1 << 3     /* prefix-nested sets X_1 c X_2 c ... (Section 2):
+  MSKM_PREFIX_NESTED = 1 << 3,    /* prefix-nested sets X_1 c X_2 c ... (Section 2):
                                      points holds only the largest level, and level
                                      l is its first level_offsets[l+1] -
                                      level_offsets[l] points */
+  MSKM_SLICED_LOWER = 1 << 4      /* also keep a sliced copy of the strict lower
+                                     blocks (64-row slices, one segment per coarser
+                                     level, 16-bit column offsets; 6-10 more bytes
+                                     per lower entry) for faster lower and full
+                                     products and FP64 residuals; left out when a
+                                     segment spans more than 65536 points */
 };
 
 /* flags of calls taking vectors */
@@ -115,7 +121,8 @@ typedef struct {
                                    With PREFIX_NESTED: [P][dim], P = the largest level size */
   const double* delta;          /* host, [L], finite and > 0 */
   int32_t kernel;               /* MSKM_WENDLAND_3_1 */
-  int32_t flags;                /* MSKM_POINTS_ON_DEVICE | MSKM_STORE_FP64 | MSKM_STORE_FP32;
+  int32_t flags;                /* MSKM_POINTS_ON_DEVICE | MSKM_STORE_FP64 | MSKM_STORE_FP32 |
+                                   MSKM_PREFIX_NESTED | MSKM_SLICED_LOWER;
                                    neither STORE flag means STORE_FP64 */
 } mskm_hier_desc;
 
@@ -149,6 +156,8 @@ typedef struct {
   int32_t ngroups;      /* independent hierarchies held (1 unless created as a batch) */
   int32_t sell_col16;   /* 1 when the sliced copy of D_L also holds 16-bit column offsets (variant 4064) */
   int64_t sell_entries; /* stored entries of the sliced copy of D_L, padding included */
+  int32_t lower_sliced; /* 1 when the sliced copy of T_L - D_L exists (MSKM_SLICED_LOWER) */
+  int64_t lower_sliced_entries; /* its stored entries, padding included */
 } mskm_hier_stats;
 
 mskm_status mskm_hier_stats_get(const mskm_hier* h, mskm_hier_stats* out);

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(HERE, "libmskm.so")
 MSKM_OK, MSKM_ENOCONV = 0, 1
 MSKM_EINVAL, MSKM_ENOMEM, MSKM_EDEVICE, MSKM_ELIMIT, MSKM_ESTATE = -1, -2, -3, -4, -5
 MSKM_WENDLAND_3_1 = 31
-MSKM_POINTS_ON_DEVICE, MSKM_STORE_FP64, MSKM_STORE_FP32, MSKM_PREFIX_NESTED = 1, 2, 4, 8
+MSKM_POINTS_ON_DEVICE, MSKM_STORE_FP64, MSKM_STORE_FP32, MSKM_PREFIX_NESTED, MSKM_SLICED_LOWER = 1, 2, 4, 8, 16
 MSKM_IO_DEVICE = 1
 MSKM_OP_DIAG, MSKM_OP_LOWER, MSKM_OP_FULL = 0, 1, 2
 MSKM_PREC_FP64, MSKM_PREC_FP32 = 0, 1
@@ -67,7 +67,8 @@ class HierStats(C.Structure):
     _fields_ = [("dim", C.c_int32), ("levels", C.c_int32), ("n_total", C.c_int64), ("nnz_diag", C.c_int64),
                 ("nnz_lower", C.c_int64), ("has_fp64", C.c_int32), ("has_fp32", C.c_int32),
                 ("device_bytes", C.c_int64), ("assemble_ms", C.c_double), ("ngroups", C.c_int32),
-                ("sell_col16", C.c_int32), ("sell_entries", C.c_int64)]
+                ("sell_col16", C.c_int32), ("sell_entries", C.c_int64), ("lower_sliced", C.c_int32),
+                ("lower_sliced_entries", C.c_int64)]
 
 
 class LevelInfo(C.Structure):
@@ -214,18 +215,20 @@ def mskm_destroy(ctx) -> None:
 # --------------------------------------------------------------- hierarchy
 
 def mskm_hier_create(ctx, points, offsets, delta, dim: int | None = None, fp64: bool = True, fp32: bool = False,
-                     prefix_nested: bool = False):
+                     prefix_nested: bool = False, sliced_lower: bool = False):
     """Assemble all blocks of a hierarchy. points: [N][dim] float64 (numpy, or
     a CUDA tensor), offsets: [L+1] int64, delta: [L] float64 (host). With
     prefix_nested, points holds only the largest level and level l is its
-    first offsets[l+1] - offsets[l] points."""
+    first offsets[l+1] - offsets[l] points; sliced_lower also keeps the
+    sliced copy of the lower blocks."""
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     delta = np.ascontiguousarray(delta, dtype=np.float64)
     if dim is None:
         dim = int(points.shape[1])
     pp, pdev = _ptr(points, np.float64)
     flags = (MSKM_POINTS_ON_DEVICE if pdev else 0) | (MSKM_STORE_FP64 if fp64 else 0) | \
-        (MSKM_STORE_FP32 if fp32 else 0) | (MSKM_PREFIX_NESTED if prefix_nested else 0)
+        (MSKM_STORE_FP32 if fp32 else 0) | (MSKM_PREFIX_NESTED if prefix_nested else 0) | \
+        (MSKM_SLICED_LOWER if sliced_lower else 0)
     d = HierDesc(dim, len(delta), offsets.ctypes.data_as(C.POINTER(C.c_int64)), pp,
                  delta.ctypes.data_as(C.POINTER(C.c_double)), MSKM_WENDLAND_3_1, flags)
     out = C.c_void_p()
@@ -233,7 +236,7 @@ def mskm_hier_create(ctx, points, offsets, delta, dim: int | None = None, fp64: 
     return out
 
 
-def mskm_hier_create_batch(ctx, hierarchies, fp64: bool = True, fp32: bool = False):
+def mskm_hier_create_batch(ctx, hierarchies, fp64: bool = True, fp32: bool = False, sliced_lower: bool = False):
     """One object holding several independent hierarchies; `hierarchies` is a
     list of (points [N_g][dim], offsets [L_g+1], delta [L_g]) host arrays."""
     keep = []
@@ -244,7 +247,7 @@ def mskm_hier_create_batch(ctx, hierarchies, fp64: bool = True, fp32: bool = Fal
         pp, pdev = _ptr(points, np.float64)
         keep += [offsets, delta, points]
         flags = (MSKM_POINTS_ON_DEVICE if pdev else 0) | (MSKM_STORE_FP64 if fp64 else 0) | \
-                (MSKM_STORE_FP32 if fp32 else 0)
+                (MSKM_STORE_FP32 if fp32 else 0) | (MSKM_SLICED_LOWER if sliced_lower else 0)
         descs[g] = HierDesc(int(points.shape[1]), len(delta), offsets.ctypes.data_as(C.POINTER(C.c_int64)), pp,
                             delta.ctypes.data_as(C.POINTER(C.c_double)), MSKM_WENDLAND_3_1, flags)
     out = C.c_void_p()
@@ -341,7 +344,7 @@ def mskm_apply_internal(ctx, h, op: int, x, y, prec: int = MSKM_PREC_FP64, repea
 
 TUNE_VARIANTS = [4, 8, 16, 32, 64, 1004, 1008, 1016, 1032, 1064, 2004, 2008, 2016, 2032, 2064,
                  3004, 3008, 3016, 3032, 3064, 4064, 4032]
-SELL_CODE = 4064  # sliced copy of the diagonal blocks, 16-bit column offsets where possible (MSKM_OP_DIAG only)
+SELL_CODE = 4064  # sliced copies (the diagonal blocks; the lower blocks too with sliced_lower), 16-bit offsets
 SELL32_CODE = 4032  # the same copy with 32-bit columns (MSKM_OP_DIAG only)
 
 

@@ -128,7 +128,8 @@ mskm_status create_groups(mskm_ctx* ctx, const mskm_hier_desc* ds, int32_t count
   for (int g = 0; g < count; ++g) {
     MSKM_TRY(check_desc(&ds[g], &gn[g]));
     if (ds[g].dim != ds[0].dim) return fail(MSKM_EINVAL, "all hierarchies of a batch need the same dim");
-    if ((ds[g].flags & (MSKM_STORE_FP64 | MSKM_STORE_FP32)) != (ds[0].flags & (MSKM_STORE_FP64 | MSKM_STORE_FP32)))
+    const int32_t store = MSKM_STORE_FP64 | MSKM_STORE_FP32 | MSKM_SLICED_LOWER;
+    if ((ds[g].flags & store) != (ds[0].flags & store))
       return fail(MSKM_EINVAL, "all hierarchies of a batch need the same storage flags");
     N += gn[g];
     Ltot += ds[g].levels;
@@ -196,7 +197,7 @@ mskm_status create_groups(mskm_ctx* ctx, const mskm_hier_desc* ds, int32_t count
       st = fail(MSKM_EDEVICE, "point upload failed");
     }
   }
-  if (st == MSKM_OK) st = mskm::assemble_hierarchy(h, pts, want64, want32);
+  if (st == MSKM_OK) st = mskm::assemble_hierarchy(h, pts, want64, want32, (ds[0].flags & MSKM_SLICED_LOWER) != 0);
   if (st == MSKM_OK) {  // widths tuned earlier on this context for the same shape
     for (const auto& t : ctx->tune_cache)
       if (t.dim == h->dim && t.L == h->L && t.N == h->N && t.nnz_diag == h->diag.nnz && t.nnz_lower == h->lower.nnz)
@@ -271,6 +272,8 @@ mskm_status mskm_hier_stats_get(const mskm_hier* h, mskm_hier_stats* o) {
   o->ngroups = h->ngroups;
   o->sell_col16 = h->sell.col16 ? 1 : 0;
   o->sell_entries = h->sell.entries;
+  o->lower_sliced = h->lsell.built ? 1 : 0;
+  o->lower_sliced_entries = h->lsell.entries;
   return MSKM_OK;
 }
 
@@ -370,7 +373,12 @@ mskm_status mskm_set_spmv_width(mskm_hier* h, int32_t op, int32_t prec, int32_t 
     return fail(MSKM_EINVAL, "unknown op or precision");
   const int g = width % mskm::kVecFlag, kind = width / mskm::kVecFlag;
   if (width == mskm::kSellCode || width == mskm::kSell32Code) {
-    if (op != MSKM_OP_DIAG) return fail(MSKM_EINVAL, "mskm_set_spmv_width: the SELL variant serves MSKM_OP_DIAG only");
+    // lower and full operators: the sliced copies, when the lower one was built
+    const bool lower_ok = width == mskm::kSellCode && h->lsell.built &&
+                          (prec == MSKM_PREC_FP64 ? h->lsell.val != nullptr : h->lsell.val32 != nullptr);
+    if (op != MSKM_OP_DIAG && !lower_ok)
+      return fail(MSKM_EINVAL, "mskm_set_spmv_width: the SELL variants serve MSKM_OP_DIAG, and 4064 the lower and "
+                               "full operators of a hierarchy created with MSKM_SLICED_LOWER");
   } else if (width < 0 || kind > 3 || (g != 4 && g != 8 && g != 16 && g != 32 && g != 64)) {
     return fail(MSKM_EINVAL, "mskm_set_spmv_width: unknown variant code " + std::to_string(width));
   }

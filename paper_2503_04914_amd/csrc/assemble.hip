@@ -102,28 +102,6 @@ mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, i
   return MSKM_OK;
 }
 
-// Pieces of one device allocation, each aligned to 256 bytes.
-struct Carve {
-  size_t bytes = 0;
-  std::vector<std::pair<void**, size_t>> want;
-  template <typename T>
-  void add(T** p, size_t count) {
-    want.push_back({reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T)});
-    bytes += (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
-  }
-  // one hipMalloc for all pieces; *base receives it (freed by the caller)
-  mskm_status alloc(void** base) {
-    char* b = nullptr;
-    MSKM_TRY(dalloc(&b, bytes));
-    *base = b;
-    size_t o = 0;
-    for (auto& w : want) {
-      *w.first = b + o;
-      o += (w.second + 255) / 256 * 256;
-    }
-    return MSKM_OK;
-  }
-};
 
 // ------------------------------------------------------------- cell lists
 
@@ -300,7 +278,7 @@ template <int DIM>
 __global__ void __launch_bounds__(kWave)
     k_nbr_tile_count(int k, const DevLevel* __restrict__ lev, const int32_t* __restrict__ cs_all,
                      const double* __restrict__ xs, int64_t N, int64_t* __restrict__ cnt_d,
-                     int64_t* __restrict__ cnt_l) {
+                     int64_t* __restrict__ cnt_l, int32_t* __restrict__ cnt_lv) {
   __shared__ double sx[kTileCap], sy[kTileCap], sz[DIM == 3 ? kTileCap : 1];
   __shared__ int64_t box_a[kMaxBoxRows];
   __shared__ int32_t box_o[kMaxBoxRows];
@@ -314,7 +292,8 @@ __global__ void __launch_bounds__(kWave)
   const double* Z = xs + 2 * N;
   const double px = X[i], py = Y[i], pz = DIM == 3 ? Z[i] : 0.0;
   int64_t nd = 0, nl = 0;
-  for (int j = Lk.first;; j = lev[j].next) {
+  int seg = 0;  // position of level j in the row's hierarchy (the lower segment index)
+  for (int j = Lk.first;; j = lev[j].next, ++seg) {
     const DevLevel Lj = lev[j];
     const bool is_diag = j == k;
     const int cx = cell_coord(px, Lj.lo[0], Lj.inv_cell, Lj.nc[0]);
@@ -394,8 +373,12 @@ __global__ void __launch_bounds__(kWave)
             hits += sqdist(DIM, px, py, pz, qx, qy, qz) < Lj.d2max;
           }
         }
-      if (is_diag) nd = hits;
-      else nl += hits;
+      if (is_diag) {
+        nd = hits;
+      } else {
+        nl += hits;
+        if (cnt_lv) cnt_lv[seg * N + i] = (int32_t)hits;  // per-level counts for the sliced lower copy
+      }
     }
     if (boxed) __syncthreads();  // before the next level reuses the LDS
     if (is_diag) break;
@@ -412,6 +395,7 @@ __global__ void __launch_bounds__(kWave)
 // count, so each row's columns and values are written as contiguous,
 // coalesced runs in ascending order. The first wave computes the box.
 constexpr int kFillWaves = 4;
+constexpr int kBoxCols = 16;  // cell starts of a box row staged in LDS (boxes of up to 15 cells in x)
 
 template <int DIM>
 __global__ void __launch_bounds__(kFillWaves * kWave)
@@ -423,7 +407,11 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
   __shared__ double sx[kTileCap], sy[kTileCap], sz[DIM == 3 ? kTileCap : 1];
   __shared__ int64_t box_a[kMaxBoxRows];
   __shared__ int32_t box_o[kMaxBoxRows];
-  __shared__ int box[7];         // X0, X1, Y0, Y1, Z0, Z1, staged
+  // the box's cell starts, cs[row key + BX0 + c] for c <= BX1 - BX0 + 1, when
+  // the box is at most kBoxCols - 1 cells wide (box[7] = 1): a row's candidate
+  // ranges are then read from LDS, not from the cell table in global memory
+  __shared__ int32_t box_cs[kMaxBoxRows * kBoxCols];
+  __shared__ int box[8];         // X0, X1, Y0, Y1, Z0, Z1, staged, cell starts staged
   __shared__ int64_t lpos_s[kWave];  // next lower-block position of each row of the tile
   const DevLevel Lk = lev[k];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -475,6 +463,13 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
         }
         staged = total <= kTileCap ? (int)total + 1 : 0;  // total + 1 when staged
       }
+      const int wcs = BX1 - BX0 + 2;  // cell starts of one box row
+      const int cs_staged = nrows >= 1 && nrows <= kMaxBoxRows && wcs <= kBoxCols;
+      if (cs_staged && lane < nrows) {
+        const int yy = BY0 + lane % ny, zz = BZ0 + lane / ny;
+        const int rk = (zz * Lj.nc[1] + yy) * Lj.nc[0];
+        for (int c = 0; c < wcs; ++c) box_cs[lane * kBoxCols + c] = cs[rk + BX0 + c];
+      }
       if (lane == 0) {
         box[0] = BX0;
         box[1] = BX1;
@@ -483,13 +478,15 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
         box[4] = BZ0;
         box[5] = BZ1;
         box[6] = staged;
+        box[7] = cs_staged;
       }
     }
     __syncthreads();
-    const int BY0 = box[2], BZ0 = box[4];
+    const int BX0 = box[0], BY0 = box[2], BZ0 = box[4];
     const int ny = box[3] - BY0 + 1;
     const int nrows = ny * (box[5] - BZ0 + 1);
     const bool staged = box[6] > 0;
+    const bool cs_staged = box[7] != 0;
     if (staged) {
       const int32_t total = box[6] - 1;
       for (int q = 0; q < nrows; ++q) {
@@ -554,8 +551,16 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
         int64_t ra[3] = {0, 0, 0}, rs[3] = {0, 0, 0}, rl[3] = {0, 0, 0};
         int nr = 0;
         for (int yy = qy0; yy <= qy1; ++yy, ++nr) {
-          const int rk = yy * Lj.nc[0];
-          const int64_t a = cs[rk + qx0], b = cs[rk + qx1 + 1];
+          int64_t a, b;
+          if (cs_staged) {  // the row's cells lie inside the box: qx0 >= BX0, qx1 + 1 <= BX1 + 1
+            const int32_t* bc = box_cs + (yy - BY0) * kBoxCols;
+            a = bc[qx0 - BX0];
+            b = bc[qx1 + 1 - BX0];
+          } else {
+            const int rk = yy * Lj.nc[0];
+            a = cs[rk + qx0];
+            b = cs[rk + qx1 + 1];
+          }
           const int64_t sh = staged ? (int64_t)box_o[yy - BY0] - box_a[yy - BY0] : 0;
           if (nr == 0) {
             ra[0] = a; rs[0] = sh; rl[0] = b - a;
@@ -584,8 +589,16 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
       } else {
         for (int zz = qz0; zz <= qz1; ++zz)
           for (int yy = qy0; yy <= qy1; ++yy) {
-            const int rk = (zz * Lj.nc[1] + yy) * Lj.nc[0];
-            const int64_t a = cs[rk + qx0], b = cs[rk + qx1 + 1];
+            int64_t a, b;
+            if (cs_staged) {
+              const int32_t* bc = box_cs + ((zz - BZ0) * ny + (yy - BY0)) * kBoxCols;
+              a = bc[qx0 - BX0];
+              b = bc[qx1 + 1 - BX0];
+            } else {
+              const int rk = (zz * Lj.nc[1] + yy) * Lj.nc[0];
+              a = cs[rk + qx0];
+              b = cs[rk + qx1 + 1];
+            }
             int64_t sh = 0;
             if (staged) {
               const int bq = (zz - BZ0) * ny + (yy - BY0);
@@ -663,9 +676,9 @@ __global__ void __launch_bounds__(kBlock) k_point_records(int dim, int L, const 
   reinterpret_cast<double4*>(rec)[i] = r;
 }
 
-static mskm_status build_sell(mskm_hier* h, bool want64, bool want32);
+static mskm_status build_sell(mskm_hier* h, bool want64, bool want32, bool with_lo);
 
-mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, bool want32) {
+mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, bool want32, bool want_lsell) {
   hipStream_t s = h->ctx->stream;
   const int L = h->L, dim = h->dim;
   const int64_t N = h->N;
@@ -756,9 +769,13 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   //    between kernels would synchronise the device)
   int32_t *key = nullptr, *count = nullptr, *tmp = nullptr;
   int64_t *count64 = nullptr, *cs64 = nullptr, *cnt_d = nullptr, *cnt_l = nullptr, *part = nullptr;
+  int32_t* cnt_lv = nullptr;  // [coarser level][N] per-level lower counts (sliced lower copy only)
+  int max_depth = 1;
+  for (int g = 0; g < h->ngroups; ++g) max_depth = std::max(max_depth, (int)h->h_group_levels[g] - 1);
   void* scratch = nullptr;
   {
     Carve cv;
+    if (want_lsell) cv.add(&cnt_lv, (size_t)N * max_depth);
     cv.add(&key, N);
     cv.add(&count, cs_total);
     cv.add(&count64, cs_total);
@@ -818,10 +835,10 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
     if (n == 0) continue;
     if (dim == 3)
       hipLaunchKernelGGL(k_nbr_tile_count<3>, dim3(grid_for(n, kWave)), dim3(kWave), 0, s, k, h->d_lev, h->cell_start,
-                         h->xs, N, cnt_d, cnt_l);
+                         h->xs, N, cnt_d, cnt_l, cnt_lv);
     else
       hipLaunchKernelGGL(k_nbr_tile_count<2>, dim3(grid_for(n, kWave)), dim3(kWave), 0, s, k, h->d_lev, h->cell_start,
-                         h->xs, N, cnt_d, cnt_l);
+                         h->xs, N, cnt_d, cnt_l, cnt_lv);
   }
   MSKM_TRY(halloc(h, &h->diag.rowptr, N + 1));
   MSKM_TRY(halloc(h, &h->lower.rowptr, N + 1));
@@ -856,7 +873,8 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
                          h->cell_start, h->xs, N, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, h->lower.rowptr,
                          h->lower.col, h->lower.val, h->lower.val32, h->diag.val32lo, h->lower.val32lo);
   }
-  MSKM_TRY(build_sell(h, want64, want32));
+  MSKM_TRY(build_sell(h, want64, want32, want_lsell));
+  if (want_lsell) MSKM_TRY(build_lsell(h, want64, want32, cnt_lv));
   MSKM_HIP_TRY(hipEventRecord(h->ctx->ev1, s));
   MSKM_HIP_TRY(hipEventSynchronize(h->ctx->ev1));
   float ms = 0.f;
@@ -895,53 +913,64 @@ __global__ void __launch_bounds__(kBlock) k_sell_width(int64_t nslices, const in
   w[s] = (m + 3) / 4 * 4 * kSellC;
 }
 
-// One wave (workgroup) per slice: copy the CSR rows into the slot-interleaved
-// layout (groups of four consecutive entries per slot: entry k of slot t at
-// e0 + (k / 4) * 4 kSellC + 4 t + k % 4) through LDS tiles of 16 entries x 64
-// slots: the loads read 4 rows x 16 consecutive entries per instruction, the
-// stores write four entries of all 64 slots (contiguous).
-constexpr int kSellTile = 16;
-__global__ void __launch_bounds__(kSellC)
+// Copy the CSR rows into the slot-interleaved layout (groups of four
+// consecutive entries per slot: entry k of slot t at e0 + (k / 4) 4 kSellC +
+// 4 t + k % 4). One workgroup of kSellFillWaves waves per slice; wave w copies
+// slots 16w .. 16w + 15, lane i taking slot 16w + i % 16 and the groups
+// g = i / 16, i / 16 + 4, ...: it loads entries 4g .. 4g + 3 of its row (one
+// 16-byte load when all four lie inside the row) and stores them as one
+// 4-wide vector. Per instruction the loads read 64 consecutive bytes of each
+// of 16 rows and the stores write 4 runs of 16 consecutive slots. No LDS and
+// no barriers.
+constexpr int kSellFillWaves = 4;
+constexpr int kSellFillRows = kSellC / kSellFillWaves;
+constexpr int kSellFillGroups = kSellC / kSellFillRows;
+__global__ void __launch_bounds__(kSellFillWaves * kSellC)
     k_sell_fill(int64_t nslices, const int32_t* __restrict__ rows, const int64_t* __restrict__ sptr,
                 const int64_t* __restrict__ rp, const int32_t* __restrict__ col, const double* __restrict__ val,
-                const float* __restrict__ val32, int32_t* __restrict__ scol, double* __restrict__ sval,
-                float* __restrict__ sval32) {
-  __shared__ int32_t tc[kSellTile][kSellC + 1];
-  __shared__ double tv[kSellTile][kSellC + 1];
-  __shared__ float tf[kSellTile][kSellC + 1];
+                const float* __restrict__ val32, const float* __restrict__ lo32, int32_t* __restrict__ scol,
+                double* __restrict__ sval, float* __restrict__ sval32, float* __restrict__ slo) {
   const int64_t s = blockIdx.x;
-  const int t = threadIdx.x;
+  const int lane = threadIdx.x % kSellC, w = threadIdx.x / kSellC;
+  const int t = w * kSellFillRows + lane % kSellFillRows, gl = lane / kSellFillRows;
   const int32_t row = rows[s * kSellC + t];
-  // pad column of an empty slot (past the level's last row): the slice's
-  // first row, so that it stays inside the slice's column span
-  const int32_t row_first = __shfl(row, 0, kSellC);
+  // pad column: the slot's own row, or for an empty slot (past the level's
+  // last row) the slice's first row, so that it stays inside the slice's span
+  const int32_t pad = row >= 0 ? row : rows[s * kSellC];
   const int64_t b = row >= 0 ? rp[row] : 0;
   const int64_t len = row >= 0 ? rp[row + 1] - b : 0;
-  const int64_t e0 = sptr[s], w = (sptr[s + 1] - e0) / kSellC;
-  constexpr int kRowsPerPass = kSellC / kSellTile;  // 4
-  for (int64_t k0 = 0; k0 < w; k0 += kSellTile) {
-    for (int j = 0; j < kSellTile; ++j) {
-      const int rr = j * kRowsPerPass + t / kSellTile, kk = t % kSellTile;
-      const int64_t brr = __shfl(b, rr, kSellC), lrr = __shfl(len, rr, kSellC);
-      const int32_t rowrr = __shfl(row, rr, kSellC);
-      const int64_t k = k0 + kk;
-      const bool in = k < lrr;
-      tc[kk][rr] = in ? col[brr + k] : (rowrr >= 0 ? rowrr : row_first);
-      if (val) tv[kk][rr] = in ? val[brr + k] : 0.0;
-      if (val32) tf[kk][rr] = in ? val32[brr + k] : 0.0f;
-    }
-    __syncthreads();
-    for (int kk = 0; kk < kSellTile && k0 + kk < w; kk += 4) {  // w and kSellTile are multiples of 4
-      const int64_t d = e0 + ((k0 + kk) / 4) * (4 * kSellC) + 4 * t;  // the slot's four entries, one store each
-      *reinterpret_cast<int4*>(scol + d) = make_int4(tc[kk][t], tc[kk + 1][t], tc[kk + 2][t], tc[kk + 3][t]);
+  const int64_t e0 = sptr[s], groups = (sptr[s + 1] - e0) / (4 * kSellC);
+  for (int64_t g = gl; g < groups; g += kSellFillGroups) {
+    const int64_t d = e0 + g * (4 * kSellC) + 4 * t;
+    const int64_t k = 4 * g, src = b + k;
+    int4 c;
+    float4 v32 = make_float4(0.f, 0.f, 0.f, 0.f), vlo = v32;
+    double2 v64a = make_double2(0.0, 0.0), v64b = v64a;
+    if (k + 4 <= len) {  // the whole group inside the row: 16-byte loads (4-byte aligned)
+      __builtin_memcpy(&c, col + src, 16);
+      if (sval32) __builtin_memcpy(&v32, val32 + src, 16);
+      if (slo) __builtin_memcpy(&vlo, lo32 + src, 16);
       if (sval) {
-        *reinterpret_cast<double2*>(sval + d) = make_double2(tv[kk][t], tv[kk + 1][t]);
-        *reinterpret_cast<double2*>(sval + d + 2) = make_double2(tv[kk + 2][t], tv[kk + 3][t]);
+        __builtin_memcpy(&v64a, val + src, 16);
+        __builtin_memcpy(&v64b, val + src + 2, 16);
       }
-      if (sval32)
-        *reinterpret_cast<float4*>(sval32 + d) = make_float4(tf[kk][t], tf[kk + 1][t], tf[kk + 2][t], tf[kk + 3][t]);
+    } else {
+      const bool in0 = k < len, in1 = k + 1 < len, in2 = k + 2 < len;  // k + 3 < len is false here
+      c = make_int4(in0 ? col[src] : pad, in1 ? col[src + 1] : pad, in2 ? col[src + 2] : pad, pad);
+      if (sval32) v32 = make_float4(in0 ? val32[src] : 0.f, in1 ? val32[src + 1] : 0.f, in2 ? val32[src + 2] : 0.f, 0.f);
+      if (slo) vlo = make_float4(in0 ? lo32[src] : 0.f, in1 ? lo32[src + 1] : 0.f, in2 ? lo32[src + 2] : 0.f, 0.f);
+      if (sval) {
+        v64a = make_double2(in0 ? val[src] : 0.0, in1 ? val[src + 1] : 0.0);
+        v64b = make_double2(in2 ? val[src + 2] : 0.0, 0.0);
+      }
     }
-    __syncthreads();
+    *reinterpret_cast<int4*>(scol + d) = c;
+    if (sval) {
+      *reinterpret_cast<double2*>(sval + d) = v64a;
+      *reinterpret_cast<double2*>(sval + d + 2) = v64b;
+    }
+    if (sval32) *reinterpret_cast<float4*>(sval32 + d) = v32;
+    if (slo) *reinterpret_cast<float4*>(slo + d) = vlo;
   }
 }
 
@@ -977,7 +1006,7 @@ __global__ void __launch_bounds__(kSellC)
   for (int64_t d = sptr[s] + threadIdx.x; d < sptr[s + 1]; d += kSellC) col16[d] = (uint16_t)(scol[d] - b);
 }
 
-static mskm_status build_sell(mskm_hier* h, bool want64, bool want32) {
+static mskm_status build_sell(mskm_hier* h, bool want64, bool want32, bool with_lo) {
   hipStream_t s = h->ctx->stream;
   Sell& S = h->sell;
   const int L = h->L;
@@ -1016,9 +1045,13 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32) {
   MSKM_TRY(halloc(h, &S.col, (size_t)S.entries));
   if (want64) MSKM_TRY(halloc(h, &S.val, (size_t)S.entries));
   if (want32) MSKM_TRY(halloc(h, &S.val32, (size_t)S.entries));
+  // the FP32 remainders too when the residual will run over the sliced copies
+  const float* lo_src = with_lo ? h->diag.val32lo : nullptr;
+  if (lo_src) MSKM_TRY(halloc(h, &S.lo, (size_t)S.entries));
   if (S.nslices > 0)
-    hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)S.nslices), dim3(kSellC), 0, s, S.nslices, S.rows, S.sptr,
-                       h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, S.col, S.val, S.val32);
+    hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)S.nslices), dim3(kSellFillWaves * kSellC), 0, s, S.nslices,
+                       S.rows, S.sptr, h->diag.rowptr, h->diag.col, h->diag.val, h->diag.val32, lo_src, S.col, S.val,
+                       S.val32, S.lo);
   // 16-bit column offsets when every slice's columns span at most 65536 rows
   if (S.nslices > 0) {
     int32_t* cbase = nullptr;

@@ -87,7 +87,26 @@ struct Sell {
   int32_t* cbase = nullptr;   // [nslices] smallest column of each slice
   double* val = nullptr;     // [entries] FP64 values (null when not stored)
   float* val32 = nullptr;    // [entries] FP32 values (null when not stored)
+  float* lo = nullptr;       // [entries] FP32 remainders (FP32-only hierarchies with the lower copy)
   std::vector<int64_t> h_slice_begin;  // [L+1] first slice of each level
+};
+
+// Sliced copy of the strictly-lower blocks (lsell.hip): the rows of each
+// level in the diagonal copy's slices; within a slice of level k one segment
+// per coarser level j of its hierarchy (coarsest first), laid out like a
+// diagonal slice with 16-bit column offsets from the segment's smallest
+// column (seg_base). Not built (built = false) when some segment spans more
+// than 65536 points.
+struct LSell {
+  bool built = false;
+  int64_t nseg = 0, entries = 0;
+  int64_t* slice_seg = nullptr;  // [nslices + 1] first segment of each slice
+  int64_t* seg_ptr = nullptr;    // [nseg + 1] first entry of each segment
+  int32_t* seg_base = nullptr;   // [nseg] smallest column of each segment
+  uint16_t* col16 = nullptr;     // [entries]
+  double* val = nullptr;         // [entries] FP64 values (when stored)
+  float* val32 = nullptr;        // [entries] FP32 values (when stored)
+  float* lo = nullptr;           // [entries] FP32 remainders (FP32-only hierarchies)
 };
 
 // Block-Jacobi preconditioner: the diagonal blocks of A_l restricted to each
@@ -219,6 +238,7 @@ struct mskm_hier {
   mskm::WorkTable wt_spmv;              // per-level one-pass SpMV blocks (CG phase 1)
   mskm::WorkTable wt_vec;               // per-level streaming blocks (CG phase 3)
   mskm::Sell sell;                      // sliced copy of the diagonal blocks
+  mskm::LSell lsell;                    // sliced copy of the strictly-lower blocks
   mskm::WorkTable wt_sell;              // per-level blocks of 4 slices ("rows" are slices)
   mskm::BlockJacobi bj;                 // cell block-Jacobi preconditioner (built at its first use)
   int32_t spmv_g[3][2] = {{8, 8}, {32, 32}, {32, 32}};  // lanes per row [op][FP64, FP32]
@@ -273,8 +293,32 @@ mskm_status dalloc(T** p, size_t count) {
   return MSKM_OK;
 }
 
+// Pieces of one device allocation, each aligned to 256 bytes.
+struct Carve {
+  size_t bytes = 0;
+  std::vector<std::pair<void**, size_t>> want;
+  template <typename T>
+  void add(T** p, size_t count) {
+    want.push_back({reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T)});
+    bytes += (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+  }
+  // one hipMalloc for all pieces; *base receives it (freed by the caller)
+  mskm_status alloc(void** base) {
+    char* b = nullptr;
+    MSKM_TRY(dalloc(&b, bytes));
+    *base = b;
+    size_t o = 0;
+    for (auto& w : want) {
+      *w.first = b + o;
+      o += (w.second + 255) / 256 * 256;
+    }
+    return MSKM_OK;
+  }
+};
+
 // assemble.hip
-mskm_status assemble_hierarchy(mskm_hier* h, const double* points_dev, bool want64, bool want32);
+mskm_status assemble_hierarchy(mskm_hier* h, const double* points_dev, bool want64, bool want32,
+                               bool want_lsell);
 // The hierarchy's points in its input order, AoS [N][dim], into device memory.
 mskm_status export_points_device(mskm_hier* h, double* pts_dev);
 // rows_host == nullptr: every row of the level; else the listed rows (indices
@@ -284,6 +328,10 @@ mskm_status export_points_device(mskm_hier* h, double* pts_dev);
 mskm_status export_block(mskm_hier* h, int row_level, int col_level, int64_t* rowptr, int32_t* col, double* val,
                          int64_t* nnz_out, const int64_t* rows_host = nullptr, int64_t nrows_sel = 0,
                          const Csr* csr = nullptr);
+// lsell.hip: the sliced copy of the lower blocks
+// cnt_lv: [q][N] each row's entry count in the q-th coarser level of its
+// hierarchy (from the neighbour count pass).
+mskm_status build_lsell(mskm_hier* h, bool want64, bool want32, const int32_t* cnt_lv);
 // Stream-ordered exclusive scan; part: scratch of scan_parts(n) entries.
 int64_t scan_parts(int64_t n);
 mskm_status exclusive_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n, int64_t* part);

@@ -317,6 +317,149 @@ __global__ void __launch_bounds__(kBlock)
   if (row >= 0) y[row] = (b ? b[row] : (T)0) + sign * acc;
 }
 
+// ------------------------------------------------- sliced lower blocks
+//
+// Products over the sliced copy of the strictly-lower blocks (lsell.hip):
+// one wave per slice, one row per lane; the slice's segments (one per coarser
+// level) in order, four entries per vector load, 16-bit column offsets from
+// each segment's smallest column.
+
+// Dot of slot t of one segment with x (entries in order, four per load).
+template <typename TV, typename TX>
+__device__ __forceinline__ TX lsell_seg_dot(int32_t base, int t, int64_t e0, int64_t e1,
+                                            const uint16_t* __restrict__ col16, const TV* __restrict__ val,
+                                            const TX* __restrict__ x) {
+  TX acc = 0;
+#pragma unroll 2
+  for (int64_t d = e0 + 4 * t; d < e1; d += 4 * kSellC) {
+    TV v[4];
+    sell_vals4(val + d, v);
+    const su4 c = __builtin_nontemporal_load(reinterpret_cast<const su4*>(col16 + d));
+    acc += (TX)v[0] * x[base + (int32_t)c.x];
+    acc += (TX)v[1] * x[base + (int32_t)c.y];
+    acc += (TX)v[2] * x[base + (int32_t)c.z];
+    acc += (TX)v[3] * x[base + (int32_t)c.w];
+  }
+  return acc;
+}
+
+// The same with split values (FP32 value + FP32 remainder), FP64 accumulation.
+template <typename VA>
+__device__ __forceinline__ double lsell_seg_dot_split(int32_t base, int t, int64_t e0, int64_t e1,
+                                                      const uint16_t* __restrict__ col16, const float* __restrict__ hi,
+                                                      const float* __restrict__ lo, const VA& x) {
+  double acc = 0.0;
+  for (int64_t d = e0 + 4 * t; d < e1; d += 4 * kSellC) {
+    const sf4 h = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(hi + d));
+    const sf4 l = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(lo + d));
+    const su4 c = __builtin_nontemporal_load(reinterpret_cast<const su4*>(col16 + d));
+    acc += ((double)h.x + (double)l.x) * x(base + (int32_t)c.x);
+    acc += ((double)h.y + (double)l.y) * x(base + (int32_t)c.y);
+    acc += ((double)h.z + (double)l.z) * x(base + (int32_t)c.z);
+    acc += ((double)h.w + (double)l.w) * x(base + (int32_t)c.w);
+  }
+  return acc;
+}
+
+// Diagonal copy's slot dot with split values (FP64 accumulation).
+template <bool C16, typename VA>
+__device__ __forceinline__ double sell_slot_dot_split(int64_t sl, int t, int64_t e0, int64_t e1,
+                                                      const SellCols<C16>& cols, const float* __restrict__ hi,
+                                                      const float* __restrict__ lo, const VA& x) {
+  double acc = 0.0;
+  for (int64_t d = e0 + 4 * t; d < e1; d += 4 * kSellC) {
+    const sf4 h = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(hi + d));
+    const sf4 l = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(lo + d));
+    int32_t c[4];
+    cols.at4(sl, d, c);
+    acc += ((double)h.x + (double)l.x) * x(c[0]);
+    acc += ((double)h.y + (double)l.y) * x(c[1]);
+    acc += ((double)h.z + (double)l.z) * x(c[2]);
+    acc += ((double)h.w + (double)l.w) * x(c[3]);
+  }
+  return acc;
+}
+
+// y = b + sign * (T - D) x, or (FULL) b + sign * T x, on slices [s0, s1).
+template <typename T, bool FULL, bool C16>
+__global__ void __launch_bounds__(kBlock)
+    k_spmv_lsell(int64_t s0, int64_t s1, const int64_t* __restrict__ sptr, const int32_t* __restrict__ rows,
+                 const SellCols<C16> dcols, const T* __restrict__ dval, const int64_t* __restrict__ slice_seg,
+                 const int64_t* __restrict__ seg_ptr, const int32_t* __restrict__ seg_base,
+                 const uint16_t* __restrict__ lcol, const T* __restrict__ lval, const T* __restrict__ x,
+                 const T* __restrict__ b, T* __restrict__ y, T sign) {
+  const int64_t sl = s0 + (int64_t)xcd_block_id(gridDim.x) * (kBlock / kSellC) + threadIdx.x / kSellC;
+  if (sl >= s1) return;
+  const int t = threadIdx.x % kSellC;
+  T acc = 0;
+  for (int64_t g = slice_seg[sl]; g < slice_seg[sl + 1]; ++g)
+    acc += lsell_seg_dot<T, T>(seg_base[g], t, seg_ptr[g], seg_ptr[g + 1], lcol, lval, x);
+  if constexpr (FULL) acc += sell_slot_dot<T, T, C16>(sl, t, sptr[sl], sptr[sl + 1], dcols, dval, x);
+  const int32_t row = rows[sl * kSellC + t];
+  if (row >= 0) y[row] = (b ? b[row] : (T)0) + sign * acc;
+}
+
+// FP64 residual r = f - T a over the sliced copies (blocks of 4 slices of the
+// sliced table, level-aligned): FP64 values when stored (SPLIT false), else
+// the FP32 values plus their remainders; partials r.r and f.f per block.
+template <bool SPLIT, bool C16, typename VA>
+__global__ void __launch_bounds__(kBlock)
+    k_residual_sell(const WorkTable wt, const int64_t* __restrict__ sptr, const int32_t* __restrict__ rows,
+                    const SellCols<C16> dcols, const double* __restrict__ dv, const float* __restrict__ dhi,
+                    const float* __restrict__ dlo, const int64_t* __restrict__ slice_seg,
+                    const int64_t* __restrict__ seg_ptr, const int32_t* __restrict__ seg_base,
+                    const uint16_t* __restrict__ lcol, const double* __restrict__ lv, const float* __restrict__ lhi,
+                    const float* __restrict__ llo, const VA a, const VA f, double* __restrict__ part,
+                    double* __restrict__ rout) {
+  __shared__ double sm[kBlock / kWave];
+  const int blk = xcd_block_id(gridDim.x);
+  const int64_t sl = wt.row0[blk] + threadIdx.x / kSellC;
+  const int t = threadIdx.x % kSellC;
+  double srr = 0.0, sff = 0.0;
+  if (sl < wt.row1[blk]) {
+    double acc = 0.0;
+    for (int64_t g = slice_seg[sl]; g < slice_seg[sl + 1]; ++g) {
+      if constexpr (SPLIT)
+        acc += lsell_seg_dot_split(seg_base[g], t, seg_ptr[g], seg_ptr[g + 1], lcol, lhi, llo, a);
+      else {
+        const int32_t base = seg_base[g];
+        for (int64_t d = seg_ptr[g] + 4 * t; d < seg_ptr[g + 1]; d += 4 * kSellC) {
+          double v[4];
+          sell_vals4(lv + d, v);
+          const su4 c = __builtin_nontemporal_load(reinterpret_cast<const su4*>(lcol + d));
+          acc += v[0] * a(base + (int32_t)c.x) + v[1] * a(base + (int32_t)c.y) + v[2] * a(base + (int32_t)c.z) +
+                 v[3] * a(base + (int32_t)c.w);
+        }
+      }
+    }
+    if constexpr (SPLIT) {
+      acc += sell_slot_dot_split(sl, t, sptr[sl], sptr[sl + 1], dcols, dhi, dlo, a);
+    } else {
+      for (int64_t d = sptr[sl] + 4 * t; d < sptr[sl + 1]; d += 4 * kSellC) {
+        double v[4];
+        int32_t c[4];
+        sell_vals4(dv + d, v);
+        dcols.at4(sl, d, c);
+        acc += v[0] * a(c[0]) + v[1] * a(c[1]) + v[2] * a(c[2]) + v[3] * a(c[3]);
+      }
+    }
+    const int32_t row = rows[sl * kSellC + t];
+    if (row >= 0) {
+      const double fi = f(row);
+      const double ri = fi - acc;
+      if (rout) rout[row] = ri;
+      srr = ri * ri;
+      sff = fi * fi;
+    }
+  }
+  srr = block_sum(srr, sm);
+  sff = block_sum(sff, sm);
+  if (threadIdx.x == 0) {
+    part[2 * blk] = srr;
+    part[2 * blk + 1] = sff;
+  }
+}
+
 // --------------------------------------------------------------------- CG
 //
 // Conjugate gradients on A_l x_l = b_l for every participating level l, all
@@ -1654,10 +1797,53 @@ static void spmv_launch(hipStream_t s, int G, const Csr* A1, const T* v1, const 
 
 // beta = f - (T - D) t on rows [r0, r1): the Jacobi update, or one level's
 // right-hand side of the forward substitution.
+// y = b + sign * (T - D) x, or (full) b + sign * T x, on rows [r0, r1) from
+// the sliced copies; false (nothing launched) when the lower copy is not
+// built, the precision's values are not stored there, or the rows are not
+// whole levels.
+template <typename T>
+static bool launch_lsell(mskm_hier* h, bool full, const T* x, const T* b, T* y, T sign, int64_t r0, int64_t r1) {
+  const LSell& X = h->lsell;
+  const Sell& S = h->sell;
+  if (!X.built) return false;
+  const T* lv;
+  const T* dv;
+  if constexpr (sizeof(T) == 8) {
+    lv = X.val;
+    dv = S.val;
+  } else {
+    lv = X.val32;
+    dv = S.val32;
+  }
+  if (!lv || (full && !dv)) return false;
+  const auto a = std::lower_bound(h->h_off.begin(), h->h_off.end(), r0);
+  const auto e = std::lower_bound(h->h_off.begin(), h->h_off.end(), r1);
+  if (a == h->h_off.end() || e == h->h_off.end() || *a != r0 || *e != r1) return false;
+  const int64_t s0 = S.h_slice_begin[a - h->h_off.begin()], s1 = S.h_slice_begin[e - h->h_off.begin()];
+  if (s1 <= s0) return true;
+  const dim3 grid(nblk(s1 - s0, kBlock / kSellC));
+  hipStream_t st = h->ctx->stream;
+  if (full && !S.col16)
+    hipLaunchKernelGGL((k_spmv_lsell<T, true, false>), grid, dim3(kBlock), 0, st, s0, s1, S.sptr, S.rows,
+                       SellCols<false>{S.col}, dv, X.slice_seg, X.seg_ptr, X.seg_base, X.col16, lv, x, b, y, sign);
+  else if (full)
+    hipLaunchKernelGGL((k_spmv_lsell<T, true, true>), grid, dim3(kBlock), 0, st, s0, s1, S.sptr, S.rows,
+                       SellCols<true>{S.col16, S.cbase}, dv, X.slice_seg, X.seg_ptr, X.seg_base, X.col16, lv, x, b, y,
+                       sign);
+  else
+    hipLaunchKernelGGL((k_spmv_lsell<T, false, true>), grid, dim3(kBlock), 0, st, s0, s1, S.sptr, S.rows,
+                       SellCols<true>{S.col16, S.cbase}, dv, X.slice_seg, X.seg_ptr, X.seg_base, X.col16, lv, x, b, y,
+                       sign);
+  return true;
+}
+
 template <typename TV, typename TX>
 static void lower_update(mskm_hier* h, const TV* lval, const TX* t, const TX* f, TX* beta, int64_t r0, int64_t r1) {
-  spmv_launch<TX>(h->ctx->stream, h->spmv_g[MSKM_OP_LOWER][sizeof(TX) == 4 ? 1 : 0], &h->lower, lval, nullptr,
-                  nullptr, t, f, beta, (TX)-1, r0, r1, h->prec, h->dim);
+  const int G = h->spmv_g[MSKM_OP_LOWER][sizeof(TX) == 4 ? 1 : 0];
+  if constexpr (sizeof(TV) == sizeof(TX))
+    if (G == kSellCode && launch_lsell<TX>(h, false, t, f, beta, (TX)-1, r0, r1)) return;
+  spmv_launch<TX>(h->ctx->stream, G == kSellCode ? 16 + kVecFlag : G, &h->lower, lval, nullptr, nullptr, t, f, beta,
+                  (TX)-1, r0, r1, h->prec, h->dim);
 }
 
 // alpha = T^-1 f in the internal order: monolithic (Jacobi sweeps on T' with
@@ -1862,6 +2048,41 @@ static void launch_residual(mskm_hier* h, const VA& a, const VA& f, double* part
   }
 }
 
+// The residual over the sliced copies (partials per block of the sliced
+// table); false when the lower copy or the needed values are missing.
+template <typename VA>
+static bool launch_residual_sell(mskm_hier* h, const VA& a, const VA& f, double* part, double* rout) {
+  const LSell& X = h->lsell;
+  const Sell& S = h->sell;
+  const WorkTable& wt = h->wt_sell;
+  if (!X.built || wt.nblocks <= 0) return false;
+  hipStream_t s = h->ctx->stream;
+  const dim3 grid(wt.nblocks);
+  if (X.val && S.val) {
+    if (S.col16)
+      hipLaunchKernelGGL((k_residual_sell<false, true, VA>), grid, dim3(kBlock), 0, s, wt, S.sptr, S.rows,
+                         SellCols<true>{S.col16, S.cbase}, S.val, nullptr, nullptr, X.slice_seg, X.seg_ptr, X.seg_base,
+                         X.col16, X.val, nullptr, nullptr, a, f, part, rout);
+    else
+      hipLaunchKernelGGL((k_residual_sell<false, false, VA>), grid, dim3(kBlock), 0, s, wt, S.sptr, S.rows,
+                         SellCols<false>{S.col}, S.val, nullptr, nullptr, X.slice_seg, X.seg_ptr, X.seg_base, X.col16,
+                         X.val, nullptr, nullptr, a, f, part, rout);
+    return true;
+  }
+  if (X.val32 && X.lo && S.val32 && S.lo) {
+    if (S.col16)
+      hipLaunchKernelGGL((k_residual_sell<true, true, VA>), grid, dim3(kBlock), 0, s, wt, S.sptr, S.rows,
+                         SellCols<true>{S.col16, S.cbase}, nullptr, S.val32, S.lo, X.slice_seg, X.seg_ptr, X.seg_base,
+                         X.col16, nullptr, X.val32, X.lo, a, f, part, rout);
+    else
+      hipLaunchKernelGGL((k_residual_sell<true, false, VA>), grid, dim3(kBlock), 0, s, wt, S.sptr, S.rows,
+                         SellCols<false>{S.col}, nullptr, S.val32, S.lo, X.slice_seg, X.seg_ptr, X.seg_base, X.col16,
+                         nullptr, X.val32, X.lo, a, f, part, rout);
+    return true;
+  }
+  return false;
+}
+
 // Residual of a = 0: r = f (partials of f.f twice).
 __global__ void __launch_bounds__(kBlock)
     k_residual_zero(const WorkTable wt, const double* __restrict__ f, double* __restrict__ part,
@@ -1890,19 +2111,22 @@ static mskm_status residual_internal(mskm_hier* h, SolveWS& W, const double* a, 
                                      double* rout, double* rel_groups = nullptr, bool a_zero = false) {
   hipStream_t s = h->ctx->stream;
   const WorkTable& wt = h->wt_spmv;
+  const WorkTable* tab = &wt;  // the table whose blocks wrote the partials
   double* part = W.part_res;
   if (a_zero)
     hipLaunchKernelGGL(k_residual_zero, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, f, part, rout);
-  else
+  else if (!launch_residual_sell(h, VecDirect{a}, VecDirect{f}, part, rout))
     launch_residual(h, VecDirect{a}, VecDirect{f}, part, rout);
+  else
+    tab = &h->wt_sell;  // partials per block of the sliced table
   const double* hp = W.h_part_res;
-  hipError_t e = hipMemcpyAsync(W.h_part_res, part, 2 * (size_t)wt.nblocks * 8, hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(W.h_part_res, part, 2 * (size_t)tab->nblocks * 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(MSKM_EDEVICE, std::string("residual: ") + hipGetErrorString(e));
   std::vector<double> rr(h->ngroups, 0.0), ff(h->ngroups, 0.0);
   for (int l = 0; l < h->L; ++l) {
     const int g = h->h_group[l];
-    for (int b = wt.h_lev_begin[l]; b < wt.h_lev_begin[l + 1]; ++b) {
+    for (int b = tab->h_lev_begin[l]; b < tab->h_lev_begin[l + 1]; ++b) {
       rr[g] += hp[2 * b];
       ff[g] += hp[2 * b + 1];
     }
@@ -2058,7 +2282,13 @@ static void launch_apply(mskm_hier* h, int op, const T* v1, const T* v2, const T
   const Csr* A1 = op == MSKM_OP_LOWER ? &h->lower : &h->diag;
   const Csr* A2 = op == MSKM_OP_FULL ? &h->lower : nullptr;
   const int G = h->spmv_g[op][sizeof(T) == 4 ? 1 : 0];
-  if (G == kSellCode || G == kSell32Code) {  // diagonal operator only
+  if (G == kSellCode && op != MSKM_OP_DIAG) {  // the sliced copies of the lower (and diagonal) blocks
+    if (!launch_lsell<T>(h, op == MSKM_OP_FULL, x, (const T*)nullptr, y, (T)1, 0, h->N))
+      spmv_launch<T>(h->ctx->stream, 16 + kVecFlag, A1, v1, A2, v2, x, (const T*)nullptr, y, (T)1, 0, h->N, h->prec,
+                     h->dim);
+    return;
+  }
+  if (G == kSellCode || G == kSell32Code) {  // diagonal operator
     const dim3 grid(nblk(h->sell.nslices, kBlock / kSellC));
     if (h->sell.nslices <= 0) return;
     if (G == kSellCode && h->sell.col16)
@@ -2115,7 +2345,9 @@ mskm_status autotune(mskm_hier* h, int repeats, float* times_out) {
       float best = 1e30f;
       int bestg = h->spmv_g[op][prec];
       for (int wi = 0; wi < kTuneVariants && st == MSKM_OK; ++wi) {
-        if (widths[wi] >= kSell32Code && op != MSKM_OP_DIAG) {  // the sliced copy holds the diagonal blocks only
+        // lower and full operators: the sliced copies when the lower one is built (16-bit columns only)
+        const bool lsell_ok = h->lsell.built && (prec == 0 ? h->lsell.val != nullptr : h->lsell.val32 != nullptr);
+        if (widths[wi] >= kSell32Code && op != MSKM_OP_DIAG && !(widths[wi] == kSellCode && lsell_ok)) {
           if (times_out) times_out[(op * 2 + prec) * kTuneVariants + wi] = 0.f;
           continue;
         }

@@ -203,14 +203,29 @@ template <typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_mr_dir(const WorkTable wt, int base, const TX* __restrict__ r, TX* __restrict__ p,
              const MrState* __restrict__ st, const int32_t* __restrict__ lev_done, MrCfg c) {
-  // r here is the direction's source: the residual, or z = M^-1 r when preconditioned
+  // r here is the direction's source: the residual, or z = M^-1 r when
+  // preconditioned. Lane gl of a row group owns right-hand sides gl + m LR:
+  // their state is read once, then the group's rows are streamed (a group's
+  // lanes touch consecutive entries of a row).
   const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
   if (lev_done[l]) return;
-  const int64_t e0 = wt.row0[blk] * c.R, e1 = wt.row1[blk] * c.R;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-    const MrState& S = st[(size_t)l * c.R + (int)(e % c.R)];
-    if (!S.done) p[e] = r[e] + (TX)S.beta * p[e];
+  const int gl = threadIdx.x % c.LR;
+  TX beta[kMaxRPerLane];
+  bool run[kMaxRPerLane];
+#pragma unroll
+  for (int m = 0; m < kMaxRPerLane; ++m) {
+    const int rr = gl + m * c.LR;
+    run[m] = m < c.RM && rr < c.R && !st[(size_t)l * c.R + rr].done;
+    beta[m] = run[m] ? (TX)st[(size_t)l * c.R + rr].beta : (TX)0;
+  }
+  for (int64_t i = wt.row0[blk] + threadIdx.x / c.LR; i < wt.row1[blk]; i += kBlock / c.LR) {
+#pragma unroll
+    for (int m = 0; m < kMaxRPerLane; ++m) {
+      if (!run[m]) continue;
+      const int64_t e = i * c.R + gl + m * c.LR;
+      p[e] = r[e] + beta[m] * p[e];
+    }
   }
 }
 
@@ -287,17 +302,24 @@ __global__ void __launch_bounds__(kBlock)
   const int l = wt.lev[blk];
   if (lev_done[l]) return;
   const int gl = threadIdx.x % c.LR;
-  double acc[kMaxRPerLane];
-  for (int m = 0; m < kMaxRPerLane; ++m) acc[m] = 0.0;
+  double acc[kMaxRPerLane], alpha[kMaxRPerLane];
+  bool has[kMaxRPerLane], run[kMaxRPerLane];
+#pragma unroll
+  for (int m = 0; m < kMaxRPerLane; ++m) {  // the lane's systems: state read once
+    const int rr = gl + m * c.LR;
+    acc[m] = 0.0;
+    has[m] = m < c.RM && rr < c.R;
+    run[m] = has[m] && !st[(size_t)l * c.R + rr].done;
+    alpha[m] = run[m] ? st[(size_t)l * c.R + rr].alpha : 0.0;
+  }
   for (int64_t i = wt.row0[blk] + threadIdx.x / c.LR; i < wt.row1[blk]; i += kBlock / c.LR) {
-    for (int m = 0; m < c.RM; ++m) {
-      const int rr = gl + m * c.LR;
-      if (rr >= c.R) continue;
-      const MrState& S = st[(size_t)l * c.R + rr];
-      const int64_t e = i * c.R + rr;
-      if (!S.done) {
-        x[e] = (TX)((double)x[e] + S.alpha * (double)p[e]);
-        r[e] = (TX)((double)r[e] - S.alpha * (double)q[e]);
+#pragma unroll
+    for (int m = 0; m < kMaxRPerLane; ++m) {
+      if (!has[m]) continue;
+      const int64_t e = i * c.R + gl + m * c.LR;
+      if (run[m]) {
+        x[e] = (TX)((double)x[e] + alpha[m] * (double)p[e]);
+        r[e] = (TX)((double)r[e] - alpha[m] * (double)q[e]);
       }
       acc[m] += (double)r[e] * (double)r[e];
     }
@@ -501,7 +523,10 @@ mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>
   hipStream_t s = h->ctx->stream;
   const MrCfg c = W.c;
   const WorkTable& ws = h->wt_spmv;
-  const WorkTable& wv = h->wt_vec;
+  // vector phases: 64-row blocks when each row carries 16 or more right-hand
+  // sides (a 1024-row block of 512 right-hand sides left small levels to a
+  // handful of workgroups), else the 1024-row streaming table
+  const WorkTable& wv = c.R >= 16 ? h->wt_spmv : h->wt_vec;
   int lo = 0, hi = h->L - 1;
   while (lo < h->L && !on[lo]) ++lo;
   while (hi >= 0 && !on[hi]) --hi;

@@ -51,7 +51,7 @@ def test_binding_names_match_header():
 def test_abi_version(lib):
     import paper_2503_04914_amd as m
 
-    assert m.mskm_abi_version() == 2
+    assert m.mskm_abi_version() == 3
 
 
 def test_null_arguments_are_rejected(lib):
