@@ -390,12 +390,26 @@ __global__ void __launch_bounds__(kWave)
 }
 
 // Fill pass on the same staged tiles, four waves per tile: wave w fills rows
-// w, w + 4, ... of the tile, one row at a time; for each row the lanes test
-// 64 candidates per step and the hits are compacted with a ballot prefix
-// count, so each row's columns and values are written as contiguous,
-// coalesced runs in ascending order. The first wave computes the box.
+// w, w + 4, ... of the tile, one row at a time (the row's quantities are
+// wave-uniform). For each level the lanes test 64 candidates per step (in
+// 2-D the row's three cell-row ranges taken as one list); the hits' squared
+// distances and columns are appended in order to the wave's LDS queue (ballot
+// prefix count), which is flushed 64 entries at a time and at the end of the
+// row's run: every lane then evaluates one phi value, and the stores of a
+// flush are one contiguous run per array, in ascending column order. So the
+// FP64 square root and division run on full waves instead of on the ~third
+// of the lanes that hit in a step. The first wave computes the box.
 constexpr int kFillWaves = 4;
-constexpr int kBoxCols = 16;  // cell starts of a box row staged in LDS (boxes of up to 15 cells in x)
+constexpr int kBoxCols = 16;     // cell starts of a box row staged in LDS (boxes of up to 15 cells in x)
+constexpr int kQueue = 2 * kWave;  // hit queue of a wave: up to 63 carried + 64 appended
+
+// Orders a wave's LDS accesses before and after this point (the queue is
+// written and read by different lanes of the same wave).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int DIM>
 __global__ void __launch_bounds__(kFillWaves * kWave)
@@ -404,9 +418,12 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
                     int32_t* __restrict__ dcol, double* __restrict__ dval, float* __restrict__ dval32,
                     const int64_t* __restrict__ lptr, int32_t* __restrict__ lcol, double* __restrict__ lval,
                     float* __restrict__ lval32, float* __restrict__ dlo, float* __restrict__ llo) {
-  __shared__ double sx[kTileCap], sy[kTileCap], sz[DIM == 3 ? kTileCap : 1];
+  __shared__ double2 sxy[kTileCap];
+  __shared__ double sz[DIM == 3 ? kTileCap : 1];
   __shared__ int64_t box_a[kMaxBoxRows];
   __shared__ int32_t box_o[kMaxBoxRows];
+  __shared__ double q_d2[kFillWaves][kQueue];
+  __shared__ int32_t q_col[kFillWaves][kQueue];
   // the box's cell starts, cs[row key + BX0 + c] for c <= BX1 - BX0 + 1, when
   // the box is at most kBoxCols - 1 cells wide (box[7] = 1): a row's candidate
   // ranges are then read from LDS, not from the cell table in global memory
@@ -414,10 +431,13 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
   __shared__ int box[8];         // X0, X1, Y0, Y1, Z0, Z1, staged, cell starts staged
   __shared__ int64_t lpos_s[kWave];  // next lower-block position of each row of the tile
   const DevLevel Lk = lev[k];
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const int64_t tile0 = (int64_t)blockIdx.x * kWave;
   const int nrow_tile = (int)min<int64_t>(kWave, Lk.n - tile0);
+  double* const qd = q_d2[w];
+  int32_t* const qc = q_col[w];
   const double* X = xs;
   const double* Y = xs + N;
   const double* Z = xs + 2 * N;
@@ -494,8 +514,7 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
         const int32_t qo = box_o[q];
         const int32_t qn = (q + 1 < nrows ? box_o[q + 1] : total) - qo;
         for (int t = threadIdx.x; t < qn; t += kFillWaves * kWave) {
-          sx[qo + t] = X[qa + t];
-          sy[qo + t] = Y[qa + t];
+          sxy[qo + t] = make_double2(X[qa + t], Y[qa + t]);
           if (DIM == 3) sz[qo + t] = Z[qa + t];
         }
       }
@@ -515,81 +534,98 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
       const int qy0 = max(cy - 1, 0), qy1 = min(cy + 1, Lj.nc[1] - 1);
       const int qz0 = DIM == 3 ? max(cz - 1, 0) : 0, qz1 = DIM == 3 ? min(cz + 1, Lj.nc[2] - 1) : 0;
       const int64_t pos = is_diag ? dptr[i] : lpos_s[q];
-      int64_t nh = 0;
-      // one candidate step: 64 lanes test candidates, hits compacted in order
-      auto step = [&](int64_t t, int64_t sh, bool valid) {
-        bool hit = false;
-        double d2 = 0.0;
-        if (valid) {
-          double cxv, cyv, czv = 0.0;
-          if (staged) {
-            cxv = sx[t + sh];
-            cyv = sy[t + sh];
-            if (DIM == 3) czv = sz[t + sh];
-          } else {
-            cxv = X[t];
-            cyv = Y[t];
-            if (DIM == 3) czv = Z[t];
-          }
-          d2 = sqdist(DIM, qx, qy, qz, cxv, cyv, czv);
-          hit = d2 < Lj.d2max;
-        }
-        const uint64_t m = __ballot(hit);
-        if (hit) {
-          const int64_t pp = pos + nh + __popcll(m & below);
-          col[pp] = (int32_t)t;
+      int64_t nh = 0;  // the row's entries written so far
+      int qn = 0;      // queued hits
+      // write queue entries 0 .. m-1 at the row's next m positions
+      auto flush = [&](int m) {
+        wave_lds_sync();
+        if (lane < m) {
+          const double d2 = qd[lane];
+          const int64_t pp = pos + nh + lane;
+          col[pp] = qc[lane];
           const double v = phi31_d2(d2, Lj.delta);
           if (val) val[pp] = v;
           if (val32) val32[pp] = (float)v;
           if (vlo) vlo[pp] = (float)(v - (double)(float)v);
         }
-        nh += __popcll(m);
+        nh += m;
+      };
+      // one candidate step: 64 lanes test candidates, hits appended in order
+      auto step = [&](int32_t t, double cxv, double cyv, double czv, bool valid) {
+        const double d2 = valid ? sqdist(DIM, qx, qy, qz, cxv, cyv, czv) : Lj.d2max;
+        const bool hit = d2 < Lj.d2max;
+        const uint64_t m = __ballot(hit);
+        if (hit) {
+          const int o = qn + __popcll(m & below);
+          qd[o] = d2;
+          qc[o] = t;
+        }
+        qn += __popcll(m);
+        if (qn >= kWave) {
+          flush(kWave);
+          const int rest = qn - kWave;
+          double dr = 0.0;
+          int32_t cr = 0;
+          if (lane < rest) {
+            dr = qd[kWave + lane];
+            cr = qc[kWave + lane];
+          }
+          wave_lds_sync();
+          if (lane < rest) {
+            qd[lane] = dr;
+            qc[lane] = cr;
+          }
+          qn = rest;
+        }
       };
       if constexpr (DIM == 2) {
-        // the row's 3 cell-row ranges taken as one concatenated candidate list,
-        // so that the steps of 64 lanes are full (ascending across the ranges)
-        int64_t ra[3] = {0, 0, 0}, rs[3] = {0, 0, 0}, rl[3] = {0, 0, 0};
-        int nr = 0;
-        for (int yy = qy0; yy <= qy1; ++yy, ++nr) {
-          int64_t a, b;
-          if (cs_staged) {  // the row's cells lie inside the box: qx0 >= BX0, qx1 + 1 <= BX1 + 1
-            const int32_t* bc = box_cs + (yy - BY0) * kBoxCols;
-            a = bc[qx0 - BX0];
-            b = bc[qx1 + 1 - BX0];
-          } else {
-            const int rk = yy * Lj.nc[0];
-            a = cs[rk + qx0];
-            b = cs[rk + qx1 + 1];
+        // the row's cell-row ranges as one list: candidate c of range r is
+        // point c + gb[r] (LDS slot c + lb[r] when staged)
+        int32_t cnt[3], gb[3], lb[3];
+        int32_t pre = 0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const int yy = qy0 + r;
+          int32_t a = 0, b = 0, sh = 0;
+          if (yy <= qy1) {
+            if (cs_staged) {  // the row's cells lie inside the box: qx0 >= BX0, qx1 + 1 <= BX1 + 1
+              const int32_t* bc = box_cs + (yy - BY0) * kBoxCols;
+              a = bc[qx0 - BX0];
+              b = bc[qx1 + 1 - BX0];
+            } else {
+              const int rk = yy * Lj.nc[0];
+              a = cs[rk + qx0];
+              b = cs[rk + qx1 + 1];
+            }
+            if (staged) sh = box_o[yy - BY0] - (int32_t)box_a[yy - BY0];
           }
-          const int64_t sh = staged ? (int64_t)box_o[yy - BY0] - box_a[yy - BY0] : 0;
-          if (nr == 0) {
-            ra[0] = a; rs[0] = sh; rl[0] = b - a;
-          } else if (nr == 1) {
-            ra[1] = a; rs[1] = sh; rl[1] = b - a;
-          } else {
-            ra[2] = a; rs[2] = sh; rl[2] = b - a;
-          }
+          cnt[r] = b - a;
+          gb[r] = a - pre;
+          lb[r] = a + sh - pre;
+          pre += b - a;
         }
-        const int64_t total = rl[0] + rl[1] + rl[2];
-        for (int64_t c0 = 0; c0 < total; c0 += kWave) {
-          const int64_t c = c0 + lane;
-          int64_t t, sh;
-          if (c < rl[0]) {
-            t = ra[0] + c;
-            sh = rs[0];
-          } else if (c < rl[0] + rl[1]) {
-            t = ra[1] + (c - rl[0]);
-            sh = rs[1];
-          } else {
-            t = ra[2] + (c - rl[0] - rl[1]);
-            sh = rs[2];
+        const int32_t total = pre, e1 = cnt[0], e2 = cnt[0] + cnt[1];
+        for (int32_t c0 = 0; c0 < total; c0 += kWave) {
+          const int32_t c = c0 + lane;
+          const bool valid = c < total;
+          const int32_t t = c + (c < e1 ? gb[0] : c < e2 ? gb[1] : gb[2]);
+          double cxv = 0.0, cyv = 0.0;
+          if (staged) {
+            if (valid) {
+              const double2 p = sxy[c + (c < e1 ? lb[0] : c < e2 ? lb[1] : lb[2])];
+              cxv = p.x;
+              cyv = p.y;
+            }
+          } else if (valid) {
+            cxv = X[t];
+            cyv = Y[t];
           }
-          step(t, sh, c < total);
+          step(t, cxv, cyv, 0.0, valid);
         }
       } else {
         for (int zz = qz0; zz <= qz1; ++zz)
           for (int yy = qy0; yy <= qy1; ++yy) {
-            int64_t a, b;
+            int32_t a, b;
             if (cs_staged) {
               const int32_t* bc = box_cs + ((zz - BZ0) * ny + (yy - BY0)) * kBoxCols;
               a = bc[qx0 - BX0];
@@ -599,14 +635,33 @@ __global__ void __launch_bounds__(kFillWaves * kWave)
               a = cs[rk + qx0];
               b = cs[rk + qx1 + 1];
             }
-            int64_t sh = 0;
+            int32_t sh = 0;
             if (staged) {
               const int bq = (zz - BZ0) * ny + (yy - BY0);
-              sh = (int64_t)box_o[bq] - box_a[bq];
+              sh = box_o[bq] - (int32_t)box_a[bq];
             }
-            for (int64_t t0 = a; t0 < b; t0 += kWave) step(t0 + lane, sh, t0 + lane < b);
+            for (int32_t t0 = a; t0 < b; t0 += kWave) {
+              const int32_t t = t0 + lane;
+              const bool valid = t < b;
+              double cxv = 0.0, cyv = 0.0, czv = 0.0;
+              if (valid) {
+                if (staged) {
+                  const double2 p = sxy[t + sh];
+                  cxv = p.x;
+                  cyv = p.y;
+                  czv = sz[t + sh];
+                } else {
+                  cxv = X[t];
+                  cyv = Y[t];
+                  czv = Z[t];
+                }
+              }
+              step(t, cxv, cyv, czv, valid);
+            }
           }
       }
+      if (qn > 0) flush(qn);
+      wave_lds_sync();  // the queue's reads are done before the next row appends
       if (!is_diag && lane == 0) lpos_s[q] = pos + nh;
     }
     __syncthreads();  // before the next level reuses the LDS and the box
