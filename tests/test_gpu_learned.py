@@ -10,7 +10,8 @@
   save/load round trip;
 * solves with the warm start, and with the network as a preconditioner inside
   flexible CG: coefficients still match the oracle (the true residual is the
-  judge), FP64 <= 1e-10, mixed <= 1e-8.
+  judge), FP64 <= 1e-10, mixed <= 1e-8; with a zero network flexible CG is
+  block-Jacobi PCG (same coefficients, about the same iterations).
 """
 import numpy as np
 import pytest
@@ -122,6 +123,39 @@ def test_train_and_solve(env):
         # the flexible form takes the sequential algorithm and one right-hand side only
         with pytest.raises(m.MskmError):
             m.mskm_solve(ctx, hd, f, a3, m.solve_opts(precond=m.MSKM_PRECOND_FLEX_LEARNED, mlp=net.value))
+    finally:
+        m.mskm_mlp_destroy(net)
+
+
+def test_flexible_cg_with_zero_network_is_block_jacobi_pcg(env):
+    """A network whose output layer is zero gives z = M_BJ^-1 r at every
+    iteration, a fixed SPD preconditioner: flexible CG then takes the
+    iterates of block-Jacobi PCG (to rounding), so it meets the oracle's
+    coefficients and needs about the same iterations per level (the two
+    recurrences round differently, and a window of slow progress restarts
+    the flexible form's direction once)."""
+    m, ctx, (h, hd), _ = env
+    F = ol.feature_count(h.dim)
+    rng = np.random.default_rng(77)
+    W1 = (rng.standard_normal((64, F)) * 0.3).astype(np.float32)
+    b1 = (rng.standard_normal(64) * 0.1).astype(np.float32)
+    net = m.mskm_mlp_load(ctx, m.mlp_blob(h.dim, W1, b1, np.zeros(64, np.float32), 0.0))
+    try:
+        f = synth.fourier_target(6001)(h.points)
+        ref = oracle.sequential_solve(ms.assemble(h.points, h.offsets, h.delta), f)
+        common = dict(cg_rtol=1e-12, algorithm=m.MSKM_ALG_SEQUENTIAL)
+        a_bj = np.zeros_like(f)
+        r_bj = m.mskm_solve(ctx, hd, f, a_bj, m.solve_opts(precond=m.MSKM_PRECOND_BLOCK_JACOBI, **common))
+        a_fx = np.zeros_like(f)
+        r_fx = m.mskm_solve(ctx, hd, f, a_fx, m.solve_opts(precond=m.MSKM_PRECOND_FLEX_LEARNED, mlp=net.value,
+                                                            **common))
+        assert r_bj.status == m.MSKM_OK and r_fx.status == m.MSKM_OK, r_fx.report
+        for a in (a_bj, a_fx):
+            assert np.linalg.norm(a - ref) / np.linalg.norm(ref) <= 1e-10
+        it_bj, it_fx = r_bj.report["cg_iters_last"], r_fx.report["cg_iters_last"]
+        print("[flex-zero] iterations per level", it_bj, it_fx, flush=True)
+        for l in range(h.levels):
+            assert abs(it_fx[l] - it_bj[l]) <= max(3, it_bj[l] // 10), (l, it_bj, it_fx)
     finally:
         m.mskm_mlp_destroy(net)
 
