@@ -110,6 +110,97 @@ __device__ __forceinline__ void mr_block_partial(const double* acc, const MrCfg&
 
 constexpr int kMrLds = kBlock * kMaxRPerLane;  // doubles of LDS for block partials
 
+// ---------------------------------------------------------------- wave rows
+// Fast path for R = 64 RM (RM = 1, 2, 4 or 8): one wave per row, lane gl owns
+// the RM consecutive right-hand sides gl RM .. gl RM + RM - 1, so a gathered
+// row of X is one RM-wide vector load per lane (1 KiB per wave for R = 256
+// in FP32). A row's entries are read 64 at a time by the lanes and broadcast
+// with readlane, and eight gathers are issued before their products, so a
+// wave keeps eight rows of X in flight instead of one dependent chain of
+// index load -> gather per entry.
+inline bool mr_wave_rows(const MrCfg& c) {
+  return c.LR == 64 && c.R == 64 * c.RM && (c.RM == 1 || c.RM == 2 || c.RM == 4 || c.RM == 8);
+}
+
+template <int RM, typename T>
+__device__ __forceinline__ void ld_rm(const T* __restrict__ p, T (&v)[RM]) {
+  typedef T vec __attribute__((ext_vector_type(RM)));
+  const vec u = *reinterpret_cast<const vec*>(p);
+#pragma unroll
+  for (int m = 0; m < RM; ++m) v[m] = u[m];
+}
+template <int RM, typename T>
+__device__ __forceinline__ void st_rm(T* __restrict__ p, const T (&v)[RM]) {
+  typedef T vec __attribute__((ext_vector_type(RM)));
+  vec u;
+#pragma unroll
+  for (int m = 0; m < RM; ++m) u[m] = v[m];
+  *reinterpret_cast<vec*>(p) = u;
+}
+template <>
+__device__ __forceinline__ void ld_rm<1, float>(const float* __restrict__ p, float (&v)[1]) { v[0] = *p; }
+template <>
+__device__ __forceinline__ void ld_rm<1, double>(const double* __restrict__ p, double (&v)[1]) { v[0] = *p; }
+template <>
+__device__ __forceinline__ void st_rm<1, float>(float* __restrict__ p, const float (&v)[1]) { *p = v[0]; }
+template <>
+__device__ __forceinline__ void st_rm<1, double>(double* __restrict__ p, const double (&v)[1]) { *p = v[0]; }
+
+__device__ __forceinline__ int32_t lane_bcast(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float lane_bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// acc[m] += sum over the entries k in [s, e) of value(k) * X[col[k]][gl RM + m],
+// in entry order. value(k) returns the entry's value in the accumulation type TA.
+template <int RM, typename TA, typename TX, typename ValueOf>
+__device__ __forceinline__ void mr_row_acc(int64_t s, int64_t e, const int32_t* __restrict__ col, ValueOf value,
+                                           const TX* __restrict__ x, int gl, TA (&acc)[RM]) {
+  constexpr int kU = 8;
+  const int lane = threadIdx.x % 64;
+  for (int64_t k0 = s; k0 < e; k0 += 64) {
+    const int n = (int)min<int64_t>(64, e - k0);
+    const int64_t k = k0 + min(lane, n - 1);
+    const int32_t cl = col[k];
+    const TA vl = lane < n ? value(k) : (TA)0;
+    for (int u = 0; u < n; u += kU) {
+      TX xv[kU][RM];
+      TA vv[kU];
+#pragma unroll
+      for (int q = 0; q < kU; ++q) {
+        const int j = min(u + q, n - 1);  // past the run: the last entry again, with value 0
+        vv[q] = u + q < n ? lane_bcast(vl, j) : (TA)0;
+        ld_rm<RM>(x + (int64_t)lane_bcast(cl, j) * (64 * RM) + gl * RM, xv[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < kU; ++q)
+#pragma unroll
+        for (int m = 0; m < RM; ++m) acc[m] += vv[q] * (TA)xv[q][m];
+    }
+  }
+}
+
+// Block partials for the wave-row mapping: acc[m] belongs to rhs gl RM + m.
+template <int RM>
+__device__ __forceinline__ void mr_block_partial_w(const double (&acc)[RM], double* sm, double* part, int blk) {
+  constexpr int R = 64 * RM, ngrp = kBlock / 64;
+  const int gl = threadIdx.x % 64, grp = threadIdx.x / 64;
+#pragma unroll
+  for (int m = 0; m < RM; ++m) sm[grp * R + gl * RM + m] = acc[m];
+  __syncthreads();
+  for (int r = threadIdx.x; r < R; r += kBlock) {
+    double t = 0.0;
+    for (int g = 0; g < ngrp; ++g) t += sm[g * R + r];
+    part[(size_t)blk * R + r] = t;
+  }
+  __syncthreads();
+}
+
 // Reductions over a level's per-block partials part[b][R]: one block of
 // kMrRedThreads threads per (level, chunk of 64 right-hand sides); thread
 // (k, r) sums the partials b = lev_begin + k, k + kMrRedLanes, ... of rhs r,
@@ -407,6 +498,212 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// Wave-row forms of the CG product, the SpMM and the FP64 residual (R = 64 RM).
+template <int RM, typename TV, typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_mr_cg_spmm_w(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                   const TV* __restrict__ val, const TX* __restrict__ p, TX* __restrict__ q,
+                   const int32_t* __restrict__ lev_done, double* __restrict__ pqp) {
+  __shared__ double sm[kMrLds];
+  constexpr int R = 64 * RM;
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (lev_done[l]) return;
+  const int gl = threadIdx.x % 64;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  double part[RM];
+#pragma unroll
+  for (int m = 0; m < RM; ++m) part[m] = 0.0;
+  for (int64_t i = wt.row0[blk] + w; i < wt.row1[blk]; i += kBlock / 64) {
+    TX acc[RM];
+#pragma unroll
+    for (int m = 0; m < RM; ++m) acc[m] = 0;
+    mr_row_acc<RM, TX, TX>(rp[i], rp[i + 1], col, [&](int64_t k) { return (TX)val[k]; }, p, gl, acc);
+    TX pi[RM];
+    ld_rm<RM>(p + i * R + gl * RM, pi);
+    st_rm<RM>(q + i * R + gl * RM, acc);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) part[m] += (double)pi[m] * (double)acc[m];
+  }
+  mr_block_partial_w<RM>(part, sm, pqp, blk);
+}
+
+// Y[i][:] = b[i][:] + sign (A X)[i][:] for rows [r0, r1) (b nullable), one wave per row.
+template <int RM, typename TV, typename TX>
+__global__ void __launch_bounds__(kBlock)
+    k_mr_spmm_w(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, const TV* __restrict__ val,
+                const TX* __restrict__ x, const TX* __restrict__ b, TX* __restrict__ y, TX sign, int64_t r0,
+                int64_t r1) {
+  constexpr int R = 64 * RM;
+  const int gl = threadIdx.x % 64;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t i = r0 + (int64_t)blockIdx.x * (kBlock / 64) + w; i < r1; i += waves) {
+    TX acc[RM];
+#pragma unroll
+    for (int m = 0; m < RM; ++m) acc[m] = 0;
+    mr_row_acc<RM, TX, TX>(rp[i], rp[i + 1], col, [&](int64_t k) { return (TX)val[k]; }, x, gl, acc);
+    TX bi[RM];
+    if (b) ld_rm<RM>(b + i * R + gl * RM, bi);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) acc[m] = (b ? bi[m] : (TX)0) + sign * acc[m];
+    st_rm<RM>(y + i * R + gl * RM, acc);
+  }
+}
+
+// FP64 residual, one wave per row: values stored FP64, else FP32 plus the
+// FP32 remainder; partials rr[blk][r], ff[blk][r].
+template <int RM>
+__global__ void __launch_bounds__(kBlock)
+    k_mr_residual_w(const WorkTable wt, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
+                    const double* __restrict__ dv, const int64_t* __restrict__ lrp, const int32_t* __restrict__ lc,
+                    const double* __restrict__ lv, const float* __restrict__ dh, const float* __restrict__ dl,
+                    const float* __restrict__ lh, const float* __restrict__ ll, const double* __restrict__ a,
+                    const double* __restrict__ f, double* __restrict__ rout, double* __restrict__ rrp,
+                    double* __restrict__ ffp) {
+  __shared__ double sm[kMrLds];
+  constexpr int R = 64 * RM;
+  const int blk = xcd_block_id(gridDim.x);
+  const int gl = threadIdx.x % 64;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  double prr[RM], pff[RM];
+#pragma unroll
+  for (int m = 0; m < RM; ++m) prr[m] = pff[m] = 0.0;
+  for (int64_t i = wt.row0[blk] + w; i < wt.row1[blk]; i += kBlock / 64) {
+    double acc[RM];
+#pragma unroll
+    for (int m = 0; m < RM; ++m) acc[m] = 0.0;
+    if (dv)
+      mr_row_acc<RM, double, double>(drp[i], drp[i + 1], dc, [&](int64_t k) { return dv[k]; }, a, gl, acc);
+    else
+      mr_row_acc<RM, double, double>(drp[i], drp[i + 1], dc,
+                                     [&](int64_t k) { return (double)dh[k] + (double)dl[k]; }, a, gl, acc);
+    if (lv)
+      mr_row_acc<RM, double, double>(lrp[i], lrp[i + 1], lc, [&](int64_t k) { return lv[k]; }, a, gl, acc);
+    else
+      mr_row_acc<RM, double, double>(lrp[i], lrp[i + 1], lc,
+                                     [&](int64_t k) { return (double)lh[k] + (double)ll[k]; }, a, gl, acc);
+    double fi[RM];
+    ld_rm<RM>(f + i * R + gl * RM, fi);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      acc[m] = fi[m] - acc[m];
+      prr[m] += acc[m] * acc[m];
+      pff[m] += fi[m] * fi[m];
+    }
+    if (rout) st_rm<RM>(rout + i * R + gl * RM, acc);
+  }
+  mr_block_partial_w<RM>(prr, sm, rrp, blk);
+  mr_block_partial_w<RM>(pff, sm, ffp, blk);
+}
+
+// Per-level sums of block partials part[b][R] -> out[l][R] (grid: levels x
+// chunks of 64 right-hand sides; fixed order).
+__global__ void __launch_bounds__(kMrRedThreads) k_mr_level_sums(const int32_t* __restrict__ lev_begin,
+                                                                 const double* __restrict__ part,
+                                                                 double* __restrict__ out, int R) {
+  __shared__ double sm[kMrRedThreads];
+  const int l = blockIdx.x;
+  const int r = blockIdx.y * 64 + (int)(threadIdx.x % 64);
+  const double v = mr_level_sum(part, lev_begin[l], lev_begin[l + 1], R, r, sm);
+  if (threadIdx.x < 64 && r < R) out[(size_t)l * R + r] = v;
+}
+
+// Block-Jacobi product in the wave-row mapping (FP32 vectors, R = 64 RM,
+// RM <= 4): wave w of a workgroup takes blocks w, w + 4, ... of its group;
+// lane gl holds the block's m rows of r for its RM right-hand sides (one
+// RM-wide load per row), and the block's inverse entries are wave-uniform
+// (scalar loads), each applied to RM right-hand sides. MB bounds the block
+// size at compile time (8, 16 or 32 by the block's m). Partial r.z per
+// (group, rhs).
+template <int RM, int MB>
+__device__ __forceinline__ void mr_bj_block(int64_t a, int m, const float* __restrict__ Mb,
+                                            const float* __restrict__ rv, float* __restrict__ z, int gl,
+                                            double (&acc)[RM]) {
+  constexpr int R = 64 * RM;
+  float x[MB][RM];
+#pragma unroll
+  for (int j = 0; j < MB; ++j) {
+    if (j < m) {
+      ld_rm<RM>(rv + (a + j) * R + gl * RM, x[j]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < RM; ++q) x[j][q] = 0.0f;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    if (i < m) {
+      float zi[RM];
+#pragma unroll
+      for (int q = 0; q < RM; ++q) zi[q] = 0.0f;
+#pragma unroll
+      for (int j = 0; j < MB; ++j) {
+        const float mij = j < m ? Mb[(int64_t)i * m + j] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < RM; ++q) zi[q] += mij * x[j][q];
+      }
+      st_rm<RM>(z + (a + i) * R + gl * RM, zi);
+#pragma unroll
+      for (int q = 0; q < RM; ++q) acc[q] += (double)x[i][q] * (double)zi[q];
+    }
+  }
+}
+
+// Blocks of more than 16 rows (rare): one right-hand side of the lane at a time.
+template <int RM>
+__device__ __forceinline__ void mr_bj_block_big(int64_t a, int m, const float* __restrict__ Mb,
+                                                const float* __restrict__ rv, float* __restrict__ z, int gl,
+                                                double (&acc)[RM]) {
+  constexpr int R = 64 * RM;
+#pragma unroll
+  for (int q = 0; q < RM; ++q) {
+    float x[kBjMax];
+#pragma unroll
+    for (int j = 0; j < kBjMax; ++j) x[j] = j < m ? rv[(a + j) * R + gl * RM + q] : 0.0f;
+    for (int i = 0; i < m; ++i) {
+      float zi = 0.0f, xi = 0.0f;
+#pragma unroll
+      for (int j = 0; j < kBjMax; ++j) {
+        zi += (j < m ? Mb[(int64_t)i * m + j] : 0.0f) * x[j];
+        if (j == i) xi = x[j];
+      }
+      z[(a + i) * R + gl * RM + q] = zi;
+      acc[q] += (double)xi * (double)zi;
+    }
+  }
+}
+
+template <int RM>
+__global__ void __launch_bounds__(kBlock)
+    k_mr_bj_apply_w(const WorkTable wt, int base, const int64_t* __restrict__ start, const int32_t* __restrict__ of_row,
+                    const int64_t* __restrict__ off, const float* __restrict__ inv, const float* __restrict__ rv,
+                    float* __restrict__ z, const int32_t* __restrict__ lev_done, double* __restrict__ rzp) {
+  __shared__ double sm[kMrLds];
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (lev_done && lev_done[l]) return;
+  const int gl = threadIdx.x % 64;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int64_t row0 = wt.row0[blk], row1 = wt.row1[blk];
+  const int32_t bfirst = of_row[row0], blast = of_row[row1 - 1];
+  double acc[RM];
+#pragma unroll
+  for (int q = 0; q < RM; ++q) acc[q] = 0.0;
+  for (int32_t b = bfirst + w; b <= blast; b += kBlock / 64) {
+    const int64_t a = start[b];
+    const int m = (int)(start[b + 1] - a);
+    const float* Mb = inv + off[b];
+    if (m <= 8)
+      mr_bj_block<RM, 8>(a, m, Mb, rv, z, gl, acc);
+    else if (m <= 16)
+      mr_bj_block<RM, 16>(a, m, Mb, rv, z, gl, acc);
+    else
+      mr_bj_block_big<RM>(a, m, Mb, rv, z, gl, acc);
+  }
+  mr_block_partial_w<RM>(acc, sm, rzp, blk);
+}
+
 // FP64 residual per rhs over the level-aligned SpMV table: partials
 // rr[blk][r], ff[blk][r]. Values: stored FP64, else the split FP32 values
 // (hi + remainder; an FP32-only hierarchy stores the remainders).
@@ -563,9 +860,26 @@ mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>
   }
   const dim3 zgrid(std::max(zbn, 1), (c.R + 63) / 64);
   auto bj_apply = [&](const int32_t* ld) {
-    if (zbn > 0)
-      hipLaunchKernelGGL(k_mr_bj_apply<TX>, zgrid, dim3(kBlock), 0, s, B.wt, zb0, B.start, B.of_row, B.off, inv,
-                         (const TX*)r, z, ld, W.part_z, c);
+    if (zbn <= 0) return;
+    if constexpr (sizeof(TX) == 4) {
+      if (mr_wave_rows(c) && c.RM <= 4) {
+        const dim3 g1(zbn);
+        const float *iv = (const float*)inv, *rr = (const float*)r;
+        float* zz = (float*)z;
+        if (c.RM == 1)
+          hipLaunchKernelGGL(k_mr_bj_apply_w<1>, g1, dim3(kBlock), 0, s, B.wt, zb0, B.start, B.of_row, B.off, iv, rr,
+                             zz, ld, W.part_z);
+        else if (c.RM == 2)
+          hipLaunchKernelGGL(k_mr_bj_apply_w<2>, g1, dim3(kBlock), 0, s, B.wt, zb0, B.start, B.of_row, B.off, iv, rr,
+                             zz, ld, W.part_z);
+        else
+          hipLaunchKernelGGL(k_mr_bj_apply_w<4>, g1, dim3(kBlock), 0, s, B.wt, zb0, B.start, B.of_row, B.off, iv, rr,
+                             zz, ld, W.part_z);
+        return;
+      }
+    }
+    hipLaunchKernelGGL(k_mr_bj_apply<TX>, zgrid, dim3(kBlock), 0, s, B.wt, zb0, B.start, B.of_row, B.off, inv,
+                       (const TX*)r, z, ld, W.part_z, c);
   };
   const int32_t* zlb = pc ? B.wt.lev_begin : nullptr;
   double* rzp = pc ? W.part_z : nullptr;
@@ -580,9 +894,31 @@ mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>
       if (vbn > 0)
         hipLaunchKernelGGL(k_mr_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, pc ? (const TX*)z : (const TX*)r, p,
                            W.st, W.lev_done, c);
-      if (sbn > 0)
-        hipLaunchKernelGGL((k_mr_cg_spmm<TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, h->diag.rowptr, h->diag.col,
-                           dval, p, q, W.lev_done, W.part_s, c);
+      if (sbn > 0) {
+        const int64_t* drp = h->diag.rowptr;
+        const int32_t* dcl = h->diag.col;
+        switch (mr_wave_rows(c) ? c.RM : 0) {
+          case 1:
+            hipLaunchKernelGGL((k_mr_cg_spmm_w<1, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, drp, dcl, dval, p,
+                               q, W.lev_done, W.part_s);
+            break;
+          case 2:
+            hipLaunchKernelGGL((k_mr_cg_spmm_w<2, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, drp, dcl, dval, p,
+                               q, W.lev_done, W.part_s);
+            break;
+          case 4:
+            hipLaunchKernelGGL((k_mr_cg_spmm_w<4, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, drp, dcl, dval, p,
+                               q, W.lev_done, W.part_s);
+            break;
+          case 8:
+            hipLaunchKernelGGL((k_mr_cg_spmm_w<8, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, drp, dcl, dval, p,
+                               q, W.lev_done, W.part_s);
+            break;
+          default:
+            hipLaunchKernelGGL((k_mr_cg_spmm<TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, drp, dcl, dval, p, q,
+                               W.lev_done, W.part_s, c);
+        }
+      }
       hipLaunchKernelGGL(k_mr_red_a, rgrid, dim3(kMrRedThreads), 0, s, lo, ws.lev_begin, W.part_s, W.st, W.lev_done,
                          c);
       if (vbn > 0)
@@ -618,8 +954,26 @@ mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>
 template <typename TV, typename TX>
 void mr_lower(mskm_hier* h, const TV* lval, const TX* t, const TX* f, TX* y, int64_t r0, int64_t r1, const MrCfg& c) {
   if (r1 <= r0) return;
-  hipLaunchKernelGGL((k_mr_spmm<TV, TX>), dim3(mr_nblk(r1 - r0, kBlock / c.LR)), dim3(kBlock), 0, h->ctx->stream,
-                     h->lower.rowptr, h->lower.col, lval, t, f, y, (TX)-1, r0, r1, c);
+  const dim3 grid(mr_nblk(r1 - r0, kBlock / c.LR));
+  hipStream_t s = h->ctx->stream;
+  const int64_t* rp = h->lower.rowptr;
+  const int32_t* cl = h->lower.col;
+  switch (mr_wave_rows(c) ? c.RM : 0) {
+    case 1:
+      hipLaunchKernelGGL((k_mr_spmm_w<1, TV, TX>), grid, dim3(kBlock), 0, s, rp, cl, lval, t, f, y, (TX)-1, r0, r1);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_mr_spmm_w<2, TV, TX>), grid, dim3(kBlock), 0, s, rp, cl, lval, t, f, y, (TX)-1, r0, r1);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_mr_spmm_w<4, TV, TX>), grid, dim3(kBlock), 0, s, rp, cl, lval, t, f, y, (TX)-1, r0, r1);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_mr_spmm_w<8, TV, TX>), grid, dim3(kBlock), 0, s, rp, cl, lval, t, f, y, (TX)-1, r0, r1);
+      break;
+    default:
+      hipLaunchKernelGGL((k_mr_spmm<TV, TX>), grid, dim3(kBlock), 0, s, rp, cl, lval, t, f, y, (TX)-1, r0, r1, c);
+  }
 }
 
 template <typename TV, typename TX>
@@ -668,25 +1022,43 @@ mskm_status mr_residual(mskm_hier* h, MrWS& W, const double* a, const double* f,
   hipStream_t s = h->ctx->stream;
   const MrCfg c = W.c;
   const WorkTable& wt = h->wt_spmv;
-  if (a_zero)
-    hipLaunchKernelGGL(k_mr_residual_zero, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, f, rout, W.part_s, W.part_v2, c);
-  else
-    hipLaunchKernelGGL(k_mr_residual, dim3(wt.nblocks), dim3(kBlock), 0, s, wt, h->diag.rowptr, h->diag.col, h->diag.val, h->lower.rowptr, h->lower.col, h->lower.val,
-                       h->diag.val32, h->diag.val32lo, h->lower.val32, h->lower.val32lo, a, f, rout, W.part_s,
-                       W.part_v2, c);
-  std::vector<double> prr((size_t)wt.nblocks * c.R), pff((size_t)wt.nblocks * c.R);
-  MSKM_HIP_TRY(hipMemcpyAsync(prr.data(), W.part_s, prr.size() * 8, hipMemcpyDeviceToHost, s));
-  MSKM_HIP_TRY(hipMemcpyAsync(pff.data(), W.part_v2, pff.size() * 8, hipMemcpyDeviceToHost, s));
+  const dim3 grid(wt.nblocks);
+  const Csr &D = h->diag, &Lw = h->lower;
+  if (a_zero) {
+    hipLaunchKernelGGL(k_mr_residual_zero, grid, dim3(kBlock), 0, s, wt, f, rout, W.part_s, W.part_v2, c);
+  } else {
+    switch (mr_wave_rows(c) ? c.RM : 0) {
+#define MSKM_MR_RES_W(RMV)                                                                                          \
+  case RMV:                                                                                                        \
+    hipLaunchKernelGGL(k_mr_residual_w<RMV>, grid, dim3(kBlock), 0, s, wt, D.rowptr, D.col, D.val, Lw.rowptr,      \
+                       Lw.col, Lw.val, D.val32, D.val32lo, Lw.val32, Lw.val32lo, a, f, rout, W.part_s, W.part_v2); \
+    break;
+      MSKM_MR_RES_W(1)
+      MSKM_MR_RES_W(2)
+      MSKM_MR_RES_W(4)
+      MSKM_MR_RES_W(8)
+#undef MSKM_MR_RES_W
+      default:
+        hipLaunchKernelGGL(k_mr_residual, grid, dim3(kBlock), 0, s, wt, D.rowptr, D.col, D.val, Lw.rowptr, Lw.col,
+                           Lw.val, D.val32, D.val32lo, Lw.val32, Lw.val32lo, a, f, rout, W.part_s, W.part_v2, c);
+    }
+  }
+  // per-level sums on the device (part_v holds 2 L R doubles), then per group on the host
+  const size_t LR = (size_t)h->L * c.R;
+  const dim3 lgrid(h->L, (c.R + 63) / 64);
+  hipLaunchKernelGGL(k_mr_level_sums, lgrid, dim3(kMrRedThreads), 0, s, wt.lev_begin, W.part_s, W.part_v, c.R);
+  hipLaunchKernelGGL(k_mr_level_sums, lgrid, dim3(kMrRedThreads), 0, s, wt.lev_begin, W.part_v2, W.part_v + LR, c.R);
+  std::vector<double> sums(2 * LR);
+  MSKM_HIP_TRY(hipMemcpyAsync(sums.data(), W.part_v, sums.size() * 8, hipMemcpyDeviceToHost, s));
   MSKM_HIP_TRY(hipStreamSynchronize(s));
   rel.assign((size_t)c.R * h->ngroups, 0.0);
   std::vector<double> rr((size_t)c.R * h->ngroups, 0.0), ff((size_t)c.R * h->ngroups, 0.0);
   for (int l = 0; l < h->L; ++l) {
     const int g = h->h_group[l];
-    for (int b = wt.h_lev_begin[l]; b < wt.h_lev_begin[l + 1]; ++b)
-      for (int r = 0; r < c.R; ++r) {
-        rr[(size_t)r * h->ngroups + g] += prr[(size_t)b * c.R + r];
-        ff[(size_t)r * h->ngroups + g] += pff[(size_t)b * c.R + r];
-      }
+    for (int r = 0; r < c.R; ++r) {
+      rr[(size_t)r * h->ngroups + g] += sums[(size_t)l * c.R + r];
+      ff[(size_t)r * h->ngroups + g] += sums[LR + (size_t)l * c.R + r];
+    }
   }
   for (size_t i = 0; i < rel.size(); ++i) rel[i] = ff[i] > 0.0 ? std::sqrt(rr[i] / ff[i]) : std::sqrt(rr[i]);
   return MSKM_OK;
@@ -717,7 +1089,7 @@ mskm_status lagrange_columns(mskm_hier* h, int l, int64_t n0, int R, double rtol
   for (void** v : {&W.r, &W.p, &W.q}) MSKM_TRY(dalloc(reinterpret_cast<char**>(v), NR * 8));
   const size_t nbp = (size_t)std::max(h->wt_spmv.nblocks, h->wt_vec.nblocks) * R;
   MSKM_TRY(dalloc(&W.part_s, nbp));
-  MSKM_TRY(dalloc(&W.part_v, nbp));
+  MSKM_TRY(dalloc(&W.part_v, std::max(nbp, (size_t)2 * h->L * R)));
   MSKM_TRY(dalloc(&W.part_v2, nbp));
   MSKM_TRY(dalloc(&W.st, (size_t)h->L * R));
   MSKM_TRY(dalloc(&W.lev_done, h->L));
@@ -763,7 +1135,7 @@ mskm_status solve_multi(mskm_hier* h, const double* f_in, int nrhs, const mskm_s
   }
   const size_t nbp = (size_t)std::max(h->wt_spmv.nblocks, h->wt_vec.nblocks) * nrhs;
   MSKM_TRY(dalloc(&W.part_s, nbp));
-  MSKM_TRY(dalloc(&W.part_v, nbp));
+  MSKM_TRY(dalloc(&W.part_v, std::max(nbp, (size_t)2 * h->L * nrhs)));  // also the residual's level sums
   MSKM_TRY(dalloc(&W.part_v2, nbp));
   if (W.pc) MSKM_TRY(dalloc(&W.part_z, (size_t)std::max(h->bj.wt.nblocks, 1) * nrhs));
   MSKM_TRY(dalloc(&W.st, (size_t)h->L * nrhs));
