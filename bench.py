@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32
 # HBM bytes per launch of the roofline kernel (the CG product on the finest
 # level): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of
 # `bench.py --spmv-only --spmv-op cg --spmv-prec fp32 --spmv-variant 4064`,
@@ -231,6 +232,25 @@ def batched(m, ctx, hd, h, pts_dev, dev, fast_opts, rt_fast, nrhs, count):
                             "max_rel_residual": float(rel.max()), "status": res.status,
                             "cg_iters_total": res.report["cg_iters_total"], "refine": res.report["refine_steps"]}
         log("multi_rhs", out["multi_rhs"])
+        # roofline of the solve's dominant kernel: its CG product on the finest level
+        top = h.levels - 1
+        ms_p = m.mskm_mr_product_time(ctx, hd, top, nrhs, prec=m.MSKM_PREC_FP32, repeats=5)
+        nnz_t, n_t = m.block_nnz(ctx, hd, top, top), int(h.sizes()[top])
+        byt = nnz_t * 8 + (n_t + 1) * 8 + 2 * n_t * nrhs * 4  # values + columns, row pointers, P read once, Q written
+        flop = 2.0 * nnz_t * nrhs
+        t_hbm, t_alu = byt / (HBM_PEAK_GBS * 1e9), flop / (FP32_PEAK_TFLOPS * 1e12)
+        bound = "hbm" if t_hbm >= t_alu else "alu"
+        achieved = byt / (ms_p * 1e-3) / 1e9 if bound == "hbm" else flop / (ms_p * 1e-3) / 1e12
+        peak = HBM_PEAK_GBS if bound == "hbm" else FP32_PEAK_TFLOPS
+        out["multi_rhs"]["roofline"] = {
+            "bound": bound, "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": f"k_mr_cg_spmm_w<1,float,float> (CG product Q = A_l P for {nrhs} right-hand sides in chunks "
+                      f"of 64, level {top}: {n_t} rows, {nnz_t} nonzeros, FP32)",
+            "ms": round(ms_p, 4), "algorithmic_bytes": byt, "flop": flop,
+            "tflops": round(flop / (ms_p * 1e-3) / 1e12, 2),
+            "gathered_bytes": nnz_t * nrhs * 4}  # the rows of P read through the caches, one per nonzero
+        log("multi_rhs roofline", out["multi_rhs"]["roofline"])
         del F, A
         torch.cuda.empty_cache()
     if count > 0:

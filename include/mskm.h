@@ -255,6 +255,17 @@ mskm_status mskm_autotune(mskm_ctx* ctx, mskm_hier* h, int32_t repeats, float* t
 mskm_status mskm_cg_product_time(mskm_ctx* ctx, mskm_hier* h, int32_t level, int32_t prec, int32_t repeats,
                                  float* avg_ms);
 
+/* Mean device time (avg_ms, host) of the CG product of the many-right-hand-
+ * side solve (Theorem cg applied to nrhs systems at once: Q = A_l P for an
+ * N x nrhs block P, point-major, with the per-system partials p.q) on level
+ * `level` alone, in the vector precision of prec (FP32 values and vectors,
+ * or FP64), launched `repeats` (>= 1) times back to back between two HIP
+ * events on the context stream: the launch shape of the solver's products.
+ * nrhs in [2, 512] (MSKM_EINVAL otherwise). Allocates and frees its own P, Q
+ * and partials (MSKM_ENOMEM when they do not fit). */
+mskm_status mskm_mr_product_time(mskm_ctx* ctx, mskm_hier* h, int32_t level, int32_t prec, int32_t nrhs,
+                                 int32_t repeats, float* avg_ms);
+
 /* Current SpMV variant code for op (MSKM_OP_*) and prec (MSKM_PREC_*). */
 mskm_status mskm_spmv_width(const mskm_hier* h, int32_t op, int32_t prec, int32_t* width);
 

@@ -39,7 +39,7 @@ EXPORTED = [
     "mskm_hier_create", "mskm_hier_create_batch", "mskm_hier_destroy", "mskm_hier_stats_get", "mskm_hier_offsets",
     "mskm_hier_level_info",
     "mskm_export_block", "mskm_export_rows", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
-    "mskm_autotune", "mskm_spmv_width", "mskm_set_spmv_width", "mskm_cg_product_time",
+    "mskm_autotune", "mskm_spmv_width", "mskm_set_spmv_width", "mskm_cg_product_time", "mskm_mr_product_time",
     "mskm_solve_opts_default", "mskm_solve", "mskm_solve_batch", "mskm_residual", "mskm_residual_noalloc",
     "mskm_evaluate",
     "mskm_trunc_create", "mskm_trunc_destroy", "mskm_trunc_info", "mskm_trunc_export_block", "mskm_trunc_solve",
@@ -134,6 +134,7 @@ def lib():
     L.mskm_spmv_width.argtypes = [vp, i32, i32, C.POINTER(i32)]
     L.mskm_set_spmv_width.argtypes = [vp, i32, i32, i32]
     L.mskm_cg_product_time.argtypes = [vp, vp, i32, i32, i32, C.POINTER(C.c_float)]
+    L.mskm_mr_product_time.argtypes = [vp, vp, i32, i32, i32, i32, C.POINTER(C.c_float)]
     L.mskm_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
     L.mskm_solve_opts_default.restype = None
     L.mskm_solve.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(Report)]
@@ -366,6 +367,13 @@ def mskm_cg_product_time(ctx, h, level: int, prec: int = MSKM_PREC_FP32, repeats
     """Mean ms per launch of the CG product kernel on one level."""
     ms = C.c_float()
     _check(lib().mskm_cg_product_time(ctx, h, level, prec, repeats, C.byref(ms)), "mskm_cg_product_time")
+    return float(ms.value)
+
+
+def mskm_mr_product_time(ctx, h, level: int, nrhs: int, prec: int = MSKM_PREC_FP32, repeats: int = 10) -> float:
+    """Mean ms per launch of the many-right-hand-side CG product on one level."""
+    ms = C.c_float()
+    _check(lib().mskm_mr_product_time(ctx, h, level, prec, nrhs, repeats, C.byref(ms)), "mskm_mr_product_time")
     return float(ms.value)
 
 

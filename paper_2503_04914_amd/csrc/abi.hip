@@ -599,6 +599,16 @@ mskm_status mskm_cg_product_time(mskm_ctx* ctx, mskm_hier* h, int32_t level, int
   return mskm::time_cg_product(h, level, prec, repeats, avg_ms);
 }
 
+mskm_status mskm_mr_product_time(mskm_ctx* ctx, mskm_hier* h, int32_t level, int32_t prec, int32_t nrhs,
+                                 int32_t repeats, float* avg_ms) {
+  if (!valid_ctx(ctx) || !h || !avg_ms) return fail(MSKM_EINVAL, "mskm_mr_product_time: NULL argument");
+  if (level < 0 || level >= h->L) return fail(MSKM_EINVAL, "level out of range");
+  if (prec != MSKM_PREC_FP64 && prec != MSKM_PREC_FP32) return fail(MSKM_EINVAL, "unknown precision");
+  if (repeats < 1) return fail(MSKM_EINVAL, "repeats must be >= 1");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::time_mr_product(h, level, prec, nrhs, repeats, avg_ms);
+}
+
 // ------------------------------------------------------- thresholded Jacobi
 
 mskm_status mskm_trunc_create(mskm_ctx* ctx, mskm_hier* h, double T, double cg_rtol, mskm_trunc** out) {

@@ -111,16 +111,21 @@ __device__ __forceinline__ void mr_block_partial(const double* acc, const MrCfg&
 constexpr int kMrLds = kBlock * kMaxRPerLane;  // doubles of LDS for block partials
 
 // ---------------------------------------------------------------- wave rows
-// Fast path for R = 64 RM (RM = 1, 2, 4 or 8): one wave per row, lane gl owns
-// the RM consecutive right-hand sides gl RM .. gl RM + RM - 1, so a gathered
-// row of X is one RM-wide vector load per lane (1 KiB per wave for R = 256
-// in FP32). A row's entries are read 64 at a time by the lanes and broadcast
-// with readlane, and eight gathers are issued before their products, so a
-// wave keeps eight rows of X in flight instead of one dependent chain of
-// index load -> gather per entry.
-inline bool mr_wave_rows(const MrCfg& c) {
-  return c.LR == 64 && c.R == 64 * c.RM && (c.RM == 1 || c.RM == 2 || c.RM == 4 || c.RM == 8);
-}
+// Fast path for R a multiple of 64: one wave per row, lane gl owns RM
+// consecutive right-hand sides gl RM .. gl RM + RM - 1 of a chunk, so a
+// gathered row of X is one RM-wide load per lane. A row's entries are read
+// 64 at a time by the lanes and broadcast with readlane, and eight gathers
+// are issued before their products, so a wave keeps eight rows of X in flight
+// instead of one dependent chain of index load -> gather per entry. The
+// CG product takes the right-hand sides in chunks of 64 (blockIdx.y, the
+// slowest launch dimension): the rows of X the running workgroups gather are
+// then 256 bytes (FP32) wide, a working set the L2 holds. On the 1M-row
+// Halton level, 256 right-hand sides, it takes 2.98 ms in chunks of 64, 3.21
+// ms in chunks of 128 and 4.12 ms unchunked. The lower products and the
+// residual read rows with entries in every coarser level, whose re-reading
+// per chunk costs more than the narrower gathers save (the top level's lower
+// product 1.6 ms unchunked, 2.3 ms in chunks of 64): one chunk of all R.
+inline bool mr_wave_rows(const MrCfg& c) { return c.LR == 64 && c.R == 64 * c.RM; }
 
 template <int RM, typename T>
 __device__ __forceinline__ void ld_rm(const T* __restrict__ p, T (&v)[RM]) {
@@ -160,7 +165,7 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
 // in entry order. value(k) returns the entry's value in the accumulation type TA.
 template <int RM, typename TA, typename TX, typename ValueOf>
 __device__ __forceinline__ void mr_row_acc(int64_t s, int64_t e, const int32_t* __restrict__ col, ValueOf value,
-                                           const TX* __restrict__ x, int gl, TA (&acc)[RM]) {
+                                           const TX* __restrict__ x, int64_t ldx, int gl, TA (&acc)[RM]) {
   constexpr int kU = 8;
   const int lane = threadIdx.x % 64;
   for (int64_t k0 = s; k0 < e; k0 += 64) {
@@ -175,7 +180,7 @@ __device__ __forceinline__ void mr_row_acc(int64_t s, int64_t e, const int32_t* 
       for (int q = 0; q < kU; ++q) {
         const int j = min(u + q, n - 1);  // past the run: the last entry again, with value 0
         vv[q] = u + q < n ? lane_bcast(vl, j) : (TA)0;
-        ld_rm<RM>(x + (int64_t)lane_bcast(cl, j) * (64 * RM) + gl * RM, xv[q]);
+        ld_rm<RM>(x + (int64_t)lane_bcast(cl, j) * ldx + gl * RM, xv[q]);
       }
 #pragma unroll
       for (int q = 0; q < kU; ++q)
@@ -185,9 +190,11 @@ __device__ __forceinline__ void mr_row_acc(int64_t s, int64_t e, const int32_t* 
   }
 }
 
-// Block partials for the wave-row mapping: acc[m] belongs to rhs gl RM + m.
+// Block partials for the wave-row mapping: acc[m] belongs to rhs c0 + gl RM
+// + m of the chunk of 64 RM right-hand sides starting at c0; part[blk][ldr].
 template <int RM>
-__device__ __forceinline__ void mr_block_partial_w(const double (&acc)[RM], double* sm, double* part, int blk) {
+__device__ __forceinline__ void mr_block_partial_w(const double (&acc)[RM], double* sm, double* part, int blk,
+                                                   int ldr = 64 * RM, int c0 = 0) {
   constexpr int R = 64 * RM, ngrp = kBlock / 64;
   const int gl = threadIdx.x % 64, grp = threadIdx.x / 64;
 #pragma unroll
@@ -196,7 +203,7 @@ __device__ __forceinline__ void mr_block_partial_w(const double (&acc)[RM], doub
   for (int r = threadIdx.x; r < R; r += kBlock) {
     double t = 0.0;
     for (int g = 0; g < ngrp; ++g) t += sm[g * R + r];
-    part[(size_t)blk * R + r] = t;
+    part[(size_t)blk * ldr + c0 + r] = t;
   }
   __syncthreads();
 }
@@ -499,18 +506,21 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Wave-row forms of the CG product, the SpMM and the FP64 residual (R = 64 RM).
+// The CG product takes the right-hand sides in chunks of 64 RM (blockIdx.y,
+// the slowest launch dimension): the rows of P that the running workgroups
+// gather are then 64 RM wide, a working set the L2 holds.
 template <int RM, typename TV, typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_mr_cg_spmm_w(const WorkTable wt, int base, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                    const TV* __restrict__ val, const TX* __restrict__ p, TX* __restrict__ q,
-                   const int32_t* __restrict__ lev_done, double* __restrict__ pqp) {
+                   const int32_t* __restrict__ lev_done, double* __restrict__ pqp, int ldr) {
   __shared__ double sm[kMrLds];
-  constexpr int R = 64 * RM;
   const int blk = base + xcd_block_id(gridDim.x);
   const int l = wt.lev[blk];
   if (lev_done[l]) return;
   const int gl = threadIdx.x % 64;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int c0 = (int)blockIdx.y * 64 * RM;
   double part[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) part[m] = 0.0;
@@ -518,41 +528,45 @@ __global__ void __launch_bounds__(kBlock)
     TX acc[RM];
 #pragma unroll
     for (int m = 0; m < RM; ++m) acc[m] = 0;
-    mr_row_acc<RM, TX, TX>(rp[i], rp[i + 1], col, [&](int64_t k) { return (TX)val[k]; }, p, gl, acc);
+    mr_row_acc<RM, TX, TX>(rp[i], rp[i + 1], col, [&](int64_t k) { return (TX)val[k]; }, p + c0, ldr, gl, acc);
     TX pi[RM];
-    ld_rm<RM>(p + i * R + gl * RM, pi);
-    st_rm<RM>(q + i * R + gl * RM, acc);
+    ld_rm<RM>(p + i * ldr + c0 + gl * RM, pi);
+    st_rm<RM>(q + i * ldr + c0 + gl * RM, acc);
 #pragma unroll
     for (int m = 0; m < RM; ++m) part[m] += (double)pi[m] * (double)acc[m];
   }
-  mr_block_partial_w<RM>(part, sm, pqp, blk);
+  mr_block_partial_w<RM>(part, sm, pqp, blk, ldr, c0);
 }
 
-// Y[i][:] = b[i][:] + sign (A X)[i][:] for rows [r0, r1) (b nullable), one wave per row.
+// Y[i][:] = b[i][:] + sign (A X)[i][:] for rows [r0, r1) (b nullable), one
+// wave per row, the right-hand sides in chunks of 64 RM (blockIdx.y; the
+// caller launches one chunk of all R).
 template <int RM, typename TV, typename TX>
 __global__ void __launch_bounds__(kBlock)
     k_mr_spmm_w(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, const TV* __restrict__ val,
                 const TX* __restrict__ x, const TX* __restrict__ b, TX* __restrict__ y, TX sign, int64_t r0,
-                int64_t r1) {
-  constexpr int R = 64 * RM;
+                int64_t r1, int ldr) {
   const int gl = threadIdx.x % 64;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int c0 = (int)blockIdx.y * 64 * RM;
   const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
   for (int64_t i = r0 + (int64_t)blockIdx.x * (kBlock / 64) + w; i < r1; i += waves) {
     TX acc[RM];
 #pragma unroll
     for (int m = 0; m < RM; ++m) acc[m] = 0;
-    mr_row_acc<RM, TX, TX>(rp[i], rp[i + 1], col, [&](int64_t k) { return (TX)val[k]; }, x, gl, acc);
+    mr_row_acc<RM, TX, TX>(rp[i], rp[i + 1], col, [&](int64_t k) { return (TX)val[k]; }, x + c0, ldr, gl, acc);
+    const int64_t o = i * ldr + c0 + gl * RM;
     TX bi[RM];
-    if (b) ld_rm<RM>(b + i * R + gl * RM, bi);
+    if (b) ld_rm<RM>(b + o, bi);
 #pragma unroll
     for (int m = 0; m < RM; ++m) acc[m] = (b ? bi[m] : (TX)0) + sign * acc[m];
-    st_rm<RM>(y + i * R + gl * RM, acc);
+    st_rm<RM>(y + o, acc);
   }
 }
 
-// FP64 residual, one wave per row: values stored FP64, else FP32 plus the
-// FP32 remainder; partials rr[blk][r], ff[blk][r].
+// FP64 residual, one wave per row, the right-hand sides in chunks of 64 RM
+// (blockIdx.y): values stored FP64, else FP32 plus the FP32 remainder;
+// partials rr[blk][r], ff[blk][r].
 template <int RM>
 __global__ void __launch_bounds__(kBlock)
     k_mr_residual_w(const WorkTable wt, const int64_t* __restrict__ drp, const int32_t* __restrict__ dc,
@@ -560,12 +574,12 @@ __global__ void __launch_bounds__(kBlock)
                     const double* __restrict__ lv, const float* __restrict__ dh, const float* __restrict__ dl,
                     const float* __restrict__ lh, const float* __restrict__ ll, const double* __restrict__ a,
                     const double* __restrict__ f, double* __restrict__ rout, double* __restrict__ rrp,
-                    double* __restrict__ ffp) {
+                    double* __restrict__ ffp, int ldr) {
   __shared__ double sm[kMrLds];
-  constexpr int R = 64 * RM;
   const int blk = xcd_block_id(gridDim.x);
   const int gl = threadIdx.x % 64;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int c0 = (int)blockIdx.y * 64 * RM;
   double prr[RM], pff[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) prr[m] = pff[m] = 0.0;
@@ -573,28 +587,30 @@ __global__ void __launch_bounds__(kBlock)
     double acc[RM];
 #pragma unroll
     for (int m = 0; m < RM; ++m) acc[m] = 0.0;
+    const double* ac = a + c0;
     if (dv)
-      mr_row_acc<RM, double, double>(drp[i], drp[i + 1], dc, [&](int64_t k) { return dv[k]; }, a, gl, acc);
+      mr_row_acc<RM, double, double>(drp[i], drp[i + 1], dc, [&](int64_t k) { return dv[k]; }, ac, ldr, gl, acc);
     else
       mr_row_acc<RM, double, double>(drp[i], drp[i + 1], dc,
-                                     [&](int64_t k) { return (double)dh[k] + (double)dl[k]; }, a, gl, acc);
+                                     [&](int64_t k) { return (double)dh[k] + (double)dl[k]; }, ac, ldr, gl, acc);
     if (lv)
-      mr_row_acc<RM, double, double>(lrp[i], lrp[i + 1], lc, [&](int64_t k) { return lv[k]; }, a, gl, acc);
+      mr_row_acc<RM, double, double>(lrp[i], lrp[i + 1], lc, [&](int64_t k) { return lv[k]; }, ac, ldr, gl, acc);
     else
       mr_row_acc<RM, double, double>(lrp[i], lrp[i + 1], lc,
-                                     [&](int64_t k) { return (double)lh[k] + (double)ll[k]; }, a, gl, acc);
+                                     [&](int64_t k) { return (double)lh[k] + (double)ll[k]; }, ac, ldr, gl, acc);
+    const int64_t o = i * ldr + c0 + gl * RM;
     double fi[RM];
-    ld_rm<RM>(f + i * R + gl * RM, fi);
+    ld_rm<RM>(f + o, fi);
 #pragma unroll
     for (int m = 0; m < RM; ++m) {
       acc[m] = fi[m] - acc[m];
       prr[m] += acc[m] * acc[m];
       pff[m] += fi[m] * fi[m];
     }
-    if (rout) st_rm<RM>(rout + i * R + gl * RM, acc);
+    if (rout) st_rm<RM>(rout + o, acc);
   }
-  mr_block_partial_w<RM>(prr, sm, rrp, blk);
-  mr_block_partial_w<RM>(pff, sm, ffp, blk);
+  mr_block_partial_w<RM>(prr, sm, rrp, blk, ldr, c0);
+  mr_block_partial_w<RM>(pff, sm, ffp, blk, ldr, c0);
 }
 
 // Per-level sums of block partials part[b][R] -> out[l][R] (grid: levels x
@@ -814,6 +830,23 @@ struct MrStats {
   bool capped = false;
 };
 
+// q = A p with the partials p.q per (block, rhs) over the blocks [b0, b0 + nb)
+// of the SpMV work table (the CG product of every running level).
+template <typename TV, typename TX>
+static void launch_mr_cg_product(mskm_hier* h, const MrCfg& c, int b0, int nb, const TV* dval, const TX* p, TX* q,
+                                 const int32_t* lev_done, double* part) {
+  hipStream_t s = h->ctx->stream;
+  const WorkTable& ws = h->wt_spmv;
+  const int64_t* drp = h->diag.rowptr;
+  const int32_t* dcl = h->diag.col;
+  if (mr_wave_rows(c))
+    hipLaunchKernelGGL((k_mr_cg_spmm_w<1, TV, TX>), dim3(nb, c.R / 64), dim3(kBlock), 0, s, ws, b0, drp, dcl, dval,
+                       p, q, lev_done, part, c.R);
+  else
+    hipLaunchKernelGGL((k_mr_cg_spmm<TV, TX>), dim3(nb), dim3(kBlock), 0, s, ws, b0, drp, dcl, dval, p, q, lev_done,
+                       part, c);
+}
+
 template <typename TV, typename TX>
 mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>& on, const TX* b, TX* x, double rtol,
                   int maxit, int K, MrStats* ms) {
@@ -862,7 +895,7 @@ mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>
   auto bj_apply = [&](const int32_t* ld) {
     if (zbn <= 0) return;
     if constexpr (sizeof(TX) == 4) {
-      if (mr_wave_rows(c) && c.RM <= 4) {
+      if (mr_wave_rows(c) && (c.RM == 1 || c.RM == 2 || c.RM == 4)) {
         const dim3 g1(zbn);
         const float *iv = (const float*)inv, *rr = (const float*)r;
         float* zz = (float*)z;
@@ -894,31 +927,7 @@ mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>
       if (vbn > 0)
         hipLaunchKernelGGL(k_mr_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, pc ? (const TX*)z : (const TX*)r, p,
                            W.st, W.lev_done, c);
-      if (sbn > 0) {
-        const int64_t* drp = h->diag.rowptr;
-        const int32_t* dcl = h->diag.col;
-        switch (mr_wave_rows(c) ? c.RM : 0) {
-          case 1:
-            hipLaunchKernelGGL((k_mr_cg_spmm_w<1, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, drp, dcl, dval, p,
-                               q, W.lev_done, W.part_s);
-            break;
-          case 2:
-            hipLaunchKernelGGL((k_mr_cg_spmm_w<2, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, drp, dcl, dval, p,
-                               q, W.lev_done, W.part_s);
-            break;
-          case 4:
-            hipLaunchKernelGGL((k_mr_cg_spmm_w<4, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, drp, dcl, dval, p,
-                               q, W.lev_done, W.part_s);
-            break;
-          case 8:
-            hipLaunchKernelGGL((k_mr_cg_spmm_w<8, TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, drp, dcl, dval, p,
-                               q, W.lev_done, W.part_s);
-            break;
-          default:
-            hipLaunchKernelGGL((k_mr_cg_spmm<TV, TX>), dim3(sbn), dim3(kBlock), 0, s, ws, sb0, drp, dcl, dval, p, q,
-                               W.lev_done, W.part_s, c);
-        }
-      }
+      if (sbn > 0) launch_mr_cg_product<TV, TX>(h, c, sb0, sbn, dval, p, q, W.lev_done, W.part_s);
       hipLaunchKernelGGL(k_mr_red_a, rgrid, dim3(kMrRedThreads), 0, s, lo, ws.lev_begin, W.part_s, W.st, W.lev_done,
                          c);
       if (vbn > 0)
@@ -958,19 +967,19 @@ void mr_lower(mskm_hier* h, const TV* lval, const TX* t, const TX* f, TX* y, int
   hipStream_t s = h->ctx->stream;
   const int64_t* rp = h->lower.rowptr;
   const int32_t* cl = h->lower.col;
-  switch (mr_wave_rows(c) ? c.RM : 0) {
-    case 1:
-      hipLaunchKernelGGL((k_mr_spmm_w<1, TV, TX>), grid, dim3(kBlock), 0, s, rp, cl, lval, t, f, y, (TX)-1, r0, r1);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_mr_spmm_w<2, TV, TX>), grid, dim3(kBlock), 0, s, rp, cl, lval, t, f, y, (TX)-1, r0, r1);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_mr_spmm_w<4, TV, TX>), grid, dim3(kBlock), 0, s, rp, cl, lval, t, f, y, (TX)-1, r0, r1);
-      break;
-    case 8:
-      hipLaunchKernelGGL((k_mr_spmm_w<8, TV, TX>), grid, dim3(kBlock), 0, s, rp, cl, lval, t, f, y, (TX)-1, r0, r1);
-      break;
+  // all right-hand sides in one chunk: the lower rows are long (all coarser
+  // levels), and re-reading them per chunk of 64 costs more than it saves
+  switch (mr_wave_rows(c) && c.RM <= 8 && (c.RM & (c.RM - 1)) == 0 ? c.RM : 0) {
+#define MSKM_MR_SPMM_W(RMV)                                                                                       \
+  case RMV:                                                                                                      \
+    hipLaunchKernelGGL((k_mr_spmm_w<RMV, TV, TX>), grid, dim3(kBlock), 0, s, rp, cl, lval, t, f, y, (TX)-1, r0, r1, \
+                       c.R);                                                                                     \
+    break;
+    MSKM_MR_SPMM_W(1)
+    MSKM_MR_SPMM_W(2)
+    MSKM_MR_SPMM_W(4)
+    MSKM_MR_SPMM_W(8)
+#undef MSKM_MR_SPMM_W
     default:
       hipLaunchKernelGGL((k_mr_spmm<TV, TX>), grid, dim3(kBlock), 0, s, rp, cl, lval, t, f, y, (TX)-1, r0, r1, c);
   }
@@ -1027,11 +1036,13 @@ mskm_status mr_residual(mskm_hier* h, MrWS& W, const double* a, const double* f,
   if (a_zero) {
     hipLaunchKernelGGL(k_mr_residual_zero, grid, dim3(kBlock), 0, s, wt, f, rout, W.part_s, W.part_v2, c);
   } else {
-    switch (mr_wave_rows(c) ? c.RM : 0) {
+    // one chunk (the rows span every level; see mr_lower)
+    switch (mr_wave_rows(c) && c.RM <= 8 && (c.RM & (c.RM - 1)) == 0 ? c.RM : 0) {
 #define MSKM_MR_RES_W(RMV)                                                                                          \
   case RMV:                                                                                                        \
     hipLaunchKernelGGL(k_mr_residual_w<RMV>, grid, dim3(kBlock), 0, s, wt, D.rowptr, D.col, D.val, Lw.rowptr,      \
-                       Lw.col, Lw.val, D.val32, D.val32lo, Lw.val32, Lw.val32lo, a, f, rout, W.part_s, W.part_v2); \
+                       Lw.col, Lw.val, D.val32, D.val32lo, Lw.val32, Lw.val32lo, a, f, rout, W.part_s, W.part_v2,  \
+                       c.R);                                                                                       \
     break;
       MSKM_MR_RES_W(1)
       MSKM_MR_RES_W(2)
@@ -1067,6 +1078,60 @@ mskm_status mr_residual(mskm_hier* h, MrWS& W, const double* a, const double* f,
 }  // namespace
 
 bool mr_supported(int nrhs) { return nrhs >= 2 && nrhs <= 64 * kMaxRPerLane; }
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mr_fill(T* __restrict__ v, int64_t n, T x) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) v[i] = x;
+}
+
+// Mean device time of the many-right-hand-side CG product (q = A_l p for R
+// right-hand sides with the partials p.q) on level `level` alone, launched
+// `repeats` times between two events; vectors of the precision the solve
+// uses for prec (FP32 values and vectors, or FP64), allocated here.
+template <typename TV, typename TX>
+static mskm_status time_mr_product_t(mskm_hier* h, const TV* dval, int level, int R, int repeats, float* avg_ms) {
+  hipStream_t s = h->ctx->stream;
+  const MrCfg c = mr_cfg(R);
+  const WorkTable& ws = h->wt_spmv;
+  const int b0 = ws.h_lev_begin[level], nb = ws.h_lev_begin[level + 1] - b0;
+  const size_t NR = (size_t)h->N * R;
+  TX *p = nullptr, *q = nullptr;
+  double* part = nullptr;
+  int32_t* done = nullptr;
+  mskm_status st = dalloc(&p, NR);
+  if (st == MSKM_OK) st = dalloc(&q, NR);
+  if (st == MSKM_OK) st = dalloc(&part, (size_t)std::max(ws.nblocks, 1) * R);
+  if (st == MSKM_OK) st = dalloc(&done, (size_t)h->L);
+  if (st == MSKM_OK) {
+    hipLaunchKernelGGL(k_mr_fill<TX>, dim3(mr_nblk((int64_t)NR, kBlock)), dim3(kBlock), 0, s, p, (int64_t)NR, (TX)1);
+    hipLaunchKernelGGL(k_mr_fill<int32_t>, dim3(1), dim3(kBlock), 0, s, done, (int64_t)h->L, 0);
+    float ms = 0.f;
+    if (hipEventRecord(h->ctx->ev0, s) != hipSuccess) st = fail(MSKM_EDEVICE, "event record");
+    for (int k = 0; st == MSKM_OK && k < repeats; ++k)
+      if (nb > 0) launch_mr_cg_product<TV, TX>(h, c, b0, nb, dval, p, q, done, part);
+    if (st == MSKM_OK && (hipEventRecord(h->ctx->ev1, s) != hipSuccess || hipEventSynchronize(h->ctx->ev1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, h->ctx->ev0, h->ctx->ev1) != hipSuccess))
+      st = fail(MSKM_EDEVICE, "event timing");
+    if (st == MSKM_OK && hipGetLastError() != hipSuccess) st = fail(MSKM_EDEVICE, "many-rhs product launch");
+    if (st == MSKM_OK) *avg_ms = ms / (float)repeats;
+  }
+  (void)hipFree(p);
+  (void)hipFree(q);
+  (void)hipFree(part);
+  (void)hipFree(done);
+  return st;
+}
+
+mskm_status time_mr_product(mskm_hier* h, int level, int prec, int R, int repeats, float* avg_ms) {
+  if (!mr_supported(R)) return fail(MSKM_EINVAL, "nrhs out of range for the many-right-hand-side product");
+  if (prec == MSKM_PREC_FP32) {
+    if (!h->diag.val32) return fail(MSKM_ESTATE, "FP32 values are not stored");
+    return time_mr_product_t<float, float>(h, h->diag.val32, level, R, repeats, avg_ms);
+  }
+  if (!h->diag.val) return fail(MSKM_ESTATE, "FP64 values are not stored");
+  return time_mr_product_t<double, double>(h, h->diag.val, level, R, repeats, avg_ms);
+}
 
 // Unit right-hand sides of level l: E[i][r] = 1 for i = off + n0 + r (r < nr).
 __global__ void __launch_bounds__(kBlock) k_mr_unit(double* __restrict__ E, int64_t off, int64_t n0, int nr, int R) {

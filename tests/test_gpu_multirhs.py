@@ -93,10 +93,13 @@ def test_multi_rhs_block_jacobi(env, name, R, prec):
     assert iters[m.MSKM_PRECOND_BLOCK_JACOBI] < iters[m.MSKM_PRECOND_NONE], iters
 
 
-@pytest.mark.parametrize("R", [64, 100])
+@pytest.mark.parametrize("R", [64, 100, 128, 192])
 def test_multi_rhs_mixed_wide_2d(env, R):
     """Mixed precision, block-Jacobi preconditioned, with R >= 64 (several
-    right-hand sides per lane) on a 2-D hierarchy."""
+    right-hand sides per lane) on a 2-D hierarchy; multiples of 64 take the
+    one-wave-per-row kernels (lanes own 1, 2 or 3 consecutive right-hand
+    sides; R = 192 has the strided lower product and block-Jacobi apply),
+    R = 100 the strided forms throughout."""
     m, ctx, get = env
     h, blk, hd = get("halton5")
     F = _targets(h, R, 3400)
@@ -180,3 +183,18 @@ def test_multi_rhs_fp32_only_hierarchy(env, name, R):
             assert rels[r] == pytest.approx(oracle.residual(blk, A[:, r], F[:, r])[0], rel=1e-6, abs=1e-15)
     finally:
         m.mskm_hier_destroy(hd)
+
+
+def test_many_rhs_product_timing(env):
+    """The timing entry point of the many-right-hand-side CG product runs the
+    solver's kernel on one level and rejects widths outside [2, 512]."""
+    m, ctx, get = env
+    h, blk, hd = get("halton5")
+    for R in (2, 64, 256):
+        ms = m.mskm_mr_product_time(ctx, hd, h.levels - 1, R, repeats=3)
+        assert 0.0 < ms < 1e3
+    for bad in (1, 513):
+        with pytest.raises(m.MskmError):
+            m.mskm_mr_product_time(ctx, hd, 0, bad)
+    with pytest.raises(m.MskmError):
+        m.mskm_mr_product_time(ctx, hd, h.levels, 64)
