@@ -242,6 +242,9 @@ struct mskm_hier {
   mskm::WorkTable wt_sell;              // per-level blocks of 4 slices ("rows" are slices)
   mskm::BlockJacobi bj;                 // cell block-Jacobi preconditioner (built at its first use)
   int32_t spmv_g[3][2] = {{8, 8}, {32, 32}, {32, 32}};  // lanes per row [op][FP64, FP32]
+  // right-hand sides per chunk of the many-rhs CG product, by R / 64 - 1 and
+  // [FP64, FP32] (0: not tuned yet; set by timing at the first solve with R)
+  int32_t mr_chunk[8][2] = {};
   int64_t device_bytes = 0;
   double assemble_ms = 0.0;
   std::vector<void*> allocs;            // everything to free

@@ -830,21 +830,79 @@ struct MrStats {
   bool capped = false;
 };
 
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mr_fill(T* __restrict__ v, int64_t n, T x) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) v[i] = x;
+}
+
 // q = A p with the partials p.q per (block, rhs) over the blocks [b0, b0 + nb)
-// of the SpMV work table (the CG product of every running level).
+// of the SpMV work table (the CG product of every running level). For R a
+// multiple of 64 the right-hand sides go in chunks of `chunk` (64, 128, 256
+// or 512, dividing R).
 template <typename TV, typename TX>
-static void launch_mr_cg_product(mskm_hier* h, const MrCfg& c, int b0, int nb, const TV* dval, const TX* p, TX* q,
-                                 const int32_t* lev_done, double* part) {
+static void launch_mr_cg_product(mskm_hier* h, const MrCfg& c, int chunk, int b0, int nb, const TV* dval,
+                                 const TX* p, TX* q, const int32_t* lev_done, double* part) {
   hipStream_t s = h->ctx->stream;
   const WorkTable& ws = h->wt_spmv;
   const int64_t* drp = h->diag.rowptr;
   const int32_t* dcl = h->diag.col;
-  if (mr_wave_rows(c))
-    hipLaunchKernelGGL((k_mr_cg_spmm_w<1, TV, TX>), dim3(nb, c.R / 64), dim3(kBlock), 0, s, ws, b0, drp, dcl, dval,
-                       p, q, lev_done, part, c.R);
-  else
+  if (!mr_wave_rows(c)) {
     hipLaunchKernelGGL((k_mr_cg_spmm<TV, TX>), dim3(nb), dim3(kBlock), 0, s, ws, b0, drp, dcl, dval, p, q, lev_done,
                        part, c);
+    return;
+  }
+  const dim3 grid(nb, c.R / chunk);
+  switch (chunk / 64) {
+#define MSKM_MR_CGP_W(RMV)                                                                                      \
+  case RMV:                                                                                                    \
+    hipLaunchKernelGGL((k_mr_cg_spmm_w<RMV, TV, TX>), grid, dim3(kBlock), 0, s, ws, b0, drp, dcl, dval, p, q,  \
+                       lev_done, part, c.R);                                                                   \
+    break;
+    MSKM_MR_CGP_W(2)
+    MSKM_MR_CGP_W(4)
+    MSKM_MR_CGP_W(8)
+#undef MSKM_MR_CGP_W
+    default:
+      hipLaunchKernelGGL((k_mr_cg_spmm_w<1, TV, TX>), dim3(nb, c.R / 64), dim3(kBlock), 0, s, ws, b0, drp, dcl, dval,
+                         p, q, lev_done, part, c.R);
+  }
+}
+
+// Chunk width of the CG product for this R: the fastest of the candidates
+// (64, 128, 256, 512 dividing R) timed once per hierarchy, R and precision on
+// its largest level, then kept (the timing overwrites q and the partials,
+// which the solve rewrites).
+template <typename TV, typename TX>
+static int mr_chunk_for(mskm_hier* h, const MrCfg& c, const TV* dval, const TX* p, TX* q, double* part,
+                        const int32_t* zeros) {
+  if (!mr_wave_rows(c) || c.R / 64 > 8) return 64;
+  int32_t& slot = h->mr_chunk[c.R / 64 - 1][sizeof(TX) == 4 ? 1 : 0];
+  if (slot > 0) return slot;
+  int big = 0;  // the largest level (a solve's first call may run only the coarsest)
+  for (int l = 1; l < h->L; ++l)
+    if (h->h_lev[l].n > h->h_lev[big].n) big = l;
+  const WorkTable& ws = h->wt_spmv;
+  const int b0 = ws.h_lev_begin[big], nb = ws.h_lev_begin[big + 1] - b0;
+  hipStream_t s = h->ctx->stream;
+  int best = 64;
+  float best_ms = 0.f;
+  for (int ch = 64; ch <= std::min(c.R, 512); ch *= 2) {
+    if (c.R % ch) continue;
+    launch_mr_cg_product<TV, TX>(h, c, ch, b0, nb, dval, p, q, zeros, part);  // warm
+    float ms = 0.f;
+    if (hipEventRecord(h->ctx->ev0, s) != hipSuccess) return 64;
+    for (int k = 0; k < 2; ++k) launch_mr_cg_product<TV, TX>(h, c, ch, b0, nb, dval, p, q, zeros, part);
+    if (hipEventRecord(h->ctx->ev1, s) != hipSuccess || hipEventSynchronize(h->ctx->ev1) != hipSuccess ||
+        hipEventElapsedTime(&ms, h->ctx->ev0, h->ctx->ev1) != hipSuccess)
+      return 64;
+    if (ch == 64 || ms < best_ms) {
+      best = ch;
+      best_ms = ms;
+    }
+  }
+  slot = best;
+  return best;
 }
 
 template <typename TV, typename TX>
@@ -916,6 +974,9 @@ mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>
   };
   const int32_t* zlb = pc ? B.wt.lev_begin : nullptr;
   double* rzp = pc ? W.part_z : nullptr;
+  // chunk width of the product (timed at the first solve with this R; levels all running)
+  hipLaunchKernelGGL(k_mr_fill<int32_t>, dim3(mr_nblk(h->L, kBlock)), dim3(kBlock), 0, s, W.lev_done, (int64_t)h->L, 0);
+  const int chunk = mr_chunk_for<TV, TX>(h, c, dval, p, q, W.part_s, W.lev_done);
   if (vbn > 0)
     hipLaunchKernelGGL(k_mr_init<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, b, x, r, p, W.st, W.part_v, c);
   if (pc) bj_apply(nullptr);
@@ -927,7 +988,7 @@ mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>
       if (vbn > 0)
         hipLaunchKernelGGL(k_mr_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, pc ? (const TX*)z : (const TX*)r, p,
                            W.st, W.lev_done, c);
-      if (sbn > 0) launch_mr_cg_product<TV, TX>(h, c, sb0, sbn, dval, p, q, W.lev_done, W.part_s);
+      if (sbn > 0) launch_mr_cg_product<TV, TX>(h, c, chunk, sb0, sbn, dval, p, q, W.lev_done, W.part_s);
       hipLaunchKernelGGL(k_mr_red_a, rgrid, dim3(kMrRedThreads), 0, s, lo, ws.lev_begin, W.part_s, W.st, W.lev_done,
                          c);
       if (vbn > 0)
@@ -1079,14 +1140,9 @@ mskm_status mr_residual(mskm_hier* h, MrWS& W, const double* a, const double* f,
 
 bool mr_supported(int nrhs) { return nrhs >= 2 && nrhs <= 64 * kMaxRPerLane; }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_mr_fill(T* __restrict__ v, int64_t n, T x) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) v[i] = x;
-}
-
 // Mean device time of the many-right-hand-side CG product (q = A_l p for R
-// right-hand sides with the partials p.q) on level `level` alone, launched
+// right-hand sides with the partials p.q) on level `level` alone, in the
+// chunk width the solver uses for R (tuned here if no solve has), launched
 // `repeats` times between two events; vectors of the precision the solve
 // uses for prec (FP32 values and vectors, or FP64), allocated here.
 template <typename TV, typename TX>
@@ -1105,11 +1161,12 @@ static mskm_status time_mr_product_t(mskm_hier* h, const TV* dval, int level, in
   if (st == MSKM_OK) st = dalloc(&done, (size_t)h->L);
   if (st == MSKM_OK) {
     hipLaunchKernelGGL(k_mr_fill<TX>, dim3(mr_nblk((int64_t)NR, kBlock)), dim3(kBlock), 0, s, p, (int64_t)NR, (TX)1);
-    hipLaunchKernelGGL(k_mr_fill<int32_t>, dim3(1), dim3(kBlock), 0, s, done, (int64_t)h->L, 0);
+    hipLaunchKernelGGL(k_mr_fill<int32_t>, dim3(mr_nblk(h->L, kBlock)), dim3(kBlock), 0, s, done, (int64_t)h->L, 0);
+    const int chunk = mr_chunk_for<TV, TX>(h, c, dval, (const TX*)p, q, part, done);
     float ms = 0.f;
     if (hipEventRecord(h->ctx->ev0, s) != hipSuccess) st = fail(MSKM_EDEVICE, "event record");
     for (int k = 0; st == MSKM_OK && k < repeats; ++k)
-      if (nb > 0) launch_mr_cg_product<TV, TX>(h, c, b0, nb, dval, p, q, done, part);
+      if (nb > 0) launch_mr_cg_product<TV, TX>(h, c, chunk, b0, nb, dval, p, q, done, part);
     if (st == MSKM_OK && (hipEventRecord(h->ctx->ev1, s) != hipSuccess || hipEventSynchronize(h->ctx->ev1) != hipSuccess ||
                           hipEventElapsedTime(&ms, h->ctx->ev0, h->ctx->ev1) != hipSuccess))
       st = fail(MSKM_EDEVICE, "event timing");
