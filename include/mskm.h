@@ -266,6 +266,13 @@ mskm_status mskm_cg_product_time(mskm_ctx* ctx, mskm_hier* h, int32_t level, int
 mskm_status mskm_mr_product_time(mskm_ctx* ctx, mskm_hier* h, int32_t level, int32_t prec, int32_t nrhs,
                                  int32_t repeats, float* avg_ms);
 
+/* Pins the CG-product layout of the many-right-hand-side solve for nrhs
+ * right-hand sides (a multiple of 64 in [64, 512]) in precision prec: chunk
+ * = 64, 128, 256 or 512 right-hand sides per launch slice (dividing nrhs).
+ * Without a pin the first solve with nrhs times the candidates on the
+ * largest level and keeps the fastest. MSKM_EINVAL for other values. */
+mskm_status mskm_set_mr_chunk(mskm_hier* h, int32_t nrhs, int32_t prec, int32_t chunk);
+
 /* Current SpMV variant code for op (MSKM_OP_*) and prec (MSKM_PREC_*). */
 mskm_status mskm_spmv_width(const mskm_hier* h, int32_t op, int32_t prec, int32_t* width);
 

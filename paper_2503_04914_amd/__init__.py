@@ -40,6 +40,7 @@ EXPORTED = [
     "mskm_hier_level_info",
     "mskm_export_block", "mskm_export_rows", "mskm_export_perm", "mskm_apply", "mskm_apply_internal",
     "mskm_autotune", "mskm_spmv_width", "mskm_set_spmv_width", "mskm_cg_product_time", "mskm_mr_product_time",
+    "mskm_set_mr_chunk",
     "mskm_solve_opts_default", "mskm_solve", "mskm_solve_batch", "mskm_residual", "mskm_residual_noalloc",
     "mskm_evaluate",
     "mskm_trunc_create", "mskm_trunc_destroy", "mskm_trunc_info", "mskm_trunc_export_block", "mskm_trunc_solve",
@@ -135,6 +136,7 @@ def lib():
     L.mskm_set_spmv_width.argtypes = [vp, i32, i32, i32]
     L.mskm_cg_product_time.argtypes = [vp, vp, i32, i32, i32, C.POINTER(C.c_float)]
     L.mskm_mr_product_time.argtypes = [vp, vp, i32, i32, i32, i32, C.POINTER(C.c_float)]
+    L.mskm_set_mr_chunk.argtypes = [vp, i32, i32, i32]
     L.mskm_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
     L.mskm_solve_opts_default.restype = None
     L.mskm_solve.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), vp, C.POINTER(Report)]
@@ -375,6 +377,11 @@ def mskm_mr_product_time(ctx, h, level: int, nrhs: int, prec: int = MSKM_PREC_FP
     ms = C.c_float()
     _check(lib().mskm_mr_product_time(ctx, h, level, prec, nrhs, repeats, C.byref(ms)), "mskm_mr_product_time")
     return float(ms.value)
+
+
+def mskm_set_mr_chunk(h, nrhs: int, prec: int, chunk: int) -> None:
+    """Pins the many-rhs CG-product chunk width (64, 128, 256 or 512 dividing nrhs)."""
+    _check(lib().mskm_set_mr_chunk(h, nrhs, prec, chunk), "mskm_set_mr_chunk")
 
 
 def mskm_set_spmv_width(h, op: int, prec: int, width: int) -> None:

@@ -609,6 +609,13 @@ mskm_status mskm_mr_product_time(mskm_ctx* ctx, mskm_hier* h, int32_t level, int
   return mskm::time_mr_product(h, level, prec, nrhs, repeats, avg_ms);
 }
 
+mskm_status mskm_set_mr_chunk(mskm_hier* h, int32_t nrhs, int32_t prec, int32_t chunk) {
+  if (!h) return fail(MSKM_EINVAL, "mskm_set_mr_chunk: NULL hierarchy");
+  if (prec != MSKM_PREC_FP64 && prec != MSKM_PREC_FP32) return fail(MSKM_EINVAL, "unknown precision");
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return fail(MSKM_EDEVICE, "hipSetDevice failed");
+  return mskm::set_mr_chunk(h, nrhs, prec, chunk);
+}
+
 // ------------------------------------------------------- thresholded Jacobi
 
 mskm_status mskm_trunc_create(mskm_ctx* ctx, mskm_hier* h, double T, double cg_rtol, mskm_trunc** out) {

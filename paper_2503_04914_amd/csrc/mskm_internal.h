@@ -357,6 +357,7 @@ mskm_status apply_internal(mskm_hier* h, int op, int prec, const void* x, void* 
 mskm_status autotune(mskm_hier* h, int repeats, float* times_out);
 mskm_status time_cg_product(mskm_hier* h, int level, int prec, int repeats, float* avg_ms);
 mskm_status time_mr_product(mskm_hier* h, int level, int prec, int R, int repeats, float* avg_ms);
+mskm_status set_mr_chunk(mskm_hier* h, int R, int prec, int chunk);
 mskm_status solve(mskm_hier* h, const double* f, int nrhs, const mskm_solve_opts* o, double* alpha,
                   mskm_report* rep);
 // trunc.hip: q per level, pattern and values of the truncated blocks

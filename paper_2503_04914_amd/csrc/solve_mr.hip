@@ -872,7 +872,10 @@ static void launch_mr_cg_product(mskm_hier* h, const MrCfg& c, int chunk, int b0
 // Chunk width of the CG product for this R: the fastest of the candidates
 // (64, 128, 256, 512 dividing R) timed once per hierarchy, R and precision on
 // its largest level, then kept (the timing overwrites q and the partials,
-// which the solve rewrites).
+// which the solve rewrites). Staging each 64-row block's distinct columns of
+// P in LDS instead (sorted lists, one byte per entry for its position) ran
+// at half the speed of the chunked gathers: the 48-64 KB of LDS per
+// workgroup leave two or three workgroups per CU.
 template <typename TV, typename TX>
 static int mr_chunk_for(mskm_hier* h, const MrCfg& c, const TV* dval, const TX* p, TX* q, double* part,
                         const int32_t* zeros) {
@@ -1139,6 +1142,15 @@ mskm_status mr_residual(mskm_hier* h, MrWS& W, const double* a, const double* f,
 }  // namespace
 
 bool mr_supported(int nrhs) { return nrhs >= 2 && nrhs <= 64 * kMaxRPerLane; }
+
+mskm_status set_mr_chunk(mskm_hier* h, int R, int prec, int chunk) {
+  if (!mr_supported(R) || R % 64) return fail(MSKM_EINVAL, "nrhs must be a multiple of 64 in [64, 512]");
+  const bool fp32 = prec == MSKM_PREC_FP32;
+  if (chunk < 64 || chunk > 512 || (chunk & (chunk - 1)) || R % chunk)
+    return fail(MSKM_EINVAL, "chunk must be a power of two in [64, 512] dividing nrhs");
+  h->mr_chunk[R / 64 - 1][fp32 ? 1 : 0] = chunk;
+  return MSKM_OK;
+}
 
 // Mean device time of the many-right-hand-side CG product (q = A_l p for R
 // right-hand sides with the partials p.q) on level `level` alone, in the

@@ -198,3 +198,35 @@ def test_many_rhs_product_timing(env):
             m.mskm_mr_product_time(ctx, hd, 0, bad)
     with pytest.raises(m.MskmError):
         m.mskm_mr_product_time(ctx, hd, h.levels, 64)
+
+
+@pytest.mark.parametrize("name", ["halton5", "uniform3d3"])
+@pytest.mark.parametrize("chunk", [64, 128])
+def test_multi_rhs_product_layouts(env, name, chunk):
+    """Each CG-product layout of the many-rhs solve, pinned (slices of 64 or
+    128 right-hand sides): each right-hand side matches the oracle."""
+    m, ctx, get = env
+    h, blk, hd = get(name)
+    R = 128
+    m.mskm_set_mr_chunk(hd, R, m.MSKM_PREC_FP32, chunk)
+    F = _targets(h, R, 3600 + chunk)
+    A = np.zeros_like(F)
+    o = m.solve_opts(precision=m.MSKM_PREC_FP32, algorithm=m.MSKM_ALG_SEQUENTIAL, cg_rtol=1e-5,
+                     target_rel_residual=1e-13, max_refine=20, precond=m.MSKM_PRECOND_BLOCK_JACOBI)
+    res = m.mskm_solve(ctx, hd, F, A, o, nrhs=R)
+    assert res.status == m.MSKM_OK, res.report
+    for r in (0, R // 3, R - 1):
+        ref = oracle.sequential_solve(blk, F[:, r])
+        for l in range(h.levels):
+            sl = slice(h.offsets[l], h.offsets[l + 1])
+            err = np.linalg.norm(A[sl, r] - ref[sl]) / np.linalg.norm(ref[sl])
+            assert err <= 1e-8, (chunk, r, l, err)
+
+
+def test_multi_rhs_layout_pin_rejects_bad_values(env):
+    m, ctx, get = env
+    h, blk, hd = get("halton5")
+    for args in ((100, m.MSKM_PREC_FP32, 64), (128, m.MSKM_PREC_FP32, 256), (128, m.MSKM_PREC_FP32, 32),
+                 (128, m.MSKM_PREC_FP32, 1), (128, m.MSKM_PREC_FP64, 96), (1024, m.MSKM_PREC_FP32, 64)):
+        with pytest.raises(m.MskmError):
+            m.mskm_set_mr_chunk(hd, *args)
