@@ -45,9 +45,21 @@ PMC_TRAFFIC = {
     ("halton2d_L8", "k_cg_spmv1_sell<float,float,true>", "level 7"): {
         "fetch_kib": 146135.97, "fetch_scale": 1048576 / 524300.42,
         "write_kib": 4192.75, "write_scale": 1048576 / 1048628.35},
+    # `bench.py --spmv-only --spmv-op mr --spmv-prec fp32 --spmv-rhs 256 --spmv-variant 4064`
+    ("halton2d_L8", "k_mr_cg_spmm_w<1,float,float> R=256", "level 7"): {
+        "fetch_kib": 3633867.2, "fetch_scale": 1048576 / 524300.0,
+        "write_kib": 1081344.0, "write_scale": 1048576 / 1048596.0},
 }
 TARGET = 1e-8
 RTOL_LADDER = [3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12]
+
+
+def pmc_traffic(key):
+    """HBM bytes per launch from the counter runs recorded for `key`, or None."""
+    pmc = PMC_TRAFFIC.get(key)
+    if pmc is None:
+        return None
+    return int(pmc["fetch_kib"] * pmc["fetch_scale"] * 1024 + pmc["write_kib"] * pmc["write_scale"] * 1024)
 
 
 def log(*a):
@@ -244,7 +256,8 @@ def batched(m, ctx, hd, h, pts_dev, dev, fast_opts, rt_fast, nrhs, count):
         peak = HBM_PEAK_GBS if bound == "hbm" else FP32_PEAK_TFLOPS
         out["multi_rhs"]["roofline"] = {
             "bound": bound, "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4), "traffic": pmc_traffic(("halton2d_L8", "k_mr_cg_spmm_w<1,float,float> R=256",
+                                                                         "level 7")) if (nrhs == 256 and h.levels == 8) else None,
             "kernel": f"k_mr_cg_spmm_w<1,float,float> (CG product Q = A_l P for {nrhs} right-hand sides in chunks "
                       f"of 64, level {top}: {n_t} rows, {nnz_t} nonzeros, FP32)",
             "ms": round(ms_p, 4), "algorithmic_bytes": byt, "flop": flop,
@@ -485,9 +498,10 @@ def main():
                          "(the counter-collection runs)")
     ap.add_argument("--spmv-variant", type=int, default=0,
                     help="with --spmv-only: pin this SpMV variant code instead of autotuning")
-    ap.add_argument("--spmv-op", choices=("diag", "lower", "full", "cg"), default="diag",
-                    help="with --spmv-only (cg: the CG product kernel on the finest level)")
+    ap.add_argument("--spmv-op", choices=("diag", "lower", "full", "cg", "mr"), default="diag",
+                    help="with --spmv-only (cg: the CG product kernel on the finest level; mr: its many-rhs form)")
     ap.add_argument("--spmv-prec", choices=("fp32", "fp64"), default="fp32", help="with --spmv-only")
+    ap.add_argument("--spmv-rhs", type=int, default=256, help="with --spmv-only --spmv-op mr: right-hand sides")
     ap.add_argument("--batch-count", type=int, default=64, help="hierarchies of the batched solve (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -516,7 +530,8 @@ def main():
     hd = m.mskm_hier_create(ctx, pts_dev, h.offsets, h.delta, fp64=True, fp32=True, sliced_lower=True)
     if args.spmv_only:
         st = m.mskm_hier_stats_get(hd)
-        op = {"diag": m.MSKM_OP_DIAG, "lower": m.MSKM_OP_LOWER, "full": m.MSKM_OP_FULL, "cg": m.MSKM_OP_DIAG}[args.spmv_op]
+        op = {"diag": m.MSKM_OP_DIAG, "lower": m.MSKM_OP_LOWER, "full": m.MSKM_OP_FULL, "cg": m.MSKM_OP_DIAG,
+              "mr": m.MSKM_OP_DIAG}[args.spmv_op]
         prec = m.MSKM_PREC_FP32 if args.spmv_prec == "fp32" else m.MSKM_PREC_FP64
         if args.spmv_variant:
             m.mskm_set_spmv_width(hd, op, prec, args.spmv_variant)
@@ -529,6 +544,10 @@ def main():
             top = args.levels - 1
             m.mskm_cg_product_time(ctx, hd, top, prec, repeats=2)
             ms = m.mskm_cg_product_time(ctx, hd, top, prec, repeats=args.spmv_repeats)
+        elif args.spmv_op == "mr":  # the many-rhs CG product on the finest level
+            top = args.levels - 1
+            m.mskm_mr_product_time(ctx, hd, top, args.spmv_rhs, prec=prec, repeats=2)
+            ms = m.mskm_mr_product_time(ctx, hd, top, args.spmv_rhs, prec=prec, repeats=args.spmv_repeats)
         else:
             m.mskm_apply_internal(ctx, hd, op, x, y, prec=prec, repeats=2)
             ms = m.mskm_apply_internal(ctx, hd, op, x, y, prec=prec, repeats=args.spmv_repeats)
@@ -549,6 +568,12 @@ def main():
             n_top = int(h.offsets[top + 1] - h.offsets[top])
             b = spmv_bytes(m.block_nnz(ctx, hd, top, top), n_top, 1, sv, sv) + n_top * sv
             kname = cg_product_kernel_name(code, bool(st["sell_col16"]))
+        elif args.spmv_op == "mr":
+            top = args.levels - 1
+            n_top = int(h.offsets[top + 1] - h.offsets[top])
+            b = m.block_nnz(ctx, hd, top, top) * (sv + 4) + (n_top + 1) * 8 + 2 * n_top * args.spmv_rhs * sv
+            tname = "float" if sv == 4 else "double"
+            kname = f"mskm::k_mr_cg_spmm_w<1, {tname}, {tname}> (or the chunk width timed fastest)"
         else:
             nnz = {"diag": st["nnz_diag"], "lower": st["nnz_lower"], "full": st["nnz_diag"] + st["nnz_lower"]}[args.spmv_op]
             sc = diag_col_bytes(code, st) if args.spmv_op == "diag" else 4
@@ -703,9 +728,7 @@ def main():
     thr = thresholded(m, ctx, dev, args.trunc_levels, (2, 4, 6)) if args.trunc_levels > 0 else None
     m.mskm_destroy(ctx)
 
-    pmc = PMC_TRAFFIC.get((f"halton2d_L{args.levels}", cg_kernel, f"level {top}"))
-    traffic = None if pmc is None else int(pmc["fetch_kib"] * pmc["fetch_scale"] * 1024
-                                           + pmc["write_kib"] * pmc["write_scale"] * 1024)
+    traffic = pmc_traffic((f"halton2d_L{args.levels}", cg_kernel, f"level {top}"))
     cg_gbps = cg_bytes / cg_ms / 1e6
     out = {
         "metric": "time-to-1e-8 rel. residual + kernel SpMV GB/s, plain FP64 vs mixed/learned",
