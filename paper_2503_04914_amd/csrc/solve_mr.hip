@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
 
 #include "device_common.h"
 
@@ -986,7 +987,10 @@ mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>
   const dim3 rgrid(nlev, (c.R + 63) / 64);
   hipLaunchKernelGGL(k_mr_red_init, rgrid, dim3(kMrRedThreads), 0, s, lo, wv.lev_begin, W.part_v, zlb, rzp, W.st, c);
   hipLaunchKernelGGL(k_mr_lev_done, dim3(nlev), dim3(kBlock), 0, s, lo, W.st, W.lev_done, c);
-  for (int it = 0; it < maxit; it += K) {
+  // K iterations of every running system, captured once into a graph: its
+  // kernels read and update the per-system state, so each replay continues
+  // the solve; the host polls the per-level stop flags between replays.
+  auto enqueue_chunk = [&]() {
     for (int kk = 0; kk < K; ++kk) {
       if (vbn > 0)
         hipLaunchKernelGGL(k_mr_dir<TX>, dim3(vbn), dim3(kBlock), 0, s, wv, vb0, pc ? (const TX*)z : (const TX*)r, p,
@@ -1002,6 +1006,23 @@ mskm_status mr_cg(mskm_hier* h, MrWS& W, const TV* dval, const std::vector<char>
                          W.lev_done, c);
       hipLaunchKernelGGL(k_mr_lev_done, dim3(nlev), dim3(kBlock), 0, s, lo, W.st, W.lev_done, c);
     }
+  };
+  hipGraphExec_t exec = nullptr;
+  {
+    hipGraph_t graph = nullptr;
+    MSKM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    enqueue_chunk();
+    MSKM_HIP_TRY(hipStreamEndCapture(s, &graph));
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(MSKM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  struct ExecGuard {
+    hipGraphExec_t e;
+    ~ExecGuard() { (void)hipGraphExecDestroy(e); }
+  } exec_guard{exec};
+  for (int it = 0; it < maxit; it += K) {
+    MSKM_HIP_TRY(hipGraphLaunch(exec, s));
     MSKM_HIP_TRY(hipMemcpyAsync(W.h_lev_done, W.lev_done, h->L * 4, hipMemcpyDeviceToHost, s));
     MSKM_HIP_TRY(hipStreamSynchronize(s));
     bool any = false;
