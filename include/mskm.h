@@ -484,7 +484,7 @@ mskm_status mskm_trunc_solve(mskm_ctx* ctx, const mskm_trunc* t, const double* f
  *   x0_i = s_i * (w2 . relu(W1 feat + b1) + b2), 64 hidden units; x0_i = 0
  *          where s_i = 0.
  * The first layer runs on BF16 MFMA with FP32 accumulation. CG starts from
- * x0 and remains the judge: a level with ||b - A x0|| >= ||b|| restarts from
+ * x0 and decides convergence itself: a level with ||b - A x0|| >= ||b|| restarts from
  * zero (counted in mskm_report.warm_fallbacks). */
 typedef struct {
   const mskm_hier* h;  /* hierarchy whose solves generate the training pairs */

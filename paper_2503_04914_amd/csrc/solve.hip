@@ -1558,7 +1558,7 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
 //   z = P(r); beta = -z.q / p.q; p = z + beta p,
 // from p = z = P(b), x = 0. Here P(r) = M^-1 r + net(r): the cell
 // block-Jacobi inverse plus the learned network's prediction of A^-1 r from
-// r's 17-point stencils. CG stays the judge: the stopping test is the true
+// r's 17-point stencils. CG decides convergence: the stopping test is the true
 // residual ||r|| <= rtol ||b||; and plain preconditioned CG is the fallback:
 // a level whose r.r has not fallen by the factor kFcgWindowDrop over a window
 // of kFcgWindow iterations drops the network for the rest of its solve

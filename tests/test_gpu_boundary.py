@@ -10,7 +10,7 @@ the FP64 oracle:
 * MSKM_PREFIX_NESTED: a hierarchy given by its largest level only has the
   same blocks (bit-exact) and coefficients as the one given level by level;
 * the learned start combined with the block-Jacobi preconditioner: same
-  coefficients (CG is the judge);
+  coefficients (CG decides convergence);
 * the sliced copy keeps 16-bit column offsets on levels whose size is not a
   multiple of 64 (the Table 1 grids, an uneven batch).
 """
