@@ -115,14 +115,14 @@ constexpr int kMrLds = kBlock * kMaxRPerLane;  // doubles of LDS for block parti
 // Fast path for R a multiple of 64: one wave per row, lane gl owns RM
 // consecutive right-hand sides gl RM .. gl RM + RM - 1 of a chunk, so a
 // gathered row of X is one RM-wide load per lane. A row's entries are read
-// 64 at a time by the lanes and broadcast with readlane, and eight gathers
-// are issued before their products, so a wave keeps eight rows of X in flight
-// instead of one dependent chain of index load -> gather per entry. The
-// CG product takes the right-hand sides in chunks of 64 (blockIdx.y, the
-// slowest launch dimension): the rows of X the running workgroups gather are
-// then 256 bytes (FP32) wide, a working set the L2 holds. On the 1M-row
-// Halton level, 256 right-hand sides, it takes 2.98 ms in chunks of 64, 3.21
-// ms in chunks of 128 and 4.12 ms unchunked. The lower products and the
+// 64 at a time by the lanes and broadcast with readlane, and gathered in
+// batches of eight, two batches in flight (mr_row_acc), instead of one
+// dependent chain of index load -> gather per entry. The CG product takes
+// the right-hand sides in chunks (blockIdx.y, the slowest launch dimension):
+// in chunks of 64 the rows of X the running workgroups gather are 256 bytes
+// (FP32) wide, a working set the L2 holds better. On the 1M-row Halton level,
+// 256 right-hand sides, it takes 2.70 ms in chunks of 64, 3.14 ms in chunks
+// of 128 and 3.22 ms unchunked. The lower products and the
 // residual read rows with entries in every coarser level, whose re-reading
 // per chunk costs more than the narrower gathers save (the top level's lower
 // product 1.6 ms unchunked, 2.3 ms in chunks of 64): one chunk of all R.
@@ -164,29 +164,44 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
 
 // acc[m] += sum over the entries k in [s, e) of value(k) * X[col[k]][gl RM + m],
 // in entry order. value(k) returns the entry's value in the accumulation type TA.
+// The entries of a 64-entry run are taken in batches of eight gathers; the
+// next batch's gathers are issued before the current batch's products, so
+// two batches are in flight. Entry j of the run is lane j's: lanes past the
+// run's end hold value 0 and the run's last column, so no batch needs a
+// bounds branch (a batch starts below the run's end and ends at lane 63 at
+// most).
+template <int RM, typename TA, typename TX>
+__device__ __forceinline__ void mr_gather8(const TX* __restrict__ x, int64_t ldx, int gl, int32_t cl, int u,
+                                           TX (&xv)[8][RM]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) ld_rm<RM>(x + (int64_t)lane_bcast(cl, u + q) * ldx + gl * RM, xv[q]);
+}
+template <int RM, typename TA, typename TX>
+__device__ __forceinline__ void mr_fma8(TA vl, int u, const TX (&xv)[8][RM], TA (&acc)[RM]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const TA v = lane_bcast(vl, u + q);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) acc[m] += v * (TA)xv[q][m];
+  }
+}
 template <int RM, typename TA, typename TX, typename ValueOf>
 __device__ __forceinline__ void mr_row_acc(int64_t s, int64_t e, const int32_t* __restrict__ col, ValueOf value,
                                            const TX* __restrict__ x, int64_t ldx, int gl, TA (&acc)[RM]) {
-  constexpr int kU = 8;
   const int lane = threadIdx.x % 64;
   for (int64_t k0 = s; k0 < e; k0 += 64) {
     const int n = (int)min<int64_t>(64, e - k0);
     const int64_t k = k0 + min(lane, n - 1);
     const int32_t cl = col[k];
     const TA vl = lane < n ? value(k) : (TA)0;
-    for (int u = 0; u < n; u += kU) {
-      TX xv[kU][RM];
-      TA vv[kU];
-#pragma unroll
-      for (int q = 0; q < kU; ++q) {
-        const int j = min(u + q, n - 1);  // past the run: the last entry again, with value 0
-        vv[q] = u + q < n ? lane_bcast(vl, j) : (TA)0;
-        ld_rm<RM>(x + (int64_t)lane_bcast(cl, j) * ldx + gl * RM, xv[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < kU; ++q)
-#pragma unroll
-        for (int m = 0; m < RM; ++m) acc[m] += vv[q] * (TA)xv[q][m];
+    const int nb = (n + 7) / 8;
+    TX xa[8][RM], xb[8][RM];
+    mr_gather8<RM, TA, TX>(x, ldx, gl, cl, 0, xa);
+    for (int b = 0; b < nb; b += 2) {
+      if (b + 1 < nb) mr_gather8<RM, TA, TX>(x, ldx, gl, cl, 8 * (b + 1), xb);
+      mr_fma8<RM, TA, TX>(vl, 8 * b, xa, acc);
+      if (b + 2 < nb) mr_gather8<RM, TA, TX>(x, ldx, gl, cl, 8 * (b + 2), xa);
+      if (b + 1 < nb) mr_fma8<RM, TA, TX>(vl, 8 * (b + 1), xb, acc);
     }
   }
 }
