@@ -103,6 +103,8 @@ typedef struct mskm_hier mskm_hier;
  * NULL to let the library create its own). The context owns nothing the
  * caller passed. Fails with MSKM_EDEVICE if the device cannot be used. */
 mskm_status mskm_create(int32_t device, void* hip_stream, mskm_ctx** out);
+/* Frees the context, including the device blocks it keeps from destroyed
+ * hierarchies (see mskm_hier_destroy). */
 mskm_status mskm_destroy(mskm_ctx* ctx);
 
 /* Thread-local description of the last failure ("" if none). */
@@ -143,6 +145,10 @@ mskm_status mskm_hier_create(mskm_ctx* ctx, const mskm_hier_desc* desc, mskm_hie
  * depth). mskm_export_* and mskm_apply work on batches; mskm_evaluate does
  * not (EINVAL). */
 mskm_status mskm_hier_create_batch(mskm_ctx* ctx, const mskm_hier_desc* descs, int32_t count, mskm_hier** out);
+/* Waits for the context stream, then frees the hierarchy. Its device blocks go
+ * to the context's cache (up to 32 GiB) and serve later allocations of the
+ * same size, so a hierarchy rebuilt with the same shape allocates nothing new;
+ * the cache is emptied when an allocation would fail, and by mskm_destroy. */
 mskm_status mskm_hier_destroy(mskm_hier* h);
 
 typedef struct {

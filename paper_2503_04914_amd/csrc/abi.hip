@@ -32,6 +32,59 @@ mskm_status fail(mskm_status st, const std::string& msg) {
 
 using mskm::fail;
 
+namespace mskm {
+
+constexpr size_t kBlockCacheCap = (size_t)32 << 30;
+
+mskm_status ctx_alloc(mskm_ctx* c, size_t bytes, void** out) {
+  *out = nullptr;
+  if (c) {
+    std::lock_guard<std::mutex> lock(c->cache_mu);
+    auto it = c->cache.find(bytes);
+    if (it != c->cache.end()) {
+      *out = it->second;
+      c->cache_bytes -= bytes;
+      c->cache.erase(it);
+      return MSKM_OK;
+    }
+  }
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess && c && c->cache_bytes > 0) {  // give the cached blocks back and try once more
+    (void)hipGetLastError();
+    ctx_trim(c);
+    e = hipMalloc(out, bytes);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return fail(MSKM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return MSKM_OK;
+}
+
+void ctx_release(mskm_ctx* c, void* p, size_t bytes) {
+  if (!p) return;
+  if (c) {
+    std::lock_guard<std::mutex> lock(c->cache_mu);
+    if (c->cache_bytes + bytes <= kBlockCacheCap) {
+      c->cache.emplace(bytes, p);
+      c->cache_bytes += bytes;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
+void ctx_trim(mskm_ctx* c) {
+  if (!c) return;
+  std::lock_guard<std::mutex> lock(c->cache_mu);
+  for (auto& kv : c->cache) (void)hipFree(kv.second);
+  c->cache.clear();
+  c->cache_bytes = 0;
+}
+
+}  // namespace mskm
+
 extern "C" {
 
 const char* mskm_last_error(void) { return g_last_error.c_str(); }
@@ -63,7 +116,8 @@ mskm_status mskm_create(int32_t device, void* hip_stream, mskm_ctx** out) {
       hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
-    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    mskm::ctx_trim(c);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return fail(MSKM_EDEVICE, "hipEventCreate / hipStreamCreate failed");
   }
@@ -252,7 +306,7 @@ mskm_status mskm_hier_destroy(mskm_hier* h) {
     }
   if (h->solve_ws_free) h->solve_ws_free(h->solve_ws);
   for (mskm_trunc* t : h->truncs) t->h = nullptr;  // they keep their own memory until destroyed
-  for (void* p : h->allocs) (void)hipFree(p);
+  for (size_t i = 0; i < h->allocs.size(); ++i) mskm::ctx_release(h->ctx, h->allocs[i], h->alloc_bytes[i]);
   delete h;
   return MSKM_OK;
 }

@@ -1122,6 +1122,7 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32, bool with_
     }
     if (st == MSKM_OK && wide == 0) {
       h->allocs.push_back(cbase);
+      h->alloc_bytes.push_back((size_t)S.nslices * 4);
       h->device_bytes += S.nslices * 4;
       S.cbase = cbase;
       st = halloc(h, &S.col16, (size_t)S.entries);

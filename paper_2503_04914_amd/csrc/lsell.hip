@@ -188,6 +188,7 @@ mskm_status build_lsell(mskm_hier* h, bool want64, bool want32, const int32_t* c
                        h->lower.val32lo, cnt_lv, h->N, X.seg_ptr, base, X.col16, X.val, X.val32, X.lo);
   }
   h->allocs.push_back(base);
+  h->alloc_bytes.push_back((size_t)X.nseg * 4);
   h->device_bytes += X.nseg * 4;
   X.seg_base = base;
   base = nullptr;

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -180,6 +182,13 @@ struct mskm_ctx {
   // hierarchy's finest levels are formed there while the main stream solves
   // the coarser levels
   hipStream_t side = nullptr;
+  // device blocks of destroyed hierarchies, kept for the next allocation of
+  // the same size (a hierarchy rebuilt with the same shape reuses all of
+  // them without hipMalloc); at most kBlockCacheCap bytes, freed by
+  // mskm_destroy or when an allocation would otherwise fail
+  std::mutex cache_mu;
+  std::multimap<size_t, void*> cache;
+  size_t cache_bytes = 0;
 };
 
 // Truncated Lagrange blocks frak X~_{kj}(T) of one hierarchy (trunc.hip):
@@ -247,7 +256,8 @@ struct mskm_hier {
   int32_t mr_chunk[8][2] = {};
   int64_t device_bytes = 0;
   double assemble_ms = 0.0;
-  std::vector<void*> allocs;            // everything to free
+  std::vector<void*> allocs;            // everything to free (given back to the context's block cache)
+  std::vector<size_t> alloc_bytes;      // their sizes
   int32_t* knn = nullptr;               // [N][16] same-level nearest neighbours (learned warm start)
   std::vector<mskm_trunc*> truncs;      // thresholded blocks built on this hierarchy (detached at destroy)
   void* solve_ws = nullptr;             // solver workspace (solve.hip), created on first solve
@@ -274,15 +284,26 @@ mskm_status fail(mskm_status st, const std::string& msg);
     if (_s < 0) return _s;          \
   } while (0)
 
+// Context block cache (abi.hip): a block of exactly `bytes` from the cache,
+// else hipMalloc (after emptying the cache if the first attempt fails).
+mskm_status ctx_alloc(mskm_ctx* c, size_t bytes, void** out);
+// Gives a block back to the cache (hipFree beyond the cap or without a context).
+void ctx_release(mskm_ctx* c, void* p, size_t bytes);
+// Frees every cached block.
+void ctx_trim(mskm_ctx* c);
+
 // device allocation tracked by the hierarchy
 template <typename T>
 mskm_status halloc(mskm_hier* h, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
-  if (e != hipSuccess) return fail(MSKM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-  h->allocs.push_back(*p);
-  h->device_bytes += static_cast<int64_t>(count * sizeof(T));
+  const size_t bytes = count * sizeof(T);
+  void* q = nullptr;
+  MSKM_TRY(ctx_alloc(h->ctx, bytes, &q));
+  *p = static_cast<T*>(q);
+  h->allocs.push_back(q);
+  h->alloc_bytes.push_back(bytes);
+  h->device_bytes += static_cast<int64_t>(bytes);
   return MSKM_OK;
 }
 
