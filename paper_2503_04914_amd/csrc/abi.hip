@@ -81,6 +81,39 @@ void ctx_trim(mskm_ctx* c) {
   for (auto& kv : c->cache) (void)hipFree(kv.second);
   c->cache.clear();
   c->cache_bytes = 0;
+  for (auto& kv : c->host_cache) (void)hipHostFree(kv.second);
+  c->host_cache.clear();
+}
+
+mskm_status ctx_host_alloc(mskm_ctx* c, size_t bytes, void** out) {
+  *out = nullptr;
+  if (c) {
+    std::lock_guard<std::mutex> lock(c->cache_mu);
+    auto it = c->host_cache.find(bytes);
+    if (it != c->host_cache.end()) {
+      *out = it->second;
+      c->host_cache.erase(it);
+      return MSKM_OK;
+    }
+  }
+  if (hipHostMalloc(out, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return fail(MSKM_ENOMEM, "pinned allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return MSKM_OK;
+}
+
+void ctx_host_release(mskm_ctx* c, void* p, size_t bytes) {
+  if (!p) return;
+  if (c) {
+    std::lock_guard<std::mutex> lock(c->cache_mu);
+    if (c->host_cache.size() < 64) {
+      c->host_cache.emplace(bytes, p);
+      return;
+    }
+  }
+  (void)hipHostFree(p);
 }
 
 }  // namespace mskm

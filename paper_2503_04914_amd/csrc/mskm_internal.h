@@ -189,6 +189,7 @@ struct mskm_ctx {
   std::mutex cache_mu;
   std::multimap<size_t, void*> cache;
   size_t cache_bytes = 0;
+  std::multimap<size_t, void*> host_cache;  // pinned host blocks, likewise (solver workspaces)
 };
 
 // Truncated Lagrange blocks frak X~_{kj}(T) of one hierarchy (trunc.hip):
@@ -291,6 +292,9 @@ mskm_status ctx_alloc(mskm_ctx* c, size_t bytes, void** out);
 void ctx_release(mskm_ctx* c, void* p, size_t bytes);
 // Frees every cached block.
 void ctx_trim(mskm_ctx* c);
+// Pinned host blocks: from the cache, else hipHostMalloc; given back likewise.
+mskm_status ctx_host_alloc(mskm_ctx* c, size_t bytes, void** out);
+void ctx_host_release(mskm_ctx* c, void* p, size_t bytes);
 
 // device allocation tracked by the hierarchy
 template <typename T>

@@ -1133,14 +1133,16 @@ struct SolveWS {
   double* part_res = nullptr;    // residual partials (r.r, f.f per block of the SpMV table)
   double* h_part_res = nullptr;  // pinned copy of them
   void* pinned = nullptr;  // h_st, the two h_chk copies, h_defer and h_part_res, one pinned allocation
+  mskm_ctx* ctx = nullptr;  // arena and pinned blocks go back to its caches
+  size_t arena_bytes = 0, pinned_bytes = 0;
   ~SolveWS() {
     if (pending) (void)hipEventSynchronize(pending);
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
-    (void)hipFree(arena);
+    mskm::ctx_release(ctx, arena, arena_bytes);
     for (hipEvent_t e : ev_chk)
       if (e) (void)hipEventDestroy(e);
     if (ev_defer) (void)hipEventDestroy(ev_defer);
-    if (pinned) (void)hipHostFree(pinned);
+    mskm::ctx_host_release(ctx, pinned, pinned_bytes);
   }
 };
 
@@ -1175,17 +1177,20 @@ static mskm_status get_ws(mskm_hier* h, SolveWS** out) {
     carve(&w->st, 2 * (size_t)h->L, base);  // two parities (fused single-reduction form)
   };
   layout(nullptr);
+  w->ctx = h->ctx;
   mskm_status st = MSKM_OK;
-  char* base = nullptr;
-  st = dalloc(&base, bytes);
+  void* base = nullptr;
+  const size_t arena_bytes = bytes;
+  st = mskm::ctx_alloc(h->ctx, arena_bytes, &base);
   if (st == MSKM_OK) {
     w->arena = base;
-    layout(base);
+    w->arena_bytes = arena_bytes;
+    layout(static_cast<char*>(base));
   }
   const size_t pin_states = 4 * (size_t)h->L * sizeof(CgLevel);  // a multiple of 8 bytes
-  if (st == MSKM_OK && hipHostMalloc(&w->pinned, pin_states + 2 * (size_t)h->wt_spmv.nblocks * sizeof(double),
-                                     hipHostMallocDefault) != hipSuccess)
-    st = fail(MSKM_ENOMEM, "pinned state allocation");
+  const size_t pin_bytes = pin_states + 2 * (size_t)h->wt_spmv.nblocks * sizeof(double);
+  if (st == MSKM_OK) st = mskm::ctx_host_alloc(h->ctx, pin_bytes, &w->pinned);
+  if (st == MSKM_OK) w->pinned_bytes = pin_bytes;
   if (st == MSKM_OK) {
     CgLevel* ps = static_cast<CgLevel*>(w->pinned);
     w->h_st = ps;
