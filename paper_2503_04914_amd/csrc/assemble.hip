@@ -753,11 +753,8 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
     Carve cv;
     cv.add(&d_off, 2 * (size_t)L);
     cv.add(&d_part, bbox.size());
-    MSKM_TRY(cv.alloc(&bb));
-    struct FreeBb {
-      void* p;
-      ~FreeBb() { (void)hipFree(p); }
-    } free_bb{bb};
+    MSKM_TRY(cv.alloc(h->ctx, &bb));
+    CtxScratch free_bb{h->ctx, bb, cv.bytes};
     MSKM_HIP_TRY(hipMemcpyAsync(d_off, rng.data(), rng.size() * 8, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks, L), dim3(kBlock), 0, s, pts, d_off, dim, d_part);
     MSKM_HIP_TRY(hipMemcpyAsync(bbox.data(), d_part, bbox.size() * 8, hipMemcpyDeviceToHost, s));
@@ -828,6 +825,7 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   int max_depth = 1;
   for (int g = 0; g < h->ngroups; ++g) max_depth = std::max(max_depth, (int)h->h_group_levels[g] - 1);
   void* scratch = nullptr;
+  size_t scratch_bytes = 0;
   {
     Carve cv;
     if (want_lsell) cv.add(&cnt_lv, (size_t)N * max_depth);
@@ -839,12 +837,10 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
     cv.add(&cnt_d, N + 1);
     cv.add(&cnt_l, N + 1);
     cv.add(&part, std::max(scan_parts(cs_total), scan_parts(N + 1)));
-    MSKM_TRY(cv.alloc(&scratch));
+    MSKM_TRY(cv.alloc(h->ctx, &scratch));
+    scratch_bytes = cv.bytes;
   }
-  struct FreeScratch {
-    void* p;
-    ~FreeScratch() { (void)hipFree(p); }
-  } free_scratch{scratch};
+  CtxScratch free_scratch{h->ctx, scratch, scratch_bytes};
   MSKM_HIP_TRY(hipMemsetAsync(count, 0, cs_total * 4, s));
   for (int l = 0; l < L; ++l) {
     const int64_t n = h->h_lev[l].n;
@@ -1081,17 +1077,16 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32, bool with_
   int64_t *d_w = nullptr, *part = nullptr;
   int32_t* d_wide = nullptr;
   void* scratch = nullptr;
+  size_t scratch_bytes = 0;
   {
     Carve cv;
     cv.add(&d_w, (size_t)S.nslices + 1);
     cv.add(&part, scan_parts(S.nslices + 1));
     cv.add(&d_wide, 1);
-    MSKM_TRY(cv.alloc(&scratch));
+    MSKM_TRY(cv.alloc(h->ctx, &scratch));
+    scratch_bytes = cv.bytes;
   }
-  struct FreeScratch {
-    void* p;
-    ~FreeScratch() { (void)hipFree(p); }
-  } free_scratch{scratch};
+  CtxScratch free_scratch{h->ctx, scratch, scratch_bytes};
   hipLaunchKernelGGL(k_sell_width, dim3(grid_for(S.nslices + 1, kBlock)), dim3(kBlock), 0, s, S.nslices, S.rows,
                      h->diag.rowptr, d_w);
   MSKM_TRY(exclusive_scan_i64(s, d_w, S.sptr, S.nslices + 1, part));
@@ -1111,7 +1106,11 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32, bool with_
   if (S.nslices > 0) {
     int32_t* cbase = nullptr;
     int32_t wide = 0;
-    MSKM_TRY(dalloc(&cbase, (size_t)S.nslices));
+    {
+      void* q = nullptr;
+      MSKM_TRY(ctx_alloc(h->ctx, (size_t)S.nslices * 4, &q));
+      cbase = static_cast<int32_t*>(q);
+    }
     mskm_status st = MSKM_OK;
     if (hipMemsetAsync(d_wide, 0, 4, s) != hipSuccess) st = fail(MSKM_EDEVICE, "memset");
     if (st == MSKM_OK) {
@@ -1130,7 +1129,7 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32, bool with_
         hipLaunchKernelGGL(k_sell_narrow, dim3((unsigned)S.nslices), dim3(kSellC), 0, s, S.sptr, S.col, S.cbase,
                            S.col16);
     } else {
-      (void)hipFree(cbase);
+      ctx_release(h->ctx, cbase, (size_t)S.nslices * 4);
     }
     MSKM_TRY(st);
   }

@@ -141,25 +141,30 @@ mskm_status build_lsell(mskm_hier* h, bool want64, bool want32, const int32_t* c
   int64_t *w = nullptr, *part = nullptr;
   int32_t* wide = nullptr;
   void* scratch = nullptr;
+  size_t scratch_bytes = 0;
   {
     Carve cv;
     cv.add(&w, (size_t)X.nseg + 1);
     cv.add(&part, scan_parts(X.nseg + 1));
     cv.add(&wide, 1);
-    MSKM_TRY(cv.alloc(&scratch));
+    MSKM_TRY(cv.alloc(h->ctx, &scratch));
+    scratch_bytes = cv.bytes;
   }
-  struct FreeScratch {
-    void* p;
-    ~FreeScratch() { (void)hipFree(p); }
-  } free_scratch{scratch};
+  CtxScratch free_scratch{h->ctx, scratch, scratch_bytes};
   int32_t* base = nullptr;
-  MSKM_TRY(dalloc(&base, (size_t)X.nseg));
-  struct FreeBase {
+  {
+    void* q = nullptr;
+    MSKM_TRY(ctx_alloc(h->ctx, (size_t)X.nseg * 4, &q));
+    base = static_cast<int32_t*>(q);
+  }
+  struct FreeBase {  // back to the cache unless the copy is built (then the hierarchy owns it)
+    mskm_ctx* c;
     int32_t** p;
+    size_t bytes;
     ~FreeBase() {
-      if (*p) (void)hipFree(*p);
+      if (*p) ctx_release(c, *p, bytes);
     }
-  } free_base{&base};
+  } free_base{h->ctx, &base, (size_t)X.nseg * 4};
   MSKM_HIP_TRY(hipMemsetAsync(wide, 0, 4, s));
   MSKM_HIP_TRY(hipMemsetAsync(w + X.nseg, 0, 8, s));
   for (int l = 0; l < L; ++l) {

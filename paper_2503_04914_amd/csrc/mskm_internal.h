@@ -296,6 +296,7 @@ void ctx_trim(mskm_ctx* c);
 mskm_status ctx_host_alloc(mskm_ctx* c, size_t bytes, void** out);
 void ctx_host_release(mskm_ctx* c, void* p, size_t bytes);
 
+
 // device allocation tracked by the hierarchy
 template <typename T>
 mskm_status halloc(mskm_hier* h, T** p, size_t count) {
@@ -335,14 +336,35 @@ struct Carve {
     char* b = nullptr;
     MSKM_TRY(dalloc(&b, bytes));
     *base = b;
+    place(b);
+    return MSKM_OK;
+  }
+  // one block from the context's cache for all pieces (given back by the caller)
+  mskm_status alloc(mskm_ctx* c, void** base);
+  void place(char* b) {
     size_t o = 0;
     for (auto& w : want) {
       *w.first = b + o;
       o += (w.second + 255) / 256 * 256;
     }
-    return MSKM_OK;
   }
 };
+
+// A scratch block of the context's cache, given back when it goes out of
+// scope (work on the context stream that uses it stays ordered before any
+// later use of the same block).
+struct CtxScratch {
+  mskm_ctx* c;
+  void* p;
+  size_t bytes;
+  ~CtxScratch();
+};
+inline mskm_status Carve::alloc(mskm_ctx* c, void** base) {
+  MSKM_TRY(ctx_alloc(c, bytes, base));
+  place(static_cast<char*>(*base));
+  return MSKM_OK;
+}
+inline CtxScratch::~CtxScratch() { ctx_release(c, p, bytes); }
 
 // assemble.hip
 mskm_status assemble_hierarchy(mskm_hier* h, const double* points_dev, bool want64, bool want32,

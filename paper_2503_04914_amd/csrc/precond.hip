@@ -218,7 +218,10 @@ mskm_status build_block_jacobi(mskm_hier* h) {
   int64_t *nch = nullptr, *bbase = nullptr, *msq = nullptr, *part = nullptr;
   const size_t a1 = ((size_t)nslots + 1 + 31) / 32 * 32, a2 = ((size_t)nb_max + 1 + 31) / 32 * 32;
   int64_t* scratch = nullptr;
-  mskm_status st = dalloc(&scratch, 2 * a1 + a2 + (size_t)std::max(scan_parts(nslots + 1), scan_parts(nb_max + 1)));
+  const size_t scratch_bytes = 8 * (2 * a1 + a2 + (size_t)std::max(scan_parts(nslots + 1), scan_parts(nb_max + 1)));
+  void* sq = nullptr;
+  mskm_status st = ctx_alloc(h->ctx, scratch_bytes, &sq);  // used on the main stream only (synchronized below)
+  scratch = static_cast<int64_t*>(sq);
   if (st == MSKM_OK) {
     nch = scratch;
     bbase = scratch + a1;
@@ -250,7 +253,7 @@ mskm_status build_block_jacobi(mskm_hier* h) {
                           hipStreamSynchronize(s) != hipSuccess))
       st = fail(MSKM_EDEVICE, "block-Jacobi counts");
   }
-  (void)hipFree(scratch);
+  ctx_release(h->ctx, scratch, scratch_bytes);
   MSKM_TRY(st);
   B.nblocks = counts[0];
   B.nvals = counts[1];
