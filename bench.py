@@ -524,6 +524,10 @@ def main():
     q_dev = torch.from_numpy(q_host).to(dev)
     ev_out = torch.zeros(args.nq, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
+    # one stream for torch's work, the library's launches and the timing
+    # events, so that an event recorded after a call is ordered after its kernels
+    work_stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(work_stream)
     ctx = m.mskm_create(0, stream="torch")
 
     # ---- calibration of the tolerances (untimed)

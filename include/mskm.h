@@ -132,6 +132,9 @@ typedef struct {
  * evaluation of all blocks B_{k,j} (Section 3) into device-resident CSR:
  * one CSR for the block diagonal D_L and one for the strict lower part
  * T_L - D_L. Points are copied; the caller may free them on return.
+ * Returns once the last passes are queued on the context stream (later
+ * calls on that stream run after them; mskm_hier_stats_get and
+ * mskm_hier_destroy wait for them).
  * MSKM_ELIMIT if N >= 2^31 or a row would exceed 2^31 entries. */
 mskm_status mskm_hier_create(mskm_ctx* ctx, const mskm_hier_desc* desc, mskm_hier** out);
 

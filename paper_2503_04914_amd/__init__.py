@@ -201,11 +201,15 @@ def mskm_last_error() -> str:
 
 def mskm_create(device: int = 0, stream=None):
     """Context on `device`. stream: None (library stream), "torch" (torch's
-    current stream) or a raw hipStream_t integer."""
+    current stream, which must not be the default stream: a null handle asks
+    the library for a stream of its own, unordered with torch's work) or a
+    raw hipStream_t integer."""
     if stream == "torch":
         import torch
 
         stream = torch.cuda.current_stream(device).cuda_stream
+        if not stream:
+            raise ValueError("torch's current stream is the default stream; set a torch.cuda.Stream first")
     out = C.c_void_p()
     _check(lib().mskm_create(int(device), C.c_void_p(stream) if stream else None, C.byref(out)), "mskm_create")
     return out

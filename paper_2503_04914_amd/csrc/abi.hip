@@ -104,6 +104,25 @@ mskm_status ctx_host_alloc(mskm_ctx* c, size_t bytes, void** out) {
   return MSKM_OK;
 }
 
+mskm_status upload_async(mskm_hier* h, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return MSKM_OK;
+  constexpr size_t kStageChunk = size_t(1) << 20;  // one cached size for the tables of most hierarchies
+  const size_t need = (bytes + 255) / 256 * 256;
+  if (h->stage_blocks.empty() || h->stage_used + need > h->stage_bytes.back()) {
+    const size_t cap = (need + kStageChunk - 1) / kStageChunk * kStageChunk;
+    void* p = nullptr;
+    MSKM_TRY(ctx_host_alloc(h->ctx, cap, &p));
+    h->stage_blocks.push_back(p);
+    h->stage_bytes.push_back(cap);
+    h->stage_used = 0;
+  }
+  char* p = static_cast<char*>(h->stage_blocks.back()) + h->stage_used;
+  h->stage_used += need;
+  std::memcpy(p, src, bytes);
+  MSKM_HIP_TRY(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, h->ctx->stream));
+  return MSKM_OK;
+}
+
 void ctx_host_release(mskm_ctx* c, void* p, size_t bytes) {
   if (!p) return;
   if (c) {
@@ -266,8 +285,13 @@ mskm_status create_groups(mskm_ctx* ctx, const mskm_hier_desc* ds, int32_t count
     h->h_first[l] = idx[g][0];
     h->h_next[l] = d + 1 < ds[g].levels ? idx[g][d + 1] : -1;
   }
+  // the input-order points, read by the assembly kernels only (the block
+  // goes back to the context's cache behind them, stream-ordered)
   double* pts = nullptr;
-  mskm_status st = mskm::dalloc(&pts, (size_t)N * h->dim);
+  const size_t pts_bytes = (size_t)N * h->dim * sizeof(double);
+  void* pv = nullptr;
+  mskm_status st = mskm::ctx_alloc(ctx, pts_bytes, &pv);
+  pts = static_cast<double*>(pv);
   for (int g = 0; g < count && st == MSKM_OK; ++g) {
     const bool dev = (ds[g].flags & MSKM_POINTS_ON_DEVICE) != 0;
     const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -294,7 +318,7 @@ mskm_status create_groups(mskm_ctx* ctx, const mskm_hier_desc* ds, int32_t count
   // lanes per row); streaming phase: 1024 rows per block (4 per thread)
   if (st == MSKM_OK) st = mskm::build_work_table(h, &h->wt_spmv, 64, 1 << 30);
   if (st == MSKM_OK) st = mskm::build_work_table(h, &h->wt_vec, 4 * mskm::kBlock, 1 << 30);
-  (void)hipFree(pts);
+  mskm::ctx_release(ctx, pts, pts_bytes);
   if (st != MSKM_OK) {
     mskm_hier_destroy(h);
     return st;
@@ -332,7 +356,7 @@ mskm_status mskm_hier_destroy(mskm_hier* h) {
     (void)hipSetDevice(h->ctx->device);
     (void)hipStreamSynchronize(h->ctx->stream);
   }
-  for (hipEvent_t e : {h->bj.ev_tables, h->bj.ev_side})
+  for (hipEvent_t e : {h->bj.ev_tables, h->bj.ev_side, h->ev_asm[0], h->ev_asm[1]})
     if (e) {
       (void)hipEventSynchronize(e);
       (void)hipEventDestroy(e);
@@ -340,6 +364,8 @@ mskm_status mskm_hier_destroy(mskm_hier* h) {
   if (h->solve_ws_free) h->solve_ws_free(h->solve_ws);
   for (mskm_trunc* t : h->truncs) t->h = nullptr;  // they keep their own memory until destroyed
   for (size_t i = 0; i < h->allocs.size(); ++i) mskm::ctx_release(h->ctx, h->allocs[i], h->alloc_bytes[i]);
+  for (size_t i = 0; i < h->stage_blocks.size(); ++i)
+    mskm::ctx_host_release(h->ctx, h->stage_blocks[i], h->stage_bytes[i]);
   delete h;
   return MSKM_OK;
 }
@@ -355,6 +381,15 @@ mskm_status mskm_hier_stats_get(const mskm_hier* h, mskm_hier_stats* o) {
   o->has_fp64 = h->diag.val != nullptr;
   o->has_fp32 = h->diag.val32 != nullptr;
   o->device_bytes = h->device_bytes;
+  if (h->asm_pending) {  // the assembly's last kernels may still have been running at creation's return
+    mskm_hier* m = const_cast<mskm_hier*>(h);
+    float ms = 0.f;
+    if (hipEventSynchronize(m->ev_asm[1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, m->ev_asm[0], m->ev_asm[1]) != hipSuccess)
+      return fail(MSKM_EDEVICE, "assembly timing events");
+    m->assemble_ms = ms;
+    m->asm_pending = false;
+  }
   o->assemble_ms = h->assemble_ms;
   o->ngroups = h->ngroups;
   o->sell_col16 = h->sell.col16 ? 1 : 0;

@@ -693,13 +693,10 @@ mskm_status build_work_table(mskm_hier* h, WorkTable* wt, int min_rows, int max_
   MSKM_TRY(halloc(h, &wt->row0, r0.size()));
   MSKM_TRY(halloc(h, &wt->row1, r1.size()));
   MSKM_TRY(halloc(h, &wt->lev_begin, wt->h_lev_begin.size()));
-  hipStream_t s = h->ctx->stream;
-  MSKM_HIP_TRY(hipMemcpyAsync(wt->lev, lev.data(), lev.size() * 4, hipMemcpyHostToDevice, s));
-  MSKM_HIP_TRY(hipMemcpyAsync(wt->row0, r0.data(), r0.size() * 8, hipMemcpyHostToDevice, s));
-  MSKM_HIP_TRY(hipMemcpyAsync(wt->row1, r1.data(), r1.size() * 8, hipMemcpyHostToDevice, s));
-  MSKM_HIP_TRY(hipMemcpyAsync(wt->lev_begin, wt->h_lev_begin.data(), wt->h_lev_begin.size() * 4,
-                              hipMemcpyHostToDevice, s));
-  MSKM_HIP_TRY(hipStreamSynchronize(s));
+  MSKM_TRY(upload_async(h, wt->lev, lev.data(), lev.size() * 4));
+  MSKM_TRY(upload_async(h, wt->row0, r0.data(), r0.size() * 8));
+  MSKM_TRY(upload_async(h, wt->row1, r1.data(), r1.size() * 8));
+  MSKM_TRY(upload_async(h, wt->lev_begin, wt->h_lev_begin.data(), wt->h_lev_begin.size() * 4));
   return MSKM_OK;
 }
 
@@ -737,7 +734,9 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   hipStream_t s = h->ctx->stream;
   const int L = h->L, dim = h->dim;
   const int64_t N = h->N;
-  MSKM_HIP_TRY(hipEventRecord(h->ctx->ev0, s));
+  for (hipEvent_t* e : {&h->ev_asm[0], &h->ev_asm[1]})
+    if (!*e) MSKM_HIP_TRY(hipEventCreate(e));
+  MSKM_HIP_TRY(hipEventRecord(h->ev_asm[0], s));
 
   std::vector<int64_t> rng(2 * (size_t)L);
   for (int l = 0; l < L; ++l) {
@@ -814,7 +813,7 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   }
   if (cs_total >= INT32_MAX) return fail(MSKM_ELIMIT, "cell tables too large");
   MSKM_TRY(halloc(h, &h->d_lev, L));
-  MSKM_HIP_TRY(hipMemcpyAsync(h->d_lev, h->h_lev.data(), L * sizeof(DevLevel), hipMemcpyHostToDevice, s));
+  MSKM_TRY(upload_async(h, h->d_lev, h->h_lev.data(), L * sizeof(DevLevel)));
 
   // 3. counting sort into cells. Scratch of the sort, the counts and the
   //    scans: one allocation, freed once the fill pass is queued (a free
@@ -926,11 +925,8 @@ mskm_status assemble_hierarchy(mskm_hier* h, const double* pts, bool want64, boo
   }
   MSKM_TRY(build_sell(h, want64, want32, want_lsell));
   if (want_lsell) MSKM_TRY(build_lsell(h, want64, want32, cnt_lv));
-  MSKM_HIP_TRY(hipEventRecord(h->ctx->ev1, s));
-  MSKM_HIP_TRY(hipEventSynchronize(h->ctx->ev1));
-  float ms = 0.f;
-  MSKM_HIP_TRY(hipEventElapsedTime(&ms, h->ctx->ev0, h->ctx->ev1));
-  h->assemble_ms = ms;
+  MSKM_HIP_TRY(hipEventRecord(h->ev_asm[1], s));
+  h->asm_pending = true;  // assemble_ms is read at the first statistics query
   MSKM_HIP_TRY(hipGetLastError());
   return MSKM_OK;
 }
@@ -1155,13 +1151,10 @@ static mskm_status build_sell(mskm_hier* h, bool want64, bool want32, bool with_
   MSKM_TRY(halloc(h, &wt.row0, r0.size()));
   MSKM_TRY(halloc(h, &wt.row1, r1.size()));
   MSKM_TRY(halloc(h, &wt.lev_begin, wt.h_lev_begin.size()));
-  if (!lev.empty()) {
-    MSKM_HIP_TRY(hipMemcpyAsync(wt.lev, lev.data(), lev.size() * 4, hipMemcpyHostToDevice, s));
-    MSKM_HIP_TRY(hipMemcpyAsync(wt.row0, r0.data(), r0.size() * 8, hipMemcpyHostToDevice, s));
-    MSKM_HIP_TRY(hipMemcpyAsync(wt.row1, r1.data(), r1.size() * 8, hipMemcpyHostToDevice, s));
-  }
-  MSKM_HIP_TRY(hipMemcpyAsync(wt.lev_begin, wt.h_lev_begin.data(), wt.h_lev_begin.size() * 4, hipMemcpyHostToDevice,
-                              s));
+  MSKM_TRY(upload_async(h, wt.lev, lev.data(), lev.size() * 4));
+  MSKM_TRY(upload_async(h, wt.row0, r0.data(), r0.size() * 8));
+  MSKM_TRY(upload_async(h, wt.row1, r1.data(), r1.size() * 8));
+  MSKM_TRY(upload_async(h, wt.lev_begin, wt.h_lev_begin.data(), wt.h_lev_begin.size() * 4));
   MSKM_HIP_TRY(hipGetLastError());
   return MSKM_OK;
 }

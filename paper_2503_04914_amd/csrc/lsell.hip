@@ -204,8 +204,7 @@ mskm_status build_lsell(mskm_hier* h, bool want64, bool want32, const int32_t* c
       ss[sl] = seg0[l] + (sl - S.h_slice_begin[l]) * h->h_depth[l];
   ss[S.nslices] = X.nseg;
   MSKM_TRY(halloc(h, &X.slice_seg, ss.size()));
-  MSKM_HIP_TRY(hipMemcpyAsync(X.slice_seg, ss.data(), ss.size() * 8, hipMemcpyHostToDevice, s));
-  MSKM_HIP_TRY(hipStreamSynchronize(s));  // the host table above is copied from the stack
+  MSKM_TRY(upload_async(h, X.slice_seg, ss.data(), ss.size() * 8));
   X.built = true;
   MSKM_HIP_TRY(hipGetLastError());
   return MSKM_OK;

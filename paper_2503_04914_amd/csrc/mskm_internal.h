@@ -257,8 +257,17 @@ struct mskm_hier {
   int32_t mr_chunk[8][2] = {};
   int64_t device_bytes = 0;
   double assemble_ms = 0.0;
+  // assembly timing: events around the assembly's launches, read at the first
+  // statistics query (creation returns without waiting for its last kernels)
+  hipEvent_t ev_asm[2] = {nullptr, nullptr};
+  bool asm_pending = false;
   std::vector<void*> allocs;            // everything to free (given back to the context's block cache)
   std::vector<size_t> alloc_bytes;      // their sizes
+  // pinned staging of host-built tables (upload_async); released at destroy,
+  // after the stream has drained, so no upload waits on its copy
+  std::vector<void*> stage_blocks;
+  std::vector<size_t> stage_bytes;
+  size_t stage_used = 0;                // bytes taken from the last staging block
   int32_t* knn = nullptr;               // [N][16] same-level nearest neighbours (learned warm start)
   std::vector<mskm_trunc*> truncs;      // thresholded blocks built on this hierarchy (detached at destroy)
   void* solve_ws = nullptr;             // solver workspace (solve.hip), created on first solve
@@ -295,6 +304,10 @@ void ctx_trim(mskm_ctx* c);
 // Pinned host blocks: from the cache, else hipHostMalloc; given back likewise.
 mskm_status ctx_host_alloc(mskm_ctx* c, size_t bytes, void** out);
 void ctx_host_release(mskm_ctx* c, void* p, size_t bytes);
+// Queues a host-to-device copy of `bytes` from host memory src to device dst
+// on the context stream through the hierarchy's pinned staging blocks: src
+// may be reused at once, and the host does not wait for the copy.
+mskm_status upload_async(mskm_hier* h, void* dst, const void* src, size_t bytes);
 
 
 // device allocation tracked by the hierarchy

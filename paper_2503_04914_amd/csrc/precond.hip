@@ -292,8 +292,7 @@ mskm_status build_block_jacobi(mskm_hier* h) {
   MSKM_TRY(halloc(h, &wt.row0, (size_t)ng));
   MSKM_TRY(halloc(h, &wt.row1, (size_t)ng));
   MSKM_TRY(halloc(h, &wt.lev_begin, wt.h_lev_begin.size()));
-  MSKM_HIP_TRY(hipMemcpyAsync(wt.lev_begin, wt.h_lev_begin.data(), wt.h_lev_begin.size() * 4, hipMemcpyHostToDevice,
-                              s));
+  MSKM_TRY(upload_async(h, wt.lev_begin, wt.h_lev_begin.data(), wt.h_lev_begin.size() * 4));
   if (B.nblocks > 0)
     hipLaunchKernelGGL(k_bj_groups, dim3((unsigned)((B.nblocks + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        B.nblocks, B.start, h->d_lev, L, wt.lev_begin, wt.lev, wt.row0, wt.row1);
