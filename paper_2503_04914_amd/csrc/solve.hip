@@ -349,6 +349,7 @@ __device__ __forceinline__ double lsell_seg_dot_split(int32_t base, int t, int64
                                                       const uint16_t* __restrict__ col16, const float* __restrict__ hi,
                                                       const float* __restrict__ lo, const VA& x) {
   double acc = 0.0;
+#pragma unroll 2
   for (int64_t d = e0 + 4 * t; d < e1; d += 4 * kSellC) {
     const sf4 h = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(hi + d));
     const sf4 l = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(lo + d));
@@ -367,6 +368,7 @@ __device__ __forceinline__ double sell_slot_dot_split(int64_t sl, int t, int64_t
                                                       const SellCols<C16>& cols, const float* __restrict__ hi,
                                                       const float* __restrict__ lo, const VA& x) {
   double acc = 0.0;
+#pragma unroll 2
   for (int64_t d = e0 + 4 * t; d < e1; d += 4 * kSellC) {
     const sf4 h = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(hi + d));
     const sf4 l = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(lo + d));
