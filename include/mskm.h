@@ -169,6 +169,9 @@ typedef struct {
   int64_t lower_sliced_entries; /* its stored entries, padding included */
 } mskm_hier_stats;
 
+/* The first call after creation waits for the assembly's last passes (it
+ * reads assemble_ms from their events); later calls do not wait.
+ * MSKM_EDEVICE when those events cannot be read. */
 mskm_status mskm_hier_stats_get(const mskm_hier* h, mskm_hier_stats* out);
 
 /* Cumulative level sizes in level order: level l holds off[l+1]-off[l]

@@ -56,3 +56,39 @@ def test_rebuild_on_cached_blocks_is_bit_identical(fp32_only):
             assert np.linalg.norm(a1[sl] - ref[sl]) / np.linalg.norm(ref[sl]) <= (1e-8 if fp32_only else 1e-10)
     finally:
         m.mskm_destroy(ctx)
+
+
+def test_creation_returns_before_its_last_passes():
+    """mskm_hier_create returns once the last assembly passes are queued: a
+    destroy right after it (which waits for the stream) and creations in a
+    row on the same blocks and pinned staging must leave every later
+    hierarchy intact; the assembly time is read at the first statistics
+    query."""
+    import paper_2503_04914_amd as m
+
+    h = synth.halton_hierarchy(5)
+    ctx = m.mskm_create(0)
+    try:
+        print("[cache] create / destroy at once", flush=True)
+        for _ in range(3):  # destroyed while its sliced copies may still be written
+            m.mskm_hier_destroy(m.mskm_hier_create(ctx, h.points, h.offsets, h.delta, fp64=True, fp32=True,
+                                                   sliced_lower=True))
+        hs = [m.mskm_hier_create(ctx, h.points, h.offsets, h.delta, fp64=True, fp32=True, sliced_lower=True)
+              for _ in range(3)]
+        try:
+            st = [m.mskm_hier_stats_get(x) for x in hs]
+            assert all(s["assemble_ms"] > 0.0 for s in st)
+            assert m.mskm_hier_stats_get(hs[0])["assemble_ms"] == st[0]["assemble_ms"]  # read once, kept
+            blks = [m.mskm_export_block(ctx, x, h.levels - 1, h.levels - 3) for x in hs]
+            for b in blks[1:]:
+                for u, v in zip(b, blks[0]):
+                    assert np.array_equal(u, v)
+            orp, ocol, oval = ms.assemble(h.points, h.offsets, h.delta).csr[(h.levels - 1, h.levels - 3)]
+            rp, col, val = blks[0]
+            assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+            np.testing.assert_allclose(val, oval, rtol=1e-15, atol=0)
+        finally:
+            for x in hs:
+                m.mskm_hier_destroy(x)
+    finally:
+        m.mskm_destroy(ctx)
