@@ -103,8 +103,9 @@ typedef struct mskm_hier mskm_hier;
  * NULL to let the library create its own). The context owns nothing the
  * caller passed. Fails with MSKM_EDEVICE if the device cannot be used. */
 mskm_status mskm_create(int32_t device, void* hip_stream, mskm_ctx** out);
-/* Frees the context, including the device blocks it keeps from destroyed
- * hierarchies (see mskm_hier_destroy). */
+/* Frees the context, including the device and pinned blocks it keeps from
+ * destroyed hierarchies (see mskm_hier_destroy). Hierarchies created on it
+ * are destroyed first: they give their blocks back to it. */
 mskm_status mskm_destroy(mskm_ctx* ctx);
 
 /* Thread-local description of the last failure ("" if none). */

@@ -192,6 +192,7 @@ mskm_status mskm_destroy(mskm_ctx* c) {
     (void)hipStreamSynchronize(c->side);
     (void)hipStreamDestroy(c->side);
   }
+  mskm::ctx_trim(c);  // the cached device and pinned blocks of destroyed hierarchies
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return MSKM_OK;

@@ -49,6 +49,9 @@ def mod():
 def ctx(mod):
     c = mod.mskm_create(0)
     yield c
+    for entry in _cache.values():  # hierarchies go before their context
+        mod.mskm_hier_destroy(entry[3])
+    _cache.clear()
     mod.mskm_destroy(c)
 
 
