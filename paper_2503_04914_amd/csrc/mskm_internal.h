@@ -115,16 +115,12 @@ struct LSell {
 // cell of the level's grid (cells hold consecutive internal rows; cells of
 // more than kBjMax rows are cut into near-equal chunks), inverted densely.
 constexpr int kBjMax = 32;         // largest block
-constexpr int kBjGroupRows = 1024; // rows of one workgroup of whole blocks (at most)
-// Window of block starts of one workgroup: groups of up to 1024 rows on
-// large levels, of up to 256 rows on levels of at most 65536 rows, whose
-// few-workgroup, latency-bound launches then spread over more CUs with one
-// row per thread.
-constexpr int kBjSmallGroupRows = 256;
-constexpr int64_t kBjSmallLevelRows = 65536;
-__host__ __device__ inline int64_t bj_group_step(int64_t level_rows) {
-  return (level_rows <= kBjSmallLevelRows ? kBjSmallGroupRows : kBjGroupRows) - kBjMax + 1;
-}
+// Rows of one workgroup of whole blocks (at most): 256, so that the
+// latency-bound preconditioned updates of small levels spread over many CUs
+// with one row per thread (1024-row groups, four rows per thread, made the
+// fast solve 4% slower).
+constexpr int kBjGroupRows = 256;
+constexpr int kBjGroupStep = kBjGroupRows - kBjMax + 1;  // window of block starts of one workgroup
 struct BlockJacobi {
   bool built = false;
   int64_t nblocks = 0, nvals = 0;
