@@ -115,12 +115,19 @@ struct LSell {
 // cell of the level's grid (cells hold consecutive internal rows; cells of
 // more than kBjMax rows are cut into near-equal chunks), inverted densely.
 constexpr int kBjMax = 32;         // largest block
-// Rows of one workgroup of whole blocks (at most): 256, so that the
-// latency-bound preconditioned updates of small levels spread over many CUs
-// with one row per thread (1024-row groups, four rows per thread, made the
-// fast solve 4% slower).
-constexpr int kBjGroupRows = 256;
-constexpr int kBjGroupStep = kBjGroupRows - kBjMax + 1;  // window of block starts of one workgroup
+// Rows of one workgroup of whole blocks (at most): 1024 on levels of more
+// than 524288 rows (at least 512 workgroups, two per CU, each thread walking
+// four rows), 256 below, so that the latency-bound preconditioned updates of
+// the smaller levels spread over many CUs with one row per thread (1024-row
+// groups there made the fast solve 4% slower; 256-row groups on a 1M-row
+// level made its update 13% slower).
+constexpr int kBjGroupRows = 1024;
+constexpr int kBjSmallGroupRows = 256;
+constexpr int64_t kBjLargeLevelRows = 524288;
+// Window of block starts of one workgroup on a level of n rows.
+__host__ __device__ inline int64_t bj_group_step(int64_t n) {
+  return (n > kBjLargeLevelRows ? kBjGroupRows : kBjSmallGroupRows) - kBjMax + 1;
+}
 struct BlockJacobi {
   bool built = false;
   int64_t nblocks = 0, nvals = 0;

@@ -139,11 +139,11 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Workgroups of whole blocks: within a level, the blocks whose first row
-// falls in one window of kBjGroupStep rows (windows counted from the level's
-// first row) form one group, so a group spans at most kBjGroupStep - 1 +
-// kBjMax = kBjGroupRows rows. Any window of at least kBjMax rows holds a
+// falls in one window of step = bj_group_step(n) rows (windows counted from
+// the level's first row) form one group, so a group spans at most step - 1 +
+// kBjMax <= kBjGroupRows rows. Any window of at least kBjMax rows holds a
 // block start (blocks have at most kBjMax rows); a shorter last window is
-// merged into the one before it (at most kBjGroupStep + kBjMax - 1 rows).
+// merged into the one before it (at most step + kBjMax - 1 rows).
 // gbase = first group of each level, its window count gbase[l+1] - gbase[l].
 __global__ void __launch_bounds__(kBlock)
     k_bj_groups(int64_t nb, const int64_t* __restrict__ start, const DevLevel* __restrict__ lev, int L,
@@ -163,8 +163,9 @@ __global__ void __launch_bounds__(kBlock)
   }
   const int64_t l0 = lev[lo].off, l1 = l0 + lev[lo].n;
   const int64_t nw = gbase[lo + 1] - gbase[lo];
-  const int64_t w = min((s - l0) / kBjGroupStep, nw - 1);
-  const int64_t w0 = l0 + w * kBjGroupStep, w1 = w == nw - 1 ? l1 : w0 + kBjGroupStep;
+  const int64_t step = bj_group_step(lev[lo].n);
+  const int64_t w = min((s - l0) / step, nw - 1);
+  const int64_t w0 = l0 + w * step, w1 = w == nw - 1 ? l1 : w0 + step;
   const int g = gbase[lo] + (int)w;
   if (b == 0 || start[b - 1] < w0) {
     row0[g] = s;
@@ -272,7 +273,7 @@ mskm_status build_block_jacobi(mskm_hier* h) {
     B.side_pending = true;
     B.side_started = false;
   }
-  // workgroups of whole blocks: one per window of kBjGroupStep rows, a last
+  // workgroups of whole blocks: one per window of bj_group_step rows, a last
   // window shorter than kBjMax merged into the one before
   WorkTable& wt = B.wt;
   wt.h_lev_begin.assign(L + 1, 0);
@@ -280,8 +281,9 @@ mskm_status build_block_jacobi(mskm_hier* h) {
   for (int l = 0; l < L; ++l) {
     wt.h_lev_begin[l] = (int32_t)ng;
     const int64_t n = h->h_lev[l].n;
-    int64_t nw = (n + kBjGroupStep - 1) / kBjGroupStep;
-    if (nw > 1 && n - (nw - 1) * kBjGroupStep < kBjMax) --nw;
+    const int64_t step = bj_group_step(n);
+    int64_t nw = (n + step - 1) / step;
+    if (nw > 1 && n - (nw - 1) * step < kBjMax) --nw;
     ng += nw;
     if (ng > (int64_t)INT32_MAX) return fail(MSKM_ELIMIT, "block-Jacobi tables too large");
   }
