@@ -327,7 +327,7 @@ enum {
  *                        same level, the final D alpha = beta from the last
  *                        sweep's (monolithic algorithm; zero elsewhere);
  *   MSKM_START_LEARNED   the network opts.mlp predicts x0 from the level's
- *                        right-hand side; combines with any precond. CG judges
+ *                        right-hand side; combines with any precond. CG checks
  *                        it: a level with ||b - A x0|| >= ||b|| restarts from 0. */
 enum { MSKM_START_ZERO = 0, MSKM_START_PREVIOUS = 1, MSKM_START_LEARNED = 2 };
 

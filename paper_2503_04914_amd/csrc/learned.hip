@@ -12,7 +12,7 @@
 // Adam on the mean squared error, the first layer with the same BF16-rounded
 // weights and features as inference) on (rhs stencil -> correction / s)
 // samples drawn from the solver's own sequential solves, or on samples the
-// caller gives. CG judges the result: a level whose warm start does
+// caller gives. CG checks the result: a level whose warm start does
 // not reduce ||b - A x0|| below ||b|| restarts from zero.
 #include <algorithm>
 #include <cmath>

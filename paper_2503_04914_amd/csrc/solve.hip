@@ -1481,7 +1481,7 @@ static mskm_status cg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::v
                        dval, b, x, (TX*)W.r, (TX*)W.p0, W.st, warm ? 1 : 0, W.part_s, W.part_s2, sb0, (TX*)W.p1);
   hipLaunchKernelGGL(k_cg_red_init, dim3(nlev), dim3(kRedBlock), 0, s, lo, ws.lev_begin, W.part_s, W.part_s2, W.st);
   if (bj) launch_bj_apply<TX>(h, lo, hi, (const TX*)W.r, (TX*)W.z);
-  if (mlp) {  // CG judges the warm start: ||b - A x0|| >= ||b|| restarts that level from zero
+  if (mlp) {  // CG checks the warm start: ||b - A x0|| >= ||b|| restarts that level from zero
     MSKM_HIP_TRY(hipMemcpyAsync(W.h_st, W.st, h->L * sizeof(CgLevel), hipMemcpyDeviceToHost, s));
     MSKM_HIP_TRY(hipStreamSynchronize(s));
     bool again = false;
@@ -2478,7 +2478,7 @@ mskm_status solve(mskm_hier* h, const double* f_in, int nrhs, const mskm_solve_o
   MSKM_TRY(stage_out_copy(s, alpha_out, (size_t)N * nrhs, io_dev, A));
   float ms = 0.f;
   MSKM_HIP_TRY(hipEventElapsedTime(&ms, h->ctx->ev0, h->ctx->ev1));
-  // the mixed path is judged by its FP64 outer residual alone (its FP32 inner
+  // the mixed path is decided by its FP64 outer residual alone (its FP32 inner
   // solves stop at their attainable accuracy by design)
   const bool enoconv = mixed ? worst_rel > o->target_rel_residual : cs.capped;
   if (rep) {

@@ -9,8 +9,8 @@
   FP64 training run; determinism; the loss falls on pairs from the solver;
   save/load round trip;
 * solves with the warm start, and with the network as a preconditioner inside
-  flexible CG: coefficients still match the oracle (the true residual is the
-  judge), FP64 <= 1e-10, mixed <= 1e-8; with a zero network flexible CG is
+  flexible CG: coefficients still match the oracle (the true residual decides
+  convergence), FP64 <= 1e-10, mixed <= 1e-8; with a zero network flexible CG is
   block-Jacobi PCG (same coefficients, about the same iterations).
 """
 import numpy as np

@@ -265,7 +265,7 @@ def test_level_size_boundaries(mod, ctx):
     preconditioner blocks merged into the one before) and 2018 rows (not
     merged). Plain and preconditioned, FP64 and mixed, both algorithms. The
     near-duplicate level pairs make some levels' right-hand sides tiny and
-    their coefficients sensitive, so every solve is judged by the oracle's
+    their coefficients sensitive, so every solve is checked by the oracle's
     monolithic residual of the GPU coefficients (and the coefficients are
     checked against the oracle's loosely)."""
     h = synth.halton_hierarchy(sizes=[64, 257, 1024, 1025, 2017, 2018, 3000])
