@@ -651,6 +651,81 @@ __global__ void __launch_bounds__(kBlock)
   if (p3) block_partial(s3, sm, p3, blk);
 }
 
+// Slot t's share of slice sl with x for one of two waves per slice: the
+// 4-entry groups of parity par (entries in order within the share), with
+// ordinary loads, so a small level's entries stay in L2 between iterations.
+template <typename TV, typename TX>
+__device__ __forceinline__ TX sell_slot_dot_half(int64_t sl, int t, int par, int64_t e0, int64_t e1,
+                                                 const SellCols<true>& cols, const TV* __restrict__ val,
+                                                 const TX* __restrict__ x) {
+  TX acc = 0;
+  const int32_t o = cols.cbase[sl];
+#pragma unroll 2
+  for (int64_t d = e0 + 4 * t + 4 * kSellC * par; d < e1; d += 8 * kSellC) {
+    TV v[4];
+    if constexpr (sizeof(TV) == 4) {
+      const sf4 a = *reinterpret_cast<const sf4*>(val + d);
+      v[0] = a.x;
+      v[1] = a.y;
+      v[2] = a.z;
+      v[3] = a.w;
+    } else {
+      const sd2 a = *reinterpret_cast<const sd2*>(val + d);
+      const sd2 b = *reinterpret_cast<const sd2*>(val + d + 2);
+      v[0] = a.x;
+      v[1] = a.y;
+      v[2] = b.x;
+      v[3] = b.y;
+    }
+    const su4 c = *reinterpret_cast<const su4*>(cols.col16 + d);
+    acc += (TX)v[0] * x[o + (int32_t)c.x];
+    acc += (TX)v[1] * x[o + (int32_t)c.y];
+    acc += (TX)v[2] * x[o + (int32_t)c.z];
+    acc += (TX)v[3] * x[o + (int32_t)c.w];
+  }
+  return acc;
+}
+
+// The product below for levels of few rows, whose launches are bound by the
+// latency of each lane's chain of dependent loads: two waves per slice (the
+// same blocks of 4 slices, 512 threads), each taking every other 4-entry
+// group of its slots, the halves added through LDS.
+template <typename TV, typename TX>
+__global__ void __launch_bounds__(2 * kBlock)
+    k_cg_spmv1_sell2(const WorkTable wt, int base, const int64_t* __restrict__ sptr, const int32_t* __restrict__ rows,
+                     const SellCols<true> cols, const TV* __restrict__ val, const TX* __restrict__ p,
+                     TX* __restrict__ q, const CgLevel* __restrict__ st, double* __restrict__ pqp,
+                     double* __restrict__ ppp, const TX* __restrict__ rv, double* __restrict__ p3) {
+  __shared__ double sm[2 * kBlock / kWave];
+  __shared__ TX half[kBlock];  // the odd groups' share of each slot
+  const int blk = base + xcd_block_id(gridDim.x);
+  const int l = wt.lev[blk];
+  if (st[l].done) return;  // uniform over the block
+  const int w = threadIdx.x / kWave, t = threadIdx.x % kSellC;
+  const int ls = w >> 1, par = w & 1;  // slice of the block, group parity
+  const int64_t sl = wt.row0[blk] + ls;
+  const bool on = sl < wt.row1[blk];
+  TX acc = 0;
+  if (on) acc = sell_slot_dot_half<TV, TX>(sl, t, par, sptr[sl], sptr[sl + 1], cols, val, p);
+  if (par) half[ls * kSellC + t] = acc;
+  __syncthreads();
+  double s = 0.0, s2 = 0.0, s3 = 0.0;
+  if (on && !par) {
+    acc += half[ls * kSellC + t];
+    const int32_t row = rows[sl * kSellC + t];
+    if (row >= 0) {
+      q[row] = acc;
+      const double vi = (double)p[row], wi = rv ? (double)rv[row] : vi;
+      s = vi * (double)acc;
+      s2 = vi * wi;
+      s3 = wi * wi;
+    }
+  }
+  block_partial(s, sm, pqp, blk);
+  if (ppp) block_partial(s2, sm, ppp, blk);
+  if (p3) block_partial(s3, sm, p3, blk);
+}
+
 // The same from the sliced copy (variant kSellCode): blocks of 4 slices of
 // one level.
 template <typename TV, typename TX, bool C16>
@@ -1251,13 +1326,20 @@ static PcArgs<TX> pc_args(mskm_hier* h, SolveWS& W) {
 // table (the sliced copy's for variants kSellCode / kSell32Code, else the
 // CSR table), with the per-block partials v.q into W.part_s and, when given,
 // v.rv (v.v without rv) into pp and rv.rv into p3.
+// Levels of at most this many rows take the two-waves-per-slice product.
+constexpr int64_t kSplitProductRows = 65536;
+
 template <typename TV, typename TX>
 static void launch_cg_product(mskm_hier* h, SolveWS& W, const TV* dval, int G, int qb0, int qbn, const TX* v, TX* q,
-                              double* pp, const TX* rv, double* p3, const CgLevel* st) {
+                              double* pp, const TX* rv, double* p3, const CgLevel* st, bool split) {
   if (qbn <= 0) return;
   hipStream_t s = h->ctx->stream;
   const bool sell = G == kSellCode || G == kSell32Code;
-  if (sell && G == kSellCode && h->sell.col16)
+  if (split && sell && G == kSellCode && h->sell.col16)
+    hipLaunchKernelGGL((k_cg_spmv1_sell2<TV, TX>), dim3(qbn), dim3(2 * kBlock), 0, s, h->wt_sell, qb0, h->sell.sptr,
+                       h->sell.rows, SellCols<true>{h->sell.col16, h->sell.cbase}, sell_values<TV>(h->sell), v, q, st,
+                       W.part_s, pp, rv, p3);
+  else if (sell && G == kSellCode && h->sell.col16)
     hipLaunchKernelGGL((k_cg_spmv1_sell<TV, TX, true>), dim3(qbn), dim3(kBlock), 0, s, h->wt_sell, qb0, h->sell.sptr,
                        h->sell.rows, SellCols<true>{h->sell.col16, h->sell.cbase}, sell_values<TV>(h->sell), v, q, st,
                        W.part_s, pp, rv, p3);
@@ -1290,8 +1372,9 @@ static void enqueue_chunk(mskm_hier* h, SolveWS& W, const TV* dval, int lo, int 
   TX* q = (TX*)W.q;
   const PcArgs<TX> pc = pc_args<TX>(h, W);
   // q = A v with partials v.q, v.rv (v.v without rv) when pp, rv.rv when p3
+  const bool split = h->h_off[hi + 1] - h->h_off[lo] <= kSplitProductRows;
   auto product = [&](const TX* v, double* pp, const TX* rv, double* p3, const CgLevel* st) {
-    launch_cg_product<TV, TX>(h, W, dval, G, qb0, qbn, v, q, pp, rv, p3, st);
+    launch_cg_product<TV, TX>(h, W, dval, G, qb0, qbn, v, q, pp, rv, p3, st, split);
   };
   // fold the reduction into the update when every level's partials are few
   int maxpart = 0;
@@ -1765,7 +1848,8 @@ static mskm_status fcg_run(mskm_hier* h, SolveWS& W, const TV* dval, const std::
   std::vector<CgLevel> fin(h->L);
   for (int it = 0; it < maxit; it += K) {
     for (int kk = 0; kk < K; ++kk) {
-      launch_cg_product<TV, TX>(h, W, dval, G, qb0, qbn, (const TX*)p, q, W.part_s2, (const TX*)r, nullptr, W.st);
+      launch_cg_product<TV, TX>(h, W, dval, G, qb0, qbn, (const TX*)p, q, W.part_s2, (const TX*)r, nullptr, W.st,
+                                h->h_off[hi + 1] - h->h_off[lo] <= kSplitProductRows);
       hipLaunchKernelGGL(k_fcg_red, dim3(nlev), dim3(kRedBlock), 0, s, 1, lo, wq.lev_begin, W.part_s, W.part_s2,
                          wv.lev_begin, W.part_v, W.st);
       if (vbn > 0)
@@ -2682,8 +2766,9 @@ static mskm_status time_cg_product_t(mskm_hier* h, const TV* dval, int level, in
   hipLaunchKernelGGL(k_fill<TX>, dim3(nblk(N)), dim3(kBlock), 0, s, r, N, (TX)1);
   MSKM_HIP_TRY(hipMemsetAsync(W.st, 0, 2 * (size_t)h->L * sizeof(CgLevel), s));  // every level running
   MSKM_HIP_TRY(hipEventRecord(h->ctx->ev0, s));
+  const bool split = h->h_off[level + 1] - h->h_off[level] <= kSplitProductRows;  // as the solver launches it
   for (int k = 0; k < repeats; ++k)
-    launch_cg_product<TV, TX>(h, W, dval, G, qb0, qbn, z, (TX*)W.q, W.part_s2, r, W.part_s3, W.st);
+    launch_cg_product<TV, TX>(h, W, dval, G, qb0, qbn, z, (TX*)W.q, W.part_s2, r, W.part_s3, W.st, split);
   MSKM_HIP_TRY(hipEventRecord(h->ctx->ev1, s));
   MSKM_HIP_TRY(hipEventSynchronize(h->ctx->ev1));
   float ms = 0.f;
