@@ -86,3 +86,19 @@ def test_solve_opts_defaults(lib):
     o = m.mskm_solve_opts_default()
     assert o.precision == m.MSKM_PREC_FP64 and o.algorithm == m.MSKM_ALG_MONOLITHIC
     assert o.cg_rtol == 1e-12 and o.sweeps == 0 and o.target_rel_residual == 1e-8
+
+
+def test_torch_stream_must_not_be_the_default_stream(lib, monkeypatch):
+    """stream="torch" shares torch's current stream with the library; torch's
+    default stream has a null handle, which the C ABI reads as "create a
+    stream of your own" (unordered with torch's work), so the binding refuses
+    it before any call into the library."""
+    import paper_2503_04914_amd as m
+    import torch
+
+    class _Default:
+        cuda_stream = 0
+
+    monkeypatch.setattr(torch.cuda, "current_stream", lambda device=None: _Default())
+    with pytest.raises(ValueError, match="default stream"):
+        m.mskm_create(0, stream="torch")
