@@ -7,8 +7,10 @@ phi_{3,1} with delta_j = sqrt(40/pi) * N_j^(-1/2) (about 40 neighbours per
 row), target = seeded sum of 32 random Fourier modes. Inputs are generated on
 the host and placed in HBM before anything is timed.
 
-One step = one pass of the whole path over that input:
-  assembly (cell lists, neighbour search, Wendland blocks into CSR) ->
+One step = one pass of the whole path over that input (each phase timed by
+HIP events on the one stream that torch and the library share):
+  assembly (cell lists, neighbour search, Wendland blocks into CSR and the
+  sliced copies) ->
   solve to ||f - T alpha|| / ||f|| <= 1e-8 with the fast form (FP32 values
   and accumulation inside, FP64 dots and FP64 residual refinement, block
   forward substitution) -> independent FP64 residual check -> evaluation of
