@@ -383,13 +383,12 @@ mskm_status mskm_hier_stats_get(const mskm_hier* h, mskm_hier_stats* o) {
   o->has_fp32 = h->diag.val32 != nullptr;
   o->device_bytes = h->device_bytes;
   if (h->asm_pending) {  // the assembly's last kernels may still have been running at creation's return
-    mskm_hier* m = const_cast<mskm_hier*>(h);
     float ms = 0.f;
-    if (hipEventSynchronize(m->ev_asm[1]) != hipSuccess ||
-        hipEventElapsedTime(&ms, m->ev_asm[0], m->ev_asm[1]) != hipSuccess)
+    if (hipEventSynchronize(h->ev_asm[1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, h->ev_asm[0], h->ev_asm[1]) != hipSuccess)
       return fail(MSKM_EDEVICE, "assembly timing events");
-    m->assemble_ms = ms;
-    m->asm_pending = false;
+    h->assemble_ms = ms;
+    h->asm_pending = false;
   }
   o->assemble_ms = h->assemble_ms;
   o->ngroups = h->ngroups;

@@ -267,11 +267,11 @@ struct mskm_hier {
   // [FP64, FP32] (0: not tuned yet; set by timing at the first solve with R)
   int32_t mr_chunk[8][2] = {};
   int64_t device_bytes = 0;
-  double assemble_ms = 0.0;
   // assembly timing: events around the assembly's launches, read at the first
   // statistics query (creation returns without waiting for its last kernels)
+  mutable double assemble_ms = 0.0;
   hipEvent_t ev_asm[2] = {nullptr, nullptr};
-  bool asm_pending = false;
+  mutable bool asm_pending = false;
   std::vector<void*> allocs;            // everything to free (given back to the context's block cache)
   std::vector<size_t> alloc_bytes;      // their sizes
   // pinned staging of host-built tables (upload_async); released at destroy,
